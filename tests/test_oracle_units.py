@@ -1,0 +1,373 @@
+"""Pins of the CPU oracle against facts fixed by the paper or by mathematics
+(hand-derived traces, closed forms, lemmas, a second algorithm)."""
+import math
+
+import numpy as np
+import pytest
+
+import lpgen
+import oracle
+from _util import golden, lp_from_dense
+
+
+# ---------------------------------------------------------------------------
+# the toy LP of Section 5.2, traced by hand
+# ---------------------------------------------------------------------------
+
+def test_toy_first_steps_match_hand_trace():
+    g = golden("toy_lp.json")
+    P = oracle.Problem.from_lpdata(lpgen.toy_lp())
+    s = oracle.Solver(P, oracle.Options(tau=g["tau"], sigma=g["sigma"], memory=5, D=10.0,
+                                        eps_sg=1.0, eta=1e-10, kkt_every=0, max_iter=10))
+    st = s.start()
+    np.testing.assert_allclose(np.r_[st.x, st.y], g["u1"], atol=1e-15)
+    np.testing.assert_allclose(st.g_prev, g["g0"], atol=1e-15)
+    xh, yh = oracle.pdhg_map(P, st.x, st.y, g["tau"], g["sigma"])
+    np.testing.assert_allclose(np.r_[xh, yh], g["T_u1"], atol=1e-15)
+    s.step()
+    st = s.state
+    np.testing.assert_allclose(st.dU[0], g["dU0"], atol=1e-15)
+    np.testing.assert_allclose(st.dG[0], g["dG0"], atol=1e-15)
+    np.testing.assert_allclose(st.g_prev, g["g1"], atol=1e-15)
+    assert s.last_branch == "aa"
+    np.testing.assert_allclose(s.last_gamma[0], g["gamma"], rtol=1e-6)
+    np.testing.assert_allclose(np.r_[st.x, st.y], g["u2"], rtol=1e-6)
+
+
+def test_toy_reaches_optimum_in_a_few_aa_steps():
+    # Section 5.2: AA-PDHG reaches (3,0) in a few iterations; while x > 0 the map
+    # is affine and AA behaves like GMRES on a 2-dimensional problem.
+    g = golden("toy_lp.json")
+    P = oracle.Problem.from_lpdata(lpgen.toy_lp())
+    res, s = oracle.solve(P, tau=0.1, sigma=0.1, memory=5, tol=1e-10, kkt_every=1, max_iter=20)
+    assert res["status"] == "converged"
+    assert res["k"] <= 5
+    np.testing.assert_allclose(np.r_[res["x"], res["y"]], g["optimum"], atol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# KKT residual and D-hat: hand-computed cases
+# ---------------------------------------------------------------------------
+
+def _kkt_lp():
+    g = golden("kkt_cases.json")["lp"]
+    return oracle.Problem.from_lpdata(lp_from_dense(g["dense_K"], g["q"], g["c"], g["l"], g["u"], g["rowtype"]))
+
+
+@pytest.mark.parametrize("case", [0, 1])
+def test_kkt_hand_cases(case):
+    g = golden("kkt_cases.json")["cases"][case]
+    P = _kkt_lp()
+    r = oracle.kkt(P, np.array(g["x"], float), np.array(g["y"], float))
+    for key in ("pobj", "dobj", "r_g", "r_p", "r_d"):
+        assert r[key] == pytest.approx(g[key], rel=1e-14, abs=1e-15), key
+    np.testing.assert_allclose(r["lam"], g["lam"], atol=0)
+    assert r["kkt"] == pytest.approx(max(g["r_g"], g["r_p"], g["r_d"]), rel=1e-14)
+
+
+def test_dhat_hand_case():
+    g = golden("kkt_cases.json")["dhat"]
+    P = _kkt_lp()
+    np.testing.assert_allclose(oracle.dhat(P, 1), g["literal"], rtol=1e-15)
+    np.testing.assert_allclose(oracle.dhat(P, 2), 1.0 / np.array(g["literal"]), rtol=1e-15)
+    np.testing.assert_array_equal(oracle.dhat(P, 0), np.ones(7))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_kkt_zero_at_planted_optimum(seed):
+    lp = lpgen.tiny_lp(seed)
+    P = oracle.Problem.from_lpdata(lp)
+    r = oracle.kkt(P, lp.planted["x"], lp.planted["y"])
+    assert r["kkt"] < 1e-12
+    assert r["pobj"] == pytest.approx(lp.planted["pstar"], rel=1e-12)
+
+
+def test_kkt_zero_at_planted_optimum_mixed_bounds():
+    lp = lpgen.mip_like_lp(5, m=300, n=700, nnz=3000, fp32=False)
+    P = oracle.Problem.from_lpdata(lp)
+    r = oracle.kkt(P, lp.planted["x"], lp.planted["y"])
+    assert r["kkt"] < 1e-12
+    np.testing.assert_allclose(r["lam"], lp.planted["s"], atol=1e-12)
+
+
+def test_projections():
+    P = _kkt_lp()
+    x = np.array([-5.0, 5.0, -5.0, 5.0, 7.0])
+    np.testing.assert_array_equal(oracle.proj_X(P, x), [-5.0, 2.0, 1.0, 3.0, 7.0])
+    np.testing.assert_array_equal(oracle.proj_Y(P, np.array([-1.0, -1.0])), [-1.0, 0.0])
+    lam = np.array([1.0, 1.0, -1.0, -1.0, 1.0])
+    np.testing.assert_array_equal(oracle.proj_Lambda(P, lam), [0.0, 0.0, 0.0, -1.0, 0.0])
+
+
+# ---------------------------------------------------------------------------
+# the AA update against Alg 1 (standard type-II AA, constrained alpha form)
+# ---------------------------------------------------------------------------
+
+def _alg1_alpha(Gcols):
+    """argmin ||G alpha|| s.t. sum alpha = 1, by the Lagrange system (a second,
+    independent formula for the same least-squares problem)."""
+    G = np.stack(Gcols, axis=1)
+    k = G.shape[1]
+    A = np.zeros((k + 1, k + 1))
+    A[:k, :k] = 2.0 * G.T @ G
+    A[:k, k] = 1.0
+    A[k, :k] = 1.0
+    rhs = np.zeros(k + 1)
+    rhs[k] = 1.0
+    return np.linalg.solve(A, rhs)[:k]
+
+
+def test_difference_form_equals_alg1_alpha_form():
+    # Free variables and equality rows: the projections are inactive and T is
+    # affine.  With D-hat = I, beta = 1, eta = 0 and the safeguard always passed,
+    # Alg 2's u^{k+1} must equal Alg 1's sum_i alpha_i T(u^i) over the window.
+    rng = np.random.default_rng(7)
+    m, n = 4, 9
+    K = rng.standard_normal((m, n))
+    lp = lp_from_dense(K, rng.standard_normal(m), rng.standard_normal(n),
+                       ["-inf"] * n, ["inf"] * n, [0] * m)
+    P = oracle.Problem.from_lpdata(lp)
+    nrm = np.linalg.norm(K, 2)
+    mem = 3
+    s = oracle.Solver(P, oracle.Options(tau=0.5 / nrm, sigma=0.5 / nrm, memory=mem, D=1e300,
+                                        eta=0.0, dhat_mode=0, beta=1.0, kkt_every=0))
+    s.start()
+    us = [s.state.u_prev, np.r_[s.state.x, s.state.y]]
+    gs = [s.state.g_prev]
+    for _ in range(8):
+        u_k = np.r_[s.state.x, s.state.y]
+        s.step()
+        assert s.last_branch == "aa"
+        gs.append(s.state.g_prev)  # g^k
+        mk = min(mem, len(gs) - 1)
+        window = list(range(len(gs) - 1 - mk, len(gs)))
+        alpha = _alg1_alpha([gs[t] for t in window])
+        expect = sum(a * (us[t] + gs[t]) for a, t in zip(alpha, window))
+        got = np.r_[s.state.x, s.state.y]
+        np.testing.assert_allclose(got, expect, rtol=1e-8, atol=1e-10)
+        us.append(got)
+        assert np.allclose(u_k, us[-2])
+
+
+# ---------------------------------------------------------------------------
+# vanilla PDHG: firm non-expansiveness (Thm th:pdhg-residual-0)
+# ---------------------------------------------------------------------------
+
+def _m_norm_sq(P, g, tau, sigma):
+    gx, gy = g[:P.n], g[P.n:]
+    return gx @ gx / tau + gy @ gy / sigma + 2.0 * gy @ (P.K @ gx)
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_pdhg_residual_monotone_in_M_norm(seed):
+    lp = lpgen.mip_like_lp(seed, m=60, n=150, nnz=700, fp32=False)
+    P = oracle.Problem.from_lpdata(lp)
+    nrm = np.linalg.norm(lpgen.to_dense(lp), 2)
+    tau = sigma = 0.9 / nrm
+    s = oracle.Solver(P, oracle.Options(variant=oracle.VARIANT_PDHG, tau=tau, sigma=sigma, kkt_every=0))
+    s.start()
+    prev = _m_norm_sq(P, s.state.g_prev, tau, sigma)
+    assert prev > 0
+    for _ in range(400):
+        s.step()
+        cur = _m_norm_sq(P, s.state.g_prev, tau, sigma)
+        assert cur <= prev * (1 + 1e-12) + 1e-300
+        prev = cur
+
+
+# ---------------------------------------------------------------------------
+# safeguard and counters (Alg 2; Lemma le-AA-use-inifite)
+# ---------------------------------------------------------------------------
+
+def test_D_zero_is_vanilla_pdhg_and_counters_add_up():
+    lp = lpgen.tiny_lp(3)
+    P = oracle.Problem.from_lpdata(lp)
+    a = oracle.Solver(P, oracle.Options(variant=oracle.VARIANT_AA, D=0.0, kkt_every=0, tau=0.05, sigma=0.05))
+    b = oracle.Solver(P, oracle.Options(variant=oracle.VARIANT_PDHG, kkt_every=0, tau=0.05, sigma=0.05))
+    a.start(); b.start()
+    for k in range(60):
+        a.step(); b.step()
+        np.testing.assert_array_equal(np.r_[a.state.x, a.state.y], np.r_[b.state.x, b.state.y])
+        assert a.state.i + a.state.j == a.state.k - 1
+    assert a.state.i == 0
+
+
+def test_infinite_D_always_accelerates_and_counters_add_up():
+    lp = lpgen.tiny_lp(4)
+    P = oracle.Problem.from_lpdata(lp)
+    s = oracle.Solver(P, oracle.Options(D=math.inf, kkt_every=0, tau=0.05, sigma=0.05))
+    s.start()
+    for _ in range(40):
+        s.step()
+        assert s.last_branch == "aa"
+        assert s.state.i + s.state.j == s.state.k - 1
+    assert s.state.j == 0
+
+
+def test_aa_used_infinitely_often_on_convergent_run():
+    lp = lpgen.tiny_lp(0)
+    P = oracle.Problem.from_lpdata(lp)
+    s = oracle.Solver(P, oracle.Options(D=10.0, kkt_every=0))
+    s.start()
+    seen = []
+    for _ in range(6000):
+        s.step()
+        seen.append(s.last_branch == "aa")
+    # AA steps keep appearing late in the run
+    assert any(seen[-1500:])
+
+
+def test_memory_window_and_singular_history_falls_back():
+    # a zero difference column makes dG^T dG + 0 I singular: the step is PDHG
+    # (reading: failed factorisation -> PDHG step; memory still updated)
+    P = oracle.Problem.from_lpdata(lpgen.tiny_lp(2))
+    s = oracle.Solver(P, oracle.Options(D=math.inf, eta=0.0, kkt_every=0, memory=3, tau=0.05, sigma=0.05))
+    s.start()
+    for _ in range(5):
+        s.step()
+        assert len(s.state.dU) <= 3
+    s.state.dG = [np.zeros_like(c) for c in s.state.dG]
+    before_j = s.state.j
+    s.step()
+    assert s.last_branch == "pdhg" and s.state.j == before_j + 1
+    assert len(s.state.dG) == 3
+
+
+# ---------------------------------------------------------------------------
+# FAA filters (Alg 4-6; Lemmas eq:lemma1.51, le:RK-1bound1,
+# lem:conditioning_after_stab)
+# ---------------------------------------------------------------------------
+
+def _angled_columns(rng, N, m, cs):
+    """Columns whose sine against the span of the previous ones is >= cs."""
+    F = np.zeros((N, m))
+    F[:, 0] = rng.standard_normal(N) * rng.uniform(0.1, 10)
+    for i in range(1, m):
+        while True:
+            v = rng.standard_normal(N) * rng.uniform(0.1, 10)
+            Q, _ = np.linalg.qr(F[:, :i])
+            perp = v - Q @ (Q.T @ v)
+            if np.linalg.norm(perp) / np.linalg.norm(v) >= cs:
+                break
+        F[:, i] = v
+    return F
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_length_bounds_dominate_columns_of_R_inverse(seed):
+    rng = np.random.default_rng(seed)
+    cs = 0.2
+    F = _angled_columns(rng, 30, 7, cs)
+    _, R = np.linalg.qr(F)
+    Rinv = np.linalg.inv(R)
+    b = oracle.length_bounds(np.linalg.norm(F, axis=0), cs)
+    col_sq = np.sum(Rinv ** 2, axis=0)
+    assert np.all(col_sq <= b * (1 + 1e-10))
+    assert col_sq[0] == pytest.approx(b[0], rel=1e-10)  # b_1 is exact
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_angle_filter_survivors_satisfy_angle_condition(seed):
+    rng = np.random.default_rng(100 + seed)
+    N, m, cs = 25, 8, 0.3
+    F = rng.standard_normal((N, m))
+    F[:, 3] = F[:, 1] + 0.01 * rng.standard_normal(N)  # nearly dependent columns
+    F[:, 6] = 2.0 * F[:, 0] - F[:, 2]
+    E = rng.standard_normal((N, m))
+    keep = oracle.angle_filter(E, F, cs)
+    assert keep[0] == 0
+    assert 3 not in keep and 6 not in keep
+    Fk = F[:, keep]
+    for i in range(1, Fk.shape[1]):
+        Q, _ = np.linalg.qr(Fk[:, :i])
+        perp = Fk[:, i] - Q @ (Q.T @ Fk[:, i])
+        assert np.linalg.norm(perp) / np.linalg.norm(Fk[:, i]) >= cs - 1e-12
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_length_filter_output_is_conditioned(seed):
+    rng = np.random.default_rng(200 + seed)
+    cs = 0.2
+    F = _angled_columns(rng, 40, 6, cs)
+    E = rng.standard_normal((40, 6)) * np.array([1, 1, 1, 1e3, 1e4, 1e5])
+    en, fn = np.linalg.norm(E, axis=0), np.linalg.norm(F, axis=0)
+    b = oracle.length_bounds(fn, cs)
+    kbar = math.sqrt(float(np.sum(en[:3] ** 2) * np.sum(b[:3]))) * 1.0001
+    k = oracle.length_filter(en, fn, cs, kbar)
+    assert k == 3
+    _, R = np.linalg.qr(F[:, :k])
+    lhs = np.linalg.norm(E[:, :k], "fro") * np.linalg.norm(np.linalg.inv(R), "fro")
+    assert lhs <= kbar
+    assert float(np.sum(en[:k] ** 2) * np.sum(b[:k])) <= kbar ** 2
+    assert oracle.length_filter(en, fn, cs, 1e-30) == 0  # nothing passes: the loop runs out
+    fz = fn.copy(); fz[0] = 0.0
+    assert oracle.length_filter(en, fz, cs, 1e150) == 0  # zero newest column never passes
+    assert oracle.length_filter(en, fn, cs, 1e300) == 6
+
+
+def test_reverse_is_involution():
+    E = np.arange(12.0).reshape(3, 4)
+    F = -E
+    E2, F2 = oracle.reverse(*oracle.reverse(E, F))
+    np.testing.assert_array_equal(E2, E)
+    np.testing.assert_array_equal(F2, F)
+    np.testing.assert_array_equal(oracle.reverse(E, F)[0][:, 0], E[:, -1])
+
+
+def test_faa_without_filtering_equals_aa_without_regularisation():
+    # c_s -> 0 and kappa_bar -> inf keep every column; then R^{-1} Q^T g is the
+    # unregularised least-squares solution, i.e. Alg 2 with eta = 0.
+    P = oracle.Problem.from_lpdata(lpgen.tiny_lp(1))
+    common = dict(D=10.0, kkt_every=0, memory=5, tau=0.05, sigma=0.05)
+    a = oracle.Solver(P, oracle.Options(variant=oracle.VARIANT_AA, eta=0.0, **common))
+    f = oracle.Solver(P, oracle.Options(variant=oracle.VARIANT_FAA, cs=1e-300, kappa_bar=1e300, **common))
+    a.start(); f.start()
+    for _ in range(40):
+        a.step(); f.step()
+        assert a.last_branch == f.last_branch
+        np.testing.assert_allclose(np.r_[f.state.x, f.state.y], np.r_[a.state.x, a.state.y],
+                                   rtol=1e-7, atol=1e-9)
+
+
+def test_faa_memory_never_exceeds_limit_and_filters_bind():
+    P = oracle.Problem.from_lpdata(lpgen.tiny_lp(0))
+    f = oracle.Solver(P, oracle.Options(variant=oracle.VARIANT_FAA, cs=0.5, kappa_bar=1e2, memory=6,
+                                        D=math.inf, kkt_every=0))
+    f.start()
+    sizes = []
+    for _ in range(60):
+        f.step()
+        sizes.append(len(f.state.dU))
+        assert len(f.state.dU) <= 6
+    assert min(sizes[10:]) < 6  # the filters removed columns
+
+
+# ---------------------------------------------------------------------------
+# power iteration and Ruiz equilibration (Sections 5.1, 5.2)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", [0, 5])
+def test_power_norm_matches_svd(seed):
+    lp = lpgen.tiny_lp(seed)
+    P = oracle.Problem.from_lpdata(lp)
+    smax = np.linalg.svd(lpgen.to_dense(lp), compute_uv=False)[0]
+    est = oracle.power_norm(P, iters=2000, rtol=1e-14)
+    assert est <= smax * (1 + 1e-12)
+    assert est >= smax * (1 - 1e-6)
+
+
+def test_ruiz_equilibrates_and_preserves_the_lp():
+    lp = lpgen.mip_like_lp(2, m=80, n=160, nnz=900, fp32=False)
+    P = oracle.Problem.from_lpdata(lp)
+    S, dr, dc = oracle.ruiz(P, 10)
+    Kd = lpgen.to_dense(lp)
+    Ks = S.K.toarray()
+    np.testing.assert_allclose(Ks, dr[:, None] * Kd * dc[None, :], rtol=1e-13, atol=1e-15)
+    rmax = np.abs(Ks).max(axis=1)
+    cmax = np.abs(Ks).max(axis=0)
+    assert np.all(np.abs(rmax[rmax > 0] - 1) < 0.02)
+    assert np.all(np.abs(cmax[cmax > 0] - 1) < 0.02)
+    # the planted optimum maps to a KKT point of the scaled LP
+    r = oracle.kkt(S, lp.planted["x"] / dc, lp.planted["y"] / dr)
+    assert r["kkt"] < 1e-12
+    assert r["pobj"] == pytest.approx(lp.planted["pstar"], rel=1e-12)
