@@ -1,0 +1,222 @@
+/*
+ * aapdhg.h -- C ABI of the MI355X AA-PDHG / FAA-PDHG library for linear programs.
+ *
+ * Problem (Section 2.1, problem LP-O, written with K = [G; A], q = [h; b]):
+ *
+ *     minimise  c^T x
+ *     subject to (K x)_i >= q_i   for rows of type AAPDHG_ROW_GE  (the G x >= h block)
+ *                (K x)_i  = q_i   for rows of type AAPDHG_ROW_EQ  (the A x  = b block)
+ *                l <= x <= u      (l_j may be -inf, u_j may be +inf)
+ *
+ * Rows of the two types may be interleaved; the row type picks the dual cone
+ * of y_i (y_i >= 0 on GE rows, free on EQ rows; Section 3, the set Y).
+ *
+ * Method: the PDHG map T of eq. pdhg, accelerated by Anderson mixing with a
+ * safeguard (Alg 2, AA-PDHG) or with angle and length filtering (Alg 3-6,
+ * FAA-PDHG), terminated on the relative KKT residual of Remark
+ * re:constrcution-termi-con.  Vanilla PDHG is the same iteration with the
+ * Anderson step switched off.
+ *
+ * Conventions for every entry point:
+ *   - Every call returns an aapdhg_status; nothing is thrown across the ABI.
+ *     On failure the handle (or, for a NULL handle, the calling thread) keeps
+ *     a message readable with aapdhg_last_error().
+ *   - "host" arrays are ordinary CPU memory owned by the caller; the library
+ *     copies what it needs before returning and never keeps the pointer.
+ *   - Device memory is owned by the library from create to destroy.
+ *   - A stream argument is a hipStream_t passed as void*; NULL means the
+ *     default stream.  A handle is used by one host thread at a time.
+ *   - Not converging is not an error: it is reported in aapdhg_info.term.
+ *
+ * Library errors: AAPDHG_E_ARG (invalid argument or problem data),
+ * AAPDHG_E_NOMEM (device or host allocation failed), AAPDHG_E_HIP (a HIP
+ * runtime call failed; the message names it), AAPDHG_E_STATE (call not valid
+ * in the handle's current state, e.g. result before solve).
+ */
+#ifndef AAPDHG_H
+#define AAPDHG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AAPDHG_MAX_MEMORY 16 /* largest Anderson memory m_A supported */
+
+typedef struct aapdhg_problem *aapdhg_t;
+typedef struct aapdhg_batch *aapdhg_batch_t;
+typedef struct aapdhg_server *aapdhg_server_t;
+
+typedef enum { AAPDHG_ROW_EQ = 0, AAPDHG_ROW_GE = 1 } aapdhg_row_type;
+
+typedef enum {
+  AAPDHG_OK = 0,
+  AAPDHG_E_ARG = -1,
+  AAPDHG_E_NOMEM = -2,
+  AAPDHG_E_HIP = -3,
+  AAPDHG_E_STATE = -4,
+  AAPDHG_PENDING = 1 /* server: the ticket is not finished yet (not an error) */
+} aapdhg_status;
+
+typedef enum {
+  AAPDHG_CONVERGED = 0,  /* relative KKT <= tol at the returned iterate       */
+  AAPDHG_ITER_LIMIT = 1, /* max_iter loop passes done                        */
+  AAPDHG_TIME_LIMIT = 2, /* wall-clock limit reached at an epoch boundary     */
+  AAPDHG_NUMERICAL = 3,  /* the fixed-point residual became NaN or infinite   */
+  AAPDHG_RUNNING = 4     /* not finished (only seen before a solve completes) */
+} aapdhg_term;
+
+typedef enum { AAPDHG_VARIANT_PDHG = 0, AAPDHG_VARIANT_AA = 1, AAPDHG_VARIANT_FAA = 2 } aapdhg_variant;
+
+typedef struct {
+  int32_t variant;    /* aapdhg_variant: PDHG, AA-PDHG (Alg 2) or FAA-PDHG (Alg 3)        */
+  int32_t precision;  /* 0: float32 data and iterates, float64 reductions, Gram, solve
+                         and KKT; 1: float64 throughout                                  */
+  int32_t memory;     /* Anderson memory m_A, 1..AAPDHG_MAX_MEMORY                        */
+  double D;           /* safeguard constant D > 0 (Alg 2, safeguard line)                 */
+  double eps_sg;      /* safeguard exponent epsilon > 0                                   */
+  double beta;        /* damping beta in (0, 1]                                           */
+  double eta;         /* Tikhonov shift eta >= 0 of (dG^T dG + eta I), AA-PDHG only       */
+  double cs;          /* angle-filter threshold c_s in (0, 1] (Alg 4), FAA only           */
+  double kappa_bar;   /* length-filter bound kappa-bar > 0 (Alg 5), FAA only              */
+  double tau, sigma;  /* step sizes; if either is <= 0 both are set to 0.9 / ||K||_2
+                         with ||K||_2 estimated by power iteration (Section 5.1)          */
+  double tol;         /* relative KKT tolerance (Remark re:constrcution-termi-con)        */
+  int64_t max_iter;   /* loop passes before AAPDHG_ITER_LIMIT                             */
+  double time_limit_s;/* wall-clock limit per solve call, <= 0 for none                   */
+  int32_t kkt_every;  /* evaluate the KKT test at iterations k with k % kkt_every == 0    */
+  int32_t dhat_mode;  /* D-hat (Remark se:Dhat_construction): 0 identity, 1 the square
+                         root of the column/row max-abs of K (literal), 2 its reciprocal */
+  int32_t ruiz_iters; /* Ruiz equilibration sweeps applied at create (Section 5.2), 0 off */
+  int32_t power_iters;/* power-iteration cap for the step size                            */
+  int32_t epoch;      /* iterations per device epoch between host checks of the status    */
+  int32_t reserved[7];
+} aapdhg_options;
+
+typedef struct {
+  int32_t term;            /* aapdhg_term                                                  */
+  int32_t reserved0;
+  int64_t iters;           /* index k of the returned iterate u^k                          */
+  int64_t aa_steps;        /* i^k: Anderson steps taken                                    */
+  int64_t pdhg_steps;      /* j^k: plain PDHG steps taken                                  */
+  double primal_obj;       /* c^T x  (on the problem as solved, i.e. after any scaling)    */
+  double dual_obj;         /* q^T y + l^T lambda+ - u^T lambda-                            */
+  double r_gap, r_pri, r_dual, kkt; /* relative KKT pieces and their max               */
+  double gnorm;            /* ||g^k|| of the last loop pass                                */
+  double g0norm;           /* ||g^0||                                                      */
+  double solve_seconds;    /* host wall time of the last solve/iterate call                */
+  double step_tau, step_sigma;
+} aapdhg_info;
+
+/* Fills *o with the defaults of Section 5.1: AA-PDHG, float32, m_A = 10, D = 10,
+ * epsilon = 1, beta = 1, eta = 1e-10, c_s = 0.2, kappa-bar = 1e8, tol = 1e-4,
+ * tau = sigma = 0 (power iteration), max_iter = 100000, kkt_every = 64,
+ * dhat_mode = 1, no Ruiz, power_iters = 200, epoch = 256. */
+void aapdhg_default_options(aapdhg_options *o);
+
+/* Create a solver for one LP.
+ *   m, n        rows and columns of K (m >= 1, n >= 1); nnz entries (0 <= nnz < 2^31).
+ *   row_ptr     host int64[m+1], CSR row offsets, row_ptr[0] = 0, non-decreasing, row_ptr[m] = nnz.
+ *   col_idx     host int32[nnz], column of each entry, in [0, n), no repeats within a row
+ *               (any order within a row; the library sorts).
+ *   val         host double[nnz], finite.
+ *   c           host double[n], finite.         q   host double[m], finite (b and h).
+ *   l, u        host double[n], l_j <= u_j, l_j < +inf, u_j > -inf; +-inf allowed.
+ *   row_type    host uint8[m], each AAPDHG_ROW_EQ or AAPDHG_ROW_GE.
+ *   opt         options (NULL for defaults); copied.
+ * The data is copied, validated (E_ARG with a message on any violation), equilibrated if
+ * requested, and moved to the current HIP device.  In float32 mode values are rounded to
+ * float32.  Step sizes must satisfy tau * sigma * ||K||^2 < 1 (the standing assumption of
+ * Section 3); when both are given this is checked against the power-iteration estimate.
+ * On success *out owns the device state until aapdhg_destroy. */
+aapdhg_status aapdhg_create(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr,
+                            const int32_t *col_idx, const double *val, const double *c,
+                            const double *q, const double *l, const double *u,
+                            const uint8_t *row_type, const aapdhg_options *opt, aapdhg_t *out);
+
+/* Solve from the start point u^0 = (clip(0, l, u), 0): the init step u^1 = T u^0, then loop
+ * passes until the KKT test passes, max_iter, or time_limit_s.  Work is enqueued on `stream`
+ * in epochs; the call returns when the solve has finished (it waits on the stream). */
+aapdhg_status aapdhg_solve(aapdhg_t h, void *stream);
+
+/* Enqueue `iters` loop passes on `stream` without waiting (asynchronous).  On a fresh or
+ * reset handle the first pass is the init step.  Passes after termination do nothing. */
+aapdhg_status aapdhg_iterate(aapdhg_t h, void *stream, int64_t iters);
+
+/* Return to the start point (discard iterate, history and counters). */
+aapdhg_status aapdhg_reset(aapdhg_t h, void *stream);
+
+/* Wait for the handle's work, evaluate the KKT quantities at the current iterate, and copy
+ * results to host memory: x double[n], y double[m], lambda double[n] (= P_Lambda(c - K^T y)),
+ * each may be NULL.  Values refer to the original (unscaled) problem when Ruiz scaling was
+ * used; info (may be NULL) reports the KKT pieces of the problem as solved. */
+aapdhg_status aapdhg_result(aapdhg_t h, double *x, double *y, double *lambda, aapdhg_info *info);
+
+/* Copy the full iteration state to host memory (checkpoint).  Buffers, all double:
+ *   u      [n+m]  current iterate u^k (x then y, scaled problem)
+ *   u_prev [n+m]  u^{k-1}            g_prev [n+m]  g^{k-1}
+ *   dG     [m_A*(n+m)] history columns by physical slot, W [m_A*(n+m)] = dU + beta D-hat dG
+ *   meta   int64[8 + 2*AAPDHG_MAX_MEMORY]: k, status, i, j, nlive, newslot, 0, 0, live slots
+ *          (oldest first, AAPDHG_MAX_MEMORY entries), then m_A entries of ||du_slot||^2 bits
+ *   gram   double[AAPDHG_MAX_MEMORY^2 + 2*AAPDHG_MAX_MEMORY + 2]: Gram by slot, rhs, du2, n0, gnorm.
+ * Any pointer may be NULL to skip it. */
+aapdhg_status aapdhg_get_state(aapdhg_t h, double *u, double *u_prev, double *g_prev, double *dG,
+                               double *W, int64_t *meta, double *gram);
+/* Restore a state written by aapdhg_get_state (same problem and options). */
+aapdhg_status aapdhg_set_state(aapdhg_t h, const double *u, const double *u_prev,
+                               const double *g_prev, const double *dG, const double *W,
+                               const int64_t *meta, const double *gram);
+
+/* Sizes of the created problem and the step sizes in use. */
+aapdhg_status aapdhg_get_dims(aapdhg_t h, int32_t *m, int32_t *n, int64_t *nnz, double *tau,
+                              double *sigma);
+
+/* Ruiz scaling factors in use (d_row[m], d_col[n]); all ones without Ruiz. */
+aapdhg_status aapdhg_get_scaling(aapdhg_t h, double *d_row, double *d_col);
+
+aapdhg_status aapdhg_destroy(aapdhg_t h);
+
+/* Text of the last error on the handle (or of the calling thread when h is NULL). */
+const char *aapdhg_last_error(aapdhg_t h);
+
+/* ---- batched solves: many LPs of uneven sizes advance in the same kernel launches ----
+ * The batch refers to the problems' device state; they must outlive the batch, must share
+ * the precision and may not be used on their own while the batch is alive.  Each problem
+ * keeps its own options, tiles and reduction order, so its iterates do not depend on the
+ * other members of the batch. */
+aapdhg_status aapdhg_batch_create(int32_t count, const aapdhg_t *problems, aapdhg_batch_t *out);
+/* Solve every member from its start point; returns when all have terminated. */
+aapdhg_status aapdhg_batch_solve(aapdhg_batch_t b, void *stream);
+/* Enqueue `iters` loop passes for every member (asynchronous). */
+aapdhg_status aapdhg_batch_iterate(aapdhg_batch_t b, void *stream, int64_t iters);
+aapdhg_status aapdhg_batch_destroy(aapdhg_batch_t b);
+
+/* ---- serving: continuous batching of LP requests ----
+ * A worker thread admits submitted LPs while their device footprint fits in
+ * hbm_budget_bytes and fewer than max_slots are resident, advances all resident LPs in
+ * shared epochs, and retires finished ones, so requests that arrive while others run share
+ * the device.  opt applies to every request (NULL: defaults). */
+aapdhg_status aapdhg_server_start(size_t hbm_budget_bytes, int32_t max_slots,
+                                  const aapdhg_options *opt, aapdhg_server_t *out);
+/* Submit one LP (arguments as aapdhg_create; copied).  Returns at once with *ticket. */
+aapdhg_status aapdhg_server_submit(aapdhg_server_t s, int32_t m, int32_t n, int64_t nnz,
+                                   const int64_t *row_ptr, const int32_t *col_idx,
+                                   const double *val, const double *c, const double *q,
+                                   const double *l, const double *u, const uint8_t *row_type,
+                                   uint64_t *ticket);
+/* AAPDHG_PENDING while the request is queued or running; AAPDHG_OK once finished, with the
+ * results copied out (x[n], y[m], each may be NULL) and the ticket released.  t_admit and
+ * t_done (may be NULL) receive seconds since server start of admission and completion. */
+aapdhg_status aapdhg_server_poll(aapdhg_server_t s, uint64_t ticket, aapdhg_info *info,
+                                 double *x, double *y, double *t_admit, double *t_done);
+/* Counters: submitted, admitted, finished, resident now, epochs run, bytes resident now. */
+aapdhg_status aapdhg_server_stats(aapdhg_server_t s, int64_t *stats6);
+/* Stop the worker (running requests are abandoned) and free everything. */
+aapdhg_status aapdhg_server_stop(aapdhg_server_t s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AAPDHG_H */

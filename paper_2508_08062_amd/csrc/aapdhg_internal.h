@@ -1,0 +1,153 @@
+// Device-side data layout shared by the HIP kernels and the host runtime of
+// the AA-PDHG library.  Nothing here is part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace aapdhg {
+
+constexpr int MAXM = 16;          // largest Anderson memory
+constexpr int BLOCK = 256;        // threads per workgroup (4 wave64)
+constexpr int CHUNK_NNZ = 2048;   // nnz staged in LDS by one multi-row chunk
+constexpr int CHUNK_ROWS = 1024;  // rows of one multi-row chunk (4 per thread at most)
+constexpr int ROWS_PER_THREAD = CHUNK_ROWS / BLOCK;
+constexpr int SPLIT_NNZ = 8192;   // nnz per part of a split (very long) row
+constexpr int GROUP = 32;         // chunks per first-level reduction group
+constexpr int MIX_TILE = 2048;    // elements per block of the mix pass
+constexpr int NDOT = 2 * MAXM + 8;  // stride of one partial-sum record (doubles)
+
+// Partial-sum record: MT = memory bound of the kernel instantiation.
+//   [0, MT)    <dg_new, dG[live t]>       [MT, 2MT)  <g, dG[live t]>
+//   2MT+0 <dg,dg>  2MT+1 <dg,g>  2MT+2 <g,g>  2MT+3 <du,du>
+//   2MT+4..2MT+6  KKT sums (pass A: c.x, l.lam+ - u.lam-, ||c-K^T y-lam||^2;
+//                           pass B: q.y, ||primal residual||^2, 0)
+template <int MT>
+struct Dot {
+  static constexpr int G = 0, R = MT, DGDG = 2 * MT, DGG = 2 * MT + 1, GG = 2 * MT + 2,
+                       DU2 = 2 * MT + 3, K0 = 2 * MT + 4, K1 = 2 * MT + 5, K2 = 2 * MT + 6,
+                       COUNT = 2 * MT + 7;
+};
+
+enum Status : int { ST_CONVERGED = 0, ST_ITER_LIMIT = 1, ST_TIME_LIMIT = 2, ST_NUMERICAL = 3, ST_RUNNING = 4 };
+enum Branch : int { BR_NONE = 0, BR_PDHG = 1, BR_AA = 2 };
+enum Variant : int { V_PDHG = 0, V_AA = 1, V_FAA = 2 };
+enum Mode : int { MODE_ITER = 0, MODE_EVAL = 1 };
+
+// Per-LP iteration state, written only by the single block that finishes a
+// loop pass (or by host set-up while the device is idle).
+struct alignas(256) Scalars {
+  long long k;       // index of the current iterate u^k (0 before the init step)
+  long long i_aa;    // Anderson steps taken
+  long long j_pdhg;  // PDHG steps taken
+  long long kkt_k;   // iteration of the last KKT evaluation
+  int status;        // Status
+  int branch;        // Branch of the last loop pass
+  int nlive;         // live history slots
+  int newslot;       // slot that receives the next difference pair
+  int live[MAXM];    // live slots, oldest first
+  int nmix;          // slots used by the pending mix
+  int mixslot[MAXM];
+  int pad0[3];
+  double n0;         // ||g^0||
+  double gnorm;      // ||g^k||
+  double G[MAXM * MAXM];  // Gram of the history columns, by physical slot
+  double rhs[MAXM];       // <dG[slot], g^k>
+  double du2[MAXM];       // ||du[slot]||^2
+  double gamma[MAXM];     // mixing coefficients for mixslot[]
+  double pobj, dobj, r_g, r_p, r_d, kkt;
+  double qnorm, cnorm;
+  unsigned int lp_cnt;    // last-arriver counter of the dual pass (reset by the last block)
+  unsigned int pad1;
+};
+
+// Per-LP immutable description (device copy).  Vectors of length N = n + m
+// hold the x part first and the y part at offset n.
+struct LPDesc {
+  int m, n, N, M;
+  int variant, kkt_every;
+  long long max_iter;
+  double tau, sigma, beta, D, eps_sg, eta, cs, kappa_bar, tol;
+  const int* rowptr;  // CSR of K
+  const int* colidx;
+  const void* val;
+  const int* colptr;  // CSC of K (CSR of K^T)
+  const int* rowidx;
+  const void* valT;
+  const void* c;
+  const void* lo;
+  const void* hi;
+  const void* q;
+  const void* dhat;  // length N
+  const unsigned char* rowtype;
+  void* u[2];  // iterates, by parity of k
+  void* g[2];  // residuals, by parity of k
+  void* xbar;  // 2 x_hat - x (length n)
+  void* dG;    // history [M][N]
+  void* W;     // dU + beta D-hat dG, [M][N]
+  void* lam;   // reduced costs written by the evaluation pass (length n)
+  Scalars* sc;
+};
+
+// One workgroup's share of an SpMV pass.  "Rows" are columns of K in the
+// primal pass (CSC) and rows of K in the dual pass (CSR).
+struct Chunk {
+  int lp;     // index into the launch's LP table
+  int kind;   // 0: multi-row (rows [r0,r1), nnz [k0,k1) staged in LDS); 1: part of a split row
+  int r0, r1;
+  int k0, k1;
+  int tpr;    // multi: threads per row (1..64, or BLOCK for a single row); split: part index
+  int split;  // split: global split-row index
+  int group;  // global reduction group
+  int pad[3];
+};
+
+struct Group {
+  int first;   // first chunk of the group (global chunk index)
+  int count;   // chunks in the group
+  int lp;
+  int pad;
+};
+
+struct SplitRow {
+  int row;      // pass-local row
+  int nparts;
+  int part0;    // first slot in the split partial buffer
+  int pad;
+};
+
+// Per-LP entry of a launch table: where this LP's groups and split rows live.
+struct LaunchLP {
+  int gA0, nA, gB0, nB;  // reduction groups of the primal / dual pass
+  int sA0, nsA, sB0, nsB;  // split rows of the primal / dual pass
+};
+
+struct MixTile {
+  int lp;
+  int e0, e1;
+  int pad;
+};
+
+// Everything a pass kernel needs; passed by value.
+struct PassArgs {
+  const LPDesc* lps;
+  const LaunchLP* llp;
+  const Chunk* chunks;
+  const Group* groups;
+  const SplitRow* splits;
+  double* cpart;        // [chunks][NDOT]
+  double* gpart;        // [groups][NDOT]
+  unsigned int* gcnt;   // [groups]
+  double* splitpart;    // [split parts][2]
+  unsigned int* splitcnt;  // [split rows]
+  double* splitdots;    // [split rows][NDOT]
+  int mode;
+};
+
+struct MixArgs {
+  const LPDesc* lps;
+  const MixTile* tiles;
+};
+
+}  // namespace aapdhg

@@ -1,0 +1,1016 @@
+// Host runtime of the AA-PDHG library: C ABI entry points, input validation,
+// set-up (CSR/CSC copies, Ruiz equilibration, D-hat, step size), the work
+// tables of the kernels, the epoch driver, results and checkpoints.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/aapdhg.h"
+#include "aapdhg_internal.h"
+#include "kernels.h"
+#include "runtime.h"
+
+namespace aapdhg {
+
+thread_local std::string g_thread_error;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+Error::Error(aapdhg_status s, const char* fmt, ...) : status(s) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  msg = buf;
+}
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    if (e == hipErrorOutOfMemory) throw Error(AAPDHG_E_NOMEM, "%s: out of device memory", what);
+    throw Error(AAPDHG_E_HIP, "%s: %s", what, hipGetErrorString(e));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// device buffers
+// ---------------------------------------------------------------------------
+
+DevBuf::~DevBuf() { release(); }
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+void DevBuf::alloc(size_t nbytes, const char* what) {
+  release();
+  if (nbytes == 0) nbytes = 8;
+  hip_check(hipMalloc(&p, nbytes), what);
+  bytes = nbytes;
+}
+void DevBuf::upload(const void* src, size_t nbytes, const char* what) {
+  alloc(nbytes, what);
+  if (src && nbytes) hip_check(hipMemcpy(p, src, nbytes, hipMemcpyHostToDevice), what);
+}
+void DevBuf::zero(const char* what) {
+  if (p) hip_check(hipMemset(p, 0, bytes), what);
+}
+
+// ---------------------------------------------------------------------------
+// options
+// ---------------------------------------------------------------------------
+
+void default_options(aapdhg_options* o) {
+  std::memset(o, 0, sizeof *o);
+  o->variant = AAPDHG_VARIANT_AA;
+  o->precision = 0;
+  o->memory = 10;
+  o->D = 10.0;
+  o->eps_sg = 1.0;
+  o->beta = 1.0;
+  o->eta = 1e-10;
+  o->cs = 0.2;
+  o->kappa_bar = 1e8;
+  o->tau = 0.0;
+  o->sigma = 0.0;
+  o->tol = 1e-4;
+  o->max_iter = 100000;
+  o->time_limit_s = 0.0;
+  o->kkt_every = 64;
+  o->dhat_mode = 1;
+  o->ruiz_iters = 0;
+  o->power_iters = 200;
+  o->epoch = 256;
+}
+
+static void check_options(const aapdhg_options& o) {
+  if (o.variant < 0 || o.variant > 2) throw Error(AAPDHG_E_ARG, "variant must be 0, 1 or 2");
+  if (o.precision != 0 && o.precision != 1) throw Error(AAPDHG_E_ARG, "precision must be 0 or 1");
+  if (o.memory < 1 || o.memory > MAXM) throw Error(AAPDHG_E_ARG, "memory must be in [1, %d]", MAXM);
+  if (!(o.D >= 0.0)) throw Error(AAPDHG_E_ARG, "D must be >= 0");
+  if (!(o.eps_sg > 0.0) || !std::isfinite(o.eps_sg)) throw Error(AAPDHG_E_ARG, "eps_sg must be > 0");
+  if (!(o.beta > 0.0 && o.beta <= 1.0)) throw Error(AAPDHG_E_ARG, "beta must be in (0, 1]");
+  if (!(o.eta >= 0.0) || !std::isfinite(o.eta)) throw Error(AAPDHG_E_ARG, "eta must be >= 0");
+  if (!(o.cs > 0.0 && o.cs <= 1.0)) throw Error(AAPDHG_E_ARG, "cs must be in (0, 1]");
+  if (!(o.kappa_bar > 0.0)) throw Error(AAPDHG_E_ARG, "kappa_bar must be > 0");
+  if (!(o.tol >= 0.0)) throw Error(AAPDHG_E_ARG, "tol must be >= 0");
+  if (o.max_iter < 0) throw Error(AAPDHG_E_ARG, "max_iter must be >= 0");
+  if (o.kkt_every < 0) throw Error(AAPDHG_E_ARG, "kkt_every must be >= 0");
+  if (o.dhat_mode < 0 || o.dhat_mode > 2) throw Error(AAPDHG_E_ARG, "dhat_mode must be 0, 1 or 2");
+  if (o.ruiz_iters < 0 || o.ruiz_iters > 1000) throw Error(AAPDHG_E_ARG, "ruiz_iters must be in [0, 1000]");
+  if (o.power_iters < 1 || o.power_iters > 100000) throw Error(AAPDHG_E_ARG, "power_iters must be in [1, 100000]");
+  if (o.epoch < 1 || o.epoch > 1000000) throw Error(AAPDHG_E_ARG, "epoch must be in [1, 1e6]");
+  if (!std::isfinite(o.tau) || !std::isfinite(o.sigma)) throw Error(AAPDHG_E_ARG, "tau and sigma must be finite");
+}
+
+// ---------------------------------------------------------------------------
+// work tables of one LP
+// ---------------------------------------------------------------------------
+
+static int pow2floor(int v) {
+  int p = 1;
+  while (p * 2 <= v) p *= 2;
+  return p;
+}
+
+// Cut the rows [0, R) of a compressed matrix into chunks (see Chunk).
+//  - a row with more than CHUNK_NNZ entries is split into parts of SPLIT_NNZ;
+//  - a row with more than LONG_ROW entries gets a chunk of its own, reduced by
+//    the whole workgroup;
+//  - other rows are packed into multi-row chunks of at most CHUNK_ROWS rows and
+//    CHUNK_NNZ entries, weighted so that short rows (whose epilogue dominates)
+//    do not crowd a chunk.
+static void build_chunks(const std::vector<int>& ptr, int R, std::vector<Chunk>& chunks,
+                         std::vector<SplitRow>& splits, int& nparts_total) {
+  constexpr int LONG_ROW = 128;
+  constexpr int ROW_WEIGHT = 4;
+  chunks.clear();
+  splits.clear();
+  nparts_total = 0;
+  int r = 0;
+  while (r < R) {
+    const int len = ptr[r + 1] - ptr[r];
+    if (len > CHUNK_NNZ) {
+      const int np = (len + SPLIT_NNZ - 1) / SPLIT_NNZ;
+      SplitRow sr{};
+      sr.row = r;
+      sr.nparts = np;
+      sr.part0 = nparts_total;
+      const int sid = (int)splits.size();
+      splits.push_back(sr);
+      nparts_total += np;
+      for (int p = 0; p < np; ++p) {
+        Chunk c{};
+        c.kind = 1;
+        c.r0 = r;
+        c.r1 = r + 1;
+        c.k0 = ptr[r] + p * SPLIT_NNZ;
+        c.k1 = std::min(ptr[r + 1], c.k0 + SPLIT_NNZ);
+        c.tpr = p;
+        c.split = sid;
+        chunks.push_back(c);
+      }
+      ++r;
+      continue;
+    }
+    if (len > LONG_ROW) {
+      Chunk c{};
+      c.kind = 0;
+      c.r0 = r;
+      c.r1 = r + 1;
+      c.k0 = ptr[r];
+      c.k1 = ptr[r + 1];
+      c.tpr = BLOCK;
+      chunks.push_back(c);
+      ++r;
+      continue;
+    }
+    const int r0 = r;
+    int nnz = 0;
+    while (r < R && r - r0 < CHUNK_ROWS) {
+      const int l2 = ptr[r + 1] - ptr[r];
+      if (l2 > LONG_ROW) break;
+      if (nnz + l2 > CHUNK_NNZ) break;
+      if (nnz + l2 + ROW_WEIGHT * (r - r0 + 1) > CHUNK_NNZ + ROW_WEIGHT * 64 && r > r0) break;
+      nnz += l2;
+      ++r;
+    }
+    const int nrows = r - r0;
+    Chunk c{};
+    c.kind = 0;
+    c.r0 = r0;
+    c.r1 = r;
+    c.k0 = ptr[r0];
+    c.k1 = ptr[r];
+    c.tpr = nrows >= BLOCK ? 1 : std::min(64, pow2floor(BLOCK / nrows));
+    chunks.push_back(c);
+  }
+  // reduction groups: runs of GROUP consecutive chunks
+  for (size_t i = 0; i < chunks.size(); ++i) chunks[i].group = (int)(i / GROUP);
+}
+
+static void build_groups(const std::vector<Chunk>& chunks, std::vector<Group>& groups) {
+  groups.clear();
+  for (size_t i = 0; i < chunks.size(); i += GROUP) {
+    Group g{};
+    g.first = (int)i;
+    g.count = (int)std::min<size_t>(GROUP, chunks.size() - i);
+    groups.push_back(g);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// problem creation
+// ---------------------------------------------------------------------------
+
+template <typename T>
+static void upload_as(DevBuf& b, const std::vector<double>& v, const char* what) {
+  std::vector<T> tmp(v.begin(), v.end());
+  b.upload(tmp.data(), tmp.size() * sizeof(T), what);
+}
+
+Problem::~Problem() = default;
+
+void Problem::create(int32_t m_, int32_t n_, int64_t nnz_, const int64_t* row_ptr, const int32_t* col_idx,
+                     const double* val_, const double* c_, const double* q_, const double* l_, const double* u_,
+                     const uint8_t* row_type, const aapdhg_options* opt_) {
+  if (opt_) opt = *opt_; else default_options(&opt);
+  check_options(opt);
+  if (m_ < 1 || n_ < 1) throw Error(AAPDHG_E_ARG, "m and n must be >= 1 (m=%d n=%d)", m_, n_);
+  if (nnz_ < 0 || nnz_ >= (int64_t)1 << 31) throw Error(AAPDHG_E_ARG, "nnz must be in [0, 2^31)");
+  if ((int64_t)m_ + n_ >= (int64_t)1 << 31) throw Error(AAPDHG_E_ARG, "m + n too large");
+  if (!row_ptr || (!col_idx && nnz_) || (!val_ && nnz_) || !c_ || !q_ || !l_ || !u_ || !row_type)
+    throw Error(AAPDHG_E_ARG, "null input array");
+  m = m_;
+  n = n_;
+  nnz = (int)nnz_;
+  N = m + n;
+  fp64 = opt.precision == 1;
+  // ---- validate and copy, sorting each row by column ----
+  if (row_ptr[0] != 0 || row_ptr[m] != nnz_) throw Error(AAPDHG_E_ARG, "row_ptr[0] must be 0 and row_ptr[m] must be nnz");
+  rowptr.assign(m + 1, 0);
+  for (int i = 0; i < m; ++i) {
+    if (row_ptr[i + 1] < row_ptr[i]) throw Error(AAPDHG_E_ARG, "row_ptr decreases at row %d", i);
+    rowptr[i + 1] = (int)row_ptr[i + 1];
+  }
+  colidx.resize(nnz);
+  val.resize(nnz);
+  {
+    std::vector<std::pair<int, double>> tmp;
+    for (int i = 0; i < m; ++i) {
+      tmp.clear();
+      for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) {
+        const int j = col_idx[q];
+        if (j < 0 || j >= n) throw Error(AAPDHG_E_ARG, "column index %d out of range at row %d", j, i);
+        if (!std::isfinite(val_[q])) throw Error(AAPDHG_E_ARG, "non-finite matrix value at row %d", i);
+        tmp.emplace_back(j, val_[q]);
+      }
+      std::sort(tmp.begin(), tmp.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+      for (size_t t = 0; t < tmp.size(); ++t) {
+        if (t > 0 && tmp[t].first == tmp[t - 1].first) throw Error(AAPDHG_E_ARG, "repeated column %d in row %d", tmp[t].first, i);
+        colidx[rowptr[i] + t] = tmp[t].first;
+        val[rowptr[i] + t] = tmp[t].second;
+      }
+    }
+  }
+  c.assign(c_, c_ + n);
+  q.assign(q_, q_ + m);
+  lo.assign(l_, l_ + n);
+  hi.assign(u_, u_ + n);
+  rowtype.assign(row_type, row_type + m);
+  for (int j = 0; j < n; ++j) {
+    if (!std::isfinite(c[j])) throw Error(AAPDHG_E_ARG, "non-finite c[%d]", j);
+    if (std::isnan(lo[j]) || std::isnan(hi[j]) || lo[j] > hi[j] || lo[j] == INFINITY || hi[j] == -INFINITY)
+      throw Error(AAPDHG_E_ARG, "invalid bounds at column %d", j);
+  }
+  for (int i = 0; i < m; ++i) {
+    if (!std::isfinite(q[i])) throw Error(AAPDHG_E_ARG, "non-finite q[%d]", i);
+    if (rowtype[i] > 1) throw Error(AAPDHG_E_ARG, "row_type[%d] must be 0 or 1", i);
+  }
+  // ---- Ruiz equilibration (Section 5.2 preprocessing) ----
+  d_row.assign(m, 1.0);
+  d_col.assign(n, 1.0);
+  if (opt.ruiz_iters > 0) {
+    std::vector<double> rmax(m), cmax(n), r(m), s(n);
+    for (int it = 0; it < opt.ruiz_iters; ++it) {
+      std::fill(rmax.begin(), rmax.end(), 0.0);
+      std::fill(cmax.begin(), cmax.end(), 0.0);
+      for (int i = 0; i < m; ++i)
+        for (int qq = rowptr[i]; qq < rowptr[i + 1]; ++qq) {
+          const double a = std::fabs(val[qq]);
+          rmax[i] = std::max(rmax[i], a);
+          cmax[colidx[qq]] = std::max(cmax[colidx[qq]], a);
+        }
+      for (int i = 0; i < m; ++i) r[i] = std::sqrt(rmax[i] > 0.0 ? rmax[i] : 1.0);
+      for (int j = 0; j < n; ++j) s[j] = std::sqrt(cmax[j] > 0.0 ? cmax[j] : 1.0);
+      for (int i = 0; i < m; ++i)
+        for (int qq = rowptr[i]; qq < rowptr[i + 1]; ++qq) val[qq] = val[qq] / (r[i] * s[colidx[qq]]);
+      for (int i = 0; i < m; ++i) d_row[i] = d_row[i] / r[i];
+      for (int j = 0; j < n; ++j) d_col[j] = d_col[j] / s[j];
+    }
+    for (int j = 0; j < n; ++j) {
+      c[j] = c[j] * d_col[j];
+      lo[j] = lo[j] / d_col[j];
+      hi[j] = hi[j] / d_col[j];
+    }
+    for (int i = 0; i < m; ++i) q[i] = q[i] * d_row[i];
+  }
+  // ---- round to the working precision (the LP the device holds) ----
+  if (!fp64) {
+    auto r32 = [](std::vector<double>& v) {
+      for (auto& x : v) x = (double)(float)x;
+    };
+    r32(val);
+    r32(c);
+    r32(q);
+    r32(lo);
+    r32(hi);
+  }
+  // ---- CSC copy (CSR of K^T), rows in increasing order within each column ----
+  colptr.assign(n + 1, 0);
+  for (int qq = 0; qq < nnz; ++qq) colptr[colidx[qq] + 1]++;
+  for (int j = 0; j < n; ++j) colptr[j + 1] += colptr[j];
+  rowidx.resize(nnz);
+  valT.resize(nnz);
+  {
+    std::vector<int> fill(colptr.begin(), colptr.end() - 1);
+    for (int i = 0; i < m; ++i)
+      for (int qq = rowptr[i]; qq < rowptr[i + 1]; ++qq) {
+        const int dst = fill[colidx[qq]]++;
+        rowidx[dst] = i;
+        valT[dst] = val[qq];
+      }
+  }
+  // ---- D-hat (Remark se:Dhat_construction): x part from columns, y part from rows ----
+  dhat.assign(N, 1.0);
+  if (opt.dhat_mode != 0) {
+    std::vector<double> cm(n, 0.0), rm(m, 0.0);
+    for (int i = 0; i < m; ++i)
+      for (int qq = rowptr[i]; qq < rowptr[i + 1]; ++qq) {
+        const double a = std::fabs(val[qq]);
+        rm[i] = std::max(rm[i], a);
+        cm[colidx[qq]] = std::max(cm[colidx[qq]], a);
+      }
+    for (int j = 0; j < n; ++j) dhat[j] = std::sqrt(std::max(cm[j], 1e-10));
+    for (int i = 0; i < m; ++i) dhat[n + i] = std::sqrt(std::max(rm[i], 1e-10));
+    if (opt.dhat_mode == 2)
+      for (auto& v : dhat) v = 1.0 / v;
+  }
+  qnorm = 0.0;
+  for (double v : q) qnorm += v * v;
+  qnorm = std::sqrt(qnorm);
+  cnorm = 0.0;
+  for (double v : c) cnorm += v * v;
+  cnorm = std::sqrt(cnorm);
+  // ---- work tables ----
+  build_chunks(colptr, n, chunksA, splitsA, npartsA);
+  build_groups(chunksA, groupsA);
+  build_chunks(rowptr, m, chunksB, splitsB, npartsB);
+  build_groups(chunksB, groupsB);
+  tiles.clear();
+  for (int e = 0; e < N; e += MIX_TILE) {
+    MixTile t{};
+    t.e0 = e;
+    t.e1 = std::min(N, e + MIX_TILE);
+    tiles.push_back(t);
+  }
+  // ---- device copies ----
+  const size_t ts = fp64 ? 8 : 4;
+  d_rowptr.upload(rowptr.data(), rowptr.size() * 4, "rowptr");
+  d_colidx.upload(colidx.data(), colidx.size() * 4, "colidx");
+  d_colptr.upload(colptr.data(), colptr.size() * 4, "colptr");
+  d_rowidx.upload(rowidx.data(), rowidx.size() * 4, "rowidx");
+  if (fp64) {
+    upload_as<double>(d_val, val, "val");
+    upload_as<double>(d_valT, valT, "valT");
+    upload_as<double>(d_c, c, "c");
+    upload_as<double>(d_lo, lo, "l");
+    upload_as<double>(d_hi, hi, "u");
+    upload_as<double>(d_q, q, "q");
+    upload_as<double>(d_dhat, dhat, "dhat");
+  } else {
+    upload_as<float>(d_val, val, "val");
+    upload_as<float>(d_valT, valT, "valT");
+    upload_as<float>(d_c, c, "c");
+    upload_as<float>(d_lo, lo, "l");
+    upload_as<float>(d_hi, hi, "u");
+    upload_as<float>(d_q, q, "q");
+    upload_as<float>(d_dhat, dhat, "dhat");
+  }
+  d_rowtype.upload(rowtype.data(), rowtype.size(), "rowtype");
+  for (int p = 0; p < 2; ++p) {
+    d_u[p].alloc(N * ts, "u");
+    d_u[p].zero("u");
+    d_g[p].alloc(N * ts, "g");
+    d_g[p].zero("g");
+  }
+  d_xbar.alloc(n * ts, "xbar");
+  d_hist_dG.alloc((size_t)opt.memory * N * ts, "history dG");
+  d_hist_dG.zero("history dG");
+  d_hist_W.alloc((size_t)opt.memory * N * ts, "history W");
+  d_hist_W.zero("history W");
+  d_lam.alloc(n * ts, "lambda");
+  d_sc.alloc(sizeof(Scalars), "scalars");
+  d_xfer.alloc((size_t)N * 8, "transfer buffer");
+  fill_desc();
+  // ---- step size (Section 5.1): tau = sigma = 0.9 / ||K||_2 by power iteration ----
+  norm_est = power_norm();
+  if (opt.tau <= 0.0 || opt.sigma <= 0.0) {
+    if (!(norm_est > 0.0)) {
+      opt.tau = opt.sigma = 1.0;  // K = 0: any step satisfies the assumption
+    } else {
+      opt.tau = opt.sigma = 0.9 / norm_est;
+    }
+  } else if (norm_est > 0.0 && opt.tau * opt.sigma * norm_est * norm_est >= 1.0) {
+    throw Error(AAPDHG_E_ARG, "tau * sigma * ||K||^2 = %g must be < 1 (||K|| ~ %g)",
+                opt.tau * opt.sigma * norm_est * norm_est, norm_est);
+  }
+  fill_desc();
+  d_desc.upload(&desc, sizeof desc, "descriptor");
+  solo = std::make_unique<LaunchSet>();
+  std::vector<Problem*> one{this};
+  solo->build(one);
+  reset_host_state();
+}
+
+void Problem::fill_desc() {
+  std::memset(&desc, 0, sizeof desc);
+  desc.m = m;
+  desc.n = n;
+  desc.N = N;
+  desc.M = opt.memory;
+  desc.variant = opt.variant;
+  desc.kkt_every = opt.kkt_every;
+  desc.max_iter = opt.max_iter;
+  desc.tau = opt.tau;
+  desc.sigma = opt.sigma;
+  desc.beta = opt.beta;
+  desc.D = opt.D;
+  desc.eps_sg = opt.eps_sg;
+  desc.eta = opt.eta;
+  desc.cs = opt.cs;
+  desc.kappa_bar = opt.kappa_bar;
+  desc.tol = opt.tol;
+  desc.rowptr = (const int*)d_rowptr.p;
+  desc.colidx = (const int*)d_colidx.p;
+  desc.val = d_val.p;
+  desc.colptr = (const int*)d_colptr.p;
+  desc.rowidx = (const int*)d_rowidx.p;
+  desc.valT = d_valT.p;
+  desc.c = d_c.p;
+  desc.lo = d_lo.p;
+  desc.hi = d_hi.p;
+  desc.q = d_q.p;
+  desc.dhat = d_dhat.p;
+  desc.rowtype = (const unsigned char*)d_rowtype.p;
+  desc.u[0] = d_u[0].p;
+  desc.u[1] = d_u[1].p;
+  desc.g[0] = d_g[0].p;
+  desc.g[1] = d_g[1].p;
+  desc.xbar = d_xbar.p;
+  desc.dG = d_hist_dG.p;
+  desc.W = d_hist_W.p;
+  desc.lam = d_lam.p;
+  desc.sc = (Scalars*)d_sc.p;
+}
+
+double Problem::power_norm() {
+  DevBuf work, est;
+  work.alloc(((size_t)2 * n + m + 1024) * 8, "power iteration work");
+  est.alloc(((size_t)opt.power_iters + 1) * 8, "power iteration estimates");
+  hip_check(launch_power_iteration(desc, fp64, opt.power_iters, (double*)work.p, (double*)est.p, nullptr),
+            "power iteration launch");
+  std::vector<double> e(opt.power_iters + 1);
+  hip_check(hipMemcpy(e.data(), est.p, e.size() * 8, hipMemcpyDeviceToHost), "power iteration result");
+  return std::sqrt(std::max(0.0, e.back()));
+}
+
+size_t Problem::device_bytes() const {
+  size_t b = 0;
+  const DevBuf* bufs[] = {&d_rowptr, &d_colidx, &d_val, &d_colptr, &d_rowidx, &d_valT, &d_c, &d_lo, &d_hi,
+                          &d_q, &d_dhat, &d_rowtype, &d_u[0], &d_u[1], &d_g[0], &d_g[1], &d_xbar, &d_hist_dG,
+                          &d_hist_W, &d_lam, &d_sc, &d_desc, &d_xfer};
+  for (auto* p : bufs) b += p->bytes;
+  if (solo) b += solo->device_bytes();
+  return b;
+}
+
+void Problem::reset_host_state() {
+  std::memset(&sc_init, 0, sizeof sc_init);
+  sc_init.k = 0;
+  sc_init.status = ST_RUNNING;
+  sc_init.branch = BR_NONE;
+  sc_init.nlive = 0;
+  sc_init.newslot = 0;
+  sc_init.qnorm = qnorm;
+  sc_init.cnorm = cnorm;
+}
+
+void Problem::enqueue_reset(hipStream_t st) {
+  hip_check(hipMemcpyAsync(d_sc.p, &sc_init, sizeof sc_init, hipMemcpyHostToDevice, st), "reset scalars");
+  hip_check(launch_start_point(desc, fp64, st), "start point");
+  started = true;
+}
+
+// ---------------------------------------------------------------------------
+// launch sets
+// ---------------------------------------------------------------------------
+
+LaunchSet::~LaunchSet() {
+  if (h_status) (void)hipHostFree(h_status);
+}
+
+size_t LaunchSet::device_bytes() const {
+  size_t b = 0;
+  const DevBuf* bufs[] = {&d_lps, &d_llp, &d_chunksA, &d_chunksB, &d_groups, &d_splits, &d_cpartA, &d_cpartB,
+                          &d_gpart, &d_gcnt, &d_splitpart, &d_splitcnt, &d_splitdots, &d_tiles, &d_status};
+  for (auto* p : bufs) b += p->bytes;
+  return b;
+}
+
+void LaunchSet::build(const std::vector<Problem*>& lps) {
+  members = lps;
+  const int count = (int)lps.size();
+  if (count == 0) throw Error(AAPDHG_E_ARG, "empty launch set");
+  std::vector<LPDesc> descs;
+  std::vector<LaunchLP> llp(count);
+  std::vector<Chunk> cA, cB;
+  std::vector<Group> groups;
+  std::vector<SplitRow> splits;
+  std::vector<MixTile> tl;
+  int parts = 0;
+  t = LaunchTables{};
+  t.fp64 = lps[0]->fp64;
+  int mt = 1;
+  for (int i = 0; i < count; ++i) {
+    Problem* p = lps[i];
+    if (p->fp64 != t.fp64) throw Error(AAPDHG_E_ARG, "all problems of a batch must share the precision");
+    mt = std::max(mt, p->opt.memory);
+    descs.push_back(p->desc);
+    LaunchLP& L = llp[i];
+    // pass A
+    L.gA0 = (int)groups.size();
+    L.nA = (int)p->groupsA.size();
+    L.sA0 = (int)splits.size();
+    L.nsA = (int)p->splitsA.size();
+    const int cA0 = (int)cA.size();
+    for (auto g : p->groupsA) {
+      g.first += cA0;
+      g.lp = i;
+      groups.push_back(g);
+    }
+    for (auto s : p->splitsA) {
+      s.part0 += parts;
+      splits.push_back(s);
+    }
+    parts += p->npartsA;
+    for (auto c : p->chunksA) {
+      c.lp = i;
+      c.group += L.gA0;
+      if (c.kind == 1) c.split += L.sA0;
+      cA.push_back(c);
+    }
+    // pass B
+    L.gB0 = (int)groups.size();
+    L.nB = (int)p->groupsB.size();
+    L.sB0 = (int)splits.size();
+    L.nsB = (int)p->splitsB.size();
+    const int cB0 = (int)cB.size();
+    for (auto g : p->groupsB) {
+      g.first += cB0;
+      g.lp = i;
+      groups.push_back(g);
+    }
+    for (auto s : p->splitsB) {
+      s.part0 += parts;
+      splits.push_back(s);
+    }
+    parts += p->npartsB;
+    for (auto c : p->chunksB) {
+      c.lp = i;
+      c.group += L.gB0;
+      if (c.kind == 1) c.split += L.sB0;
+      cB.push_back(c);
+    }
+    for (auto x : p->tiles) {
+      x.lp = i;
+      tl.push_back(x);
+    }
+  }
+  t.mt = mt;
+  t.nlps = count;
+  d_lps.upload(descs.data(), descs.size() * sizeof(LPDesc), "lp table");
+  d_llp.upload(llp.data(), llp.size() * sizeof(LaunchLP), "lp ranges");
+  d_chunksA.upload(cA.data(), cA.size() * sizeof(Chunk), "chunks A");
+  d_chunksB.upload(cB.data(), cB.size() * sizeof(Chunk), "chunks B");
+  d_groups.upload(groups.data(), groups.size() * sizeof(Group), "groups");
+  d_splits.upload(splits.data(), splits.size() * sizeof(SplitRow), "splits");
+  d_cpartA.alloc(cA.size() * NDOT * 8, "chunk partials A");
+  d_cpartB.alloc(cB.size() * NDOT * 8, "chunk partials B");
+  d_gpart.alloc(groups.size() * NDOT * 8, "group partials");
+  d_gcnt.alloc(groups.size() * 4, "group counters");
+  d_gcnt.zero("group counters");
+  d_splitpart.alloc((size_t)std::max(parts, 1) * 2 * 8, "split partials");
+  d_splitcnt.alloc(std::max<size_t>(splits.size(), 1) * 4, "split counters");
+  d_splitcnt.zero("split counters");
+  d_splitdots.alloc(std::max<size_t>(splits.size(), 1) * NDOT * 8, "split dots");
+  d_splitdots.zero("split dots");
+  d_tiles.upload(tl.data(), tl.size() * sizeof(MixTile), "mix tiles");
+  d_status.alloc(count * 4, "status");
+  if (!h_status) hip_check(hipHostMalloc((void**)&h_status, sizeof(int) * 2 * MAX_STATUS, hipHostMallocDefault), "pinned status");
+  if (count > MAX_STATUS) throw Error(AAPDHG_E_ARG, "at most %d problems per batch", MAX_STATUS);
+  t.lps = (const LPDesc*)d_lps.p;
+  t.llp = (const LaunchLP*)d_llp.p;
+  t.chunksA = (const Chunk*)d_chunksA.p;
+  t.nchunksA = (int)cA.size();
+  t.chunksB = (const Chunk*)d_chunksB.p;
+  t.nchunksB = (int)cB.size();
+  t.groups = (const Group*)d_groups.p;
+  t.splits = (const SplitRow*)d_splits.p;
+  t.cpartA = (double*)d_cpartA.p;
+  t.cpartB = (double*)d_cpartB.p;
+  t.gpart = (double*)d_gpart.p;
+  t.gcnt = (unsigned int*)d_gcnt.p;
+  t.splitpart = (double*)d_splitpart.p;
+  t.splitcnt = (unsigned int*)d_splitcnt.p;
+  t.splitdots = (double*)d_splitdots.p;
+  t.tiles = (const MixTile*)d_tiles.p;
+  t.ntiles = (int)tl.size();
+  // scalars' lp counters start at zero (they are part of the reset image)
+}
+
+void LaunchSet::enqueue_passes(hipStream_t st, int64_t iters) {
+  for (int64_t it = 0; it < iters; ++it) hip_check(launch_loop_pass(t, st, MODE_ITER), "loop pass");
+}
+
+void LaunchSet::enqueue_eval(hipStream_t st) { hip_check(launch_loop_pass(t, st, MODE_EVAL), "evaluation pass"); }
+
+// Run epochs until every member has stopped.  The status of epoch e is read
+// while epoch e+1 is already queued, so the device does not wait for the host.
+double LaunchSet::run_to_completion(hipStream_t st, int epoch, double time_limit_s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const int count = t.nlps;
+  hipEvent_t ev[2];
+  hip_check(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming), "event");
+  hip_check(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming), "event");
+  int slot = 0;
+  bool pending = false;
+  int pend_slot = 0;
+  bool done = false;
+  int64_t epochs = 0;
+  while (!done) {
+    enqueue_passes(st, epoch);
+    hip_check(launch_gather_status(t.lps, count, (int*)d_status.p, st), "status gather");
+    hip_check(hipMemcpyAsync(h_status + slot * MAX_STATUS, d_status.p, count * 4, hipMemcpyDeviceToHost, st), "status copy");
+    hip_check(hipEventRecord(ev[slot], st), "event record");
+    ++epochs;
+    if (pending) {
+      hip_check(hipEventSynchronize(ev[pend_slot]), "event wait");
+      bool any = false;
+      for (int i = 0; i < count; ++i) any |= h_status[pend_slot * MAX_STATUS + i] == ST_RUNNING;
+      if (!any) done = true;
+    }
+    pending = true;
+    pend_slot = slot;
+    slot ^= 1;
+    const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (!done && time_limit_s > 0.0 && el > time_limit_s) {
+      hip_check(launch_time_limit(t.lps, count, st), "time limit");
+      done = true;
+    }
+  }
+  hip_check(hipStreamSynchronize(st), "solve sync");
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  last_epochs = epochs;
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// ---------------------------------------------------------------------------
+// results
+// ---------------------------------------------------------------------------
+
+void Problem::read_scalars(Scalars& s) {
+  hip_check(hipMemcpy(&s, d_sc.p, sizeof s, hipMemcpyDeviceToHost), "read scalars");
+}
+
+void Problem::download(const void* dev, size_t len, double* host, hipStream_t st) {
+  hip_check(launch_to_f64(dev, fp64, (double*)d_xfer.p, len, st), "convert");
+  hip_check(hipMemcpyAsync(host, d_xfer.p, len * 8, hipMemcpyDeviceToHost, st), "download");
+  hip_check(hipStreamSynchronize(st), "download sync");
+}
+
+void Problem::upload_vec(void* dev, const double* host, size_t len, hipStream_t st) {
+  hip_check(hipMemcpyAsync(d_xfer.p, host, len * 8, hipMemcpyHostToDevice, st), "upload");
+  hip_check(launch_from_f64((const double*)d_xfer.p, dev, fp64, len, st), "convert");
+  hip_check(hipStreamSynchronize(st), "upload sync");
+}
+
+void Problem::result(double* x, double* y, double* lam, aapdhg_info* info, bool run_eval) {
+  hip_check(hipDeviceSynchronize(), "result sync");
+  if (!started) throw Error(AAPDHG_E_STATE, "no solve has been run on this handle");
+  if (run_eval) {
+    solo->enqueue_eval(nullptr);
+    hip_check(hipStreamSynchronize(nullptr), "evaluation sync");
+  }
+  Scalars s;
+  read_scalars(s);
+  const int par = (int)(s.k & 1);
+  const size_t ts = fp64 ? 8 : 4;
+  std::vector<double> u(N);
+  download(d_u[par].p, N, u.data(), nullptr);
+  if (x)
+    for (int j = 0; j < n; ++j) x[j] = u[j] * d_col[j];
+  if (y)
+    for (int i = 0; i < m; ++i) y[i] = u[n + i] * d_row[i];
+  if (lam) {
+    std::vector<double> l(n);
+    download(d_lam.p, n, l.data(), nullptr);
+    for (int j = 0; j < n; ++j) lam[j] = l[j] / d_col[j];
+  }
+  (void)ts;
+  if (info) {
+    std::memset(info, 0, sizeof *info);
+    info->term = s.status;
+    info->iters = s.k;
+    info->aa_steps = s.i_aa;
+    info->pdhg_steps = s.j_pdhg;
+    info->primal_obj = s.pobj;
+    info->dual_obj = s.dobj;
+    info->r_gap = s.r_g;
+    info->r_pri = s.r_p;
+    info->r_dual = s.r_d;
+    info->kkt = s.kkt;
+    info->gnorm = s.gnorm;
+    info->g0norm = s.n0;
+    info->solve_seconds = last_solve_seconds;
+    info->step_tau = opt.tau;
+    info->step_sigma = opt.sigma;
+  }
+}
+
+// checkpoint layout: see aapdhg_get_state in aapdhg.h
+void Problem::get_state(double* u, double* u_prev, double* g_prev, double* dG, double* W, int64_t* meta,
+                        double* gram) {
+  hip_check(hipDeviceSynchronize(), "state sync");
+  Scalars s;
+  read_scalars(s);
+  const int par = (int)(s.k & 1);
+  if (u) download(d_u[par].p, N, u, nullptr);
+  if (u_prev) download(d_u[par ^ 1].p, N, u_prev, nullptr);
+  if (g_prev) download(d_g[par ^ 1].p, N, g_prev, nullptr);
+  const size_t ts = fp64 ? 8 : 4;
+  for (int sl = 0; sl < opt.memory; ++sl) {
+    if (dG) download((char*)d_hist_dG.p + (size_t)sl * N * ts, N, dG + (size_t)sl * N, nullptr);
+    if (W) download((char*)d_hist_W.p + (size_t)sl * N * ts, N, W + (size_t)sl * N, nullptr);
+  }
+  if (meta) {
+    std::memset(meta, 0, sizeof(int64_t) * (8 + 2 * MAXM));
+    meta[0] = s.k;
+    meta[1] = s.status;
+    meta[2] = s.i_aa;
+    meta[3] = s.j_pdhg;
+    meta[4] = s.nlive;
+    meta[5] = s.newslot;
+    for (int t = 0; t < MAXM; ++t) meta[8 + t] = s.live[t];
+  }
+  if (gram) {
+    std::memcpy(gram, s.G, sizeof s.G);
+    std::memcpy(gram + MAXM * MAXM, s.rhs, sizeof s.rhs);
+    std::memcpy(gram + MAXM * MAXM + MAXM, s.du2, sizeof s.du2);
+    gram[MAXM * MAXM + 2 * MAXM] = s.n0;
+    gram[MAXM * MAXM + 2 * MAXM + 1] = s.gnorm;
+  }
+}
+
+void Problem::set_state(const double* u, const double* u_prev, const double* g_prev, const double* dG,
+                        const double* W, const int64_t* meta, const double* gram) {
+  if (!meta || !gram || !u || !u_prev || !g_prev || !dG || !W)
+    throw Error(AAPDHG_E_ARG, "set_state needs every buffer");
+  hip_check(hipDeviceSynchronize(), "state sync");
+  Scalars s = sc_init;
+  s.k = meta[0];
+  s.status = (int)meta[1];
+  s.i_aa = meta[2];
+  s.j_pdhg = meta[3];
+  s.nlive = (int)meta[4];
+  s.newslot = (int)meta[5];
+  if (s.k < 0 || s.nlive < 0 || s.nlive > opt.memory || s.newslot < 0 || s.newslot >= opt.memory)
+    throw Error(AAPDHG_E_ARG, "invalid state metadata");
+  for (int t = 0; t < MAXM; ++t) s.live[t] = (int)meta[8 + t];
+  for (int t = 0; t < s.nlive; ++t)
+    if (s.live[t] < 0 || s.live[t] >= opt.memory) throw Error(AAPDHG_E_ARG, "invalid live slot");
+  std::memcpy(s.G, gram, sizeof s.G);
+  std::memcpy(s.rhs, gram + MAXM * MAXM, sizeof s.rhs);
+  std::memcpy(s.du2, gram + MAXM * MAXM + MAXM, sizeof s.du2);
+  s.n0 = gram[MAXM * MAXM + 2 * MAXM];
+  s.gnorm = gram[MAXM * MAXM + 2 * MAXM + 1];
+  s.branch = BR_PDHG;
+  const int par = (int)(s.k & 1);
+  upload_vec(d_u[par].p, u, N, nullptr);
+  upload_vec(d_u[par ^ 1].p, u_prev, N, nullptr);
+  upload_vec(d_g[par ^ 1].p, g_prev, N, nullptr);
+  const size_t ts = fp64 ? 8 : 4;
+  for (int sl = 0; sl < opt.memory; ++sl) {
+    upload_vec((char*)d_hist_dG.p + (size_t)sl * N * ts, dG + (size_t)sl * N, N, nullptr);
+    upload_vec((char*)d_hist_W.p + (size_t)sl * N * ts, W + (size_t)sl * N, N, nullptr);
+  }
+  hip_check(hipMemcpy(d_sc.p, &s, sizeof s, hipMemcpyHostToDevice), "write scalars");
+  started = true;
+}
+
+}  // namespace aapdhg
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+using namespace aapdhg;
+
+struct aapdhg_problem {
+  Problem p;
+  std::string err;
+};
+
+struct aapdhg_batch {
+  std::vector<aapdhg_problem*> members;
+  LaunchSet set;
+  std::string err;
+};
+
+template <typename F>
+static aapdhg_status guard(std::string* err, F&& f) {
+  try {
+    f();
+    return AAPDHG_OK;
+  } catch (const Error& e) {
+    if (err) *err = e.msg;
+    g_thread_error = e.msg;
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    if (err) *err = "host allocation failed";
+    g_thread_error = "host allocation failed";
+    return AAPDHG_E_NOMEM;
+  } catch (const std::exception& e) {
+    if (err) *err = e.what();
+    g_thread_error = e.what();
+    return AAPDHG_E_ARG;
+  }
+}
+
+extern "C" {
+
+void aapdhg_default_options(aapdhg_options* o) {
+  if (o) default_options(o);
+}
+
+aapdhg_status aapdhg_create(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                            const double* val, const double* c, const double* q, const double* l, const double* u,
+                            const uint8_t* row_type, const aapdhg_options* opt, aapdhg_t* out) {
+  if (!out) {
+    g_thread_error = "out is NULL";
+    return AAPDHG_E_ARG;
+  }
+  *out = nullptr;
+  auto* h = new (std::nothrow) aapdhg_problem;
+  if (!h) {
+    g_thread_error = "host allocation failed";
+    return AAPDHG_E_NOMEM;
+  }
+  aapdhg_status st = guard(nullptr, [&] { h->p.create(m, n, nnz, row_ptr, col_idx, val, c, q, l, u, row_type, opt); });
+  if (st != AAPDHG_OK) {
+    delete h;
+    return st;
+  }
+  *out = h;
+  return AAPDHG_OK;
+}
+
+aapdhg_status aapdhg_solve(aapdhg_t h, void* stream) {
+  if (!h) return AAPDHG_E_ARG;
+  return guard(&h->err, [&] {
+    if (h->p.in_batch) throw Error(AAPDHG_E_STATE, "problem belongs to a live batch");
+    hipStream_t st = (hipStream_t)stream;
+    h->p.enqueue_reset(st);
+    h->p.last_solve_seconds = h->p.solo->run_to_completion(st, h->p.opt.epoch, h->p.opt.time_limit_s);
+  });
+}
+
+aapdhg_status aapdhg_iterate(aapdhg_t h, void* stream, int64_t iters) {
+  if (!h) return AAPDHG_E_ARG;
+  return guard(&h->err, [&] {
+    if (iters < 0) throw Error(AAPDHG_E_ARG, "iters must be >= 0");
+    if (h->p.in_batch) throw Error(AAPDHG_E_STATE, "problem belongs to a live batch");
+    hipStream_t st = (hipStream_t)stream;
+    if (!h->p.started) h->p.enqueue_reset(st);
+    h->p.solo->enqueue_passes(st, iters);
+  });
+}
+
+aapdhg_status aapdhg_reset(aapdhg_t h, void* stream) {
+  if (!h) return AAPDHG_E_ARG;
+  return guard(&h->err, [&] { h->p.enqueue_reset((hipStream_t)stream); });
+}
+
+aapdhg_status aapdhg_result(aapdhg_t h, double* x, double* y, double* lambda, aapdhg_info* info) {
+  if (!h) return AAPDHG_E_ARG;
+  return guard(&h->err, [&] { h->p.result(x, y, lambda, info, true); });
+}
+
+aapdhg_status aapdhg_get_state(aapdhg_t h, double* u, double* u_prev, double* g_prev, double* dG, double* W,
+                               int64_t* meta, double* gram) {
+  if (!h) return AAPDHG_E_ARG;
+  return guard(&h->err, [&] { h->p.get_state(u, u_prev, g_prev, dG, W, meta, gram); });
+}
+
+aapdhg_status aapdhg_set_state(aapdhg_t h, const double* u, const double* u_prev, const double* g_prev,
+                               const double* dG, const double* W, const int64_t* meta, const double* gram) {
+  if (!h) return AAPDHG_E_ARG;
+  return guard(&h->err, [&] { h->p.set_state(u, u_prev, g_prev, dG, W, meta, gram); });
+}
+
+aapdhg_status aapdhg_get_dims(aapdhg_t h, int32_t* m, int32_t* n, int64_t* nnz, double* tau, double* sigma) {
+  if (!h) return AAPDHG_E_ARG;
+  if (m) *m = h->p.m;
+  if (n) *n = h->p.n;
+  if (nnz) *nnz = h->p.nnz;
+  if (tau) *tau = h->p.opt.tau;
+  if (sigma) *sigma = h->p.opt.sigma;
+  return AAPDHG_OK;
+}
+
+aapdhg_status aapdhg_get_scaling(aapdhg_t h, double* d_row, double* d_col) {
+  if (!h) return AAPDHG_E_ARG;
+  if (d_row) std::copy(h->p.d_row.begin(), h->p.d_row.end(), d_row);
+  if (d_col) std::copy(h->p.d_col.begin(), h->p.d_col.end(), d_col);
+  return AAPDHG_OK;
+}
+
+aapdhg_status aapdhg_destroy(aapdhg_t h) {
+  if (!h) return AAPDHG_E_ARG;
+  (void)hipDeviceSynchronize();
+  delete h;
+  return AAPDHG_OK;
+}
+
+const char* aapdhg_last_error(aapdhg_t h) {
+  if (h) return h->err.c_str();
+  return g_thread_error.c_str();
+}
+
+aapdhg_status aapdhg_batch_create(int32_t count, const aapdhg_t* problems, aapdhg_batch_t* out) {
+  if (!out || !problems || count < 1) {
+    g_thread_error = "invalid batch arguments";
+    return AAPDHG_E_ARG;
+  }
+  *out = nullptr;
+  auto* b = new (std::nothrow) aapdhg_batch;
+  if (!b) return AAPDHG_E_NOMEM;
+  aapdhg_status st = guard(nullptr, [&] {
+    std::vector<Problem*> ps;
+    for (int i = 0; i < count; ++i) {
+      if (!problems[i]) throw Error(AAPDHG_E_ARG, "problem %d is NULL", i);
+      if (problems[i]->p.in_batch) throw Error(AAPDHG_E_STATE, "problem %d already belongs to a batch", i);
+      for (int j = 0; j < i; ++j)
+        if (problems[j] == problems[i]) throw Error(AAPDHG_E_ARG, "problem %d appears twice", i);
+      ps.push_back(&problems[i]->p);
+      b->members.push_back(problems[i]);
+    }
+    b->set.build(ps);
+    for (auto* p : ps) p->in_batch = true;
+  });
+  if (st != AAPDHG_OK) {
+    delete b;
+    return st;
+  }
+  *out = b;
+  return AAPDHG_OK;
+}
+
+aapdhg_status aapdhg_batch_solve(aapdhg_batch_t b, void* stream) {
+  if (!b) return AAPDHG_E_ARG;
+  return guard(&b->err, [&] {
+    hipStream_t st = (hipStream_t)stream;
+    int epoch = 1 << 30;
+    double tl = 0.0;
+    for (auto* h : b->members) {
+      h->p.enqueue_reset(st);
+      epoch = std::min(epoch, h->p.opt.epoch);
+      tl = std::max(tl, h->p.opt.time_limit_s);
+    }
+    const double secs = b->set.run_to_completion(st, epoch, tl);
+    for (auto* h : b->members) h->p.last_solve_seconds = secs;
+  });
+}
+
+aapdhg_status aapdhg_batch_iterate(aapdhg_batch_t b, void* stream, int64_t iters) {
+  if (!b) return AAPDHG_E_ARG;
+  return guard(&b->err, [&] {
+    if (iters < 0) throw Error(AAPDHG_E_ARG, "iters must be >= 0");
+    hipStream_t st = (hipStream_t)stream;
+    for (auto* h : b->members)
+      if (!h->p.started) h->p.enqueue_reset(st);
+    b->set.enqueue_passes(st, iters);
+  });
+}
+
+aapdhg_status aapdhg_batch_destroy(aapdhg_batch_t b) {
+  if (!b) return AAPDHG_E_ARG;
+  (void)hipDeviceSynchronize();
+  for (auto* h : b->members) h->p.in_batch = false;
+  delete b;
+  return AAPDHG_OK;
+}
+
+}  // extern "C"

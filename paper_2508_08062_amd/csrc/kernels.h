@@ -1,0 +1,47 @@
+// Launchers of the HIP kernels (kernels.hip), used by the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "aapdhg_internal.h"
+
+namespace aapdhg {
+
+// Device tables of one launch set: the LPs that advance together.
+struct LaunchTables {
+  bool fp64 = false;
+  int mt = 4;  // memory bound of the kernel instantiation (>= every member's m_A)
+  const LPDesc* lps = nullptr;
+  const LaunchLP* llp = nullptr;
+  int nlps = 0;
+  const Chunk* chunksA = nullptr;
+  int nchunksA = 0;
+  const Chunk* chunksB = nullptr;
+  int nchunksB = 0;
+  const Group* groups = nullptr;
+  const SplitRow* splits = nullptr;
+  double* cpartA = nullptr;
+  double* cpartB = nullptr;
+  double* gpart = nullptr;
+  unsigned int* gcnt = nullptr;
+  double* splitpart = nullptr;
+  unsigned int* splitcnt = nullptr;
+  double* splitdots = nullptr;
+  const MixTile* tiles = nullptr;
+  int ntiles = 0;
+};
+
+// One loop pass (passes A, B and, in MODE_ITER, C) for every LP of the table.
+hipError_t launch_loop_pass(const LaunchTables& t, hipStream_t st, int mode);
+hipError_t launch_start_point(const LPDesc& d, bool fp64, hipStream_t st);
+// Power iteration on K^T K from the all-ones vector; est[0..iters] receives
+// ||K^T K v|| of each step (the square of the ||K|| estimate).  work holds
+// 2n + m + 1024 doubles.
+hipError_t launch_power_iteration(const LPDesc& d, bool fp64, int iters, double* work, double* est,
+                                  hipStream_t st);
+hipError_t launch_gather_status(const LPDesc* lps, int count, int* out, hipStream_t st);
+hipError_t launch_time_limit(const LPDesc* lps, int count, hipStream_t st);
+hipError_t launch_to_f64(const void* src, bool fp64, double* dst, size_t len, hipStream_t st);
+hipError_t launch_from_f64(const double* src, void* dst, bool fp64, size_t len, hipStream_t st);
+
+}  // namespace aapdhg

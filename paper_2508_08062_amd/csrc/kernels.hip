@@ -1,0 +1,835 @@
+// HIP kernels of the AA-PDHG / FAA-PDHG hot path for gfx950 (MI355X).
+//
+// One loop pass of Alg 2 / Alg 3 is three launches over a table of work items
+// that may mix many LPs:
+//   pass A  primal: w = K^T y by CSC gather, x_hat = P_X(x - tau (c - w)),
+//           x_bar = 2 x_hat - x, g_x = x_hat - x, history column x-part and its
+//           dot products, KKT sums at u^k (eq. pdhg; Alg 2 memory lines;
+//           Remark re:constrcution-termi-con)
+//   pass B  dual: v = K x_bar by CSR gather, y_hat = P_Y(y + sigma (q - v)),
+//           g_y, history y-part and dots; the last block of each LP reduces all
+//           partial sums in a fixed order and takes the decisions of the pass
+//           in float64 (termination, memory update, safeguard, filters, the
+//           m x m least-squares solve)
+//   pass C  mix: u^{k+1} = P(u^k + beta D-hat g^k - sum_t gamma_t W_t) on
+//           Anderson steps (W = dU + beta D-hat dG, so this is u^k - H^k g^k).
+// A PDHG step needs no pass C: passes A/B already wrote u_hat^{k+1} into the
+// buffer of the next iterate.
+//
+// Reductions are deterministic: every partial sum has a fixed place and is
+// added in a fixed order, so a run is bitwise repeatable and an LP's iterates
+// do not depend on which other LPs share the launch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "aapdhg_internal.h"
+#include "kernels.h"
+
+namespace aapdhg {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block-wide sum of one value per thread; the result is valid in thread 0.
+// Fixed butterfly inside each wave, then the four wave sums in wave order.
+__device__ __forceinline__ double block_sum(double v, double* s_tmp) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) s_tmp[wv] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = ((s_tmp[0] + s_tmp[1]) + s_tmp[2]) + s_tmp[3];
+  return r;
+}
+
+template <typename T>
+__device__ __forceinline__ T clampT(T v, T lo, T hi) {
+  return v < lo ? lo : (v > hi ? hi : v);
+}
+
+__device__ __forceinline__ double proj_lambda(double lam, bool lf, bool uf) {
+  // eq. lambda-case: {0} both infinite, R- only u finite, R+ only l finite, R both finite
+  if (!lf && !uf) return 0.0;
+  if (!lf) return lam < 0.0 ? lam : 0.0;
+  if (!uf) return lam > 0.0 ? lam : 0.0;
+  return lam;
+}
+
+// ---------------------------------------------------------------------------
+// decisions of a loop pass (one thread of the last block of an LP)
+// ---------------------------------------------------------------------------
+
+// Cholesky of the n x n matrix A (row-major, stride MAXM), in place (lower).
+// Returns false on a non-positive or non-finite pivot.
+__device__ bool chol(double* A, int n) {
+  for (int j = 0; j < n; ++j) {
+    double s = A[j * MAXM + j];
+    for (int p = 0; p < j; ++p) s -= A[j * MAXM + p] * A[j * MAXM + p];
+    if (!(s > 0.0) || !isfinite(s)) return false;
+    const double r = sqrt(s);
+    A[j * MAXM + j] = r;
+    for (int i = j + 1; i < n; ++i) {
+      double t = A[i * MAXM + j];
+      for (int p = 0; p < j; ++p) t -= A[i * MAXM + p] * A[j * MAXM + p];
+      A[i * MAXM + j] = t / r;
+    }
+  }
+  return true;
+}
+
+// Solve L L^T x = b with the factor from chol (b overwritten by x).
+__device__ void chol_solve(const double* L, double* b, int n) {
+  for (int i = 0; i < n; ++i) {
+    double s = b[i];
+    for (int p = 0; p < i; ++p) s -= L[i * MAXM + p] * b[p];
+    b[i] = s / L[i * MAXM + i];
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double s = b[i];
+    for (int p = i + 1; p < n; ++p) s -= L[p * MAXM + i] * b[p];
+    b[i] = s / L[i * MAXM + i];
+  }
+}
+
+// LDS workspace of the decisions (used by one thread of the finishing block).
+struct SolveWork {
+  double A[MAXM * MAXM];
+  double R[MAXM * MAXM];
+  double gam[MAXM];
+  double fn[MAXM], rii[MAXM], b[MAXM], e2[MAXM];
+  int live[MAXM], ord[MAXM], keep[MAXM];
+  bool dep[MAXM];
+};
+
+// gamma for the history columns `slots` (oldest first): (G + shift I) gamma = rhs.
+__device__ bool solve_gamma(const Scalars* sc, const int* slots, int n, double shift, double* gamma, double* A) {
+  for (int a = 0; a < n; ++a) {
+    for (int b = 0; b <= a; ++b) A[a * MAXM + b] = sc->G[slots[a] * MAXM + slots[b]];
+    A[a * MAXM + a] += shift;
+    gamma[a] = sc->rhs[slots[a]];
+  }
+  if (!chol(A, n)) return false;
+  chol_solve(A, gamma, n);
+  for (int a = 0; a < n; ++a)
+    if (!isfinite(gamma[a])) return false;
+  return true;
+}
+
+// FAA filters (Alg 3 lines Reverse..Reverse; Alg 4 AngleFilter, Alg 5
+// LengthFilter with the bounds of Lemma le:RK-1bound1).  `live` holds nl slots
+// oldest first; on return it holds the survivors, oldest first.  The R factor
+// of the reversed history is taken from the Gram (R^T R = F^T F): r_ii^2 is
+// the squared distance of column i from the span of the newer columns.
+__device__ int faa_filter(const LPDesc& d, const Scalars* sc, int* live, int nl, SolveWork* w) {
+  int* ord = w->ord;  // newest first (Reverse)
+  for (int t = 0; t < nl; ++t) ord[t] = live[nl - 1 - t];
+  double* R = w->R;
+  bool* dep = w->dep;
+  double* fn = w->fn;
+  double* rii = w->rii;
+  for (int i = 0; i < nl; ++i) {
+    const double gii = sc->G[ord[i] * MAXM + ord[i]];
+    fn[i] = sqrt(gii > 0.0 ? gii : 0.0);
+    double s = gii;
+    for (int j = 0; j < i; ++j) {
+      if (dep[j]) { R[j * MAXM + i] = 0.0; continue; }
+      double t = sc->G[ord[j] * MAXM + ord[i]];
+      for (int p = 0; p < j; ++p)
+        if (!dep[p]) t -= R[p * MAXM + j] * R[p * MAXM + i];
+      t /= R[j * MAXM + j];
+      R[j * MAXM + i] = t;
+      s -= t * t;
+    }
+    if (!(s > 1e-28 * gii) || !isfinite(s)) {
+      dep[i] = true;
+      rii[i] = 0.0;
+      R[i * MAXM + i] = 0.0;
+    } else {
+      dep[i] = false;
+      rii[i] = sqrt(s);
+      R[i * MAXM + i] = rii[i];
+    }
+  }
+  // AngleFilter: the newest column is always kept; column i >= 2 is removed
+  // when |r_ii| / ||f_i|| < c_s (a zero column has no angle and is removed).
+  int* keep = w->keep;
+  int nk = 0;
+  keep[nk++] = 0;
+  for (int i = 1; i < nl; ++i)
+    if (fn[i] > 0.0 && rii[i] / fn[i] >= d.cs) keep[nk++] = i;
+  // LengthFilter on the kept columns (newest first, 1-based j in the lemma).
+  const double cs = d.cs, ct = sqrt(1.0 - cs * cs);
+  double* b = w->b;
+  double* e2 = w->e2;
+  for (int jj = 0; jj < nk; ++jj) {
+    const int slot = ord[keep[jj]];
+    e2[jj] = sc->du2[slot];
+    const double fj2 = fn[keep[jj]] * fn[keep[jj]];
+    if (jj == 0) {
+      b[jj] = 1.0 / fj2;
+      continue;
+    }
+    const int j = jj + 1;
+    const double f12 = fn[keep[0]] * fn[keep[0]];
+    double tot = ct * ct * pow(ct + cs, 2.0 * (j - 2)) / (f12 * pow(cs, 2.0 * (j - 2)));
+    for (int i = 2; i <= j - 1; ++i) {
+      const double fi2 = fn[keep[i - 1]] * fn[keep[i - 1]];
+      tot += ct * ct * pow(ct + cs, 2.0 * (j - i - 1)) / (fi2 * pow(cs, 2.0 * (j - i)));
+    }
+    tot += 1.0 / fj2;
+    b[jj] = tot / (cs * cs);
+  }
+  int kk = nk;
+  const double kb2 = d.kappa_bar * d.kappa_bar;
+  while (kk >= 1) {
+    double se = 0.0, sb = 0.0;
+    for (int j = 0; j < kk; ++j) {
+      se += e2[j];
+      sb += b[j];
+    }
+    if (se * sb <= kb2) break;
+    --kk;
+  }
+  // survivors: first kk kept columns (newest first) -> oldest first
+  for (int t = 0; t < kk; ++t) live[t] = ord[keep[kk - 1 - t]];
+  return kk;
+}
+
+template <int MT>
+__device__ void final_step(const LPDesc& d, Scalars* sc, const double* fa, const double* fb,
+                           bool eval, bool kkt, bool init, SolveWork* w) {
+  using DT = Dot<MT>;
+  if (kkt) {
+    // Remark re:constrcution-termi-con: relative gap, primal and dual infeasibility
+    const double pobj = fa[DT::K0];
+    const double dobj = fb[DT::K0] + fa[DT::K1];
+    const double rg = fabs(dobj - pobj) / (1.0 + fabs(dobj) + fabs(pobj));
+    const double rp = sqrt(fb[DT::K1]) / (1.0 + sc->qnorm);
+    const double rd = sqrt(fa[DT::K2]) / (1.0 + sc->cnorm);
+    sc->pobj = pobj;
+    sc->dobj = dobj;
+    sc->r_g = rg;
+    sc->r_p = rp;
+    sc->r_d = rd;
+    sc->kkt = fmax(rg, fmax(rp, rd));
+    sc->kkt_k = sc->k;
+  }
+  if (eval) return;
+  const double gnorm = sqrt(fa[DT::GG] + fb[DT::GG]);
+  const long long k = sc->k;
+  sc->gnorm = gnorm;
+  if (init) {  // Alg 2 set-up: g^0 = u^1 - u^0
+    sc->n0 = gnorm;
+    if (!isfinite(gnorm)) {
+      sc->status = ST_NUMERICAL;
+      sc->branch = BR_NONE;
+    } else if (gnorm == 0.0) {
+      sc->status = ST_CONVERGED;  // u^0 is a fixed point
+      sc->branch = BR_NONE;
+    } else {
+      sc->branch = BR_PDHG;
+      sc->k = 1;
+    }
+    return;
+  }
+  if (k > d.max_iter) {
+    sc->status = ST_ITER_LIMIT;
+    sc->branch = BR_NONE;
+    return;
+  }
+  if (kkt && sc->kkt <= d.tol) {
+    sc->status = ST_CONVERGED;
+    sc->branch = BR_NONE;
+    return;
+  }
+  if (!isfinite(gnorm)) {
+    sc->status = ST_NUMERICAL;
+    sc->branch = BR_NONE;
+    return;
+  }
+  // memory update (both branches): the pair written this pass goes to newslot
+  const int s = sc->newslot;
+  const int nl_old = sc->nlive;
+  int* live = w->live;
+  int nl = 0;
+  for (int t = 0; t < nl_old; ++t) {
+    const int slot = sc->live[t];
+    if (slot == s) continue;  // the oldest column is replaced
+    const double gv = fa[DT::G + t] + fb[DT::G + t];
+    sc->G[s * MAXM + slot] = gv;
+    sc->G[slot * MAXM + s] = gv;
+    sc->rhs[slot] = fa[DT::R + t] + fb[DT::R + t];
+    live[nl++] = slot;
+  }
+  sc->G[s * MAXM + s] = fa[DT::DGDG] + fb[DT::DGDG];
+  sc->rhs[s] = fa[DT::DGG] + fb[DT::DGG];
+  sc->du2[s] = fa[DT::DU2] + fb[DT::DU2];
+  live[nl++] = s;
+
+  bool aa = false;
+  int nmix = 0;
+  if (d.variant != V_PDHG) {
+    // safeguard (Alg 2): ||g^k|| <= D ||g^0|| (i^k + 1)^{-(1+eps)}; ties accelerate
+    const double thr = d.D * sc->n0 * pow((double)(sc->i_aa + 1), -(1.0 + d.eps_sg));
+    if (gnorm <= thr) {
+      double* gam = w->gam;
+      if (d.variant == V_AA) {
+        if (solve_gamma(sc, live, nl, d.eta, gam, w->A)) {
+          aa = true;
+          nmix = nl;
+          for (int t = 0; t < nl; ++t) {
+            sc->mixslot[t] = live[t];
+            sc->gamma[t] = gam[t];
+          }
+        }
+      } else {
+        nl = faa_filter(d, sc, live, nl, w);  // the survivors become the memory
+        if (nl == 0) {
+          aa = true;  // no history left: u_AA = u^k + beta D-hat g^k
+        } else if (solve_gamma(sc, live, nl, 0.0, gam, w->A)) {
+          aa = true;
+          nmix = nl;
+          for (int t = 0; t < nl; ++t) {
+            sc->mixslot[t] = live[t];
+            sc->gamma[t] = gam[t];
+          }
+        }
+      }
+    }
+  }
+  sc->nmix = nmix;
+  if (aa) {
+    sc->branch = BR_AA;
+    sc->i_aa += 1;
+  } else {
+    sc->branch = BR_PDHG;
+    sc->j_pdhg += 1;
+  }
+  for (int t = 0; t < nl; ++t) sc->live[t] = live[t];
+  sc->nlive = nl;
+  // slot for the next difference pair: a free one, else the oldest
+  int ns = live[0];
+  if (nl < d.M) {
+    for (int cand = 0; cand < d.M; ++cand) {
+      bool used = false;
+      for (int t = 0; t < nl; ++t) used |= (live[t] == cand);
+      if (!used) {
+        ns = cand;
+        break;
+      }
+    }
+  }
+  sc->newslot = ns;
+  sc->k = k + 1;
+}
+
+// ---------------------------------------------------------------------------
+// pass A (PASS = 0, columns of K via CSC) and pass B (PASS = 1, rows via CSR)
+// ---------------------------------------------------------------------------
+
+template <typename T, int MT, int PASS>
+__global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
+  using DT = Dot<MT>;
+  __shared__ double s_prod[CHUNK_NNZ];
+  __shared__ double s_red[BLOCK / 64][NDOT];
+  __shared__ double s_fin[2][NDOT];
+  __shared__ double s_tmp[4];
+  __shared__ int s_live[MAXM];
+  __shared__ int s_flag;
+  __shared__ SolveWork s_work;
+
+  const int tid = threadIdx.x;
+  const Chunk ch = a.chunks[blockIdx.x];
+  const LPDesc& d = a.lps[ch.lp];
+  Scalars* sc = d.sc;
+  const bool eval = a.mode == MODE_EVAL;
+  if (!eval && sc->status != ST_RUNNING) return;
+
+  const long long k = sc->k;
+  const bool init = !eval && k == 0;
+  const bool kkt = eval || (!init && d.kkt_every > 0 && (k % d.kkt_every) == 0);
+  const int nl = sc->nlive;
+  const int s_new = sc->newslot;
+  if (tid < MAXM) s_live[tid] = sc->live[tid];
+  const bool skip0 = nl > 0 && sc->live[0] == s_new;
+
+  const int n = d.n, N = d.N;
+  const int par = (int)(k & 1);
+  const T* ucur = (const T*)d.u[par];
+  T* unext = (T*)d.u[par ^ 1];  // u^{k-1} on entry, u_hat^{k+1} on exit
+  T* gcur = (T*)d.g[par];
+  const T* gprev = (const T*)d.g[par ^ 1];
+  T* dG = (T*)d.dG;
+  T* W = (T*)d.W;
+  const T* dhat = (const T*)d.dhat;
+  const double beta = d.beta;
+
+  const int* ptr = PASS == 0 ? d.colptr : d.rowptr;
+  const int* idx = PASS == 0 ? d.rowidx : d.colidx;
+  const T* val = (const T*)(PASS == 0 ? d.valT : d.val);
+  // gathered vectors: pass A gathers y^k; pass B gathers x_bar (and x^k for KKT)
+  const T* gv1 = PASS == 0 ? ucur + n : (eval ? ucur : (const T*)d.xbar);
+  const T* gv2 = ucur;
+  const bool two = PASS == 1 && kkt && !eval;
+
+  double acc[DT::COUNT];
+#pragma unroll
+  for (int q = 0; q < DT::COUNT; ++q) acc[q] = 0.0;
+
+  __syncthreads();  // s_live
+
+  // history part of the epilogue for vector entry e
+  auto history = [&](int e, T g_st, T u_prev, T u_cur) {
+    const T dgT = (T)((double)g_st - (double)gprev[e]);
+    const T duT = (T)((double)u_cur - (double)u_prev);
+    const double dg = (double)dgT, du = (double)duT, gd = (double)g_st;
+    dG[(size_t)s_new * N + e] = dgT;
+    W[(size_t)s_new * N + e] = (T)(du + beta * (double)dhat[e] * dg);
+    acc[DT::DGDG] += dg * dg;
+    acc[DT::DGG] += dg * gd;
+    acc[DT::DU2] += du * du;
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      if (t < nl && !(t == 0 && skip0)) {
+        const double v = (double)dG[(size_t)s_live[t] * N + e];
+        acc[DT::G + t] += dg * v;
+        acc[DT::R + t] += gd * v;
+      }
+    }
+  };
+
+  // epilogue for one row/column with its gathered sums
+  auto epilogue = [&](int r, double s1, double s2) {
+    if (PASS == 0) {
+      const int j = r;
+      const T x = ucur[j];
+      const double w = s1;  // (K^T y)_j
+      const double cj = (double)((const T*)d.c)[j];
+      const T lj = ((const T*)d.lo)[j], uj = ((const T*)d.hi)[j];
+      if (!eval) {
+        const T up = unext[j];  // u^{k-1}, read before it is overwritten
+        const T xh = clampT((T)((double)x - d.tau * (cj - w)), lj, uj);
+        ((T*)d.xbar)[j] = (T)(2.0 * (double)xh - (double)x);
+        const T g = (T)((double)xh - (double)x);
+        gcur[j] = g;
+        unext[j] = xh;
+        acc[DT::GG] += (double)g * (double)g;
+        if (!init) history(j, g, up, x);
+      }
+      if (kkt) {
+        const bool lf = isfinite((double)lj), uf = isfinite((double)uj);
+        const double lam = proj_lambda(cj - w, lf, uf);
+        acc[DT::K0] += cj * (double)x;
+        acc[DT::K1] += (lf ? (double)lj * fmax(lam, 0.0) : 0.0) - (uf ? (double)uj * fmax(-lam, 0.0) : 0.0);
+        const double rd = cj - w - lam;
+        acc[DT::K2] += rd * rd;
+        if (eval) ((T*)d.lam)[j] = (T)lam;
+      }
+    } else {
+      const int i = r;
+      const int e = n + i;
+      const T y = ucur[e];
+      const double qi = (double)((const T*)d.q)[i];
+      const bool ge = d.rowtype[i] != 0;
+      if (!eval) {
+        const T up = unext[e];
+        T yh = (T)((double)y + d.sigma * (qi - s1));
+        if (ge && yh < (T)0) yh = (T)0;
+        const T g = (T)((double)yh - (double)y);
+        gcur[e] = g;
+        unext[e] = yh;
+        acc[DT::GG] += (double)g * (double)g;
+        if (!init) history(e, g, up, y);
+      }
+      if (kkt) {
+        const double kx = eval ? s1 : s2;  // (K x^k)_i
+        acc[DT::K0] += qi * (double)y;
+        double res = qi - kx;
+        if (ge && res < 0.0) res = 0.0;
+        acc[DT::K1] += res * res;
+      }
+    }
+  };
+
+  bool split_owner = false;
+  if (ch.kind == 0) {
+    // ---- multi-row chunk: stage products in LDS, reduce rows, epilogue ----
+    const int r0 = ch.r0, r1 = ch.r1, kb = ch.k0, ke = ch.k1, tpr = ch.tpr;
+    double sum1[ROWS_PER_THREAD], sum2[ROWS_PER_THREAD];
+    const int nsweep = two ? 2 : 1;
+    for (int sw = 0; sw < nsweep; ++sw) {
+      const T* gv = sw == 0 ? gv1 : gv2;
+      double* out = sw == 0 ? sum1 : sum2;
+      for (int q = kb + tid; q < ke; q += BLOCK) s_prod[q - kb] = (double)val[q] * (double)gv[idx[q]];
+      __syncthreads();
+      if (tpr == BLOCK) {
+        double s = 0.0;
+        const int a0 = ptr[r0] - kb, a1 = ptr[r0 + 1] - kb;
+        for (int q = a0 + tid; q < a1; q += BLOCK) s += s_prod[q];
+        s = block_sum(s, s_tmp);
+        out[0] = s;
+#pragma unroll
+        for (int rr = 1; rr < ROWS_PER_THREAD; ++rr) out[rr] = 0.0;
+      } else {
+        const int grp = tid / tpr, lane = tid % tpr, ngrp = BLOCK / tpr;
+#pragma unroll
+        for (int rr = 0; rr < ROWS_PER_THREAD; ++rr) {
+          const int r = r0 + grp + rr * ngrp;
+          double s = 0.0;
+          if (r < r1) {
+            const int a0 = ptr[r] - kb, a1 = ptr[r + 1] - kb;
+            for (int q = a0 + lane; q < a1; q += tpr) s += s_prod[q];
+          }
+          for (int off = 1; off < tpr; off <<= 1) s += __shfl_xor(s, off, 64);
+          out[rr] = s;
+        }
+      }
+      __syncthreads();
+    }
+    if (tpr == BLOCK) {
+      if (tid == 0) epilogue(r0, sum1[0], two ? sum2[0] : 0.0);
+    } else {
+      const int grp = tid / tpr, lane = tid % tpr, ngrp = BLOCK / tpr;
+#pragma unroll
+      for (int rr = 0; rr < ROWS_PER_THREAD; ++rr) {
+        const int r = r0 + grp + rr * ngrp;
+        if (lane == 0 && r < r1) epilogue(r, sum1[rr], two ? sum2[rr] : 0.0);
+      }
+    }
+  } else {
+    // ---- one part of a split row: partial sums, the last part finishes ----
+    const SplitRow sr = a.splits[ch.split];
+    const int kb = ch.k0, ke = ch.k1, part = ch.tpr;
+    double s1 = 0.0, s2 = 0.0;
+    for (int q = kb + tid; q < ke; q += BLOCK) {
+      const double v = (double)val[q];
+      const int c = idx[q];
+      s1 += v * (double)gv1[c];
+      if (two) s2 += v * (double)gv2[c];
+    }
+    s1 = block_sum(s1, s_tmp);
+    s2 = block_sum(s2, s_tmp);
+    if (tid == 0) {
+      a.splitpart[2 * (sr.part0 + part) + 0] = s1;
+      a.splitpart[2 * (sr.part0 + part) + 1] = s2;
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) s_flag = atomicAdd(&a.splitcnt[ch.split], 1u) == (unsigned)(sr.nparts - 1);
+    __syncthreads();
+    if (s_flag) {
+      __threadfence();
+      if (tid == 0) {
+        a.splitcnt[ch.split] = 0u;
+        double t1 = 0.0, t2 = 0.0;
+        for (int p = 0; p < sr.nparts; ++p) {
+          t1 += a.splitpart[2 * (sr.part0 + p) + 0];
+          t2 += a.splitpart[2 * (sr.part0 + p) + 1];
+        }
+        epilogue(sr.row, t1, t2);
+        split_owner = true;
+      }
+    }
+  }
+
+  // ---- chunk partial sums ----
+  const int lane = tid & 63, wv = tid >> 6;
+  double* cp = a.cpart + (size_t)blockIdx.x * NDOT;
+  if (ch.kind == 0) {
+#pragma unroll
+    for (int q = 0; q < DT::COUNT; ++q) {
+      const double v = wave_sum(acc[q]);
+      if (lane == 0) s_red[wv][q] = v;
+    }
+    __syncthreads();
+    if (tid < DT::COUNT) cp[tid] = ((s_red[0][tid] + s_red[1][tid]) + s_red[2][tid]) + s_red[3][tid];
+  } else {
+    // a split row's sums live in its own record; the chunk contributes zeros
+    if (tid < DT::COUNT) cp[tid] = 0.0;
+    if (split_owner) {
+      double* sd = a.splitdots + (size_t)ch.split * NDOT;
+#pragma unroll
+      for (int q = 0; q < DT::COUNT; ++q) sd[q] = acc[q];
+    }
+  }
+  __threadfence();
+  __syncthreads();
+
+  // ---- first level: the last chunk of a group adds the group's chunks in order ----
+  const Group grp = a.groups[ch.group];
+  if (tid == 0) s_flag = atomicAdd(&a.gcnt[ch.group], 1u) == (unsigned)(grp.count - 1);
+  __syncthreads();
+  if (!s_flag) return;
+  __threadfence();
+  if (tid < DT::COUNT) {
+    double s = 0.0;
+    for (int c = grp.first; c < grp.first + grp.count; ++c) s += a.cpart[(size_t)c * NDOT + tid];
+    a.gpart[(size_t)ch.group * NDOT + tid] = s;
+  }
+  if (tid == 0) a.gcnt[ch.group] = 0u;
+  if (PASS == 0) return;
+
+  // ---- second level (dual pass): the last group of an LP finishes the loop pass ----
+  __threadfence();
+  __syncthreads();
+  const LaunchLP L = a.llp[ch.lp];
+  if (tid == 0) s_flag = atomicAdd(&sc->lp_cnt, 1u) == (unsigned)(L.nB - 1);
+  __syncthreads();
+  if (!s_flag) return;
+  __threadfence();
+  if (tid < DT::COUNT) {
+    double sa = 0.0, sb = 0.0;
+    for (int g = L.gA0; g < L.gA0 + L.nA; ++g) sa += a.gpart[(size_t)g * NDOT + tid];
+    for (int s = L.sA0; s < L.sA0 + L.nsA; ++s) sa += a.splitdots[(size_t)s * NDOT + tid];
+    for (int g = L.gB0; g < L.gB0 + L.nB; ++g) sb += a.gpart[(size_t)g * NDOT + tid];
+    for (int s = L.sB0; s < L.sB0 + L.nsB; ++s) sb += a.splitdots[(size_t)s * NDOT + tid];
+    s_fin[0][tid] = sa;
+    s_fin[1][tid] = sb;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    sc->lp_cnt = 0u;
+    final_step<MT>(d, sc, s_fin[0], s_fin[1], eval, kkt, init, &s_work);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pass C: Anderson mix and projection (Alg 2: u^{k+1} = P(u^k - H^k g^k))
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_mix(MixArgs a) {
+  __shared__ double s_gam[MAXM];
+  __shared__ int s_slot[MAXM];
+  const MixTile tl = a.tiles[blockIdx.x];
+  const LPDesc& d = a.lps[tl.lp];
+  const Scalars* sc = d.sc;
+  if (sc->status != ST_RUNNING || sc->branch != BR_AA) return;
+  const int nmix = sc->nmix;
+  if (threadIdx.x < MAXM) {
+    s_gam[threadIdx.x] = sc->gamma[threadIdx.x];
+    s_slot[threadIdx.x] = sc->mixslot[threadIdx.x];
+  }
+  __syncthreads();
+  const int par = (int)((sc->k - 1) & 1);  // the pass that decided was k-1
+  const T* ucur = (const T*)d.u[par];
+  T* unext = (T*)d.u[par ^ 1];
+  const T* g = (const T*)d.g[par];
+  const T* W = (const T*)d.W;
+  const T* dhat = (const T*)d.dhat;
+  const int n = d.n, N = d.N;
+  for (int e = tl.e0 + threadIdx.x; e < tl.e1; e += BLOCK) {
+    double v = (double)ucur[e] + d.beta * (double)dhat[e] * (double)g[e];
+    for (int t = 0; t < nmix; ++t) v -= s_gam[t] * (double)W[(size_t)s_slot[t] * N + e];
+    T r = (T)v;
+    if (e < n) {
+      r = clampT(r, ((const T*)d.lo)[e], ((const T*)d.hi)[e]);
+    } else if (d.rowtype[e - n] != 0 && r < (T)0) {
+      r = (T)0;
+    }
+    unext[e] = r;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// set-up kernels
+// ---------------------------------------------------------------------------
+
+// u^0 = (clip(0, l, u), 0)
+template <typename T>
+__global__ void k_start_point(LPDesc d) {
+  T* u0 = (T*)d.u[0];
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < d.N; e += gridDim.x * blockDim.x) {
+    if (e < d.n) {
+      u0[e] = clampT((T)0, ((const T*)d.lo)[e], ((const T*)d.hi)[e]);
+    } else {
+      u0[e] = (T)0;
+    }
+  }
+}
+
+// y = A x for CSR (ptr, idx, val), one wave per row, float64 vectors.
+template <typename T>
+__global__ void k_spmv_wave(const int* ptr, const int* idx, const T* val, const double* x, double* y, int rows) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int nw = (gridDim.x * blockDim.x) >> 6;
+  for (int r = wave; r < rows; r += nw) {
+    double s = 0.0;
+    for (int q = ptr[r] + lane; q < ptr[r + 1]; q += 64) s += (double)val[q] * x[idx[q]];
+    s = wave_sum(s);
+    if (lane == 0) y[r] = s;
+  }
+}
+
+__global__ void k_sqnorm_part(const double* x, int len, double* part) {
+  __shared__ double s_tmp[4];
+  double s = 0.0;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < len; e += gridDim.x * blockDim.x) s += x[e] * x[e];
+  s = block_sum(s, s_tmp);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// x = z / ||z|| with ||z||^2 = sum of nparts partials (every block adds them in
+// the same order); block 0 records ||z|| in est[slot].
+__global__ void k_normalize(const double* z, double* x, int len, const double* part, int nparts, double* est, int slot) {
+  __shared__ double s_norm;
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int p = 0; p < nparts; ++p) s += part[p];
+    s_norm = sqrt(s);
+    if (blockIdx.x == 0) est[slot] = s_norm;
+  }
+  __syncthreads();
+  const double nz = s_norm;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < len; e += gridDim.x * blockDim.x) x[e] = nz > 0.0 ? z[e] / nz : 0.0;
+}
+
+__global__ void k_fill(double* x, int len, double v) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < len; e += gridDim.x * blockDim.x) x[e] = v;
+}
+
+// Copy the status word of every LP of a launch table into out[].
+__global__ void k_gather_status(const LPDesc* lps, int count, int* out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) out[i] = lps[i].sc->status;
+}
+
+// Time limit reached: running LPs stop at their current iterate.
+__global__ void k_time_limit(const LPDesc* lps, int count) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+    Scalars* sc = lps[i].sc;
+    if (sc->status == ST_RUNNING) {
+      sc->status = ST_TIME_LIMIT;
+      sc->branch = BR_NONE;
+    }
+  }
+}
+
+// float64 <-> T conversions for host transfers
+template <typename S, typename D>
+__global__ void k_convert(const S* src, D* dst, size_t len) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x) dst[e] = (D)src[e];
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+
+template <typename T, int MT>
+static hipError_t launch_passes_mt(const LaunchTables& t, hipStream_t st, int mode) {
+  PassArgs pa{};
+  pa.lps = t.lps;
+  pa.llp = t.llp;
+  pa.groups = t.groups;
+  pa.splits = t.splits;
+  pa.gcnt = t.gcnt;
+  pa.splitpart = t.splitpart;
+  pa.splitcnt = t.splitcnt;
+  pa.splitdots = t.splitdots;
+  pa.mode = mode;
+  pa.chunks = t.chunksA;
+  pa.cpart = t.cpartA;
+  pa.gpart = t.gpart;
+  if (t.nchunksA > 0) hipLaunchKernelGGL((k_pass<T, MT, 0>), dim3(t.nchunksA), dim3(BLOCK), 0, st, pa);
+  pa.chunks = t.chunksB;
+  pa.cpart = t.cpartB;
+  if (t.nchunksB > 0) hipLaunchKernelGGL((k_pass<T, MT, 1>), dim3(t.nchunksB), dim3(BLOCK), 0, st, pa);
+  if (mode == MODE_ITER && t.ntiles > 0) {
+    MixArgs ma{t.lps, t.tiles};
+    hipLaunchKernelGGL((k_mix<T>), dim3(t.ntiles), dim3(BLOCK), 0, st, ma);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_passes_t(const LaunchTables& t, hipStream_t st, int mode) {
+  if (t.mt <= 4) return launch_passes_mt<T, 4>(t, st, mode);
+  if (t.mt <= 8) return launch_passes_mt<T, 8>(t, st, mode);
+  if (t.mt <= 10) return launch_passes_mt<T, 10>(t, st, mode);
+  return launch_passes_mt<T, 16>(t, st, mode);
+}
+
+hipError_t launch_loop_pass(const LaunchTables& t, hipStream_t st, int mode) {
+  return t.fp64 ? launch_passes_t<double>(t, st, mode) : launch_passes_t<float>(t, st, mode);
+}
+
+hipError_t launch_start_point(const LPDesc& d, bool fp64, hipStream_t st) {
+  const int grid = (d.N + BLOCK - 1) / BLOCK < 4096 ? (d.N + BLOCK - 1) / BLOCK : 4096;
+  if (fp64)
+    hipLaunchKernelGGL(k_start_point<double>, dim3(grid > 0 ? grid : 1), dim3(BLOCK), 0, st, d);
+  else
+    hipLaunchKernelGGL(k_start_point<float>, dim3(grid > 0 ? grid : 1), dim3(BLOCK), 0, st, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_power_iteration(const LPDesc& d, bool fp64, int iters, double* work, double* est,
+                                  hipStream_t st) {
+  // work: v[n], z[n], w[m], part[1024]
+  const int n = d.n, m = d.m;
+  double* v = work;
+  double* z = work + n;
+  double* w = work + 2 * (size_t)n;
+  double* part = work + 2 * (size_t)n + m;
+  const int nparts = 1024;
+  const int gridv = 1024;
+  const int gridr = 2048;
+  hipLaunchKernelGGL(k_fill, dim3(gridv), dim3(BLOCK), 0, st, v, n, 1.0);
+  hipLaunchKernelGGL(k_sqnorm_part, dim3(nparts), dim3(BLOCK), 0, st, (const double*)v, n, part);
+  hipLaunchKernelGGL(k_normalize, dim3(gridv), dim3(BLOCK), 0, st, (const double*)v, v, n, (const double*)part, nparts, est, 0);
+  for (int it = 0; it < iters; ++it) {
+    if (fp64) {
+      hipLaunchKernelGGL(k_spmv_wave<double>, dim3(gridr), dim3(BLOCK), 0, st, d.rowptr, d.colidx, (const double*)d.val, (const double*)v, w, m);
+      hipLaunchKernelGGL(k_spmv_wave<double>, dim3(gridr), dim3(BLOCK), 0, st, d.colptr, d.rowidx, (const double*)d.valT, (const double*)w, z, n);
+    } else {
+      hipLaunchKernelGGL(k_spmv_wave<float>, dim3(gridr), dim3(BLOCK), 0, st, d.rowptr, d.colidx, (const float*)d.val, (const double*)v, w, m);
+      hipLaunchKernelGGL(k_spmv_wave<float>, dim3(gridr), dim3(BLOCK), 0, st, d.colptr, d.rowidx, (const float*)d.valT, (const double*)w, z, n);
+    }
+    hipLaunchKernelGGL(k_sqnorm_part, dim3(nparts), dim3(BLOCK), 0, st, (const double*)z, n, part);
+    hipLaunchKernelGGL(k_normalize, dim3(gridv), dim3(BLOCK), 0, st, (const double*)z, v, n, (const double*)part, nparts, est, 1 + it);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_status(const LPDesc* lps, int count, int* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_status, dim3((count + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, st, lps, count, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_time_limit(const LPDesc* lps, int count, hipStream_t st) {
+  hipLaunchKernelGGL(k_time_limit, dim3((count + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, st, lps, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_f64(const void* src, bool fp64, double* dst, size_t len, hipStream_t st) {
+  if (len == 0) return hipSuccess;
+  const size_t g = (len + BLOCK - 1) / BLOCK;
+  const int grid = g < 4096 ? (int)g : 4096;
+  if (fp64)
+    hipLaunchKernelGGL((k_convert<double, double>), dim3(grid), dim3(BLOCK), 0, st, (const double*)src, dst, len);
+  else
+    hipLaunchKernelGGL((k_convert<float, double>), dim3(grid), dim3(BLOCK), 0, st, (const float*)src, dst, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_from_f64(const double* src, void* dst, bool fp64, size_t len, hipStream_t st) {
+  if (len == 0) return hipSuccess;
+  const size_t g = (len + BLOCK - 1) / BLOCK;
+  const int grid = g < 4096 ? (int)g : 4096;
+  if (fp64)
+    hipLaunchKernelGGL((k_convert<double, double>), dim3(grid), dim3(BLOCK), 0, st, src, (double*)dst, len);
+  else
+    hipLaunchKernelGGL((k_convert<double, float>), dim3(grid), dim3(BLOCK), 0, st, src, (float*)dst, len);
+  return hipGetLastError();
+}
+
+}  // namespace aapdhg

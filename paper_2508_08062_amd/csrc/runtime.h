@@ -1,0 +1,103 @@
+// Host-side objects of the AA-PDHG runtime (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/aapdhg.h"
+#include "aapdhg_internal.h"
+#include "kernels.h"
+
+namespace aapdhg {
+
+struct Error {
+  aapdhg_status status;
+  std::string msg;
+  Error(aapdhg_status s, const char* fmt, ...);
+};
+
+void hip_check(hipError_t e, const char* what);
+void default_options(aapdhg_options* o);
+extern thread_local std::string g_thread_error;
+
+// Owning device allocation.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf();
+  void release();
+  void alloc(size_t nbytes, const char* what);
+  void upload(const void* src, size_t nbytes, const char* what);
+  void zero(const char* what);
+};
+
+struct Problem;
+
+// The device work tables of a set of LPs that advance in the same launches.
+struct LaunchSet {
+  static constexpr int MAX_STATUS = 65536;
+  std::vector<Problem*> members;
+  LaunchTables t;
+  DevBuf d_lps, d_llp, d_chunksA, d_chunksB, d_groups, d_splits, d_cpartA, d_cpartB, d_gpart, d_gcnt,
+      d_splitpart, d_splitcnt, d_splitdots, d_tiles, d_status;
+  int* h_status = nullptr;  // pinned, 2 x MAX_STATUS
+  int64_t last_epochs = 0;
+  ~LaunchSet();
+  void build(const std::vector<Problem*>& lps);
+  void enqueue_passes(hipStream_t st, int64_t iters);
+  void enqueue_eval(hipStream_t st);
+  double run_to_completion(hipStream_t st, int epoch, double time_limit_s);
+  size_t device_bytes() const;
+};
+
+// One LP: host copies of the data as solved, its device arrays and state.
+struct Problem {
+  aapdhg_options opt{};
+  int m = 0, n = 0, N = 0, nnz = 0;
+  bool fp64 = false;
+  bool started = false;
+  bool in_batch = false;
+  double qnorm = 0.0, cnorm = 0.0, norm_est = 0.0;
+  double last_solve_seconds = 0.0;
+  // host data (after scaling and rounding)
+  std::vector<int> rowptr, colidx, colptr, rowidx;
+  std::vector<double> val, valT, c, q, lo, hi, dhat, d_row, d_col;
+  std::vector<uint8_t> rowtype;
+  // work tables (LP-local indices)
+  std::vector<Chunk> chunksA, chunksB;
+  std::vector<Group> groupsA, groupsB;
+  std::vector<SplitRow> splitsA, splitsB;
+  int npartsA = 0, npartsB = 0;
+  std::vector<MixTile> tiles;
+  // device data
+  DevBuf d_rowptr, d_colidx, d_val, d_colptr, d_rowidx, d_valT, d_c, d_lo, d_hi, d_q, d_dhat, d_rowtype;
+  DevBuf d_u[2], d_g[2], d_xbar, d_hist_dG, d_hist_W, d_lam, d_sc, d_desc, d_xfer;
+  LPDesc desc{};
+  Scalars sc_init{};
+  std::unique_ptr<LaunchSet> solo;
+
+  ~Problem();
+  void create(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+              const double* val, const double* c, const double* q, const double* l, const double* u,
+              const uint8_t* row_type, const aapdhg_options* opt);
+  void fill_desc();
+  double power_norm();
+  void reset_host_state();
+  void enqueue_reset(hipStream_t st);
+  void read_scalars(Scalars& s);
+  void download(const void* dev, size_t len, double* host, hipStream_t st);
+  void upload_vec(void* dev, const double* host, size_t len, hipStream_t st);
+  void result(double* x, double* y, double* lam, aapdhg_info* info, bool run_eval);
+  void get_state(double* u, double* u_prev, double* g_prev, double* dG, double* W, int64_t* meta, double* gram);
+  void set_state(const double* u, const double* u_prev, const double* g_prev, const double* dG, const double* W,
+                 const int64_t* meta, const double* gram);
+  size_t device_bytes() const;
+};
+
+}  // namespace aapdhg

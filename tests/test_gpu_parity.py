@@ -1,0 +1,224 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs, element by element.  Tolerances:
+  * float64 path: iterates to 1e-9 relative (summation order differs; AA
+    least-squares conditioning amplifies rounding);
+  * float32 path: iterates to 1e-5 relative over the first 50 loop passes
+    (float32 storage of data, iterates and history; float64 reductions).
+"""
+import numpy as np
+import pytest
+
+import lpgen
+import oracle
+from _util import golden
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2508_08062_amd")
+
+
+def _gpu(lp, **kw):
+    return P.Solver(lp, **kw)
+
+
+def _oracle(lp, **kw):
+    return oracle.Solver(oracle.Problem.from_lpdata(lp), oracle.Options(**kw))
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _trajectories(lp, steps, precision, variant=1, memory=5, **kw):
+    """Run both sides for `steps` loop passes from the start point and return
+    the per-pass iterates and branch counters."""
+    Po = oracle.Problem.from_lpdata(lp)
+    nrm = oracle.power_norm(Po)
+    tau = sigma = 0.9 / nrm
+    common = dict(variant=variant, memory=memory, tau=tau, sigma=sigma, kkt_every=kw.pop("kkt_every", 1),
+                  tol=kw.pop("tol", 0.0), max_iter=10 ** 6, **kw)
+    g = _gpu(lp, precision=precision, **common)
+    o = _oracle(lp, **common)
+    o.start()
+    g.iterate(1)
+    us_g, us_o, ctr = [], [], []
+    st = g.get_state()
+    us_g.append(st["u"].copy())
+    us_o.append(np.r_[o.state.x, o.state.y])
+    for _ in range(steps):
+        o.step()
+        g.iterate(1)
+        st = g.get_state()
+        us_g.append(st["u"].copy())
+        us_o.append(np.r_[o.state.x, o.state.y])
+        ctr.append(((st["i"], st["j"]), (o.state.i, o.state.j)))
+    return us_g, us_o, ctr, g, o
+
+
+# ---------------------------------------------------------------------------
+
+def test_toy_lp_hand_trace_on_gpu():
+    gld = golden("toy_lp.json")
+    g = _gpu(lpgen.toy_lp(), precision=1, memory=5, tau=0.1, sigma=0.1, kkt_every=1, tol=1e-10, max_iter=50)
+    g.iterate(1)
+    st = g.get_state()
+    np.testing.assert_allclose(st["u"], gld["u1"], atol=1e-15)
+    np.testing.assert_allclose(st["u_prev"], [0.0, 0.0], atol=0)
+    g.iterate(1)
+    st = g.get_state()
+    np.testing.assert_allclose(st["u"], gld["u2"], rtol=1e-6)
+    assert st["i"] == 1 and st["j"] == 0
+    g.solve()
+    r = g.result()
+    assert r["status"] == "converged" and r["iters"] <= 5
+    np.testing.assert_allclose(np.r_[r["x"], r["y"]], gld["optimum"], atol=1e-9)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_tiny_fp64_trajectory_50(seed):
+    lp = lpgen.tiny_lp(seed)
+    ug, uo, ctr, _, _ = _trajectories(lp, 50, precision=1, memory=5)
+    errs = [_rel(a, b) for a, b in zip(ug, uo)]
+    assert max(errs) < 1e-9, errs
+    for (gi, oi) in ctr:
+        assert gi == oi
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_mip_like_fp32_trajectory_50(variant):
+    lp = lpgen.mip_like_lp(11, m=2000, n=5000, nnz=25000)
+    ug, uo, ctr, _, _ = _trajectories(lp, 50, precision=0, variant=variant, memory=10)
+    errs = [_rel(a, b) for a, b in zip(ug, uo)]
+    assert max(errs) < 1e-5, (max(errs), int(np.argmax(errs)))
+    assert ctr[-1][0] == ctr[-1][1]
+
+
+def test_mip_like_fp64_trajectory_faa():
+    lp = lpgen.mip_like_lp(12, m=1500, n=3500, nnz=20000, fp32=False)
+    ug, uo, ctr, _, _ = _trajectories(lp, 50, precision=1, variant=2, memory=10)
+    errs = [_rel(a, b) for a, b in zip(ug, uo)]
+    assert max(errs) < 1e-8, errs
+    assert ctr[-1][0] == ctr[-1][1]
+
+
+def _teacher_forced(lp, g, o, steps, tol):
+    """For `steps` loop passes: load the GPU's state into the oracle, let both
+    take one pass, compare the next iterates.  Isolates the rounding of one
+    pass from its amplification by later passes."""
+    errs = []
+    for _ in range(steps):
+        st = g.get_state()
+        S = o.state
+        beta = o.opt.beta
+        S.k = st["k"]
+        S.x, S.y = st["u"][:lp.n].copy(), st["u"][lp.n:].copy()
+        S.u_prev, S.g_prev = st["u_prev"].copy(), st["g_prev"].copy()
+        S.dG = [st["dG"][t].copy() for t in st["live"]]
+        S.dU = [st["W"][t] - beta * o.Dhat * st["dG"][t] for t in st["live"]]
+        S.i, S.j, S.n0 = st["i"], st["j"], st["n0"]
+        o.step()
+        g.iterate(1)
+        st2 = g.get_state()
+        errs.append(_rel(st2["u"], np.r_[o.state.x, o.state.y]))
+        assert (st2["i"], st2["j"]) == (o.state.i, o.state.j)
+    assert max(errs) < tol, errs
+    return errs
+
+
+def _ragged_lp():
+    # rows longer than one chunk (split into parts with a fix-up), a row long
+    # enough for a whole-block reduction, empty rows and empty columns
+    rng = np.random.default_rng(5)
+    m, n = 40, 30000
+    lens = np.full(m, 3)
+    lens[0] = 20000   # split row (> 2048 entries): 3 parts
+    lens[1] = 1500    # one-row chunk
+    lens[2] = 0       # empty row
+    rows, cols = [], []
+    for i, L in enumerate(lens):
+        c = np.sort(rng.choice(n - 100, L, replace=False))  # the last 100 columns stay empty
+        rows += [i] * L
+        cols += list(c)
+    rows, cols = np.array(rows), np.array(cols)
+    rowptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=m), out=rowptr[1:])
+    val = np.round(rng.standard_normal(rows.size) * 8) / 8
+    lp = lpgen.LPData(m=m, n=n, rowptr=rowptr, colidx=cols.astype(np.int32), val=val,
+                      c=np.round(rng.standard_normal(n) * 8) / 8, q=np.round(rng.standard_normal(m) * 8) / 8,
+                      l=np.where(np.arange(n) % 3 == 0, -np.inf, 0.0), u=np.where(np.arange(n) % 2 == 0, np.inf, 2.0),
+                      rowtype=(np.arange(m) % 2).astype(np.uint8))
+    return lpgen.round_fp32(lp)
+
+
+def test_long_rows_split_and_empty_rows_and_columns_fp64():
+    lp = _ragged_lp()
+    ug, uo, ctr, _, _ = _trajectories(lp, 30, precision=1, memory=4)
+    errs = [_rel(a, b) for a, b in zip(ug, uo)]
+    assert max(errs) < 1e-9, errs
+    assert ctr[-1][0] == ctr[-1][1]
+
+
+def test_long_rows_split_and_empty_rows_and_columns_fp32():
+    lp = _ragged_lp()
+    # free-running on the (non-expansive) PDHG map
+    ug, uo, _, _, _ = _trajectories(lp, 50, precision=0, variant=0)
+    errs = [_rel(a, b) for a, b in zip(ug, uo)]
+    assert max(errs) < 1e-5, errs
+    # AA-PDHG: one pass at a time from the GPU's own state
+    _, _, _, g, o = _trajectories(lp, 3, precision=0, memory=4)
+    _teacher_forced(lp, g, o, 30, 1e-5)
+
+
+def test_columns_longer_than_a_chunk_in_the_primal_pass():
+    lp = lpgen.powerlaw_lp(7, m=20000, n=40000, nnz=400000)
+    colcnt = np.bincount(lp.colidx, minlength=lp.n)
+    assert colcnt.max() > 2048  # exercises the split path of the CSC pass
+    ug, uo, _, _, _ = _trajectories(lp, 20, precision=0, memory=6, kkt_every=5)
+    errs = [_rel(a, b) for a, b in zip(ug, uo)]
+    assert max(errs) < 1e-5, errs
+
+
+def test_kkt_and_lambda_match_oracle_at_returned_iterate():
+    lp = lpgen.mip_like_lp(13, m=1000, n=2500, nnz=12000)
+    g = _gpu(lp, precision=0, memory=10, tol=1e-4, kkt_every=16, max_iter=3000)
+    g.solve()
+    r = g.result()
+    Po = oracle.Problem.from_lpdata(lp)
+    ref = oracle.kkt(Po, r["x"], r["y"])
+    for key, gkey in (("pobj", "primal_obj"), ("dobj", "dual_obj"), ("r_g", "r_gap"), ("r_p", "r_pri"),
+                      ("r_d", "r_dual")):
+        assert r[gkey] == pytest.approx(ref[key], rel=1e-5, abs=1e-7), key
+    np.testing.assert_allclose(r["lam"], ref["lam"], rtol=1e-5, atol=1e-5)
+    if r["status"] == "converged":
+        assert r["kkt"] <= 1e-4
+
+
+def test_bitwise_repeatable():
+    lp = lpgen.mip_like_lp(14, m=3000, n=7000, nnz=40000)
+    outs = []
+    for _ in range(2):
+        g = _gpu(lp, precision=0, memory=10, kkt_every=8, max_iter=200, tol=0.0)
+        g.solve()
+        outs.append(g.get_state())
+    assert np.array_equal(outs[0]["u"], outs[1]["u"])
+    assert np.array_equal(outs[0]["dG"], outs[1]["dG"])
+
+
+def test_batch_member_equals_solo_run():
+    lps = [lpgen.mip_like_lp(20 + i, m=m, n=2 * m, nnz=6 * m) for i, m in enumerate((800, 3000, 1500, 5000))]
+    kw = dict(precision=0, memory=8, kkt_every=8, max_iter=300, tol=1e-4)
+    solo = []
+    for lp in lps:
+        g = _gpu(lp, **kw)
+        g.solve()
+        solo.append((g.get_state(), g.result()))
+    members = [_gpu(lp, **kw) for lp in lps]
+    b = P.Batch(members)
+    b.solve()
+    for (st, res), g in zip(solo, members):
+        st2 = g.get_state()
+        assert st2["k"] == st["k"]
+        assert np.array_equal(st2["u"], st["u"])
+        r2 = g.result()
+        assert r2["status"] == res["status"] and r2["kkt"] == res["kkt"]
+    b.close()
