@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Benchmark of the AA-PDHG hot path on one MI355X.
+
+A step is one loop pass of AA-PDHG (Alg 2) over the whole LP: the CSC pass
+(K^T y and the primal update), the CSR pass (K x_bar, the dual update and the
+float64 decisions) and, on Anderson steps, the mix pass; the KKT test runs
+every 64 passes as in a solve.  The KKT tolerance is set to 0 inside the timed
+region so that no pass is skipped by early termination.
+
+Workloads (synthetic, seeded; see lpgen):
+  c1  20k x 50k LP, 250k nonzeros, Zipf(1.8) rows, float32, m_A = 10 (default)
+  c2  1M x 2M LP, 20M nonzeros, power-law columns, Ruiz-scaled, FAA-PDHG, m_A = 10
+  c3  256 LPs of uneven sizes advanced together (batched), m_A = 8
+
+Prints one JSON line (see the keys below).  --gpus N with N > 1 is refused:
+this build measures one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+
+
+def _bytes_model(n, m, Z, M, kkt_frac):
+    """Algorithmic bytes of one launch of each pass (float32 data, int32
+    indices), with a full memory of M columns.  See the design doc."""
+    hist = (M - 1) * 4  # dot products read the live columns except the replaced one
+    primal = 8 * Z + 4 * (n + 1) + 4 * m + n * (7 * 4 + hist + 5 * 4)
+    dual = 8 * Z + 4 * (m + 1) + 4 * n * (1 + kkt_frac) + m * (5 * 4 + 1 + hist + 4 * 4)
+    mix = n * (5 * 4 + M * 4 + 4) + m * (3 * 4 + 1 + M * 4 + 4)
+    spmv = 16 * Z + 8 * (n + m)
+    return {"primal": primal, "dual": dual, "mix": mix, "spmv": spmv}
+
+
+def _src_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "aapdhg_internal.h"):
+        with open(os.path.join(ROOT, "paper_2508_08062_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(workload, kernel):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_hash") != _src_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def _workload(name):
+    import lpgen
+    if name == "c1":
+        lp = lpgen.mip_like_lp(1)
+        opts = dict(variant=1, precision=0, memory=10, kkt_every=64, ruiz_iters=10, dhat_mode=0)
+        return [lp], opts, {"workload": "single LP 20000x50000, 250000 nnz, Zipf(1.8) rows (mip_like_lp seed 1)",
+                            "variant": "AA-PDHG", "m_A": 10, "ruiz_iters": 10, "dhat_mode": 0}
+    if name == "c2":
+        lp = lpgen.powerlaw_lp(2)
+        opts = dict(variant=2, precision=0, memory=10, kkt_every=64, ruiz_iters=10, dhat_mode=0)
+        return [lp], opts, {"workload": "single LP 1000000x2000000, 20000000 nnz, power-law columns "
+                                        "(powerlaw_lp seed 2)", "variant": "FAA-PDHG", "m_A": 10,
+                            "ruiz_iters": 10, "dhat_mode": 0}
+    if name == "c3":
+        lps = lpgen.batch_lps(256, 3)
+        opts = dict(variant=1, precision=0, memory=8, kkt_every=64, ruiz_iters=10, dhat_mode=0)
+        return lps, opts, {"workload": "batch of 256 LPs, rows log-uniform 1k..50k, cols 2x rows, "
+                                       "3..12 nnz/col (batch_lps seed 3)", "variant": "AA-PDHG", "m_A": 8,
+                           "ruiz_iters": 10, "dhat_mode": 0}
+    raise ValueError(name)
+
+
+def _cpu_baseline(lps, opts, seconds):
+    """The oracle on the host, one thread, on the first LP of the workload,
+    for about `seconds` of loop passes; returns passes per second."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    lp = lps[0]
+    with threadpool_limits(limits=1):
+        P = oracle.Problem.from_lpdata(lp)
+        if opts.get("ruiz_iters", 0):
+            P, _, _ = oracle.ruiz(P, opts["ruiz_iters"])
+            P = P.rounded_fp32()
+        nrm = oracle.power_norm(P)
+        o = oracle.Solver(P, oracle.Options(variant=opts["variant"], memory=opts["memory"],
+                                            kkt_every=opts["kkt_every"], tol=0.0, tau=0.9 / nrm,
+                                            sigma=0.9 / nrm, dhat_mode=opts.get("dhat_mode", 1)))
+        o.start()
+        for _ in range(3):
+            o.step()
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < seconds:
+            o.step()
+            k += 1
+        el = time.perf_counter() - t0
+    return k / el, k, el
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=300)
+    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solve", action="store_true", help="skip the solve-to-tolerance leg")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="only the timed loop passes (for rocprofv3 runs)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU; --gpus N with N > 1 is not supported by this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2508_08062_amd as P
+
+    lps, opts, cfg = _workload(args.workload)
+    torch.cuda.init()
+    stream = torch.cuda.Stream()
+    solvers = [P.Solver(lp, tol=0.0, max_iter=10 ** 9, **opts) for lp in lps]
+    runner = solvers[0] if len(solvers) == 1 else P.Batch(solvers)
+    torch.cuda.synchronize()
+    print(f"# created {len(solvers)} LP(s); warmup {args.warmup}", file=sys.stderr, flush=True)
+    runner.iterate(args.warmup, stream)
+    torch.cuda.synchronize()
+
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    runner.iterate(args.steps, stream)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    print(f"# timed {args.steps} passes in {ms:.1f} ms", file=sys.stderr, flush=True)
+    if args.profile_run:
+        return
+
+    # per-launch durations on the launch stream (HIP events around each launch)
+    kt = runner.iterate_timed(min(args.steps, 1000), stream)
+    n = sum(lp.n for lp in lps)
+    m = sum(lp.m for lp in lps)
+    Z = sum(lp.nnz for lp in lps)
+    M = opts["memory"]
+    bm = _bytes_model(n, m, Z, M, 1.0 / opts["kkt_every"])
+    dom = max(("primal", "dual", "mix"), key=lambda k: kt[k])
+    achieved = bm[dom] / (kt[dom] * 1e-3) / 1e9
+    spmv_gbs = bm["spmv"] / ((kt["primal"] + kt["dual"]) * 1e-3) / 1e9
+    kernel_names = {"primal": "k_pass<float, MT, 0>", "dual": "k_pass<float, MT, 1>", "mix": "k_mix<float>"}
+
+    value = args.steps / (ms * 1e-3)
+    line = {
+        "metric": "PDHG iters/s + SpMV HBM GB/s; LPs solved/s & p99 latency at rel KKT 1e-4",
+        "value": value,
+        "unit": "iters/s" if len(lps) == 1 else "batch iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {**cfg, "m": m, "n": n, "nnz": Z},
+        "spmv_gbps": spmv_gbs,
+        "launch_ms": kt,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": _traffic(args.workload, dom),
+                     "kernel": kernel_names[dom], "algorithmic_bytes_per_launch": bm[dom]},
+    }
+
+    if not args.no_solve and len(lps) == 1:
+        # solve to relative KKT 1e-4 in float32, and the same LP in float64
+        res = {}
+        for prec, key in ((0, "solve_fp32"), (1, "solve_fp64")):
+            s = P.Solver(lps[0], tol=1e-4, max_iter=200000, **{**opts, "precision": prec})
+            t0 = time.perf_counter()
+            s.solve(stream)
+            el = time.perf_counter() - t0
+            r = s.result()
+            res[key] = {"status": r["status"], "iters": r["iters"], "seconds": el, "kkt": r["kkt"],
+                        "primal_obj": r["primal_obj"], "aa_steps": r["aa_steps"]}
+            s.close()
+        line.update(res)
+
+    if not args.no_cpu_baseline:
+        rate, k, el = _cpu_baseline(lps, opts, args.cpu_seconds)
+        line["cpu_baseline"] = {"value": rate, "unit": "iters/s", "cores": 1, "kind": "oracle",
+                                "sample": f"{k} loop passes of the float64 oracle on the first LP of the "
+                                          f"workload ({el:.1f} s, one thread)"}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -92,7 +92,8 @@ typedef struct {
   int32_t ruiz_iters; /* Ruiz equilibration sweeps applied at create (Section 5.2), 0 off */
   int32_t power_iters;/* power-iteration cap for the step size                            */
   int32_t epoch;      /* iterations per device epoch between host checks of the status    */
-  int32_t reserved[7];
+  int32_t chunks_per_block; /* work items per workgroup of the SpMV passes, 0 = automatic   */
+  int32_t reserved[6];
 } aapdhg_options;
 
 typedef struct {
@@ -145,6 +146,13 @@ aapdhg_status aapdhg_solve(aapdhg_t h, void *stream);
  * reset handle the first pass is the init step.  Passes after termination do nothing. */
 aapdhg_status aapdhg_iterate(aapdhg_t h, void *stream, int64_t iters);
 
+/* Measurement variant of aapdhg_iterate: the same `iters` loop passes, with HIP events
+ * recorded on `stream` before and after each of the three launches of a pass (primal CSC
+ * pass, dual CSR pass with the float64 decisions, mix pass).  Waits for completion and
+ * writes the mean duration in milliseconds of each launch to ms3[0..2].  The events add a
+ * small gap between launches, so use aapdhg_iterate for throughput. */
+aapdhg_status aapdhg_iterate_timed(aapdhg_t h, void *stream, int64_t iters, double *ms3);
+
 /* Return to the start point (discard iterate, history and counters). */
 aapdhg_status aapdhg_reset(aapdhg_t h, void *stream);
 
@@ -191,6 +199,8 @@ aapdhg_status aapdhg_batch_create(int32_t count, const aapdhg_t *problems, aapdh
 aapdhg_status aapdhg_batch_solve(aapdhg_batch_t b, void *stream);
 /* Enqueue `iters` loop passes for every member (asynchronous). */
 aapdhg_status aapdhg_batch_iterate(aapdhg_batch_t b, void *stream, int64_t iters);
+/* Measurement variant of aapdhg_batch_iterate (see aapdhg_iterate_timed). */
+aapdhg_status aapdhg_batch_iterate_timed(aapdhg_batch_t b, void *stream, int64_t iters, double *ms3);
 aapdhg_status aapdhg_batch_destroy(aapdhg_batch_t b);
 
 /* ---- serving: continuous batching of LP requests ----

@@ -32,7 +32,8 @@ class Options(C.Structure):
                 ("cs", C.c_double), ("kappa_bar", C.c_double), ("tau", C.c_double), ("sigma", C.c_double),
                 ("tol", C.c_double), ("max_iter", C.c_int64), ("time_limit_s", C.c_double),
                 ("kkt_every", C.c_int32), ("dhat_mode", C.c_int32), ("ruiz_iters", C.c_int32),
-                ("power_iters", C.c_int32), ("epoch", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("power_iters", C.c_int32), ("epoch", C.c_int32), ("chunks_per_block", C.c_int32),
+                ("reserved", C.c_int32 * 6)]
 
 
 class Info(C.Structure):
@@ -50,10 +51,11 @@ class Info(C.Structure):
 
 
 EXPORTS = [
-    "aapdhg_default_options", "aapdhg_create", "aapdhg_solve", "aapdhg_iterate", "aapdhg_reset",
+    "aapdhg_default_options", "aapdhg_create", "aapdhg_solve", "aapdhg_iterate", "aapdhg_iterate_timed",
+    "aapdhg_reset",
     "aapdhg_result", "aapdhg_get_state", "aapdhg_set_state", "aapdhg_get_dims", "aapdhg_get_scaling",
     "aapdhg_destroy", "aapdhg_last_error", "aapdhg_batch_create", "aapdhg_batch_solve",
-    "aapdhg_batch_iterate", "aapdhg_batch_destroy", "aapdhg_server_start", "aapdhg_server_submit",
+    "aapdhg_batch_iterate", "aapdhg_batch_iterate_timed", "aapdhg_batch_destroy", "aapdhg_server_start", "aapdhg_server_submit",
     "aapdhg_server_poll", "aapdhg_server_stats", "aapdhg_server_stop",
 ]
 
@@ -77,6 +79,7 @@ def lib():
                                 _dp, _dp, _dp, _dp, _dp, C.POINTER(C.c_uint8), C.POINTER(Options), C.POINTER(_P)]
     L.aapdhg_solve.argtypes = [_P, _P]
     L.aapdhg_iterate.argtypes = [_P, _P, C.c_int64]
+    L.aapdhg_iterate_timed.argtypes = [_P, _P, C.c_int64, _dp]
     L.aapdhg_reset.argtypes = [_P, _P]
     L.aapdhg_result.argtypes = [_P, _dp, _dp, _dp, C.POINTER(Info)]
     L.aapdhg_get_state.argtypes = [_P, _dp, _dp, _dp, _dp, _dp, _i64p, _dp]
@@ -89,6 +92,7 @@ def lib():
     L.aapdhg_batch_create.argtypes = [C.c_int32, C.POINTER(_P), C.POINTER(_P)]
     L.aapdhg_batch_solve.argtypes = [_P, _P]
     L.aapdhg_batch_iterate.argtypes = [_P, _P, C.c_int64]
+    L.aapdhg_batch_iterate_timed.argtypes = [_P, _P, C.c_int64, _dp]
     L.aapdhg_batch_destroy.argtypes = [_P]
     L.aapdhg_server_start.argtypes = [C.c_size_t, C.c_int32, C.POINTER(Options), C.POINTER(_P)]
     L.aapdhg_server_submit.argtypes = [_P, C.c_int32, C.c_int32, C.c_int64, C.POINTER(C.c_int64),
@@ -195,6 +199,12 @@ class Solver:
         _check(lib().aapdhg_iterate(self.h, _stream(stream), int(iters)), self.h)
         return self
 
+    def iterate_timed(self, iters: int, stream=None):
+        """Mean milliseconds of the primal, dual and mix launches over `iters` passes."""
+        ms = np.zeros(3)
+        _check(lib().aapdhg_iterate_timed(self.h, _stream(stream), int(iters), _ptr(ms, C.c_double)), self.h)
+        return {"primal": ms[0], "dual": ms[1], "mix": ms[2]}
+
     def reset(self, stream=None):
         _check(lib().aapdhg_reset(self.h, _stream(stream)), self.h)
         return self
@@ -274,6 +284,11 @@ class Batch:
     def iterate(self, iters, stream=None):
         _check(lib().aapdhg_batch_iterate(self.h, _stream(stream), int(iters)), None)
         return self
+
+    def iterate_timed(self, iters: int, stream=None):
+        ms = np.zeros(3)
+        _check(lib().aapdhg_batch_iterate_timed(self.h, _stream(stream), int(iters), _ptr(ms, C.c_double)), None)
+        return {"primal": ms[0], "dual": ms[1], "mix": ms[2]}
 
     def results(self):
         return [s.result() for s in self.solvers]

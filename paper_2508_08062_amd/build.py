@@ -51,6 +51,8 @@ def build(verbose: bool = True) -> str:
         cmd = [hipcc] + COMMON + ["-I", CSRC]
         if device:
             cmd += [f"--offload-arch={ARCH}"] + DEVICE_FLAGS + ["-x", "hip"]
+        else:  # host-only runtime code: plain C++ against the HIP headers
+            cmd += ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include"]
         cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
         _run(cmd)
         objs.append(obj)

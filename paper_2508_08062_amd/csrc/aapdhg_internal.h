@@ -11,10 +11,10 @@ namespace aapdhg {
 constexpr int MAXM = 16;          // largest Anderson memory
 constexpr int BLOCK = 256;        // threads per workgroup (4 wave64)
 constexpr int CHUNK_NNZ = 2048;   // nnz staged in LDS by one multi-row chunk
-constexpr int CHUNK_ROWS = 1024;  // rows of one multi-row chunk (4 per thread at most)
+constexpr int CHUNK_ROWS = 256;   // rows of one multi-row chunk (one per thread at most)
 constexpr int ROWS_PER_THREAD = CHUNK_ROWS / BLOCK;
 constexpr int SPLIT_NNZ = 8192;   // nnz per part of a split (very long) row
-constexpr int GROUP = 32;         // chunks per first-level reduction group
+constexpr int FAN = 48;           // children per node of the reduction tree
 constexpr int MIX_TILE = 2048;    // elements per block of the mix pass
 constexpr int NDOT = 2 * MAXM + 8;  // stride of one partial-sum record (doubles)
 
@@ -99,14 +99,16 @@ struct Chunk {
   int k0, k1;
   int tpr;    // multi: threads per row (1..64, or BLOCK for a single row); split: part index
   int split;  // split: global split-row index
-  int group;  // global reduction group
-  int pad[3];
+  int pad[4];
 };
 
-struct Group {
-  int first;   // first chunk of the group (global chunk index)
-  int count;   // chunks in the group
-  int lp;
+// Node of the per-LP reduction tree of a pass.  Its children are the records
+// [first, first + count) of the record array (chunk records first, then node
+// records); node i owns record (nleaves + i).
+struct Node {
+  int first;
+  int count;
+  int parent;  // node index, -1 at the root
   int pad;
 };
 
@@ -114,13 +116,27 @@ struct SplitRow {
   int row;      // pass-local row
   int nparts;
   int part0;    // first slot in the split partial buffer
-  int pad;
+  int leaf;     // record that receives the row's dot sums (written by the last part)
+  int parent;   // tree node above that record
+  int pad[3];
 };
 
-// Per-LP entry of a launch table: where this LP's groups and split rows live.
+// One workgroup of an SpMV pass.  kind 0: the multi-row chunks [c0, c1) of
+// one LP, streamed in order, whose dot sums go to record `leaf`; kind 1: the
+// split-row part in chunk c0 (its row's sums go to the split row's record).
+struct BlockWork {
+  int lp;
+  int kind;
+  int c0, c1;
+  int leaf;
+  int parent;
+  int pad[2];
+};
+
+// Per-LP entry of a launch table: the roots of its two reduction trees.
 struct LaunchLP {
-  int gA0, nA, gB0, nB;  // reduction groups of the primal / dual pass
-  int sA0, nsA, sB0, nsB;  // split rows of the primal / dual pass
+  int rootA, rootB;  // node indices
+  int pad[2];
 };
 
 struct MixTile {
@@ -133,15 +149,15 @@ struct MixTile {
 struct PassArgs {
   const LPDesc* lps;
   const LaunchLP* llp;
+  const BlockWork* blocks;
   const Chunk* chunks;
-  const Group* groups;
+  const Node* nodes;
   const SplitRow* splits;
-  double* cpart;        // [chunks][NDOT]
-  double* gpart;        // [groups][NDOT]
-  unsigned int* gcnt;   // [groups]
+  double* rec;          // [nleaves + nnodes][NDOT] partial-sum records
+  unsigned int* ncnt;   // [nnodes] arrival counters
   double* splitpart;    // [split parts][2]
   unsigned int* splitcnt;  // [split rows]
-  double* splitdots;    // [split rows][NDOT]
+  int nleaves;          // leaf records of both passes (workgroups and split rows)
   int mode;
 };
 

@@ -92,6 +92,7 @@ void default_options(aapdhg_options* o) {
   o->ruiz_iters = 0;
   o->power_iters = 200;
   o->epoch = 256;
+  o->chunks_per_block = 0;
 }
 
 static void check_options(const aapdhg_options& o) {
@@ -111,6 +112,7 @@ static void check_options(const aapdhg_options& o) {
   if (o.ruiz_iters < 0 || o.ruiz_iters > 1000) throw Error(AAPDHG_E_ARG, "ruiz_iters must be in [0, 1000]");
   if (o.power_iters < 1 || o.power_iters > 100000) throw Error(AAPDHG_E_ARG, "power_iters must be in [1, 100000]");
   if (o.epoch < 1 || o.epoch > 1000000) throw Error(AAPDHG_E_ARG, "epoch must be in [1, 1e6]");
+  if (o.chunks_per_block < 0 || o.chunks_per_block > 4096) throw Error(AAPDHG_E_ARG, "chunks_per_block must be in [0, 4096]");
   if (!std::isfinite(o.tau) || !std::isfinite(o.sigma)) throw Error(AAPDHG_E_ARG, "tau and sigma must be finite");
 }
 
@@ -196,18 +198,39 @@ static void build_chunks(const std::vector<int>& ptr, int R, std::vector<Chunk>&
     c.tpr = nrows >= BLOCK ? 1 : std::min(64, pow2floor(BLOCK / nrows));
     chunks.push_back(c);
   }
-  // reduction groups: runs of GROUP consecutive chunks
-  for (size_t i = 0; i < chunks.size(); ++i) chunks[i].group = (int)(i / GROUP);
 }
 
-static void build_groups(const std::vector<Chunk>& chunks, std::vector<Group>& groups) {
-  groups.clear();
-  for (size_t i = 0; i < chunks.size(); i += GROUP) {
-    Group g{};
-    g.first = (int)i;
-    g.count = (int)std::min<size_t>(GROUP, chunks.size() - i);
-    groups.push_back(g);
+// Reduction tree over `nleaf` consecutive leaf records starting at record
+// `leaf_base`: nodes of at most FAN children, appended to `nodes`; parent[i]
+// receives the node above leaf i.  Returns the root node.
+static int build_tree(int leaf_base, int nleaf, int nleaves_total, std::vector<Node>& nodes, std::vector<int>& parent) {
+  parent.assign(nleaf, -1);
+  std::vector<int> level;
+  for (int c = 0; c < nleaf; c += FAN) {
+    Node nd{};
+    nd.first = leaf_base + c;
+    nd.count = std::min(FAN, nleaf - c);
+    nd.parent = -1;
+    const int id = (int)nodes.size();
+    for (int t = 0; t < nd.count; ++t) parent[c + t] = id;
+    nodes.push_back(nd);
+    level.push_back(id);
   }
+  while (level.size() > 1) {
+    std::vector<int> next;
+    for (size_t i = 0; i < level.size(); i += FAN) {
+      Node nd{};
+      nd.first = nleaves_total + level[i];
+      nd.count = (int)std::min<size_t>(FAN, level.size() - i);
+      nd.parent = -1;
+      const int id = (int)nodes.size();
+      for (int t = 0; t < nd.count; ++t) nodes[level[i + t]].parent = id;
+      nodes.push_back(nd);
+      next.push_back(id);
+    }
+    level.swap(next);
+  }
+  return level[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -355,9 +378,7 @@ void Problem::create(int32_t m_, int32_t n_, int64_t nnz_, const int64_t* row_pt
   cnorm = std::sqrt(cnorm);
   // ---- work tables ----
   build_chunks(colptr, n, chunksA, splitsA, npartsA);
-  build_groups(chunksA, groupsA);
   build_chunks(rowptr, m, chunksB, splitsB, npartsB);
-  build_groups(chunksB, groupsB);
   tiles.clear();
   for (int e = 0; e < N; e += MIX_TILE) {
     MixTile t{};
@@ -513,8 +534,8 @@ LaunchSet::~LaunchSet() {
 
 size_t LaunchSet::device_bytes() const {
   size_t b = 0;
-  const DevBuf* bufs[] = {&d_lps, &d_llp, &d_chunksA, &d_chunksB, &d_groups, &d_splits, &d_cpartA, &d_cpartB,
-                          &d_gpart, &d_gcnt, &d_splitpart, &d_splitcnt, &d_splitdots, &d_tiles, &d_status};
+  const DevBuf* bufs[] = {&d_lps, &d_llp, &d_chunks, &d_blocksA, &d_blocksB, &d_nodes, &d_splits, &d_rec,
+                          &d_ncnt, &d_splitpart, &d_splitcnt, &d_tiles, &d_status};
   for (auto* p : bufs) b += p->bytes;
   return b;
 }
@@ -523,115 +544,165 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
   members = lps;
   const int count = (int)lps.size();
   if (count == 0) throw Error(AAPDHG_E_ARG, "empty launch set");
+  if (count > MAX_STATUS) throw Error(AAPDHG_E_ARG, "at most %d problems per batch", MAX_STATUS);
   std::vector<LPDesc> descs;
   std::vector<LaunchLP> llp(count);
-  std::vector<Chunk> cA, cB;
-  std::vector<Group> groups;
+  std::vector<Chunk> chunks;
+  std::vector<BlockWork> bA, bB;
+  std::vector<Node> nodes;
   std::vector<SplitRow> splits;
   std::vector<MixTile> tl;
-  int parts = 0;
   t = LaunchTables{};
   t.fp64 = lps[0]->fp64;
   int mt = 1;
+  int parts = 0;
+  // per LP and pass: chunks, split rows, workgroups; leaves are the
+  // workgroups followed by the split rows
+  struct PassInfo {
+    int b0, nb;   // workgroups in bA / bB
+    int s0, ns;   // split rows
+    int leaf0;    // first leaf record
+  };
+  std::vector<PassInfo> info(2 * count);
+  int nleaves = 0;
   for (int i = 0; i < count; ++i) {
     Problem* p = lps[i];
     if (p->fp64 != t.fp64) throw Error(AAPDHG_E_ARG, "all problems of a batch must share the precision");
     mt = std::max(mt, p->opt.memory);
     descs.push_back(p->desc);
-    LaunchLP& L = llp[i];
-    // pass A
-    L.gA0 = (int)groups.size();
-    L.nA = (int)p->groupsA.size();
-    L.sA0 = (int)splits.size();
-    L.nsA = (int)p->splitsA.size();
-    const int cA0 = (int)cA.size();
-    for (auto g : p->groupsA) {
-      g.first += cA0;
-      g.lp = i;
-      groups.push_back(g);
-    }
-    for (auto s : p->splitsA) {
-      s.part0 += parts;
-      splits.push_back(s);
-    }
-    parts += p->npartsA;
-    for (auto c : p->chunksA) {
-      c.lp = i;
-      c.group += L.gA0;
-      if (c.kind == 1) c.split += L.sA0;
-      cA.push_back(c);
-    }
-    // pass B
-    L.gB0 = (int)groups.size();
-    L.nB = (int)p->groupsB.size();
-    L.sB0 = (int)splits.size();
-    L.nsB = (int)p->splitsB.size();
-    const int cB0 = (int)cB.size();
-    for (auto g : p->groupsB) {
-      g.first += cB0;
-      g.lp = i;
-      groups.push_back(g);
-    }
-    for (auto s : p->splitsB) {
-      s.part0 += parts;
-      splits.push_back(s);
-    }
-    parts += p->npartsB;
-    for (auto c : p->chunksB) {
-      c.lp = i;
-      c.group += L.gB0;
-      if (c.kind == 1) c.split += L.sB0;
-      cB.push_back(c);
+    for (int pass = 0; pass < 2; ++pass) {
+      const auto& pc = pass == 0 ? p->chunksA : p->chunksB;
+      const auto& ps = pass == 0 ? p->splitsA : p->splitsB;
+      const int np = pass == 0 ? p->npartsA : p->npartsB;
+      auto& bw = pass == 0 ? bA : bB;
+      PassInfo& pi = info[2 * i + pass];
+      const int c_off = (int)chunks.size();
+      pi.s0 = (int)splits.size();
+      pi.ns = (int)ps.size();
+      for (auto sr : ps) {
+        sr.part0 += parts;
+        splits.push_back(sr);
+      }
+      parts += np;
+      for (auto c : pc) {
+        c.lp = i;
+        if (c.kind == 1) c.split += pi.s0;
+        chunks.push_back(c);
+      }
+      const int nch = (int)pc.size();
+      int cpb = p->opt.chunks_per_block;
+      if (cpb <= 0) cpb = std::max(1, (nch + 1023) / 1024);
+      // workgroups: runs of up to cpb multi-row chunks (leaves, listed first),
+      // then one workgroup per split-row part (no leaf of their own)
+      pi.b0 = (int)bw.size();
+      for (int c = 0; c < nch;) {
+        if (pc[c].kind == 1) {
+          ++c;
+          continue;
+        }
+        BlockWork w{};
+        w.lp = i;
+        w.kind = 0;
+        w.c0 = c_off + c;
+        int e = c;
+        while (e < nch && e - c < cpb && pc[e].kind == 0) ++e;
+        w.c1 = c_off + e;
+        bw.push_back(w);
+        c = e;
+      }
+      pi.nb = (int)bw.size() - pi.b0;
+      for (int c = 0; c < nch; ++c) {
+        if (pc[c].kind != 1) continue;
+        BlockWork w{};
+        w.lp = i;
+        w.kind = 1;
+        w.c0 = w.c1 = c_off + c;
+        w.leaf = w.parent = -1;
+        bw.push_back(w);
+      }
+      pi.leaf0 = nleaves;
+      nleaves += pi.nb + pi.ns;
     }
     for (auto x : p->tiles) {
       x.lp = i;
       tl.push_back(x);
     }
   }
+  // leaves and trees
+  for (int i = 0; i < count; ++i) {
+    for (int pass = 0; pass < 2; ++pass) {
+      PassInfo& pi = info[2 * i + pass];
+      auto& bw = pass == 0 ? bA : bB;
+      std::vector<int> parent;
+      const int root = build_tree(pi.leaf0, pi.nb + pi.ns, nleaves, nodes, parent);
+      for (int b = 0; b < pi.nb; ++b) {
+        bw[pi.b0 + b].leaf = pi.leaf0 + b;
+        bw[pi.b0 + b].parent = parent[b];
+      }
+      for (int q = 0; q < pi.ns; ++q) {
+        splits[pi.s0 + q].leaf = pi.leaf0 + pi.nb + q;
+        splits[pi.s0 + q].parent = parent[pi.nb + q];
+      }
+      if (pass == 0) llp[i].rootA = root; else llp[i].rootB = root;
+    }
+  }
   t.mt = mt;
   t.nlps = count;
   d_lps.upload(descs.data(), descs.size() * sizeof(LPDesc), "lp table");
-  d_llp.upload(llp.data(), llp.size() * sizeof(LaunchLP), "lp ranges");
-  d_chunksA.upload(cA.data(), cA.size() * sizeof(Chunk), "chunks A");
-  d_chunksB.upload(cB.data(), cB.size() * sizeof(Chunk), "chunks B");
-  d_groups.upload(groups.data(), groups.size() * sizeof(Group), "groups");
-  d_splits.upload(splits.data(), splits.size() * sizeof(SplitRow), "splits");
-  d_cpartA.alloc(cA.size() * NDOT * 8, "chunk partials A");
-  d_cpartB.alloc(cB.size() * NDOT * 8, "chunk partials B");
-  d_gpart.alloc(groups.size() * NDOT * 8, "group partials");
-  d_gcnt.alloc(groups.size() * 4, "group counters");
-  d_gcnt.zero("group counters");
+  d_llp.upload(llp.data(), llp.size() * sizeof(LaunchLP), "lp roots");
+  d_chunks.upload(chunks.data(), chunks.size() * sizeof(Chunk), "chunks");
+  d_blocksA.upload(bA.data(), bA.size() * sizeof(BlockWork), "workgroups A");
+  d_blocksB.upload(bB.data(), bB.size() * sizeof(BlockWork), "workgroups B");
+  d_nodes.upload(nodes.data(), nodes.size() * sizeof(Node), "tree nodes");
+  d_splits.upload(splits.data(), std::max<size_t>(splits.size(), 1) * sizeof(SplitRow), "splits");
+  d_rec.alloc(((size_t)nleaves + nodes.size()) * NDOT * 8, "partial records");
+  d_rec.zero("partial records");
+  d_ncnt.alloc(nodes.size() * 4, "tree counters");
+  d_ncnt.zero("tree counters");
   d_splitpart.alloc((size_t)std::max(parts, 1) * 2 * 8, "split partials");
   d_splitcnt.alloc(std::max<size_t>(splits.size(), 1) * 4, "split counters");
   d_splitcnt.zero("split counters");
-  d_splitdots.alloc(std::max<size_t>(splits.size(), 1) * NDOT * 8, "split dots");
-  d_splitdots.zero("split dots");
   d_tiles.upload(tl.data(), tl.size() * sizeof(MixTile), "mix tiles");
   d_status.alloc(count * 4, "status");
   if (!h_status) hip_check(hipHostMalloc((void**)&h_status, sizeof(int) * 2 * MAX_STATUS, hipHostMallocDefault), "pinned status");
-  if (count > MAX_STATUS) throw Error(AAPDHG_E_ARG, "at most %d problems per batch", MAX_STATUS);
   t.lps = (const LPDesc*)d_lps.p;
   t.llp = (const LaunchLP*)d_llp.p;
-  t.chunksA = (const Chunk*)d_chunksA.p;
-  t.nchunksA = (int)cA.size();
-  t.chunksB = (const Chunk*)d_chunksB.p;
-  t.nchunksB = (int)cB.size();
-  t.groups = (const Group*)d_groups.p;
+  t.chunks = (const Chunk*)d_chunks.p;
+  t.blocksA = (const BlockWork*)d_blocksA.p;
+  t.nblocksA = (int)bA.size();
+  t.blocksB = (const BlockWork*)d_blocksB.p;
+  t.nblocksB = (int)bB.size();
+  t.nleaves = nleaves;
+  t.nodes = (const Node*)d_nodes.p;
+  t.nnodes = (int)nodes.size();
   t.splits = (const SplitRow*)d_splits.p;
-  t.cpartA = (double*)d_cpartA.p;
-  t.cpartB = (double*)d_cpartB.p;
-  t.gpart = (double*)d_gpart.p;
-  t.gcnt = (unsigned int*)d_gcnt.p;
+  t.rec = (double*)d_rec.p;
+  t.ncnt = (unsigned int*)d_ncnt.p;
   t.splitpart = (double*)d_splitpart.p;
   t.splitcnt = (unsigned int*)d_splitcnt.p;
-  t.splitdots = (double*)d_splitdots.p;
   t.tiles = (const MixTile*)d_tiles.p;
   t.ntiles = (int)tl.size();
-  // scalars' lp counters start at zero (they are part of the reset image)
 }
 
 void LaunchSet::enqueue_passes(hipStream_t st, int64_t iters) {
   for (int64_t it = 0; it < iters; ++it) hip_check(launch_loop_pass(t, st, MODE_ITER), "loop pass");
+}
+
+void LaunchSet::timed_passes(hipStream_t st, int64_t iters, double* ms3) {
+  if (iters < 1) throw Error(AAPDHG_E_ARG, "iters must be >= 1");
+  std::vector<hipEvent_t> ev((size_t)iters * 4);
+  for (auto& e : ev) hip_check(hipEventCreate(&e), "event");
+  for (int64_t it = 0; it < iters; ++it) hip_check(launch_loop_pass(t, st, MODE_ITER, &ev[(size_t)it * 4]), "loop pass");
+  hip_check(hipStreamSynchronize(st), "timed sync");
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int64_t it = 0; it < iters; ++it)
+    for (int q = 0; q < 3; ++q) {
+      float ms = 0.f;
+      hip_check(hipEventElapsedTime(&ms, ev[(size_t)it * 4 + q], ev[(size_t)it * 4 + q + 1]), "event time");
+      acc[q] += ms;
+    }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  for (int q = 0; q < 3; ++q) ms3[q] = acc[q] / (double)iters;
 }
 
 void LaunchSet::enqueue_eval(hipStream_t st) { hip_check(launch_loop_pass(t, st, MODE_EVAL), "evaluation pass"); }
@@ -898,6 +969,16 @@ aapdhg_status aapdhg_iterate(aapdhg_t h, void* stream, int64_t iters) {
   });
 }
 
+aapdhg_status aapdhg_iterate_timed(aapdhg_t h, void* stream, int64_t iters, double* ms3) {
+  if (!h || !ms3) return AAPDHG_E_ARG;
+  return guard(&h->err, [&] {
+    if (h->p.in_batch) throw Error(AAPDHG_E_STATE, "problem belongs to a live batch");
+    hipStream_t st = (hipStream_t)stream;
+    if (!h->p.started) h->p.enqueue_reset(st);
+    h->p.solo->timed_passes(st, iters, ms3);
+  });
+}
+
 aapdhg_status aapdhg_reset(aapdhg_t h, void* stream) {
   if (!h) return AAPDHG_E_ARG;
   return guard(&h->err, [&] { h->p.enqueue_reset((hipStream_t)stream); });
@@ -1002,6 +1083,16 @@ aapdhg_status aapdhg_batch_iterate(aapdhg_batch_t b, void* stream, int64_t iters
     for (auto* h : b->members)
       if (!h->p.started) h->p.enqueue_reset(st);
     b->set.enqueue_passes(st, iters);
+  });
+}
+
+aapdhg_status aapdhg_batch_iterate_timed(aapdhg_batch_t b, void* stream, int64_t iters, double* ms3) {
+  if (!b || !ms3) return AAPDHG_E_ARG;
+  return guard(&b->err, [&] {
+    hipStream_t st = (hipStream_t)stream;
+    for (auto* h : b->members)
+      if (!h->p.started) h->p.enqueue_reset(st);
+    b->set.timed_passes(st, iters, ms3);
   });
 }
 

@@ -14,25 +14,27 @@ struct LaunchTables {
   const LPDesc* lps = nullptr;
   const LaunchLP* llp = nullptr;
   int nlps = 0;
-  const Chunk* chunksA = nullptr;
-  int nchunksA = 0;
-  const Chunk* chunksB = nullptr;
-  int nchunksB = 0;
-  const Group* groups = nullptr;
+  const Chunk* chunks = nullptr;  // both passes
+  const BlockWork* blocksA = nullptr;
+  int nblocksA = 0;
+  const BlockWork* blocksB = nullptr;
+  int nblocksB = 0;
+  int nleaves = 0;
+  const Node* nodes = nullptr;
+  int nnodes = 0;
   const SplitRow* splits = nullptr;
-  double* cpartA = nullptr;
-  double* cpartB = nullptr;
-  double* gpart = nullptr;
-  unsigned int* gcnt = nullptr;
+  double* rec = nullptr;
+  unsigned int* ncnt = nullptr;
   double* splitpart = nullptr;
   unsigned int* splitcnt = nullptr;
-  double* splitdots = nullptr;
   const MixTile* tiles = nullptr;
   int ntiles = 0;
 };
 
 // One loop pass (passes A, B and, in MODE_ITER, C) for every LP of the table.
-hipError_t launch_loop_pass(const LaunchTables& t, hipStream_t st, int mode);
+// With ev != nullptr, events ev[0..3] are recorded before A, after A, after B
+// and after C on the same stream.
+hipError_t launch_loop_pass(const LaunchTables& t, hipStream_t st, int mode, hipEvent_t* ev = nullptr);
 hipError_t launch_start_point(const LPDesc& d, bool fp64, hipStream_t st);
 // Power iteration on K^T K from the all-ones vector; est[0..iters] receives
 // ||K^T K v|| of each step (the square of the ||K|| estimate).  work holds

@@ -52,6 +52,36 @@ __device__ __forceinline__ double block_sum(double v, double* s_tmp) {
   return r;
 }
 
+// Cross-block data (partial sums, counters) inside one kernel: stores and
+// loads at agent scope go straight to the device-coherent level for just those
+// words, so no fence has to write back or invalidate a whole L2.  A writer
+// waits for its stores to complete (vmcnt 0) before it bumps the counter; the
+// block that sees the final count reads the words back at agent scope.
+__device__ __forceinline__ void st_agent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_agent(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Coherent load of cross-block data that the compiler may keep in flight with
+// others (a buffer load with the sc1 cache policy).
+__device__ __forceinline__ double ld_coh(const double* base, int idx) {
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), 0, 0x7fffffff, 0x00020000);
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, idx * 8, 0, 16));
+}
+__device__ __forceinline__ void wait_stores() {
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's stores are complete
+}
+// Count one arrival; true for the block that arrives last (thread 0 only).
+__device__ __forceinline__ bool arrive(unsigned int* cnt, unsigned int total) {
+  wait_stores();
+  const unsigned int prev = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return prev == total - 1u;
+}
+__device__ __forceinline__ void reset_counter(unsigned int* cnt) {
+  __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <typename T>
 __device__ __forceinline__ T clampT(T v, T lo, T hi) {
   return v < lo ? lo : (v > hi ? hi : v);
@@ -337,49 +367,70 @@ __device__ void final_step(const LPDesc& d, Scalars* sc, const double* fa, const
 // pass A (PASS = 0, columns of K via CSC) and pass B (PASS = 1, rows via CSR)
 // ---------------------------------------------------------------------------
 
+// Inputs of one row's (or column's) epilogue, loaded before anything is stored
+// so that the loads of a thread's rows and of the SpMV are in flight together.
+template <typename T, int MT>
+struct RowIn {
+  T u, up, gp, cq, lo, hi, dh;
+  unsigned char ge;
+  T hv[MT];
+};
+
 template <typename T, int MT, int PASS>
 __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
   using DT = Dot<MT>;
+  constexpr int UNR = CHUNK_NNZ / BLOCK;  // staged entries per thread
+  constexpr int RPT = ROWS_PER_THREAD;    // rows per thread in a multi-row chunk
   __shared__ double s_prod[CHUNK_NNZ];
   __shared__ double s_red[BLOCK / 64][NDOT];
   __shared__ double s_fin[2][NDOT];
+  __shared__ double s_racc[NDOT];  // dot sums of one split row
   __shared__ double s_tmp[4];
   __shared__ int s_live[MAXM];
   __shared__ int s_flag;
+  __shared__ int s_own;
   __shared__ SolveWork s_work;
+  __shared__ Scalars s_sc;
 
   const int tid = threadIdx.x;
-  const Chunk ch = a.chunks[blockIdx.x];
-  const LPDesc& d = a.lps[ch.lp];
-  Scalars* sc = d.sc;
+  const int lane = tid & 63, wv = tid >> 6;
+  const BlockWork bw = a.blocks[blockIdx.x];
+  const LPDesc* dp = a.lps + bw.lp;
+  Scalars* sc = dp->sc;
   const bool eval = a.mode == MODE_EVAL;
   if (!eval && sc->status != ST_RUNNING) return;
 
   const long long k = sc->k;
-  const bool init = !eval && k == 0;
-  const bool kkt = eval || (!init && d.kkt_every > 0 && (k % d.kkt_every) == 0);
   const int nl = sc->nlive;
   const int s_new = sc->newslot;
+  const int live0 = sc->live[0];
   if (tid < MAXM) s_live[tid] = sc->live[tid];
-  const bool skip0 = nl > 0 && sc->live[0] == s_new;
+  const bool skip0 = nl > 0 && live0 == s_new;
+  const int kkt_every = dp->kkt_every;
+  const bool init = !eval && k == 0;
+  const bool kkt = eval || (!init && kkt_every > 0 && (k % kkt_every) == 0);
+  const bool hist_on = !eval && !init;
 
-  const int n = d.n, N = d.N;
+  const int n = dp->n, N = dp->N;
   const int par = (int)(k & 1);
-  const T* ucur = (const T*)d.u[par];
-  T* unext = (T*)d.u[par ^ 1];  // u^{k-1} on entry, u_hat^{k+1} on exit
-  T* gcur = (T*)d.g[par];
-  const T* gprev = (const T*)d.g[par ^ 1];
-  T* dG = (T*)d.dG;
-  T* W = (T*)d.W;
-  const T* dhat = (const T*)d.dhat;
-  const double beta = d.beta;
-
-  const int* ptr = PASS == 0 ? d.colptr : d.rowptr;
-  const int* idx = PASS == 0 ? d.rowidx : d.colidx;
-  const T* val = (const T*)(PASS == 0 ? d.valT : d.val);
+  const T* __restrict__ ucur = (const T*)dp->u[par];
+  T* __restrict__ unext = (T*)dp->u[par ^ 1];  // u^{k-1} on entry, u_hat^{k+1} on exit
+  T* __restrict__ gcur = (T*)dp->g[par];
+  const T* __restrict__ gprev = (const T*)dp->g[par ^ 1];
+  T* __restrict__ dG = (T*)dp->dG;
+  T* __restrict__ W = (T*)dp->W;
+  const T* __restrict__ dhat = (const T*)dp->dhat;
+  const double beta = dp->beta, tau = dp->tau, sigma = dp->sigma;
+  const int* __restrict__ ptr = PASS == 0 ? dp->colptr : dp->rowptr;
+  const int* __restrict__ idx = PASS == 0 ? dp->rowidx : dp->colidx;
+  const T* __restrict__ val = (const T*)(PASS == 0 ? dp->valT : dp->val);
   // gathered vectors: pass A gathers y^k; pass B gathers x_bar (and x^k for KKT)
-  const T* gv1 = PASS == 0 ? ucur + n : (eval ? ucur : (const T*)d.xbar);
+  const T* gv1 = PASS == 0 ? ucur + n : (eval ? ucur : (const T*)dp->xbar);
   const T* gv2 = ucur;
+  const T* __restrict__ cq = (const T*)(PASS == 0 ? dp->c : dp->q);
+  const T* __restrict__ lov = (const T*)dp->lo;
+  const T* __restrict__ hiv = (const T*)dp->hi;
+  const unsigned char* __restrict__ rtype = dp->rowtype;
   const bool two = PASS == 1 && kkt && !eval;
 
   double acc[DT::COUNT];
@@ -388,219 +439,267 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
 
   __syncthreads();  // s_live
 
-  // history part of the epilogue for vector entry e
-  auto history = [&](int e, T g_st, T u_prev, T u_cur) {
-    const T dgT = (T)((double)g_st - (double)gprev[e]);
-    const T duT = (T)((double)u_cur - (double)u_prev);
-    const double dg = (double)dgT, du = (double)duT, gd = (double)g_st;
-    dG[(size_t)s_new * N + e] = dgT;
-    W[(size_t)s_new * N + e] = (T)(du + beta * (double)dhat[e] * dg);
-    acc[DT::DGDG] += dg * dg;
-    acc[DT::DGG] += dg * gd;
-    acc[DT::DU2] += du * du;
-#pragma unroll
-    for (int t = 0; t < MT; ++t) {
-      if (t < nl && !(t == 0 && skip0)) {
-        const double v = (double)dG[(size_t)s_live[t] * N + e];
-        acc[DT::G + t] += dg * v;
-        acc[DT::R + t] += gd * v;
-      }
-    }
-  };
-
-  // epilogue for one row/column with its gathered sums
-  auto epilogue = [&](int r, double s1, double s2) {
+  // ---- epilogue, part 1: loads ----
+  auto load_row = [&](int r, RowIn<T, MT>& in) {
+    const int e = PASS == 0 ? r : n + r;
+    in.u = ucur[e];
+    in.cq = cq[r];
     if (PASS == 0) {
-      const int j = r;
-      const T x = ucur[j];
-      const double w = s1;  // (K^T y)_j
-      const double cj = (double)((const T*)d.c)[j];
-      const T lj = ((const T*)d.lo)[j], uj = ((const T*)d.hi)[j];
-      if (!eval) {
-        const T up = unext[j];  // u^{k-1}, read before it is overwritten
-        const T xh = clampT((T)((double)x - d.tau * (cj - w)), lj, uj);
-        ((T*)d.xbar)[j] = (T)(2.0 * (double)xh - (double)x);
-        const T g = (T)((double)xh - (double)x);
-        gcur[j] = g;
-        unext[j] = xh;
-        acc[DT::GG] += (double)g * (double)g;
-        if (!init) history(j, g, up, x);
-      }
-      if (kkt) {
-        const bool lf = isfinite((double)lj), uf = isfinite((double)uj);
-        const double lam = proj_lambda(cj - w, lf, uf);
-        acc[DT::K0] += cj * (double)x;
-        acc[DT::K1] += (lf ? (double)lj * fmax(lam, 0.0) : 0.0) - (uf ? (double)uj * fmax(-lam, 0.0) : 0.0);
-        const double rd = cj - w - lam;
-        acc[DT::K2] += rd * rd;
-        if (eval) ((T*)d.lam)[j] = (T)lam;
-      }
+      in.lo = lov[r];
+      in.hi = hiv[r];
     } else {
-      const int i = r;
-      const int e = n + i;
-      const T y = ucur[e];
-      const double qi = (double)((const T*)d.q)[i];
-      const bool ge = d.rowtype[i] != 0;
-      if (!eval) {
-        const T up = unext[e];
-        T yh = (T)((double)y + d.sigma * (qi - s1));
-        if (ge && yh < (T)0) yh = (T)0;
-        const T g = (T)((double)yh - (double)y);
-        gcur[e] = g;
-        unext[e] = yh;
-        acc[DT::GG] += (double)g * (double)g;
-        if (!init) history(e, g, up, y);
-      }
-      if (kkt) {
-        const double kx = eval ? s1 : s2;  // (K x^k)_i
-        acc[DT::K0] += qi * (double)y;
-        double res = qi - kx;
-        if (ge && res < 0.0) res = 0.0;
-        acc[DT::K1] += res * res;
-      }
+      in.ge = rtype[r];
+    }
+    if (hist_on) {
+      in.up = unext[e];
+      in.gp = gprev[e];
+      in.dh = dhat[e];
+#pragma unroll
+      for (int t = 0; t < MT; ++t)
+        if (t < nl && !(t == 0 && skip0)) in.hv[t] = dG[(size_t)s_live[t] * N + e];
     }
   };
 
-  bool split_owner = false;
-  if (ch.kind == 0) {
-    // ---- multi-row chunk: stage products in LDS, reduce rows, epilogue ----
-    const int r0 = ch.r0, r1 = ch.r1, kb = ch.k0, ke = ch.k1, tpr = ch.tpr;
-    double sum1[ROWS_PER_THREAD], sum2[ROWS_PER_THREAD];
-    const int nsweep = two ? 2 : 1;
-    for (int sw = 0; sw < nsweep; ++sw) {
-      const T* gv = sw == 0 ? gv1 : gv2;
-      double* out = sw == 0 ? sum1 : sum2;
-      for (int q = kb + tid; q < ke; q += BLOCK) s_prod[q - kb] = (double)val[q] * (double)gv[idx[q]];
-      __syncthreads();
-      if (tpr == BLOCK) {
-        double s = 0.0;
-        const int a0 = ptr[r0] - kb, a1 = ptr[r0 + 1] - kb;
-        for (int q = a0 + tid; q < a1; q += BLOCK) s += s_prod[q];
-        s = block_sum(s, s_tmp);
-        out[0] = s;
-#pragma unroll
-        for (int rr = 1; rr < ROWS_PER_THREAD; ++rr) out[rr] = 0.0;
+  // ---- epilogue, part 2: eq. pdhg update, residual, history, dots, KKT sums ----
+  auto finish_row = [&](int r, const RowIn<T, MT>& in, double s1, double s2, auto* accv) {
+    const int e = PASS == 0 ? r : n + r;
+    T g = (T)0;
+    if (!eval) {
+      T nx;
+      if (PASS == 0) {
+        // x_hat = P_X(x - tau (c - K^T y)), x_bar = 2 x_hat - x
+        nx = clampT((T)((double)in.u - tau * ((double)in.cq - s1)), in.lo, in.hi);
+        ((T*)dp->xbar)[r] = (T)(2.0 * (double)nx - (double)in.u);
       } else {
-        const int grp = tid / tpr, lane = tid % tpr, ngrp = BLOCK / tpr;
+        // y_hat = P_Y(y + sigma (q - K x_bar))
+        nx = (T)((double)in.u + sigma * ((double)in.cq - s1));
+        if (in.ge && nx < (T)0) nx = (T)0;
+      }
+      g = (T)((double)nx - (double)in.u);
+      gcur[e] = g;
+      unext[e] = nx;
+      accv[DT::GG] += (double)g * (double)g;
+    }
+    if (hist_on) {
+      // memory pair of this pass: dg = g^k - g^{k-1}, du = u^k - u^{k-1}
+      const T dgT = (T)((double)g - (double)in.gp);
+      const T duT = (T)((double)in.u - (double)in.up);
+      const double dg = (double)dgT, du = (double)duT, gd = (double)g;
+      dG[(size_t)s_new * N + e] = dgT;
+      W[(size_t)s_new * N + e] = (T)(du + beta * (double)in.dh * dg);
+      accv[DT::DGDG] += dg * dg;
+      accv[DT::DGG] += dg * gd;
+      accv[DT::DU2] += du * du;
 #pragma unroll
-        for (int rr = 0; rr < ROWS_PER_THREAD; ++rr) {
-          const int r = r0 + grp + rr * ngrp;
-          double s = 0.0;
-          if (r < r1) {
-            const int a0 = ptr[r] - kb, a1 = ptr[r + 1] - kb;
-            for (int q = a0 + lane; q < a1; q += tpr) s += s_prod[q];
-          }
-          for (int off = 1; off < tpr; off <<= 1) s += __shfl_xor(s, off, 64);
-          out[rr] = s;
+      for (int t = 0; t < MT; ++t) {
+        if (t < nl && !(t == 0 && skip0)) {
+          const double v = (double)in.hv[t];
+          accv[DT::G + t] += dg * v;
+          accv[DT::R + t] += gd * v;
         }
       }
-      __syncthreads();
     }
-    if (tpr == BLOCK) {
-      if (tid == 0) epilogue(r0, sum1[0], two ? sum2[0] : 0.0);
-    } else {
-      const int grp = tid / tpr, lane = tid % tpr, ngrp = BLOCK / tpr;
-#pragma unroll
-      for (int rr = 0; rr < ROWS_PER_THREAD; ++rr) {
-        const int r = r0 + grp + rr * ngrp;
-        if (lane == 0 && r < r1) epilogue(r, sum1[rr], two ? sum2[rr] : 0.0);
+    if (kkt) {
+      if (PASS == 0) {
+        const bool lf = isfinite((double)in.lo), uf = isfinite((double)in.hi);
+        const double cj = (double)in.cq;
+        const double lamv = proj_lambda(cj - s1, lf, uf);
+        accv[DT::K0] += cj * (double)in.u;
+        accv[DT::K1] += (lf ? (double)in.lo * fmax(lamv, 0.0) : 0.0) - (uf ? (double)in.hi * fmax(-lamv, 0.0) : 0.0);
+        const double rd = cj - s1 - lamv;
+        accv[DT::K2] += rd * rd;
+        if (eval) ((T*)dp->lam)[r] = (T)lamv;
+      } else {
+        const double kx = eval ? s1 : s2;  // (K x^k)_i
+        const double qi = (double)in.cq;
+        accv[DT::K0] += qi * (double)in.u;
+        double res = qi - kx;
+        if (in.ge && res < 0.0) res = 0.0;
+        accv[DT::K1] += res * res;
       }
     }
-  } else {
-    // ---- one part of a split row: partial sums, the last part finishes ----
+  };
+
+  // ---- reduction tree: the last child of a node adds the children in order.
+  // Every thread calls it; returns true in the block that completed the root.
+  auto climb = [&](int node) -> bool {
+    for (;;) {
+      const Node nd = a.nodes[node];
+      __syncthreads();
+      if (wv == 0) {
+        wait_stores();
+        if (tid == 0) s_flag = arrive(&a.ncnt[node], (unsigned)nd.count);
+      }
+      __syncthreads();
+      if (!s_flag) return false;
+      if (tid == 0) reset_counter(&a.ncnt[node]);
+      double sum = 0.0;
+      const int per = CHUNK_NNZ / DT::COUNT;  // records per round through LDS
+      for (int c0 = 0; c0 < nd.count; c0 += per) {
+        const int nrec = min(per, nd.count - c0);
+        const int nval = nrec * DT::COUNT;
+        __syncthreads();
+#pragma unroll 4
+        for (int i = tid; i < nval; i += BLOCK) {
+          const int c = i / DT::COUNT, q = i - c * DT::COUNT;
+          s_prod[i] = ld_coh(a.rec, (nd.first + c0 + c) * NDOT + q);
+        }
+        __syncthreads();
+        if (tid < DT::COUNT)
+          for (int c = 0; c < nrec; ++c) sum += s_prod[c * DT::COUNT + tid];
+      }
+      if (tid < DT::COUNT) st_agent(&a.rec[(size_t)(a.nleaves + node) * NDOT + tid], sum);
+      if (nd.parent < 0) return true;
+      node = nd.parent;
+    }
+  };
+
+  // ---- dual-pass root: finish the loop pass of this LP ----
+  auto finish_lp = [&]() {
+    const LaunchLP L = a.llp[bw.lp];
+    __syncthreads();
+    if (wv == 0) wait_stores();
+    if (tid < DT::COUNT) {
+      s_fin[0][tid] = ld_coh(a.rec, (a.nleaves + L.rootA) * NDOT + tid);
+      s_fin[1][tid] = ld_coh(a.rec, (a.nleaves + L.rootB) * NDOT + tid);
+    }
+    // the decisions run on an LDS copy of the LP's scalars
+    constexpr int SW = sizeof(Scalars) / 8;
+    unsigned long long* gsc = reinterpret_cast<unsigned long long*>(sc);
+    unsigned long long* lsc = reinterpret_cast<unsigned long long*>(&s_sc);
+    for (int q = tid; q < SW; q += BLOCK) lsc[q] = gsc[q];
+    __syncthreads();
+    if (tid == 0) final_step<MT>(*dp, &s_sc, s_fin[0], s_fin[1], eval, kkt, init, &s_work);
+    __syncthreads();
+    for (int q = tid; q < SW; q += BLOCK) gsc[q] = lsc[q];
+  };
+
+  if (bw.kind == 1) {
+    // ---- one part of a split row: partial sums; the last part finishes ----
+    const Chunk ch = a.chunks[bw.c0];
     const SplitRow sr = a.splits[ch.split];
     const int kb = ch.k0, ke = ch.k1, part = ch.tpr;
     double s1 = 0.0, s2 = 0.0;
-    for (int q = kb + tid; q < ke; q += BLOCK) {
-      const double v = (double)val[q];
-      const int c = idx[q];
-      s1 += v * (double)gv1[c];
-      if (two) s2 += v * (double)gv2[c];
+    for (int base = kb; base < ke; base += UNR * BLOCK) {
+      int ci[UNR];
+      T vv[UNR], g1[UNR], g2[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int q = base + tid + u * BLOCK;
+        ci[u] = 0;
+        vv[u] = (T)0;
+        if (q < ke) {
+          ci[u] = idx[q];
+          vv[u] = val[q];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const bool ok = base + tid + u * BLOCK < ke;
+        g1[u] = ok ? gv1[ci[u]] : (T)0;
+        g2[u] = (ok && two) ? gv2[ci[u]] : (T)0;
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        s1 += (double)vv[u] * (double)g1[u];
+        s2 += (double)vv[u] * (double)g2[u];
+      }
     }
     s1 = block_sum(s1, s_tmp);
     s2 = block_sum(s2, s_tmp);
     if (tid == 0) {
-      a.splitpart[2 * (sr.part0 + part) + 0] = s1;
-      a.splitpart[2 * (sr.part0 + part) + 1] = s2;
+      st_agent(&a.splitpart[2 * (sr.part0 + part) + 0], s1);
+      st_agent(&a.splitpart[2 * (sr.part0 + part) + 1], s2);
+      s_own = arrive(&a.splitcnt[ch.split], (unsigned)sr.nparts);
     }
-    __threadfence();
     __syncthreads();
-    if (tid == 0) s_flag = atomicAdd(&a.splitcnt[ch.split], 1u) == (unsigned)(sr.nparts - 1);
-    __syncthreads();
-    if (s_flag) {
-      __threadfence();
-      if (tid == 0) {
-        a.splitcnt[ch.split] = 0u;
-        double t1 = 0.0, t2 = 0.0;
-        for (int p = 0; p < sr.nparts; ++p) {
-          t1 += a.splitpart[2 * (sr.part0 + p) + 0];
-          t2 += a.splitpart[2 * (sr.part0 + p) + 1];
-        }
-        epilogue(sr.row, t1, t2);
-        split_owner = true;
+    if (!s_own) return;
+    if (tid == 0) {
+      reset_counter(&a.splitcnt[ch.split]);
+      RowIn<T, MT> in;
+      load_row(sr.row, in);
+      double t1 = 0.0, t2 = 0.0;
+      for (int p = 0; p < sr.nparts; ++p) {
+        t1 += ld_coh(a.splitpart, 2 * (sr.part0 + p) + 0);
+        t2 += ld_coh(a.splitpart, 2 * (sr.part0 + p) + 1);
+      }
+      for (int q = 0; q < DT::COUNT; ++q) s_racc[q] = 0.0;
+      finish_row(sr.row, in, t1, t2, s_racc);
+      double* rp = a.rec + (size_t)sr.leaf * NDOT;
+      for (int q = 0; q < DT::COUNT; ++q) st_agent(&rp[q], s_racc[q]);
+    }
+    if (climb(sr.parent) && PASS == 1) finish_lp();
+    return;
+  }
+
+  for (int c = bw.c0; c < bw.c1; ++c) {
+    // ---- multi-row chunk: stage products in LDS, reduce rows, epilogue ----
+    const Chunk ch = a.chunks[c];
+    const int r0 = ch.r0, r1 = ch.r1, kb = ch.k0, ke = ch.k1, tpr = ch.tpr;
+    const bool blockmode = tpr == BLOCK;
+    const int grp = blockmode ? 0 : tid / tpr;
+    const int lane_r = blockmode ? tid : tid % tpr;
+    const int r = r0 + grp;  // this thread group's row (at most one)
+    const bool has_row = r < r1 && (!blockmode || tid == 0);
+    int ci[UNR];
+    T vv[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int q = kb + tid + u * BLOCK;
+      ci[u] = 0;
+      vv[u] = (T)0;
+      if (q < ke) {
+        ci[u] = idx[q];
+        vv[u] = val[q];
       }
     }
-  }
-
-  // ---- chunk partial sums ----
-  const int lane = tid & 63, wv = tid >> 6;
-  double* cp = a.cpart + (size_t)blockIdx.x * NDOT;
-  if (ch.kind == 0) {
-#pragma unroll
-    for (int q = 0; q < DT::COUNT; ++q) {
-      const double v = wave_sum(acc[q]);
-      if (lane == 0) s_red[wv][q] = v;
+    int a0 = 0, a1 = 0;
+    RowIn<T, MT> rin;
+    if (r < r1) {
+      a0 = ptr[r] - kb;
+      a1 = ptr[r + 1] - kb;
+      if (has_row && lane_r == 0) load_row(r, rin);
     }
-    __syncthreads();
-    if (tid < DT::COUNT) cp[tid] = ((s_red[0][tid] + s_red[1][tid]) + s_red[2][tid]) + s_red[3][tid];
-  } else {
-    // a split row's sums live in its own record; the chunk contributes zeros
-    if (tid < DT::COUNT) cp[tid] = 0.0;
-    if (split_owner) {
-      double* sd = a.splitdots + (size_t)ch.split * NDOT;
+    double sum1 = 0.0, sum2 = 0.0;
+    const int nsweep = two ? 2 : 1;
+    for (int sw = 0; sw < nsweep; ++sw) {
+      const T* gv = sw == 0 ? gv1 : gv2;
+      T gg[UNR];
 #pragma unroll
-      for (int q = 0; q < DT::COUNT; ++q) sd[q] = acc[q];
+      for (int u = 0; u < UNR; ++u) gg[u] = (kb + tid + u * BLOCK < ke) ? gv[ci[u]] : (T)0;
+      __syncthreads();  // s_prod is free
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int q = tid + u * BLOCK;
+        if (kb + q < ke) s_prod[q] = (double)vv[u] * (double)gg[u];
+      }
+      __syncthreads();
+      double sres;
+      if (blockmode) {
+        double s = 0.0;
+        for (int q = a0 + tid; q < a1; q += BLOCK) s += s_prod[q];
+        sres = block_sum(s, s_tmp);
+      } else {
+        double s = 0.0;
+        for (int q = a0 + lane_r; q < a1; q += tpr) s += s_prod[q];
+        for (int off = 1; off < tpr; off <<= 1) s += __shfl_xor(s, off, 64);
+        sres = s;
+      }
+      if (sw == 0) sum1 = sres; else sum2 = sres;
     }
+    if (has_row && lane_r == 0) finish_row(r, rin, sum1, sum2, acc);
   }
-  __threadfence();
-  __syncthreads();
 
-  // ---- first level: the last chunk of a group adds the group's chunks in order ----
-  const Group grp = a.groups[ch.group];
-  if (tid == 0) s_flag = atomicAdd(&a.gcnt[ch.group], 1u) == (unsigned)(grp.count - 1);
-  __syncthreads();
-  if (!s_flag) return;
-  __threadfence();
-  if (tid < DT::COUNT) {
-    double s = 0.0;
-    for (int c = grp.first; c < grp.first + grp.count; ++c) s += a.cpart[(size_t)c * NDOT + tid];
-    a.gpart[(size_t)ch.group * NDOT + tid] = s;
-  }
-  if (tid == 0) a.gcnt[ch.group] = 0u;
-  if (PASS == 0) return;
-
-  // ---- second level (dual pass): the last group of an LP finishes the loop pass ----
-  __threadfence();
-  __syncthreads();
-  const LaunchLP L = a.llp[ch.lp];
-  if (tid == 0) s_flag = atomicAdd(&sc->lp_cnt, 1u) == (unsigned)(L.nB - 1);
-  __syncthreads();
-  if (!s_flag) return;
-  __threadfence();
-  if (tid < DT::COUNT) {
-    double sa = 0.0, sb = 0.0;
-    for (int g = L.gA0; g < L.gA0 + L.nA; ++g) sa += a.gpart[(size_t)g * NDOT + tid];
-    for (int s = L.sA0; s < L.sA0 + L.nsA; ++s) sa += a.splitdots[(size_t)s * NDOT + tid];
-    for (int g = L.gB0; g < L.gB0 + L.nB; ++g) sb += a.gpart[(size_t)g * NDOT + tid];
-    for (int s = L.sB0; s < L.sB0 + L.nsB; ++s) sb += a.splitdots[(size_t)s * NDOT + tid];
-    s_fin[0][tid] = sa;
-    s_fin[1][tid] = sb;
+  // ---- this workgroup's record, then up the tree ----
+#pragma unroll
+  for (int q = 0; q < DT::COUNT; ++q) {
+    const double v = wave_sum(acc[q]);
+    if (lane == 0) s_red[wv][q] = v;
   }
   __syncthreads();
-  if (tid == 0) {
-    sc->lp_cnt = 0u;
-    final_step<MT>(d, sc, s_fin[0], s_fin[1], eval, kkt, init, &s_work);
-  }
+  if (tid < DT::COUNT)
+    st_agent(&a.rec[(size_t)bw.leaf * NDOT + tid], ((s_red[0][tid] + s_red[1][tid]) + s_red[2][tid]) + s_red[3][tid]);
+  if (climb(bw.parent) && PASS == 1) finish_lp();
 }
 
 // ---------------------------------------------------------------------------
@@ -726,41 +825,44 @@ __global__ void k_convert(const S* src, D* dst, size_t len) {
 // ---------------------------------------------------------------------------
 
 template <typename T, int MT>
-static hipError_t launch_passes_mt(const LaunchTables& t, hipStream_t st, int mode) {
+static hipError_t launch_passes_mt(const LaunchTables& t, hipStream_t st, int mode, hipEvent_t* ev) {
   PassArgs pa{};
   pa.lps = t.lps;
   pa.llp = t.llp;
-  pa.groups = t.groups;
+  pa.chunks = t.chunks;
+  pa.nodes = t.nodes;
   pa.splits = t.splits;
-  pa.gcnt = t.gcnt;
+  pa.rec = t.rec;
+  pa.ncnt = t.ncnt;
   pa.splitpart = t.splitpart;
   pa.splitcnt = t.splitcnt;
-  pa.splitdots = t.splitdots;
+  pa.nleaves = t.nleaves;
   pa.mode = mode;
-  pa.chunks = t.chunksA;
-  pa.cpart = t.cpartA;
-  pa.gpart = t.gpart;
-  if (t.nchunksA > 0) hipLaunchKernelGGL((k_pass<T, MT, 0>), dim3(t.nchunksA), dim3(BLOCK), 0, st, pa);
-  pa.chunks = t.chunksB;
-  pa.cpart = t.cpartB;
-  if (t.nchunksB > 0) hipLaunchKernelGGL((k_pass<T, MT, 1>), dim3(t.nchunksB), dim3(BLOCK), 0, st, pa);
+  pa.blocks = t.blocksA;
+  if (ev) (void)hipEventRecord(ev[0], st);
+  if (t.nblocksA > 0) hipLaunchKernelGGL((k_pass<T, MT, 0>), dim3(t.nblocksA), dim3(BLOCK), 0, st, pa);
+  if (ev) (void)hipEventRecord(ev[1], st);
+  pa.blocks = t.blocksB;
+  if (t.nblocksB > 0) hipLaunchKernelGGL((k_pass<T, MT, 1>), dim3(t.nblocksB), dim3(BLOCK), 0, st, pa);
+  if (ev) (void)hipEventRecord(ev[2], st);
   if (mode == MODE_ITER && t.ntiles > 0) {
     MixArgs ma{t.lps, t.tiles};
     hipLaunchKernelGGL((k_mix<T>), dim3(t.ntiles), dim3(BLOCK), 0, st, ma);
   }
+  if (ev) (void)hipEventRecord(ev[3], st);
   return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t launch_passes_t(const LaunchTables& t, hipStream_t st, int mode) {
-  if (t.mt <= 4) return launch_passes_mt<T, 4>(t, st, mode);
-  if (t.mt <= 8) return launch_passes_mt<T, 8>(t, st, mode);
-  if (t.mt <= 10) return launch_passes_mt<T, 10>(t, st, mode);
-  return launch_passes_mt<T, 16>(t, st, mode);
+static hipError_t launch_passes_t(const LaunchTables& t, hipStream_t st, int mode, hipEvent_t* ev) {
+  if (t.mt <= 4) return launch_passes_mt<T, 4>(t, st, mode, ev);
+  if (t.mt <= 8) return launch_passes_mt<T, 8>(t, st, mode, ev);
+  if (t.mt <= 10) return launch_passes_mt<T, 10>(t, st, mode, ev);
+  return launch_passes_mt<T, 16>(t, st, mode, ev);
 }
 
-hipError_t launch_loop_pass(const LaunchTables& t, hipStream_t st, int mode) {
-  return t.fp64 ? launch_passes_t<double>(t, st, mode) : launch_passes_t<float>(t, st, mode);
+hipError_t launch_loop_pass(const LaunchTables& t, hipStream_t st, int mode, hipEvent_t* ev) {
+  return t.fp64 ? launch_passes_t<double>(t, st, mode, ev) : launch_passes_t<float>(t, st, mode, ev);
 }
 
 hipError_t launch_start_point(const LPDesc& d, bool fp64, hipStream_t st) {

@@ -44,13 +44,15 @@ struct LaunchSet {
   static constexpr int MAX_STATUS = 65536;
   std::vector<Problem*> members;
   LaunchTables t;
-  DevBuf d_lps, d_llp, d_chunksA, d_chunksB, d_groups, d_splits, d_cpartA, d_cpartB, d_gpart, d_gcnt,
-      d_splitpart, d_splitcnt, d_splitdots, d_tiles, d_status;
+  DevBuf d_lps, d_llp, d_chunks, d_blocksA, d_blocksB, d_nodes, d_splits, d_rec, d_ncnt, d_splitpart,
+      d_splitcnt, d_tiles, d_status;
   int* h_status = nullptr;  // pinned, 2 x MAX_STATUS
   int64_t last_epochs = 0;
   ~LaunchSet();
   void build(const std::vector<Problem*>& lps);
   void enqueue_passes(hipStream_t st, int64_t iters);
+  // enqueue passes with events around each launch; wait; mean ms of A, B, C
+  void timed_passes(hipStream_t st, int64_t iters, double* ms3);
   void enqueue_eval(hipStream_t st);
   double run_to_completion(hipStream_t st, int epoch, double time_limit_s);
   size_t device_bytes() const;
@@ -71,7 +73,6 @@ struct Problem {
   std::vector<uint8_t> rowtype;
   // work tables (LP-local indices)
   std::vector<Chunk> chunksA, chunksB;
-  std::vector<Group> groupsA, groupsB;
   std::vector<SplitRow> splitsA, splitsB;
   int npartsA = 0, npartsB = 0;
   std::vector<MixTile> tiles;
