@@ -1,0 +1,94 @@
+"""Batched and served solves on the GPU: every LP's result is the same alone,
+in a batch and in the serving mix (continuous batching)."""
+import time
+
+import numpy as np
+import pytest
+
+import lpgen
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2508_08062_amd")
+
+OPTS = dict(precision=0, memory=8, kkt_every=16, tol=1e-4, max_iter=4000, ruiz_iters=10, dhat_mode=0, epoch=32)
+
+
+def _lps(count, seed0):
+    rng = np.random.default_rng(seed0)
+    out = []
+    for i in range(count):
+        m = int(rng.integers(300, 3000))
+        out.append(lpgen.mip_like_lp(seed0 * 100 + i, m=m, n=2 * m, nnz=int(rng.integers(3, 8)) * 2 * m))
+    return out
+
+
+def _solo(lp):
+    s = P.Solver(lp, **OPTS)
+    s.solve()
+    r = s.result()
+    s.close()
+    return r
+
+
+def test_served_results_equal_solo_results():
+    lps = _lps(10, 7)
+    solo = [_solo(lp) for lp in lps]
+    srv = P.Server(hbm_budget_bytes=1 << 30, max_slots=4, **OPTS)
+    tickets = []
+    for i, lp in enumerate(lps):  # staggered arrivals: some join while others run
+        tickets.append(srv.submit(lp))
+        time.sleep(0.002 * (i % 3))
+    results = {}
+    t0 = time.time()
+    while len(results) < len(tickets):
+        assert time.time() - t0 < 90, srv.stats()
+        for t in tickets:
+            if t not in results:
+                r = srv.poll(t)
+                if r is not None:
+                    results[t] = r
+        time.sleep(0.001)
+    st = srv.stats()
+    srv.close()
+    assert st["submitted"] == st["admitted"] == st["finished"] == len(lps)
+    for t, ref in zip(tickets, solo):
+        r = results[t]
+        assert r["status"] == ref["status"] and r["iters"] == ref["iters"]
+        assert np.array_equal(r["x"], ref["x"]) and np.array_equal(r["y"], ref["y"])
+        assert r["t_done"] >= r["t_admit"] >= 0.0
+
+
+def test_server_budget_queues_and_rejects():
+    lps = _lps(3, 8)
+    est = 40 * 1024 * 1024
+    srv = P.Server(hbm_budget_bytes=est, max_slots=8, **OPTS)
+    big = lpgen.mip_like_lp(99, m=200000, n=400000, nnz=2000000)
+    tb = srv.submit(big)  # larger than the whole budget: rejected, not a crash
+    ts = [srv.submit(lp) for lp in lps]
+    done = {}
+    t0 = time.time()
+    while len(done) < len(ts):
+        assert time.time() - t0 < 60
+        for t in ts:
+            if t not in done:
+                r = srv.poll(t, want_solution=False)
+                if r is not None:
+                    done[t] = r
+    with pytest.raises(P.AAPDHGError) as e:
+        srv.poll(tb)
+    assert e.value.status == P.E_NOMEM
+    srv.close()
+
+
+def test_batch_of_uneven_lps_equals_solo():
+    lps = _lps(12, 9)
+    solo = [_solo(lp) for lp in lps]
+    members = [P.Solver(lp, **OPTS) for lp in lps]
+    b = P.Batch(members)
+    b.solve()
+    for g, ref in zip(members, solo):
+        r = g.result()
+        assert r["status"] == ref["status"] and r["iters"] == ref["iters"]
+        assert np.array_equal(r["x"], ref["x"])
+    b.close()
