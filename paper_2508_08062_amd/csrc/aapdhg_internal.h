@@ -16,18 +16,20 @@ constexpr int ROWS_PER_THREAD = CHUNK_ROWS / BLOCK;
 constexpr int SPLIT_NNZ = 8192;   // nnz per part of a split (very long) row
 constexpr int FAN = 48;           // children per node of the reduction tree
 constexpr int MIX_TILE = 2048;    // elements per block of the mix pass
-constexpr int NDOT = 2 * MAXM + 8;  // stride of one partial-sum record (doubles)
+constexpr int NDOT = 2 * MAXM + 16;  // stride of one partial-sum record (doubles)
 
 // Partial-sum record: MT = memory bound of the kernel instantiation.
 //   [0, MT)    <dg_new, dG[live t]>       [MT, 2MT)  <g, dG[live t]>
 //   2MT+0 <dg,dg>  2MT+1 <dg,g>  2MT+2 <g,g>  2MT+3 <du,du>
-//   2MT+4..2MT+6  KKT sums (pass A: c.x, l.lam+ - u.lam-, ||c-K^T y-lam||^2;
-//                           pass B: q.y, ||primal residual||^2, 0)
+//   2MT+4..2MT+6  KKT sums of the primal pass: c.x, l.lam+ - u.lam-, ||c-K^T y-lam||^2
+//   2MT+7..2MT+8  KKT sums of the dual pass: q.y, ||primal residual||^2
+// Both passes fill disjoint KKT slots, so the records of a loop pass are
+// simply added.
 template <int MT>
 struct Dot {
   static constexpr int G = 0, R = MT, DGDG = 2 * MT, DGG = 2 * MT + 1, GG = 2 * MT + 2,
-                       DU2 = 2 * MT + 3, K0 = 2 * MT + 4, K1 = 2 * MT + 5, K2 = 2 * MT + 6,
-                       COUNT = 2 * MT + 7;
+                       DU2 = 2 * MT + 3, KA0 = 2 * MT + 4, KA1 = 2 * MT + 5, KA2 = 2 * MT + 6,
+                       KB0 = 2 * MT + 7, KB1 = 2 * MT + 8, COUNT = 2 * MT + 9;
 };
 
 enum Status : int { ST_CONVERGED = 0, ST_ITER_LIMIT = 1, ST_TIME_LIMIT = 2, ST_NUMERICAL = 3, ST_RUNNING = 4 };
@@ -102,14 +104,18 @@ struct Chunk {
   int pad[4];
 };
 
-// Node of the per-LP reduction tree of a pass.  Its children are the records
-// [first, first + count) of the record array (chunk records first, then node
-// records); node i owns record (nleaves + i).
+// Node of the per-LP reduction tree.  Its children are records of the record
+// array (leaf records first, then node records); node i owns record
+// (nleaves + i).  Only dual-pass records arrive; each first-level node also
+// adds a slice of the primal pass's leaf records, written by the previous
+// launch.
 struct Node {
-  int first;
+  int first;   // children that arrive (records [first, first + count))
   int count;
   int parent;  // node index, -1 at the root
-  int pad;
+  int first2;  // records complete before the launch, added after the children
+  int count2;
+  int pad[3];
 };
 
 struct SplitRow {
@@ -133,10 +139,11 @@ struct BlockWork {
   int pad[2];
 };
 
-// Per-LP entry of a launch table: the roots of its two reduction trees.
+// Per-LP entry of a launch table: the root of its reduction tree (built over
+// the records of both passes; the dual pass climbs it).
 struct LaunchLP {
-  int rootA, rootB;  // node indices
-  int pad[2];
+  int root;
+  int pad[3];
 };
 
 struct MixTile {

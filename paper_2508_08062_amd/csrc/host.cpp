@@ -200,19 +200,26 @@ static void build_chunks(const std::vector<int>& ptr, int R, std::vector<Chunk>&
   }
 }
 
-// Reduction tree over `nleaf` consecutive leaf records starting at record
-// `leaf_base`: nodes of at most FAN children, appended to `nodes`; parent[i]
-// receives the node above leaf i.  Returns the root node.
-static int build_tree(int leaf_base, int nleaf, int nleaves_total, std::vector<Node>& nodes, std::vector<int>& parent) {
-  parent.assign(nleaf, -1);
+// Reduction tree of one LP: the nB dual-pass leaf records starting at record
+// leafB arrive; the nA primal-pass leaf records starting at record leafA are
+// complete before the dual pass starts and are spread over the first-level
+// nodes.  Nodes of at most FAN arriving children are appended to `nodes`;
+// parent[i] receives the node above dual leaf i.  Returns the root.
+static int build_tree(int leafB, int nB, int leafA, int nA, int nleaves_total, std::vector<Node>& nodes,
+                      std::vector<int>& parent) {
+  parent.assign(nB, -1);
   std::vector<int> level;
-  for (int c = 0; c < nleaf; c += FAN) {
+  const int nl1 = (nB + FAN - 1) / FAN;
+  for (int j = 0; j < nl1; ++j) {
     Node nd{};
-    nd.first = leaf_base + c;
-    nd.count = std::min(FAN, nleaf - c);
+    nd.first = leafB + j * FAN;
+    nd.count = std::min(FAN, nB - j * FAN);
     nd.parent = -1;
+    const int a0 = (int)((long long)j * nA / nl1), a1 = (int)((long long)(j + 1) * nA / nl1);
+    nd.first2 = leafA + a0;
+    nd.count2 = a1 - a0;
     const int id = (int)nodes.size();
-    for (int t = 0; t < nd.count; ++t) parent[c + t] = id;
+    for (int t = 0; t < nd.count; ++t) parent[j * FAN + t] = id;
     nodes.push_back(nd);
     level.push_back(id);
   }
@@ -628,22 +635,28 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
       tl.push_back(x);
     }
   }
-  // leaves and trees
+  // leaves and trees: primal leaves need no parent (the primal pass does not
+  // climb); the dual pass climbs one tree per LP over both passes' leaves
   for (int i = 0; i < count; ++i) {
-    for (int pass = 0; pass < 2; ++pass) {
-      PassInfo& pi = info[2 * i + pass];
-      auto& bw = pass == 0 ? bA : bB;
-      std::vector<int> parent;
-      const int root = build_tree(pi.leaf0, pi.nb + pi.ns, nleaves, nodes, parent);
-      for (int b = 0; b < pi.nb; ++b) {
-        bw[pi.b0 + b].leaf = pi.leaf0 + b;
-        bw[pi.b0 + b].parent = parent[b];
-      }
-      for (int q = 0; q < pi.ns; ++q) {
-        splits[pi.s0 + q].leaf = pi.leaf0 + pi.nb + q;
-        splits[pi.s0 + q].parent = parent[pi.nb + q];
-      }
-      if (pass == 0) llp[i].rootA = root; else llp[i].rootB = root;
+    PassInfo& pa = info[2 * i];
+    PassInfo& pb = info[2 * i + 1];
+    for (int b = 0; b < pa.nb; ++b) {
+      bA[pa.b0 + b].leaf = pa.leaf0 + b;
+      bA[pa.b0 + b].parent = -1;
+    }
+    for (int q = 0; q < pa.ns; ++q) {
+      splits[pa.s0 + q].leaf = pa.leaf0 + pa.nb + q;
+      splits[pa.s0 + q].parent = -1;
+    }
+    std::vector<int> parent;
+    llp[i].root = build_tree(pb.leaf0, pb.nb + pb.ns, pa.leaf0, pa.nb + pa.ns, nleaves, nodes, parent);
+    for (int b = 0; b < pb.nb; ++b) {
+      bB[pb.b0 + b].leaf = pb.leaf0 + b;
+      bB[pb.b0 + b].parent = parent[b];
+    }
+    for (int q = 0; q < pb.ns; ++q) {
+      splits[pb.s0 + q].leaf = pb.leaf0 + pb.nb + q;
+      splits[pb.s0 + q].parent = parent[pb.nb + q];
     }
   }
   t.mt = mt;

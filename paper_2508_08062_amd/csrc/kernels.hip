@@ -236,16 +236,16 @@ __device__ int faa_filter(const LPDesc& d, const Scalars* sc, int* live, int nl,
 }
 
 template <int MT>
-__device__ void final_step(const LPDesc& d, Scalars* sc, const double* fa, const double* fb,
-                           bool eval, bool kkt, bool init, SolveWork* w) {
+__device__ void final_step(const LPDesc& d, Scalars* sc, const double* f, bool eval, bool kkt, bool init,
+                           SolveWork* w) {
   using DT = Dot<MT>;
   if (kkt) {
     // Remark re:constrcution-termi-con: relative gap, primal and dual infeasibility
-    const double pobj = fa[DT::K0];
-    const double dobj = fb[DT::K0] + fa[DT::K1];
+    const double pobj = f[DT::KA0];
+    const double dobj = f[DT::KB0] + f[DT::KA1];
     const double rg = fabs(dobj - pobj) / (1.0 + fabs(dobj) + fabs(pobj));
-    const double rp = sqrt(fb[DT::K1]) / (1.0 + sc->qnorm);
-    const double rd = sqrt(fa[DT::K2]) / (1.0 + sc->cnorm);
+    const double rp = sqrt(f[DT::KB1]) / (1.0 + sc->qnorm);
+    const double rd = sqrt(f[DT::KA2]) / (1.0 + sc->cnorm);
     sc->pobj = pobj;
     sc->dobj = dobj;
     sc->r_g = rg;
@@ -255,7 +255,7 @@ __device__ void final_step(const LPDesc& d, Scalars* sc, const double* fa, const
     sc->kkt_k = sc->k;
   }
   if (eval) return;
-  const double gnorm = sqrt(fa[DT::GG] + fb[DT::GG]);
+  const double gnorm = sqrt(f[DT::GG]);
   const long long k = sc->k;
   sc->gnorm = gnorm;
   if (init) {  // Alg 2 set-up: g^0 = u^1 - u^0
@@ -295,15 +295,15 @@ __device__ void final_step(const LPDesc& d, Scalars* sc, const double* fa, const
   for (int t = 0; t < nl_old; ++t) {
     const int slot = sc->live[t];
     if (slot == s) continue;  // the oldest column is replaced
-    const double gv = fa[DT::G + t] + fb[DT::G + t];
+    const double gv = f[DT::G + t];
     sc->G[s * MAXM + slot] = gv;
     sc->G[slot * MAXM + s] = gv;
-    sc->rhs[slot] = fa[DT::R + t] + fb[DT::R + t];
+    sc->rhs[slot] = f[DT::R + t];
     live[nl++] = slot;
   }
-  sc->G[s * MAXM + s] = fa[DT::DGDG] + fb[DT::DGDG];
-  sc->rhs[s] = fa[DT::DGG] + fb[DT::DGG];
-  sc->du2[s] = fa[DT::DU2] + fb[DT::DU2];
+  sc->G[s * MAXM + s] = f[DT::DGDG];
+  sc->rhs[s] = f[DT::DGG];
+  sc->du2[s] = f[DT::DU2];
   live[nl++] = s;
 
   bool aa = false;
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
   constexpr int RPT = ROWS_PER_THREAD;    // rows per thread in a multi-row chunk
   __shared__ double s_prod[CHUNK_NNZ];
   __shared__ double s_red[BLOCK / 64][NDOT];
-  __shared__ double s_fin[2][NDOT];
+  __shared__ double s_fin[NDOT];
   __shared__ double s_racc[NDOT];  // dot sums of one split row
   __shared__ double s_tmp[4];
   __shared__ int s_live[MAXM];
@@ -504,18 +504,18 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
         const bool lf = isfinite((double)in.lo), uf = isfinite((double)in.hi);
         const double cj = (double)in.cq;
         const double lamv = proj_lambda(cj - s1, lf, uf);
-        accv[DT::K0] += cj * (double)in.u;
-        accv[DT::K1] += (lf ? (double)in.lo * fmax(lamv, 0.0) : 0.0) - (uf ? (double)in.hi * fmax(-lamv, 0.0) : 0.0);
+        accv[DT::KA0] += cj * (double)in.u;
+        accv[DT::KA1] += (lf ? (double)in.lo * fmax(lamv, 0.0) : 0.0) - (uf ? (double)in.hi * fmax(-lamv, 0.0) : 0.0);
         const double rd = cj - s1 - lamv;
-        accv[DT::K2] += rd * rd;
+        accv[DT::KA2] += rd * rd;
         if (eval) ((T*)dp->lam)[r] = (T)lamv;
       } else {
         const double kx = eval ? s1 : s2;  // (K x^k)_i
         const double qi = (double)in.cq;
-        accv[DT::K0] += qi * (double)in.u;
+        accv[DT::KB0] += qi * (double)in.u;
         double res = qi - kx;
         if (in.ge && res < 0.0) res = 0.0;
-        accv[DT::K1] += res * res;
+        accv[DT::KB1] += res * res;
       }
     }
   };
@@ -535,14 +535,16 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
       if (tid == 0) reset_counter(&a.ncnt[node]);
       double sum = 0.0;
       const int per = CHUNK_NNZ / DT::COUNT;  // records per round through LDS
-      for (int c0 = 0; c0 < nd.count; c0 += per) {
-        const int nrec = min(per, nd.count - c0);
+      const int total = nd.count + nd.count2;
+      for (int c0 = 0; c0 < total; c0 += per) {
+        const int nrec = min(per, total - c0);
         const int nval = nrec * DT::COUNT;
         __syncthreads();
 #pragma unroll 4
         for (int i = tid; i < nval; i += BLOCK) {
-          const int c = i / DT::COUNT, q = i - c * DT::COUNT;
-          s_prod[i] = ld_coh(a.rec, (nd.first + c0 + c) * NDOT + q);
+          const int c = c0 + i / DT::COUNT, q = i % DT::COUNT;
+          const int rix = c < nd.count ? nd.first + c : nd.first2 + (c - nd.count);
+          s_prod[i] = ld_coh(a.rec, rix * NDOT + q);
         }
         __syncthreads();
         if (tid < DT::COUNT)
@@ -559,17 +561,14 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
     const LaunchLP L = a.llp[bw.lp];
     __syncthreads();
     if (wv == 0) wait_stores();
-    if (tid < DT::COUNT) {
-      s_fin[0][tid] = ld_coh(a.rec, (a.nleaves + L.rootA) * NDOT + tid);
-      s_fin[1][tid] = ld_coh(a.rec, (a.nleaves + L.rootB) * NDOT + tid);
-    }
+    if (tid < DT::COUNT) s_fin[tid] = ld_coh(a.rec, (a.nleaves + L.root) * NDOT + tid);
     // the decisions run on an LDS copy of the LP's scalars
     constexpr int SW = sizeof(Scalars) / 8;
     unsigned long long* gsc = reinterpret_cast<unsigned long long*>(sc);
     unsigned long long* lsc = reinterpret_cast<unsigned long long*>(&s_sc);
     for (int q = tid; q < SW; q += BLOCK) lsc[q] = gsc[q];
     __syncthreads();
-    if (tid == 0) final_step<MT>(*dp, &s_sc, s_fin[0], s_fin[1], eval, kkt, init, &s_work);
+    if (tid == 0) final_step<MT>(*dp, &s_sc, s_fin, eval, kkt, init, &s_work);
     __syncthreads();
     for (int q = tid; q < SW; q += BLOCK) gsc[q] = lsc[q];
   };
@@ -628,7 +627,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
       double* rp = a.rec + (size_t)sr.leaf * NDOT;
       for (int q = 0; q < DT::COUNT; ++q) st_agent(&rp[q], s_racc[q]);
     }
-    if (climb(sr.parent) && PASS == 1) finish_lp();
+    if (PASS == 1 && climb(sr.parent)) finish_lp();
     return;
   }
 
@@ -690,16 +689,24 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
     if (has_row && lane_r == 0) finish_row(r, rin, sum1, sum2, acc);
   }
 
-  // ---- this workgroup's record, then up the tree ----
+  // ---- this workgroup's record, then (dual pass) up the tree ----
+  // every butterfly step reduces all accumulators together
 #pragma unroll
-  for (int q = 0; q < DT::COUNT; ++q) {
-    const double v = wave_sum(acc[q]);
-    if (lane == 0) s_red[wv][q] = v;
+  for (int off = 32; off > 0; off >>= 1) {
+    double sh[DT::COUNT];
+#pragma unroll
+    for (int q = 0; q < DT::COUNT; ++q) sh[q] = __shfl_xor(acc[q], off, 64);
+#pragma unroll
+    for (int q = 0; q < DT::COUNT; ++q) acc[q] += sh[q];
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < DT::COUNT; ++q) s_red[wv][q] = acc[q];
   }
   __syncthreads();
   if (tid < DT::COUNT)
     st_agent(&a.rec[(size_t)bw.leaf * NDOT + tid], ((s_red[0][tid] + s_red[1][tid]) + s_red[2][tid]) + s_red[3][tid]);
-  if (climb(bw.parent) && PASS == 1) finish_lp();
+  if (PASS == 1 && climb(bw.parent)) finish_lp();
 }
 
 // ---------------------------------------------------------------------------
