@@ -123,6 +123,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the solve-to-tolerance leg")
+    ap.add_argument("--chunks-per-block", type=int, default=0, help="workgroup size in chunks (0 = automatic)")
     ap.add_argument("--profile-run", action="store_true",
                     help="only the timed loop passes (for rocprofv3 runs)")
     args = ap.parse_args()
@@ -137,6 +138,8 @@ def main():
     import paper_2508_08062_amd as P
 
     lps, opts, cfg = _workload(args.workload)
+    if args.chunks_per_block:
+        opts["chunks_per_block"] = args.chunks_per_block
     torch.cuda.init()
     stream = torch.cuda.Stream()
     solvers = [P.Solver(lp, tol=0.0, max_iter=10 ** 9, **opts) for lp in lps]

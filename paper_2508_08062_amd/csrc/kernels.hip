@@ -33,10 +33,28 @@ namespace aapdhg {
 // small helpers
 // ---------------------------------------------------------------------------
 
+// One DPP data-movement step on the two 32-bit halves of a double (VALU only).
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), CTRL, ROWMASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), CTRL, ROWMASK, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave, returned to every lane.  A fixed sequence
+// of DPP steps: pairs, quads, half rows and rows (all lanes of a 16-lane row
+// then hold the row sum), then row 0 into row 1, row 2 into row 3, rows 0-1
+// into rows 2-3; lane 63 ends with the total.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += dpp_mov<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+  v += dpp_mov<0x141, 0xF>(v);  // row_half_mirror
+  v += dpp_mov<0x140, 0xF>(v);  // row_mirror
+  v += dpp_mov<0x142, 0xA>(v);  // row_bcast:15
+  v += dpp_mov<0x143, 0xC>(v);  // row_bcast:31
+  const int lo = __builtin_amdgcn_readlane((int)__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane((int)__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 
 // Block-wide sum of one value per thread; the result is valid in thread 0.
@@ -99,146 +117,186 @@ __device__ __forceinline__ double proj_lambda(double lam, bool lf, bool uf) {
 // decisions of a loop pass (one thread of the last block of an LP)
 // ---------------------------------------------------------------------------
 
-// Cholesky of the n x n matrix A (row-major, stride MAXM), in place (lower).
-// Returns false on a non-positive or non-finite pivot.
-__device__ bool chol(double* A, int n) {
-  for (int j = 0; j < n; ++j) {
-    double s = A[j * MAXM + j];
-    for (int p = 0; p < j; ++p) s -= A[j * MAXM + p] * A[j * MAXM + p];
-    if (!(s > 0.0) || !isfinite(s)) return false;
-    const double r = sqrt(s);
-    A[j * MAXM + j] = r;
-    for (int i = j + 1; i < n; ++i) {
-      double t = A[i * MAXM + j];
-      for (int p = 0; p < j; ++p) t -= A[i * MAXM + p] * A[j * MAXM + p];
-      A[i * MAXM + j] = t / r;
-    }
-  }
-  return true;
+// The decisions of a loop pass run on the 64 lanes of one wave, on LDS data.
+// Values read from LDS by every lane are uniform; lane 0 writes scalars.  LDS
+// instructions of one wave complete in order, so a value written by one lane
+// is seen by every lane's later read.
+
+// Orders one wave's LDS writes before its later reads by other lanes: LDS
+// instructions of a wave complete in order; this keeps the compiler from
+// moving or caching accesses across the point.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
 }
 
-// Solve L L^T x = b with the factor from chol (b overwritten by x).
-__device__ void chol_solve(const double* L, double* b, int n) {
-  for (int i = 0; i < n; ++i) {
-    double s = b[i];
-    for (int p = 0; p < i; ++p) s -= L[i * MAXM + p] * b[p];
-    b[i] = s / L[i * MAXM + i];
-  }
-  for (int i = n - 1; i >= 0; --i) {
-    double s = b[i];
-    for (int p = i + 1; p < n; ++p) s -= L[p * MAXM + i] * b[p];
-    b[i] = s / L[i * MAXM + i];
-  }
-}
-
-// LDS workspace of the decisions (used by one thread of the finishing block).
+// LDS workspace of the decisions.
 struct SolveWork {
   double A[MAXM * MAXM];
-  double R[MAXM * MAXM];
   double gam[MAXM];
-  double fn[MAXM], rii[MAXM], b[MAXM], e2[MAXM];
+  double fn[MAXM], gdiag[MAXM], b[MAXM], e2[MAXM];
   int live[MAXM], ord[MAXM], keep[MAXM];
+  int nl, nk, kk, pad;
   bool dep[MAXM];
 };
 
-// gamma for the history columns `slots` (oldest first): (G + shift I) gamma = rhs.
-__device__ bool solve_gamma(const Scalars* sc, const int* slots, int n, double shift, double* gamma, double* A) {
-  for (int a = 0; a < n; ++a) {
-    for (int b = 0; b <= a; ++b) A[a * MAXM + b] = sc->G[slots[a] * MAXM + slots[b]];
-    A[a * MAXM + a] += shift;
-    gamma[a] = sc->rhs[slots[a]];
+// Cholesky A = L L^T of the n x n matrix in A (row-major, stride MAXM, lower
+// part), right-looking: step j scales column j and updates the trailing
+// triangle, so every entry receives its updates in the order of a
+// column-by-column factorisation.  With gdiag != nullptr a pivot that is not
+// above 1e-28 gdiag[j] marks column j dependent (zero column, dep[j] = true)
+// and the factorisation continues; without it such a pivot fails.
+__device__ bool wave_chol(double* A, int n, int lane, const double* gdiag, bool* dep) {
+  for (int j = 0; j < n; ++j) {
+    const double piv = A[j * MAXM + j];
+    bool isdep = false;
+    if (gdiag) {
+      isdep = !(piv > 1e-28 * gdiag[j]) || !isfinite(piv);
+    } else if (!(piv > 0.0) || !isfinite(piv)) {
+      return false;
+    }
+    const double r = isdep ? 0.0 : sqrt(piv);
+    wave_sync();
+    if (lane == 0) {
+      A[j * MAXM + j] = r;
+      if (gdiag) dep[j] = isdep;
+    }
+    for (int i = j + 1 + lane; i < n; i += 64) A[i * MAXM + j] = isdep ? 0.0 : A[i * MAXM + j] / r;
+    wave_sync();
+    const int mm = n - j - 1;
+    const int np = mm * (mm + 1) / 2;
+    for (int p = lane; p < np; p += 64) {
+      int a = (int)((sqrtf(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
+      while ((a + 1) * (a + 2) / 2 <= p) ++a;
+      while (a * (a + 1) / 2 > p) --a;
+      const int b = p - a * (a + 1) / 2;
+      const int i = j + 1 + a, k = j + 1 + b;
+      A[i * MAXM + k] -= A[i * MAXM + j] * A[k * MAXM + j];
+    }
+    wave_sync();
   }
-  if (!chol(A, n)) return false;
-  chol_solve(A, gamma, n);
-  for (int a = 0; a < n; ++a)
-    if (!isfinite(gamma[a])) return false;
   return true;
 }
 
+// Solve L L^T x = b with the factor from wave_chol (b overwritten by x).
+__device__ void wave_chol_solve(const double* L, double* b, int n, int lane) {
+  for (int i = 0; i < n; ++i) {
+    const double bi = b[i] / L[i * MAXM + i];
+    wave_sync();
+    if (lane == 0) b[i] = bi;
+    for (int k = i + 1 + lane; k < n; k += 64) b[k] -= L[k * MAXM + i] * bi;
+    wave_sync();
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    const double bi = b[i] / L[i * MAXM + i];
+    wave_sync();
+    if (lane == 0) b[i] = bi;
+    for (int k = lane; k < i; k += 64) b[k] -= L[i * MAXM + k] * bi;
+    wave_sync();
+  }
+}
+
+// gamma for the history columns `slots` (oldest first): (G + shift I) gamma = rhs.
+__device__ bool solve_gamma(const Scalars* sc, const int* slots, int n, double shift, SolveWork* w, int lane) {
+  for (int q = lane; q < n * n; q += 64) {
+    const int a = q / n, b = q - a * n;
+    if (b <= a) w->A[a * MAXM + b] = sc->G[slots[a] * MAXM + slots[b]] + (a == b ? shift : 0.0);
+  }
+  if (lane < n) w->gam[lane] = sc->rhs[slots[lane]];
+  wave_sync();
+  if (!wave_chol(w->A, n, lane, nullptr, nullptr)) return false;
+  wave_chol_solve(w->A, w->gam, n, lane);
+  bool ok = true;
+  for (int a = 0; a < n; ++a) ok &= isfinite(w->gam[a]);
+  return ok;
+}
+
 // FAA filters (Alg 3 lines Reverse..Reverse; Alg 4 AngleFilter, Alg 5
-// LengthFilter with the bounds of Lemma le:RK-1bound1).  `live` holds nl slots
-// oldest first; on return it holds the survivors, oldest first.  The R factor
-// of the reversed history is taken from the Gram (R^T R = F^T F): r_ii^2 is
-// the squared distance of column i from the span of the newer columns.
-__device__ int faa_filter(const LPDesc& d, const Scalars* sc, int* live, int nl, SolveWork* w) {
+// LengthFilter with the bounds of Lemma le:RK-1bound1).  w->live holds nl
+// slots oldest first; on return it holds the survivors, oldest first, and the
+// count is returned.  The R factor of the reversed history comes from the
+// Gram (R^T R = F^T F): r_ii^2 is the squared distance of column i from the
+// span of the newer columns.
+__device__ int faa_filter(const LPDesc& d, const Scalars* sc, int nl, SolveWork* w, int lane) {
   int* ord = w->ord;  // newest first (Reverse)
-  for (int t = 0; t < nl; ++t) ord[t] = live[nl - 1 - t];
-  double* R = w->R;
-  bool* dep = w->dep;
-  double* fn = w->fn;
-  double* rii = w->rii;
-  for (int i = 0; i < nl; ++i) {
-    const double gii = sc->G[ord[i] * MAXM + ord[i]];
-    fn[i] = sqrt(gii > 0.0 ? gii : 0.0);
-    double s = gii;
-    for (int j = 0; j < i; ++j) {
-      if (dep[j]) { R[j * MAXM + i] = 0.0; continue; }
-      double t = sc->G[ord[j] * MAXM + ord[i]];
-      for (int p = 0; p < j; ++p)
-        if (!dep[p]) t -= R[p * MAXM + j] * R[p * MAXM + i];
-      t /= R[j * MAXM + j];
-      R[j * MAXM + i] = t;
-      s -= t * t;
-    }
-    if (!(s > 1e-28 * gii) || !isfinite(s)) {
-      dep[i] = true;
-      rii[i] = 0.0;
-      R[i * MAXM + i] = 0.0;
-    } else {
-      dep[i] = false;
-      rii[i] = sqrt(s);
-      R[i * MAXM + i] = rii[i];
+  if (lane < nl) {
+    ord[lane] = w->live[nl - 1 - lane];
+  }
+  for (int q = lane; q < nl * nl; q += 64) {
+    const int a = q / nl, b = q - a * nl;
+    const int oa = w->live[nl - 1 - a], ob = w->live[nl - 1 - b];
+    if (b <= a) w->A[a * MAXM + b] = sc->G[oa * MAXM + ob];
+    if (a == b) {
+      w->gdiag[a] = sc->G[oa * MAXM + oa];
+      w->fn[a] = sqrt(w->gdiag[a] > 0.0 ? w->gdiag[a] : 0.0);
     }
   }
+  wave_sync();
+  wave_chol(w->A, nl, lane, w->gdiag, w->dep);
   // AngleFilter: the newest column is always kept; column i >= 2 is removed
-  // when |r_ii| / ||f_i|| < c_s (a zero column has no angle and is removed).
-  int* keep = w->keep;
-  int nk = 0;
-  keep[nk++] = 0;
-  for (int i = 1; i < nl; ++i)
-    if (fn[i] > 0.0 && rii[i] / fn[i] >= d.cs) keep[nk++] = i;
-  // LengthFilter on the kept columns (newest first, 1-based j in the lemma).
+  // when |r_ii| / ||f_i|| < c_s (a zero or dependent column is removed).
+  bool keepme = false;
+  if (lane < nl) {
+    const double rii = w->dep[lane] ? 0.0 : w->A[lane * MAXM + lane];
+    keepme = lane == 0 || (w->fn[lane] > 0.0 && rii / w->fn[lane] >= d.cs);
+  }
+  const unsigned long long bal = __ballot(keepme);
+  const int nk = __popcll(bal);
+  if (keepme) w->keep[__popcll(bal & ((1ull << lane) - 1ull))] = lane;
+  wave_sync();
+  // LengthFilter on the kept columns (newest first, 1-based j in the lemma)
   const double cs = d.cs, ct = sqrt(1.0 - cs * cs);
-  double* b = w->b;
-  double* e2 = w->e2;
-  for (int jj = 0; jj < nk; ++jj) {
-    const int slot = ord[keep[jj]];
-    e2[jj] = sc->du2[slot];
-    const double fj2 = fn[keep[jj]] * fn[keep[jj]];
+  if (lane < nk) {
+    const int jj = lane;
+    w->e2[jj] = sc->du2[ord[w->keep[jj]]];
+    const double fj2 = w->fn[w->keep[jj]] * w->fn[w->keep[jj]];
     if (jj == 0) {
-      b[jj] = 1.0 / fj2;
-      continue;
+      w->b[jj] = 1.0 / fj2;
+    } else {
+      const int j = jj + 1;
+      const double f12 = w->fn[w->keep[0]] * w->fn[w->keep[0]];
+      double tot = ct * ct * pow(ct + cs, 2.0 * (j - 2)) / (f12 * pow(cs, 2.0 * (j - 2)));
+      for (int i = 2; i <= j - 1; ++i) {
+        const double fi2 = w->fn[w->keep[i - 1]] * w->fn[w->keep[i - 1]];
+        tot += ct * ct * pow(ct + cs, 2.0 * (j - i - 1)) / (fi2 * pow(cs, 2.0 * (j - i)));
+      }
+      tot += 1.0 / fj2;
+      w->b[jj] = tot / (cs * cs);
     }
-    const int j = jj + 1;
-    const double f12 = fn[keep[0]] * fn[keep[0]];
-    double tot = ct * ct * pow(ct + cs, 2.0 * (j - 2)) / (f12 * pow(cs, 2.0 * (j - 2)));
-    for (int i = 2; i <= j - 1; ++i) {
-      const double fi2 = fn[keep[i - 1]] * fn[keep[i - 1]];
-      tot += ct * ct * pow(ct + cs, 2.0 * (j - i - 1)) / (fi2 * pow(cs, 2.0 * (j - i)));
-    }
-    tot += 1.0 / fj2;
-    b[jj] = tot / (cs * cs);
   }
-  int kk = nk;
-  const double kb2 = d.kappa_bar * d.kappa_bar;
-  while (kk >= 1) {
-    double se = 0.0, sb = 0.0;
-    for (int j = 0; j < kk; ++j) {
-      se += e2[j];
-      sb += b[j];
+  wave_sync();
+  if (lane == 0) {
+    int kk = nk;
+    const double kb2 = d.kappa_bar * d.kappa_bar;
+    while (kk >= 1) {
+      double se = 0.0, sb = 0.0;
+      for (int j = 0; j < kk; ++j) {
+        se += w->e2[j];
+        sb += w->b[j];
+      }
+      if (se * sb <= kb2) break;
+      --kk;
     }
-    if (se * sb <= kb2) break;
-    --kk;
+    w->kk = kk;
   }
+  wave_sync();
+  const int kk = w->kk;
   // survivors: first kk kept columns (newest first) -> oldest first
-  for (int t = 0; t < kk; ++t) live[t] = ord[keep[kk - 1 - t]];
+  if (lane < kk) w->live[lane] = ord[w->keep[kk - 1 - lane]];
+  wave_sync();
   return kk;
 }
 
+// Decisions of loop pass k, on the summed records f: KKT test, memory update,
+// safeguard, Anderson coefficients (Alg 2) or filters (Alg 3).  Every lane of
+// one wave calls it; sc points at an LDS copy of the LP's scalars.
 template <int MT>
 __device__ void final_step(const LPDesc& d, Scalars* sc, const double* f, bool eval, bool kkt, bool init,
-                           SolveWork* w) {
+                           SolveWork* w, int lane) {
   using DT = Dot<MT>;
+  const bool L0 = lane == 0;
+  double kktv = 0.0;
   if (kkt) {
     // Remark re:constrcution-termi-con: relative gap, primal and dual infeasibility
     const double pobj = f[DT::KA0];
@@ -246,121 +304,126 @@ __device__ void final_step(const LPDesc& d, Scalars* sc, const double* f, bool e
     const double rg = fabs(dobj - pobj) / (1.0 + fabs(dobj) + fabs(pobj));
     const double rp = sqrt(f[DT::KB1]) / (1.0 + sc->qnorm);
     const double rd = sqrt(f[DT::KA2]) / (1.0 + sc->cnorm);
-    sc->pobj = pobj;
-    sc->dobj = dobj;
-    sc->r_g = rg;
-    sc->r_p = rp;
-    sc->r_d = rd;
-    sc->kkt = fmax(rg, fmax(rp, rd));
-    sc->kkt_k = sc->k;
+    kktv = fmax(rg, fmax(rp, rd));
+    if (L0) {
+      sc->pobj = pobj;
+      sc->dobj = dobj;
+      sc->r_g = rg;
+      sc->r_p = rp;
+      sc->r_d = rd;
+      sc->kkt = kktv;
+      sc->kkt_k = sc->k;
+    }
   }
   if (eval) return;
   const double gnorm = sqrt(f[DT::GG]);
   const long long k = sc->k;
-  sc->gnorm = gnorm;
+  const double n0 = sc->n0;
+  const long long i_aa = sc->i_aa;
+  if (L0) sc->gnorm = gnorm;
   if (init) {  // Alg 2 set-up: g^0 = u^1 - u^0
-    sc->n0 = gnorm;
-    if (!isfinite(gnorm)) {
-      sc->status = ST_NUMERICAL;
-      sc->branch = BR_NONE;
-    } else if (gnorm == 0.0) {
-      sc->status = ST_CONVERGED;  // u^0 is a fixed point
-      sc->branch = BR_NONE;
-    } else {
-      sc->branch = BR_PDHG;
-      sc->k = 1;
+    if (L0) {
+      sc->n0 = gnorm;
+      if (!isfinite(gnorm)) {
+        sc->status = ST_NUMERICAL;
+        sc->branch = BR_NONE;
+      } else if (gnorm == 0.0) {
+        sc->status = ST_CONVERGED;  // u^0 is a fixed point
+        sc->branch = BR_NONE;
+      } else {
+        sc->branch = BR_PDHG;
+        sc->k = 1;
+      }
     }
     return;
   }
-  if (k > d.max_iter) {
-    sc->status = ST_ITER_LIMIT;
-    sc->branch = BR_NONE;
-    return;
-  }
-  if (kkt && sc->kkt <= d.tol) {
-    sc->status = ST_CONVERGED;
-    sc->branch = BR_NONE;
-    return;
-  }
-  if (!isfinite(gnorm)) {
-    sc->status = ST_NUMERICAL;
-    sc->branch = BR_NONE;
+  if (k > d.max_iter || (kkt && kktv <= d.tol) || !isfinite(gnorm)) {
+    if (L0) {
+      sc->status = k > d.max_iter ? ST_ITER_LIMIT : (kkt && kktv <= d.tol) ? ST_CONVERGED : ST_NUMERICAL;
+      sc->branch = BR_NONE;
+    }
     return;
   }
   // memory update (both branches): the pair written this pass goes to newslot
   const int s = sc->newslot;
   const int nl_old = sc->nlive;
-  int* live = w->live;
-  int nl = 0;
-  for (int t = 0; t < nl_old; ++t) {
-    const int slot = sc->live[t];
-    if (slot == s) continue;  // the oldest column is replaced
-    const double gv = f[DT::G + t];
-    sc->G[s * MAXM + slot] = gv;
-    sc->G[slot * MAXM + s] = gv;
-    sc->rhs[slot] = f[DT::R + t];
-    live[nl++] = slot;
+  wave_sync();
+  if (lane < nl_old) {
+    const int slot = sc->live[lane];
+    if (slot != s) {  // the oldest column is replaced
+      const double gv = f[DT::G + lane];
+      sc->G[s * MAXM + slot] = gv;
+      sc->G[slot * MAXM + s] = gv;
+      sc->rhs[slot] = f[DT::R + lane];
+    }
   }
-  sc->G[s * MAXM + s] = f[DT::DGDG];
-  sc->rhs[s] = f[DT::DGG];
-  sc->du2[s] = f[DT::DU2];
-  live[nl++] = s;
+  if (L0) {
+    int nl = 0;
+    for (int t = 0; t < nl_old; ++t)
+      if (sc->live[t] != s) w->live[nl++] = sc->live[t];
+    w->live[nl++] = s;
+    w->nl = nl;
+    sc->G[s * MAXM + s] = f[DT::DGDG];
+    sc->rhs[s] = f[DT::DGG];
+    sc->du2[s] = f[DT::DU2];
+  }
+  wave_sync();
+  int nl = w->nl;
 
   bool aa = false;
   int nmix = 0;
   if (d.variant != V_PDHG) {
     // safeguard (Alg 2): ||g^k|| <= D ||g^0|| (i^k + 1)^{-(1+eps)}; ties accelerate
-    const double thr = d.D * sc->n0 * pow((double)(sc->i_aa + 1), -(1.0 + d.eps_sg));
+    const double thr = d.D * n0 * pow((double)(i_aa + 1), -(1.0 + d.eps_sg));
     if (gnorm <= thr) {
-      double* gam = w->gam;
       if (d.variant == V_AA) {
-        if (solve_gamma(sc, live, nl, d.eta, gam, w->A)) {
+        if (solve_gamma(sc, w->live, nl, d.eta, w, lane)) {
           aa = true;
           nmix = nl;
-          for (int t = 0; t < nl; ++t) {
-            sc->mixslot[t] = live[t];
-            sc->gamma[t] = gam[t];
-          }
         }
       } else {
-        nl = faa_filter(d, sc, live, nl, w);  // the survivors become the memory
+        nl = faa_filter(d, sc, nl, w, lane);  // the survivors become the memory
         if (nl == 0) {
           aa = true;  // no history left: u_AA = u^k + beta D-hat g^k
-        } else if (solve_gamma(sc, live, nl, 0.0, gam, w->A)) {
+        } else if (solve_gamma(sc, w->live, nl, 0.0, w, lane)) {
           aa = true;
           nmix = nl;
-          for (int t = 0; t < nl; ++t) {
-            sc->mixslot[t] = live[t];
-            sc->gamma[t] = gam[t];
-          }
         }
       }
     }
   }
-  sc->nmix = nmix;
-  if (aa) {
-    sc->branch = BR_AA;
-    sc->i_aa += 1;
-  } else {
-    sc->branch = BR_PDHG;
-    sc->j_pdhg += 1;
+  wave_sync();
+  if (lane < nmix) {
+    sc->mixslot[lane] = w->live[lane];
+    sc->gamma[lane] = w->gam[lane];
   }
-  for (int t = 0; t < nl; ++t) sc->live[t] = live[t];
-  sc->nlive = nl;
-  // slot for the next difference pair: a free one, else the oldest
-  int ns = live[0];
-  if (nl < d.M) {
-    for (int cand = 0; cand < d.M; ++cand) {
-      bool used = false;
-      for (int t = 0; t < nl; ++t) used |= (live[t] == cand);
-      if (!used) {
-        ns = cand;
-        break;
+  if (lane < nl) sc->live[lane] = w->live[lane];
+  wave_sync();
+  if (L0) {
+    sc->nmix = nmix;
+    if (aa) {
+      sc->branch = BR_AA;
+      sc->i_aa = i_aa + 1;
+    } else {
+      sc->branch = BR_PDHG;
+      sc->j_pdhg += 1;
+    }
+    sc->nlive = nl;
+    // slot for the next difference pair: a free one, else the oldest
+    int ns = w->live[0];
+    if (nl < d.M) {
+      for (int cand = 0; cand < d.M; ++cand) {
+        bool used = false;
+        for (int t = 0; t < nl; ++t) used |= (w->live[t] == cand);
+        if (!used) {
+          ns = cand;
+          break;
+        }
       }
     }
+    sc->newslot = ns;
+    sc->k = k + 1;
   }
-  sc->newslot = ns;
-  sc->k = k + 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -568,7 +631,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
     unsigned long long* lsc = reinterpret_cast<unsigned long long*>(&s_sc);
     for (int q = tid; q < SW; q += BLOCK) lsc[q] = gsc[q];
     __syncthreads();
-    if (tid == 0) final_step<MT>(*dp, &s_sc, s_fin, eval, kkt, init, &s_work);
+    if (wv == 0) final_step<MT>(*dp, &s_sc, s_fin, eval, kkt, init, &s_work, lane);
     __syncthreads();
     for (int q = tid; q < SW; q += BLOCK) gsc[q] = lsc[q];
   };
@@ -690,15 +753,8 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
   }
 
   // ---- this workgroup's record, then (dual pass) up the tree ----
-  // every butterfly step reduces all accumulators together
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    double sh[DT::COUNT];
-#pragma unroll
-    for (int q = 0; q < DT::COUNT; ++q) sh[q] = __shfl_xor(acc[q], off, 64);
-#pragma unroll
-    for (int q = 0; q < DT::COUNT; ++q) acc[q] += sh[q];
-  }
+  for (int q = 0; q < DT::COUNT; ++q) acc[q] = wave_sum(acc[q]);
   if (lane == 0) {
 #pragma unroll
     for (int q = 0; q < DT::COUNT; ++q) s_red[wv][q] = acc[q];
