@@ -71,12 +71,14 @@ struct LPDesc {
   int variant, kkt_every;
   long long max_iter;
   double tau, sigma, beta, D, eps_sg, eta, cs, kappa_bar, tol;
-  const int* rowptr;  // CSR of K
+  const int* rowptr;  // CSR of K, rows in the order rmapB
   const int* colidx;
   const void* val;
-  const int* colptr;  // CSC of K (CSR of K^T)
+  const int* colptr;  // CSC of K (CSR of K^T), columns in the order rmapA
   const int* rowidx;
   const void* valT;
+  const int* rmapA;   // original column at each position of the CSC
+  const int* rmapB;   // original row at each position of the CSR
   const void* c;
   const void* lo;
   const void* hi;
@@ -93,7 +95,8 @@ struct LPDesc {
 };
 
 // One workgroup's share of an SpMV pass.  "Rows" are columns of K in the
-// primal pass (CSC) and rows of K in the dual pass (CSR).
+// primal pass (CSC) and rows of K in the dual pass (CSR); r0, r1 and split
+// rows are positions in the pass's row order (rmapA / rmapB).
 struct Chunk {
   int lp;     // index into the launch's LP table
   int kind;   // 0: multi-row (rows [r0,r1), nnz [k0,k1) staged in LDS); 1: part of a split row

@@ -126,16 +126,50 @@ static int pow2floor(int v) {
   return p;
 }
 
-// Cut the rows [0, R) of a compressed matrix into chunks (see Chunk).
-//  - a row with more than CHUNK_NNZ entries is split into parts of SPLIT_NNZ;
-//  - a row with more than LONG_ROW entries gets a chunk of its own, reduced by
-//    the whole workgroup;
-//  - other rows are packed into multi-row chunks of at most CHUNK_ROWS rows and
-//    CHUNK_NNZ entries, weighted so that short rows (whose epilogue dominates)
-//    do not crowd a chunk.
+constexpr int LONG_ROW = 128;  // rows above this length leave the multi-row chunks
+
+// Order of the rows of one pass on the device: rows of at most LONG_ROW
+// entries keep their original order (their epilogue accesses stay
+// coalesced), longer rows follow by decreasing length so that a few of them
+// can share a workgroup, and rows longer than a chunk come last.  rmap[pos]
+// is the original row at position pos; ptr2/idx2/val2 are the matrix with its
+// rows in that order.
+static void reorder_rows(const std::vector<int>& ptr, const std::vector<int>& idx, const std::vector<double>& v,
+                         int R, std::vector<int>& rmap, std::vector<int>& ptr2, std::vector<int>& idx2,
+                         std::vector<double>& v2) {
+  rmap.clear();
+  std::vector<int> longr, split;
+  for (int r = 0; r < R; ++r) {
+    const int len = ptr[r + 1] - ptr[r];
+    if (len <= LONG_ROW) rmap.push_back(r);
+    else if (len <= CHUNK_NNZ) longr.push_back(r);
+    else split.push_back(r);
+  }
+  std::stable_sort(longr.begin(), longr.end(),
+                   [&](int a, int b) { return ptr[a + 1] - ptr[a] > ptr[b + 1] - ptr[b]; });
+  rmap.insert(rmap.end(), longr.begin(), longr.end());
+  rmap.insert(rmap.end(), split.begin(), split.end());
+  ptr2.assign(R + 1, 0);
+  idx2.resize(idx.size());
+  v2.resize(v.size());
+  for (int pos = 0; pos < R; ++pos) {
+    const int r = rmap[pos];
+    const int len = ptr[r + 1] - ptr[r];
+    ptr2[pos + 1] = ptr2[pos] + len;
+    std::copy(idx.begin() + ptr[r], idx.begin() + ptr[r + 1], idx2.begin() + ptr2[pos]);
+    std::copy(v.begin() + ptr[r], v.begin() + ptr[r + 1], v2.begin() + ptr2[pos]);
+  }
+}
+
+// Cut the positions [0, R) of a reordered matrix into chunks (see Chunk):
+//  - runs of short rows form multi-row chunks of at most CHUNK_ROWS rows and
+//    CHUNK_NNZ entries, weighted so that short rows (whose epilogue
+//    dominates) do not crowd a chunk;
+//  - longer rows are grouped by up to four (one wave each), at most CHUNK_NNZ
+//    entries per group; a group of one is reduced by the whole workgroup;
+//  - a row with more than CHUNK_NNZ entries is split into parts of SPLIT_NNZ.
 static void build_chunks(const std::vector<int>& ptr, int R, std::vector<Chunk>& chunks,
                          std::vector<SplitRow>& splits, int& nparts_total) {
-  constexpr int LONG_ROW = 128;
   constexpr int ROW_WEIGHT = 4;
   chunks.clear();
   splits.clear();
@@ -166,20 +200,25 @@ static void build_chunks(const std::vector<int>& ptr, int R, std::vector<Chunk>&
       ++r;
       continue;
     }
-    if (len > LONG_ROW) {
-      Chunk c{};
-      c.kind = 0;
-      c.r0 = r;
-      c.r1 = r + 1;
-      c.k0 = ptr[r];
-      c.k1 = ptr[r + 1];
-      c.tpr = BLOCK;
-      chunks.push_back(c);
-      ++r;
-      continue;
-    }
     const int r0 = r;
     int nnz = 0;
+    if (len > LONG_ROW) {
+      while (r < R && r - r0 < BLOCK / 64) {
+        const int l2 = ptr[r + 1] - ptr[r];
+        if (l2 <= LONG_ROW || l2 > CHUNK_NNZ || nnz + l2 > CHUNK_NNZ) break;
+        nnz += l2;
+        ++r;
+      }
+      Chunk c{};
+      c.kind = 0;
+      c.r0 = r0;
+      c.r1 = r;
+      c.k0 = ptr[r0];
+      c.k1 = ptr[r];
+      c.tpr = r - r0 == 1 ? BLOCK : 64;
+      chunks.push_back(c);
+      continue;
+    }
     while (r < R && r - r0 < CHUNK_ROWS) {
       const int l2 = ptr[r + 1] - ptr[r];
       if (l2 > LONG_ROW) break;
@@ -383,9 +422,13 @@ void Problem::create(int32_t m_, int32_t n_, int64_t nnz_, const int64_t* row_pt
   cnorm = 0.0;
   for (double v : c) cnorm += v * v;
   cnorm = std::sqrt(cnorm);
-  // ---- work tables ----
-  build_chunks(colptr, n, chunksA, splitsA, npartsA);
-  build_chunks(rowptr, m, chunksB, splitsB, npartsB);
+  // ---- device row orders and work tables ----
+  std::vector<int> rmapA, rmapB, ptrA, idxA, ptrB, idxB;
+  std::vector<double> valA, valB;
+  reorder_rows(colptr, rowidx, valT, n, rmapA, ptrA, idxA, valA);
+  reorder_rows(rowptr, colidx, val, m, rmapB, ptrB, idxB, valB);
+  build_chunks(ptrA, n, chunksA, splitsA, npartsA);
+  build_chunks(ptrB, m, chunksB, splitsB, npartsB);
   tiles.clear();
   for (int e = 0; e < N; e += MIX_TILE) {
     MixTile t{};
@@ -395,21 +438,23 @@ void Problem::create(int32_t m_, int32_t n_, int64_t nnz_, const int64_t* row_pt
   }
   // ---- device copies ----
   const size_t ts = fp64 ? 8 : 4;
-  d_rowptr.upload(rowptr.data(), rowptr.size() * 4, "rowptr");
-  d_colidx.upload(colidx.data(), colidx.size() * 4, "colidx");
-  d_colptr.upload(colptr.data(), colptr.size() * 4, "colptr");
-  d_rowidx.upload(rowidx.data(), rowidx.size() * 4, "rowidx");
+  d_rowptr.upload(ptrB.data(), ptrB.size() * 4, "rowptr");
+  d_colidx.upload(idxB.data(), idxB.size() * 4, "colidx");
+  d_colptr.upload(ptrA.data(), ptrA.size() * 4, "colptr");
+  d_rowidx.upload(idxA.data(), idxA.size() * 4, "rowidx");
+  d_rmapA.upload(rmapA.data(), rmapA.size() * 4, "column order");
+  d_rmapB.upload(rmapB.data(), rmapB.size() * 4, "row order");
   if (fp64) {
-    upload_as<double>(d_val, val, "val");
-    upload_as<double>(d_valT, valT, "valT");
+    upload_as<double>(d_val, valB, "val");
+    upload_as<double>(d_valT, valA, "valT");
     upload_as<double>(d_c, c, "c");
     upload_as<double>(d_lo, lo, "l");
     upload_as<double>(d_hi, hi, "u");
     upload_as<double>(d_q, q, "q");
     upload_as<double>(d_dhat, dhat, "dhat");
   } else {
-    upload_as<float>(d_val, val, "val");
-    upload_as<float>(d_valT, valT, "valT");
+    upload_as<float>(d_val, valB, "val");
+    upload_as<float>(d_valT, valA, "valT");
     upload_as<float>(d_c, c, "c");
     upload_as<float>(d_lo, lo, "l");
     upload_as<float>(d_hi, hi, "u");
@@ -476,6 +521,8 @@ void Problem::fill_desc() {
   desc.colptr = (const int*)d_colptr.p;
   desc.rowidx = (const int*)d_rowidx.p;
   desc.valT = d_valT.p;
+  desc.rmapA = (const int*)d_rmapA.p;
+  desc.rmapB = (const int*)d_rmapB.p;
   desc.c = d_c.p;
   desc.lo = d_lo.p;
   desc.hi = d_hi.p;
@@ -506,7 +553,7 @@ double Problem::power_norm() {
 
 size_t Problem::device_bytes() const {
   size_t b = 0;
-  const DevBuf* bufs[] = {&d_rowptr, &d_colidx, &d_val, &d_colptr, &d_rowidx, &d_valT, &d_c, &d_lo, &d_hi,
+  const DevBuf* bufs[] = {&d_rowptr, &d_colidx, &d_val, &d_colptr, &d_rowidx, &d_valT, &d_rmapA, &d_rmapB, &d_c, &d_lo, &d_hi,
                           &d_q, &d_dhat, &d_rowtype, &d_u[0], &d_u[1], &d_g[0], &d_g[1], &d_xbar, &d_hist_dG,
                           &d_hist_W, &d_lam, &d_sc, &d_desc, &d_xfer};
   for (auto* p : bufs) b += p->bytes;

@@ -487,6 +487,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
   const int* __restrict__ ptr = PASS == 0 ? dp->colptr : dp->rowptr;
   const int* __restrict__ idx = PASS == 0 ? dp->rowidx : dp->colidx;
   const T* __restrict__ val = (const T*)(PASS == 0 ? dp->valT : dp->val);
+  const int* __restrict__ rmap = PASS == 0 ? dp->rmapA : dp->rmapB;
   // gathered vectors: pass A gathers y^k; pass B gathers x_bar (and x^k for KKT)
   const T* gv1 = PASS == 0 ? ucur + n : (eval ? ucur : (const T*)dp->xbar);
   const T* gv2 = ucur;
@@ -679,14 +680,15 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
     if (tid == 0) {
       reset_counter(&a.splitcnt[ch.split]);
       RowIn<T, MT> in;
-      load_row(sr.row, in);
+      const int row = rmap[sr.row];
+      load_row(row, in);
       double t1 = 0.0, t2 = 0.0;
       for (int p = 0; p < sr.nparts; ++p) {
         t1 += ld_coh(a.splitpart, 2 * (sr.part0 + p) + 0);
         t2 += ld_coh(a.splitpart, 2 * (sr.part0 + p) + 1);
       }
       for (int q = 0; q < DT::COUNT; ++q) s_racc[q] = 0.0;
-      finish_row(sr.row, in, t1, t2, s_racc);
+      finish_row(row, in, t1, t2, s_racc);
       double* rp = a.rec + (size_t)sr.leaf * NDOT;
       for (int q = 0; q < DT::COUNT; ++q) st_agent(&rp[q], s_racc[q]);
     }
@@ -701,8 +703,9 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
     const bool blockmode = tpr == BLOCK;
     const int grp = blockmode ? 0 : tid / tpr;
     const int lane_r = blockmode ? tid : tid % tpr;
-    const int r = r0 + grp;  // this thread group's row (at most one)
+    const int r = r0 + grp;  // this thread group's position (at most one)
     const bool has_row = r < r1 && (!blockmode || tid == 0);
+    const int row = has_row ? rmap[r] : 0;  // its original row
     int ci[UNR];
     T vv[UNR];
 #pragma unroll
@@ -720,7 +723,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
     if (r < r1) {
       a0 = ptr[r] - kb;
       a1 = ptr[r + 1] - kb;
-      if (has_row && lane_r == 0) load_row(r, rin);
+      if (has_row && lane_r == 0) load_row(row, rin);
     }
     double sum1 = 0.0, sum2 = 0.0;
     const int nsweep = two ? 2 : 1;
@@ -749,7 +752,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
       }
       if (sw == 0) sum1 = sres; else sum2 = sres;
     }
-    if (has_row && lane_r == 0) finish_row(r, rin, sum1, sum2, acc);
+    if (has_row && lane_r == 0) finish_row(row, rin, sum1, sum2, acc);
   }
 
   // ---- this workgroup's record, then (dual pass) up the tree ----
@@ -822,7 +825,8 @@ __global__ void k_start_point(LPDesc d) {
 
 // y = A x for CSR (ptr, idx, val), one wave per row, float64 vectors.
 template <typename T>
-__global__ void k_spmv_wave(const int* ptr, const int* idx, const T* val, const double* x, double* y, int rows) {
+__global__ void k_spmv_wave(const int* ptr, const int* idx, const T* val, const int* rmap, const double* x,
+                            double* y, int rows) {
   const int lane = threadIdx.x & 63;
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int nw = (gridDim.x * blockDim.x) >> 6;
@@ -830,7 +834,7 @@ __global__ void k_spmv_wave(const int* ptr, const int* idx, const T* val, const 
     double s = 0.0;
     for (int q = ptr[r] + lane; q < ptr[r + 1]; q += 64) s += (double)val[q] * x[idx[q]];
     s = wave_sum(s);
-    if (lane == 0) y[r] = s;
+    if (lane == 0) y[rmap[r]] = s;
   }
 }
 
@@ -953,11 +957,11 @@ hipError_t launch_power_iteration(const LPDesc& d, bool fp64, int iters, double*
   hipLaunchKernelGGL(k_normalize, dim3(gridv), dim3(BLOCK), 0, st, (const double*)v, v, n, (const double*)part, nparts, est, 0);
   for (int it = 0; it < iters; ++it) {
     if (fp64) {
-      hipLaunchKernelGGL(k_spmv_wave<double>, dim3(gridr), dim3(BLOCK), 0, st, d.rowptr, d.colidx, (const double*)d.val, (const double*)v, w, m);
-      hipLaunchKernelGGL(k_spmv_wave<double>, dim3(gridr), dim3(BLOCK), 0, st, d.colptr, d.rowidx, (const double*)d.valT, (const double*)w, z, n);
+      hipLaunchKernelGGL(k_spmv_wave<double>, dim3(gridr), dim3(BLOCK), 0, st, d.rowptr, d.colidx, (const double*)d.val, d.rmapB, (const double*)v, w, m);
+      hipLaunchKernelGGL(k_spmv_wave<double>, dim3(gridr), dim3(BLOCK), 0, st, d.colptr, d.rowidx, (const double*)d.valT, d.rmapA, (const double*)w, z, n);
     } else {
-      hipLaunchKernelGGL(k_spmv_wave<float>, dim3(gridr), dim3(BLOCK), 0, st, d.rowptr, d.colidx, (const float*)d.val, (const double*)v, w, m);
-      hipLaunchKernelGGL(k_spmv_wave<float>, dim3(gridr), dim3(BLOCK), 0, st, d.colptr, d.rowidx, (const float*)d.valT, (const double*)w, z, n);
+      hipLaunchKernelGGL(k_spmv_wave<float>, dim3(gridr), dim3(BLOCK), 0, st, d.rowptr, d.colidx, (const float*)d.val, d.rmapB, (const double*)v, w, m);
+      hipLaunchKernelGGL(k_spmv_wave<float>, dim3(gridr), dim3(BLOCK), 0, st, d.colptr, d.rowidx, (const float*)d.valT, d.rmapA, (const double*)w, z, n);
     }
     hipLaunchKernelGGL(k_sqnorm_part, dim3(nparts), dim3(BLOCK), 0, st, (const double*)z, n, part);
     hipLaunchKernelGGL(k_normalize, dim3(gridv), dim3(BLOCK), 0, st, (const double*)z, v, n, (const double*)part, nparts, est, 1 + it);

@@ -77,7 +77,8 @@ struct Problem {
   int npartsA = 0, npartsB = 0;
   std::vector<MixTile> tiles;
   // device data
-  DevBuf d_rowptr, d_colidx, d_val, d_colptr, d_rowidx, d_valT, d_c, d_lo, d_hi, d_q, d_dhat, d_rowtype;
+  DevBuf d_rowptr, d_colidx, d_val, d_colptr, d_rowidx, d_valT, d_rmapA, d_rmapB, d_c, d_lo, d_hi, d_q, d_dhat,
+      d_rowtype;
   DevBuf d_u[2], d_g[2], d_xbar, d_hist_dG, d_hist_W, d_lam, d_sc, d_desc, d_xfer;
   LPDesc desc{};
   Scalars sc_init{};

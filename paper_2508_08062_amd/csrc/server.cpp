@@ -54,7 +54,7 @@ struct Request {
 size_t estimate_bytes(const aapdhg_options& o, int32_t m, int32_t n, int64_t nnz) {
   const size_t ts = o.precision == 1 ? 8 : 4;
   const size_t N = (size_t)m + n;
-  size_t b = 2 * ((size_t)nnz * (4 + ts)) + 4 * ((size_t)m + n + 2);  // CSR + CSC
+  size_t b = 2 * ((size_t)nnz * (4 + ts)) + 8 * ((size_t)m + n + 1);  // CSR + CSC, row orders
   b += ts * ((size_t)3 * n + m + N) + m;                                // c, l, u, q, D-hat, row types
   b += ts * (4 * N + 2 * (size_t)n + 2 * (size_t)o.memory * N);         // iterates, residuals, x_bar, lambda, history
   b += 8 * N + sizeof(Scalars) + 64 * 1024;                             // transfer buffer, scalars, tables
