@@ -93,7 +93,10 @@ typedef struct {
   int32_t power_iters;/* power-iteration cap for the step size                            */
   int32_t epoch;      /* iterations per device epoch between host checks of the status    */
   int32_t chunks_per_block; /* work items per workgroup of the SpMV passes, 0 = automatic   */
-  int32_t reserved[6];
+  int32_t loop_kernel;/* 0: loop passes run in one persistent cooperative launch per epoch
+                         when the LPs fit the resident workgroups, else three launches per
+                         pass; 1: always three launches per pass                          */
+  int32_t reserved[5];
 } aapdhg_options;
 
 typedef struct {
@@ -146,12 +149,15 @@ aapdhg_status aapdhg_solve(aapdhg_t h, void *stream);
  * reset handle the first pass is the init step.  Passes after termination do nothing. */
 aapdhg_status aapdhg_iterate(aapdhg_t h, void *stream, int64_t iters);
 
-/* Measurement variant of aapdhg_iterate: the same `iters` loop passes, with HIP events
- * recorded on `stream` before and after each of the three launches of a pass (primal CSC
- * pass, dual CSR pass with the float64 decisions, mix pass).  Waits for completion and
- * writes the mean duration in milliseconds of each launch to ms3[0..2].  The events add a
- * small gap between launches, so use aapdhg_iterate for throughput. */
-aapdhg_status aapdhg_iterate_timed(aapdhg_t h, void *stream, int64_t iters, double *ms3);
+/* Measurement variant of aapdhg_iterate: `iters` loop passes (after the init step, which is
+ * run first and not timed on a fresh or reset handle) with HIP events recorded on `stream`
+ * around the launches; waits for completion and fills ms4[0..3]:
+ *   persistent loop kernel: {1, duration in ms of its one launch, iters, 1}
+ *     (iters <= 65536);
+ *   three launches per pass: {0, mean ms of the primal CSC launch, of the dual CSR launch
+ *     with the float64 decisions, of the mix launch}; the events add a small gap between
+ *     launches, so use aapdhg_iterate for throughput. */
+aapdhg_status aapdhg_iterate_timed(aapdhg_t h, void *stream, int64_t iters, double *ms4);
 
 /* Return to the start point (discard iterate, history and counters). */
 aapdhg_status aapdhg_reset(aapdhg_t h, void *stream);
@@ -197,10 +203,11 @@ const char *aapdhg_last_error(aapdhg_t h);
 aapdhg_status aapdhg_batch_create(int32_t count, const aapdhg_t *problems, aapdhg_batch_t *out);
 /* Solve every member from its start point; returns when all have terminated. */
 aapdhg_status aapdhg_batch_solve(aapdhg_batch_t b, void *stream);
-/* Enqueue `iters` loop passes for every member (asynchronous). */
+/* Enqueue `iters` loop passes for every member (asynchronous).  A member that has not
+ * started takes its init step first, in a launch of its own. */
 aapdhg_status aapdhg_batch_iterate(aapdhg_batch_t b, void *stream, int64_t iters);
 /* Measurement variant of aapdhg_batch_iterate (see aapdhg_iterate_timed). */
-aapdhg_status aapdhg_batch_iterate_timed(aapdhg_batch_t b, void *stream, int64_t iters, double *ms3);
+aapdhg_status aapdhg_batch_iterate_timed(aapdhg_batch_t b, void *stream, int64_t iters, double *ms4);
 aapdhg_status aapdhg_batch_destroy(aapdhg_batch_t b);
 
 /* ---- serving: continuous batching of LP requests ----

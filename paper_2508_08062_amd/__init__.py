@@ -33,7 +33,7 @@ class Options(C.Structure):
                 ("tol", C.c_double), ("max_iter", C.c_int64), ("time_limit_s", C.c_double),
                 ("kkt_every", C.c_int32), ("dhat_mode", C.c_int32), ("ruiz_iters", C.c_int32),
                 ("power_iters", C.c_int32), ("epoch", C.c_int32), ("chunks_per_block", C.c_int32),
-                ("reserved", C.c_int32 * 6)]
+                ("loop_kernel", C.c_int32), ("reserved", C.c_int32 * 5)]
 
 
 class Info(C.Structure):
@@ -159,6 +159,12 @@ def _lp_arrays(lp):
     return arrs
 
 
+def _timing(ms):
+    if ms[0] == 1.0:
+        return {"kernel": "persistent", "launch_ms": float(ms[1]), "passes": int(ms[2])}
+    return {"kernel": "three", "primal": float(ms[1]), "dual": float(ms[2]), "mix": float(ms[3])}
+
+
 class Solver:
     """One LP on the GPU (aapdhg_create ... aapdhg_destroy)."""
 
@@ -200,10 +206,12 @@ class Solver:
         return self
 
     def iterate_timed(self, iters: int, stream=None):
-        """Mean milliseconds of the primal, dual and mix launches over `iters` passes."""
-        ms = np.zeros(3)
+        """`iters` loop passes with HIP events around the launches (see
+        aapdhg_iterate_timed): the persistent kernel's launch time, or the mean
+        milliseconds of the primal, dual and mix launches."""
+        ms = np.zeros(4)
         _check(lib().aapdhg_iterate_timed(self.h, _stream(stream), int(iters), _ptr(ms, C.c_double)), self.h)
-        return {"primal": ms[0], "dual": ms[1], "mix": ms[2]}
+        return _timing(ms)
 
     def reset(self, stream=None):
         _check(lib().aapdhg_reset(self.h, _stream(stream)), self.h)
@@ -286,9 +294,9 @@ class Batch:
         return self
 
     def iterate_timed(self, iters: int, stream=None):
-        ms = np.zeros(3)
+        ms = np.zeros(4)
         _check(lib().aapdhg_batch_iterate_timed(self.h, _stream(stream), int(iters), _ptr(ms, C.c_double)), None)
-        return {"primal": ms[0], "dual": ms[1], "mix": ms[2]}
+        return _timing(ms)
 
     def results(self):
         return [s.result() for s in self.solvers]

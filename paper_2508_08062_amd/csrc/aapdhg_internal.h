@@ -176,4 +176,67 @@ struct MixArgs {
   const MixTile* tiles;
 };
 
+// ---- persistent loop kernel ----
+
+// One workgroup of the persistent loop kernel: its LP, its rank in the LP's
+// group, and the units (BlockWork entries) it handles in the CSC pass
+// [a0, a1) and in the CSR pass [b0, b1), for the whole launch.
+struct LoopWG {
+  int lp;
+  int rank;
+  int a0, a1;
+  int b0, b1;
+  int pad[2];
+};
+
+// Per-LP entry: the size of its workgroup group and its partial-sum records
+// (the leaves of both passes, [leaf0, leaf0 + nleaf)).
+struct LoopLP {
+  int nwg;
+  int leaf0;
+  int nleaf;   // records of both passes
+  int nleafA;  // of which the CSC pass's come first
+};
+
+// Per-LP counters of one launch (zeroed before the launch).  Arrivals are
+// spread over NSUB counters 128 bytes apart (workgroup rank modulo NSUB), so
+// that the atomics of a group do not queue on one address; a waiter adds the
+// NSUB counters.
+constexpr int NSUB = 8;
+constexpr int SUB_STRIDE = 32;  // unsigned ints between sub-counters
+struct alignas(256) LoopSync {
+  unsigned int bar[NSUB * SUB_STRIDE];  // group-barrier arrivals
+  unsigned int arr[NSUB * SUB_STRIDE];  // arrivals after the CSR phase
+  unsigned int flag;                    // passes whose decisions are published
+  unsigned int abort;                   // set when a wait gave up
+  unsigned int pad[62];
+};
+
+// Decisions of a pass, published by rank 0 of the group.
+struct alignas(64) Bcast {
+  long long k;
+  int status, branch, nmix, nlive, newslot, pad;
+  int mixslot[MAXM];
+  int live[MAXM];
+  double gamma[MAXM];
+};
+
+struct LoopArgs {
+  const LPDesc* lps;
+  const LoopLP* llp;
+  const LoopWG* wgs;
+  const BlockWork* blocksA;
+  const BlockWork* blocksB;
+  const Chunk* chunks;
+  const SplitRow* splits;
+  double* rec;
+  double* splitpart;
+  unsigned int* splitcnt;
+  LoopSync* sync;
+  Bcast* bc;
+  int* err;  // set to 1 when a wait gave up
+  long long max_passes;
+  unsigned long long timeout_ticks;  // bound of one wait, in wall-clock ticks
+};
+
 }  // namespace aapdhg

@@ -93,6 +93,7 @@ void default_options(aapdhg_options* o) {
   o->power_iters = 200;
   o->epoch = 256;
   o->chunks_per_block = 0;
+  o->loop_kernel = 0;
 }
 
 static void check_options(const aapdhg_options& o) {
@@ -113,6 +114,7 @@ static void check_options(const aapdhg_options& o) {
   if (o.power_iters < 1 || o.power_iters > 100000) throw Error(AAPDHG_E_ARG, "power_iters must be in [1, 100000]");
   if (o.epoch < 1 || o.epoch > 1000000) throw Error(AAPDHG_E_ARG, "epoch must be in [1, 1e6]");
   if (o.chunks_per_block < 0 || o.chunks_per_block > 4096) throw Error(AAPDHG_E_ARG, "chunks_per_block must be in [0, 4096]");
+  if (o.loop_kernel < 0 || o.loop_kernel > 1) throw Error(AAPDHG_E_ARG, "loop_kernel must be 0 or 1");
   if (!std::isfinite(o.tau) || !std::isfinite(o.sigma)) throw Error(AAPDHG_E_ARG, "tau and sigma must be finite");
 }
 
@@ -576,6 +578,15 @@ void Problem::enqueue_reset(hipStream_t st) {
   hip_check(hipMemcpyAsync(d_sc.p, &sc_init, sizeof sc_init, hipMemcpyHostToDevice, st), "reset scalars");
   hip_check(launch_start_point(desc, fp64, st), "start point");
   started = true;
+  pending_init = true;
+}
+
+// Alg 2 set-up: u^1 = T u^0, g^0 and ||g^0|| (the pass with k = 0), on the
+// LP's own three-launch tables.
+void Problem::enqueue_init(hipStream_t st) {
+  if (!pending_init) return;
+  hip_check(launch_loop_pass(solo->t, st, MODE_ITER), "initial pass");
+  pending_init = false;
 }
 
 // ---------------------------------------------------------------------------
@@ -589,7 +600,8 @@ LaunchSet::~LaunchSet() {
 size_t LaunchSet::device_bytes() const {
   size_t b = 0;
   const DevBuf* bufs[] = {&d_lps, &d_llp, &d_chunks, &d_blocksA, &d_blocksB, &d_nodes, &d_splits, &d_rec,
-                          &d_ncnt, &d_splitpart, &d_splitcnt, &d_tiles, &d_status};
+                          &d_ncnt, &d_splitpart, &d_splitcnt, &d_tiles, &d_status, &d_wgs, &d_looplps,
+                          &d_sync, &d_bc, &d_err};
   for (auto* p : bufs) b += p->bytes;
   return b;
 }
@@ -609,11 +621,24 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
   t = LaunchTables{};
   t.fp64 = lps[0]->fp64;
   int mt = 1;
+  for (auto* p : lps) mt = std::max(mt, p->opt.memory);
+  // The persistent loop kernel pays off while every resident workgroup has
+  // about one chunk per pass (then each workgroup owns one chunk); larger
+  // sets use three launches per pass, which the hardware balances.
+  bool want = true;
+  long long need = 0;
+  for (auto* p : lps) {
+    want &= p->opt.loop_kernel == 0;
+    need += (long long)std::max(p->chunksA.size(), p->chunksB.size());
+  }
+  const int cap = want ? loop_capacity(lps[0]->fp64, mt) : 0;
+  const bool persist = cap >= count && need <= 2LL * cap;
   int parts = 0;
   // per LP and pass: chunks, split rows, workgroups; leaves are the
   // workgroups followed by the split rows
   struct PassInfo {
-    int b0, nb;   // workgroups in bA / bB
+    int b0, nb;   // workgroups in bA / bB (multi-row units)
+    int bend;     // end of the LP's units (split parts follow the multi-row units)
     int s0, ns;   // split rows
     int leaf0;    // first leaf record
   };
@@ -646,6 +671,7 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
       const int nch = (int)pc.size();
       int cpb = p->opt.chunks_per_block;
       if (cpb <= 0) cpb = std::max(1, (nch + 1023) / 1024);
+      if (persist) cpb = 1;
       // workgroups: runs of up to cpb multi-row chunks (leaves, listed first),
       // then one workgroup per split-row part (no leaf of their own)
       pi.b0 = (int)bw.size();
@@ -674,6 +700,7 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
         w.leaf = w.parent = -1;
         bw.push_back(w);
       }
+      pi.bend = (int)bw.size();
       pi.leaf0 = nleaves;
       nleaves += pi.nb + pi.ns;
     }
@@ -742,14 +769,144 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
   t.splitcnt = (unsigned int*)d_splitcnt.p;
   t.tiles = (const MixTile*)d_tiles.p;
   t.ntiles = (int)tl.size();
+
+  // ---- persistent loop kernel: a group of resident workgroups per LP ----
+  t.persistent = false;
+  if (!persist) return;
+  // cost of a unit (one chunk): a chunk's dependent chain of loads costs
+  // about as much as 3000 gathered entries
+  auto unit_weight = [&](const BlockWork& w) -> double {
+    const Chunk& ch = chunks[w.c0];
+    return 3000.0 + (double)(ch.k1 - ch.k0) + (w.kind == 1 ? 0.0 : 2.0 * (ch.r1 - ch.r0));
+  };
+  std::vector<double> wlp(count);
+  std::vector<int> umax(count), G(count);
+  double wtot = 0.0;
+  for (int i = 0; i < count; ++i) {
+    double wa = 0.0, wb = 0.0;
+    for (int u = info[2 * i].b0; u < info[2 * i].bend; ++u) wa += unit_weight(bA[u]);
+    for (int u = info[2 * i + 1].b0; u < info[2 * i + 1].bend; ++u) wb += unit_weight(bB[u]);
+    wlp[i] = std::max(wa, wb);
+    umax[i] = std::max(info[2 * i].bend - info[2 * i].b0, info[2 * i + 1].bend - info[2 * i + 1].b0);
+    wtot += wlp[i];
+  }
+  int gsum = 0;
+  for (int i = 0; i < count; ++i) {
+    G[i] = need <= cap ? std::max(1, umax[i])
+                       : std::max(1, std::min(umax[i], (int)std::floor((double)cap * wlp[i] / wtot)));
+    gsum += G[i];
+  }
+  while (gsum > cap) {  // trim the largest groups
+    int big = 0;
+    for (int i = 1; i < count; ++i)
+      if (G[i] > G[big]) big = i;
+    --G[big];
+    --gsum;
+  }
+  // units of rank j: a contiguous run, cut by cumulative weight
+  auto assign = [&](const std::vector<BlockWork>& bw, int u0, int u1, int g, std::vector<int>& first) {
+    first.assign(g + 1, u1);
+    double tot = 0.0;
+    for (int u = u0; u < u1; ++u) tot += unit_weight(bw[u]);
+    double cum = 0.0;
+    int rank_prev = -1;
+    for (int u = u0; u < u1; ++u) {
+      const double w = unit_weight(bw[u]);
+      const int r = std::min(g - 1, (int)((cum + 0.5 * w) * g / tot));
+      for (int q = rank_prev + 1; q <= r; ++q) first[q] = u;
+      rank_prev = std::max(rank_prev, r);
+      cum += w;
+    }
+    for (int q = rank_prev + 1; q <= g; ++q) first[q] = u1;
+  };
+  std::vector<LoopWG> wgs;
+  std::vector<LoopLP> llps(count);
+  std::vector<int> fa, fb;
+  for (int i = 0; i < count; ++i) {
+    const PassInfo& pa = info[2 * i];
+    const PassInfo& pb = info[2 * i + 1];
+    assign(bA, pa.b0, pa.bend, G[i], fa);
+    assign(bB, pb.b0, pb.bend, G[i], fb);
+    for (int j = 0; j < G[i]; ++j) {
+      LoopWG w{};
+      w.lp = i;
+      w.rank = j;
+      w.a0 = fa[j];
+      w.a1 = fa[j + 1];
+      w.b0 = fb[j];
+      w.b1 = fb[j + 1];
+      wgs.push_back(w);
+    }
+    llps[i].nwg = G[i];
+    llps[i].leaf0 = pa.leaf0;
+    llps[i].nleafA = pa.nb + pa.ns;
+    llps[i].nleaf = pb.leaf0 + pb.nb + pb.ns - pa.leaf0;
+  }
+  d_wgs.upload(wgs.data(), wgs.size() * sizeof(LoopWG), "loop workgroups");
+  d_looplps.upload(llps.data(), llps.size() * sizeof(LoopLP), "loop groups");
+  d_sync.alloc(sizeof(LoopSync) * (size_t)count, "loop counters");
+  d_bc.alloc(sizeof(Bcast) * (size_t)count, "loop decisions");
+  d_err.alloc(sizeof(int), "loop error word");
+  d_err.zero("loop error word");
+  int dev = 0, khz = 0;
+  hip_check(hipGetDevice(&dev), "device");
+  hip_check(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev), "wall clock rate");
+  t.timeout_ticks = (unsigned long long)std::max(khz, 1000) * 4000ull;  // about 4 s
+  t.wgs = (const LoopWG*)d_wgs.p;
+  t.nwgs = (int)wgs.size();
+  t.looplps = (const LoopLP*)d_looplps.p;
+  t.sync = (LoopSync*)d_sync.p;
+  t.bc = (Bcast*)d_bc.p;
+  t.err = (int*)d_err.p;
+  t.persistent = true;
+}
+
+// Raise if a wait of the persistent loop kernel gave up (the LPs it served
+// were stopped with status NUMERICAL).
+void LaunchSet::check_loop_error(hipStream_t st) {
+  if (!t.persistent) return;
+  int e = 0;
+  hip_check(hipMemcpyAsync(&e, d_err.p, sizeof e, hipMemcpyDeviceToHost, st), "loop error word");
+  hip_check(hipStreamSynchronize(st), "loop error sync");
+  if (e != 0) {
+    d_err.zero("loop error word");
+    throw Error(AAPDHG_E_HIP, "a wait of the persistent loop kernel timed out");
+  }
 }
 
 void LaunchSet::enqueue_passes(hipStream_t st, int64_t iters) {
+  if (t.persistent) {
+    for (int64_t done = 0; done < iters;) {
+      const int64_t np = std::min<int64_t>(iters - done, MAX_LOOP_PASSES);
+      hip_check(launch_loop(t, st, np), "loop launch");
+      done += np;
+    }
+    return;
+  }
   for (int64_t it = 0; it < iters; ++it) hip_check(launch_loop_pass(t, st, MODE_ITER), "loop pass");
 }
 
-void LaunchSet::timed_passes(hipStream_t st, int64_t iters, double* ms3) {
+void LaunchSet::timed_passes(hipStream_t st, int64_t iters, double* ms4) {
   if (iters < 1) throw Error(AAPDHG_E_ARG, "iters must be >= 1");
+  if (t.persistent) {
+    if (iters > MAX_LOOP_PASSES) throw Error(AAPDHG_E_ARG, "at most %d passes per timed launch", (int)MAX_LOOP_PASSES);
+    hipEvent_t ev[2];
+    for (auto& e : ev) hip_check(hipEventCreate(&e), "event");
+    hip_check(hipEventRecord(ev[0], st), "event record");
+    hip_check(launch_loop(t, st, iters), "loop launch");
+    hip_check(hipEventRecord(ev[1], st), "event record");
+    hip_check(hipStreamSynchronize(st), "timed sync");
+    float ms = 0.f;
+    hip_check(hipEventElapsedTime(&ms, ev[0], ev[1]), "event time");
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    ms4[0] = 1.0;
+    ms4[1] = ms;
+    ms4[2] = (double)iters;
+    ms4[3] = 1.0;
+    return;
+  }
+  double* ms3 = ms4 + 1;
+  ms4[0] = 0.0;
   std::vector<hipEvent_t> ev((size_t)iters * 4);
   for (auto& e : ev) hip_check(hipEventCreate(&e), "event");
   for (int64_t it = 0; it < iters; ++it) hip_check(launch_loop_pass(t, st, MODE_ITER, &ev[(size_t)it * 4]), "loop pass");
@@ -805,6 +962,7 @@ double LaunchSet::run_to_completion(hipStream_t st, int epoch, double time_limit
   (void)hipEventDestroy(ev[0]);
   (void)hipEventDestroy(ev[1]);
   last_epochs = epochs;
+  check_loop_error(st);
   return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
@@ -917,7 +1075,7 @@ void Problem::set_state(const double* u, const double* u_prev, const double* g_p
   s.j_pdhg = meta[3];
   s.nlive = (int)meta[4];
   s.newslot = (int)meta[5];
-  if (s.k < 0 || s.nlive < 0 || s.nlive > opt.memory || s.newslot < 0 || s.newslot >= opt.memory)
+  if (s.k < 1 || s.nlive < 0 || s.nlive > opt.memory || s.newslot < 0 || s.newslot >= opt.memory)
     throw Error(AAPDHG_E_ARG, "invalid state metadata");
   for (int t = 0; t < MAXM; ++t) s.live[t] = (int)meta[8 + t];
   for (int t = 0; t < s.nlive; ++t)
@@ -939,6 +1097,7 @@ void Problem::set_state(const double* u, const double* u_prev, const double* g_p
   }
   hip_check(hipMemcpy(d_sc.p, &s, sizeof s, hipMemcpyHostToDevice), "write scalars");
   started = true;
+  pending_init = false;
 }
 
 }  // namespace aapdhg
@@ -1014,6 +1173,7 @@ aapdhg_status aapdhg_solve(aapdhg_t h, void* stream) {
     if (h->p.in_batch) throw Error(AAPDHG_E_STATE, "problem belongs to a live batch");
     hipStream_t st = (hipStream_t)stream;
     h->p.enqueue_reset(st);
+    h->p.enqueue_init(st);
     h->p.last_solve_seconds = h->p.solo->run_to_completion(st, h->p.opt.epoch, h->p.opt.time_limit_s);
   });
 }
@@ -1025,17 +1185,22 @@ aapdhg_status aapdhg_iterate(aapdhg_t h, void* stream, int64_t iters) {
     if (h->p.in_batch) throw Error(AAPDHG_E_STATE, "problem belongs to a live batch");
     hipStream_t st = (hipStream_t)stream;
     if (!h->p.started) h->p.enqueue_reset(st);
+    if (h->p.pending_init && iters > 0) {  // the init step is the first pass
+      h->p.enqueue_init(st);
+      --iters;
+    }
     h->p.solo->enqueue_passes(st, iters);
   });
 }
 
-aapdhg_status aapdhg_iterate_timed(aapdhg_t h, void* stream, int64_t iters, double* ms3) {
-  if (!h || !ms3) return AAPDHG_E_ARG;
+aapdhg_status aapdhg_iterate_timed(aapdhg_t h, void* stream, int64_t iters, double* ms4) {
+  if (!h || !ms4) return AAPDHG_E_ARG;
   return guard(&h->err, [&] {
     if (h->p.in_batch) throw Error(AAPDHG_E_STATE, "problem belongs to a live batch");
     hipStream_t st = (hipStream_t)stream;
     if (!h->p.started) h->p.enqueue_reset(st);
-    h->p.solo->timed_passes(st, iters, ms3);
+    h->p.enqueue_init(st);
+    h->p.solo->timed_passes(st, iters, ms4);
   });
 }
 
@@ -1127,6 +1292,7 @@ aapdhg_status aapdhg_batch_solve(aapdhg_batch_t b, void* stream) {
     double tl = 0.0;
     for (auto* h : b->members) {
       h->p.enqueue_reset(st);
+      h->p.enqueue_init(st);
       epoch = std::min(epoch, h->p.opt.epoch);
       tl = std::max(tl, h->p.opt.time_limit_s);
     }
@@ -1140,19 +1306,23 @@ aapdhg_status aapdhg_batch_iterate(aapdhg_batch_t b, void* stream, int64_t iters
   return guard(&b->err, [&] {
     if (iters < 0) throw Error(AAPDHG_E_ARG, "iters must be >= 0");
     hipStream_t st = (hipStream_t)stream;
-    for (auto* h : b->members)
+    for (auto* h : b->members) {
       if (!h->p.started) h->p.enqueue_reset(st);
+      h->p.enqueue_init(st);
+    }
     b->set.enqueue_passes(st, iters);
   });
 }
 
-aapdhg_status aapdhg_batch_iterate_timed(aapdhg_batch_t b, void* stream, int64_t iters, double* ms3) {
-  if (!b || !ms3) return AAPDHG_E_ARG;
+aapdhg_status aapdhg_batch_iterate_timed(aapdhg_batch_t b, void* stream, int64_t iters, double* ms4) {
+  if (!b || !ms4) return AAPDHG_E_ARG;
   return guard(&b->err, [&] {
     hipStream_t st = (hipStream_t)stream;
-    for (auto* h : b->members)
+    for (auto* h : b->members) {
       if (!h->p.started) h->p.enqueue_reset(st);
-    b->set.timed_passes(st, iters, ms3);
+      h->p.enqueue_init(st);
+    }
+    b->set.timed_passes(st, iters, ms4);
   });
 }
 

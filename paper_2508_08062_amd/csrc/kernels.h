@@ -29,12 +29,26 @@ struct LaunchTables {
   unsigned int* splitcnt = nullptr;
   const MixTile* tiles = nullptr;
   int ntiles = 0;
+  // persistent loop kernel (when the set fits the resident workgroups)
+  bool persistent = false;
+  const LoopWG* wgs = nullptr;
+  int nwgs = 0;
+  const LoopLP* looplps = nullptr;
+  LoopSync* sync = nullptr;
+  Bcast* bc = nullptr;
+  int* err = nullptr;
+  unsigned long long timeout_ticks = 0;
 };
 
 // One loop pass (passes A, B and, in MODE_ITER, C) for every LP of the table.
 // With ev != nullptr, events ev[0..3] are recorded before A, after A, after B
 // and after C on the same stream.
 hipError_t launch_loop_pass(const LaunchTables& t, hipStream_t st, int mode, hipEvent_t* ev = nullptr);
+// `passes` loop passes of every LP of the table in one cooperative launch of
+// the persistent loop kernel (t.persistent must be set).
+hipError_t launch_loop(const LaunchTables& t, hipStream_t st, long long passes);
+// Workgroups of the persistent loop kernel that fit on the device at once.
+int loop_capacity(bool fp64, int mt);
 hipError_t launch_start_point(const LPDesc& d, bool fp64, hipStream_t st);
 // Power iteration on K^T K from the all-ones vector; est[0..iters] receives
 // ||K^T K v|| of each step (the square of the ||K|| estimate).  work holds

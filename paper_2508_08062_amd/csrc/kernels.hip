@@ -430,6 +430,29 @@ __device__ void final_step(const LPDesc& d, Scalars* sc, const double* f, bool e
 // pass A (PASS = 0, columns of K via CSC) and pass B (PASS = 1, rows via CSR)
 // ---------------------------------------------------------------------------
 
+// Data that other workgroups of the same launch write, read and written at
+// agent scope (buffer instructions with the sc1 policy) without a fence.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t coh_rsrc(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, 0x7fffffff, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T ldc(const T* base, int i) {
+  if constexpr (sizeof(T) == 8) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(coh_rsrc(base), i * 8, 0, 16));
+  } else {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(coh_rsrc(base), i * 4, 0, 16));
+  }
+}
+template <typename T>
+__device__ __forceinline__ void stc(T* base, int i, T v) {
+  if constexpr (sizeof(T) == 8) {
+    using B64 = decltype(__builtin_amdgcn_raw_buffer_load_b64(coh_rsrc(base), 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(B64, v), coh_rsrc(base), i * 8, 0, 16);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), coh_rsrc(base), i * 4, 0, 16);
+  }
+}
+
 // Inputs of one row's (or column's) epilogue, loaded before anything is stored
 // so that the loads of a thread's rows and of the SpMV are in flight together.
 template <typename T, int MT>
@@ -439,11 +462,337 @@ struct RowIn {
   T hv[MT];
 };
 
+// What every workgroup of an LP needs to know about the pass it works on.
+struct PassView {
+  long long k;
+  int nl, s_new;
+  const int* live;  // live history slots, oldest first (LDS)
+  bool eval, init, kkt, hist_on, skip0;
+};
+
+__device__ __forceinline__ PassView make_view(const LPDesc& d, long long k, int nl, int s_new, const int* live,
+                                              bool eval) {
+  PassView v;
+  v.k = k;
+  v.nl = nl;
+  v.s_new = s_new;
+  v.live = live;
+  v.eval = eval;
+  v.init = !eval && k == 0;
+  v.kkt = eval || (!v.init && d.kkt_every > 0 && (k % d.kkt_every) == 0);
+  v.hist_on = !eval && !v.init;
+  // a full memory replaces its oldest column: that column takes no dots
+  v.skip0 = nl > 0 && live[0] == s_new;
+  return v;
+}
+
+// One pass over one LP.  COH is set inside the persistent loop kernel, where
+// other workgroups of the launch read what this one writes: the iterates and
+// x_bar are written and read at agent scope.  Everything else of a row is
+// read and written only by the workgroup that owns the row, except for split
+// rows, which are finished by whichever part arrives last: their epilogue
+// (row_coh) reads and writes everything of the row at agent scope.
+template <typename T, int MT, int PASS, bool COH>
+struct PassCtx {
+  using DT = Dot<MT>;
+  const LPDesc* dp;
+  PassView v;
+  int n, N;
+  const T* ucur;  // u^k
+  T* unext;       // u^{k-1} on entry, u_hat^{k+1} on exit
+  T* gcur;
+  const T* gprev;
+  T* dG;
+  T* W;
+  T* xbar;
+  const T* dhat;
+  const int* ptr;
+  const int* idx;
+  const T* val;
+  const int* rmap;
+  const T* gv1;  // pass A gathers y^k; pass B gathers x_bar (and x^k for KKT)
+  const T* gv2;
+  const T* cq;
+  const T* lov;
+  const T* hiv;
+  const unsigned char* rtype;
+  double beta, tau, sigma;
+  bool two;
+
+  __device__ __forceinline__ PassCtx(const LPDesc* d, const PassView& pv) : dp(d), v(pv) {
+    n = d->n;
+    N = d->N;
+    const int par = (int)(pv.k & 1);
+    ucur = (const T*)d->u[par];
+    unext = (T*)d->u[par ^ 1];
+    gcur = (T*)d->g[par];
+    gprev = (const T*)d->g[par ^ 1];
+    dG = (T*)d->dG;
+    W = (T*)d->W;
+    xbar = (T*)d->xbar;
+    dhat = (const T*)d->dhat;
+    ptr = PASS == 0 ? d->colptr : d->rowptr;
+    idx = PASS == 0 ? d->rowidx : d->colidx;
+    val = (const T*)(PASS == 0 ? d->valT : d->val);
+    rmap = PASS == 0 ? d->rmapA : d->rmapB;
+    gv1 = PASS == 0 ? ucur + n : (pv.eval ? ucur : (const T*)xbar);
+    gv2 = ucur;
+    cq = (const T*)(PASS == 0 ? d->c : d->q);
+    lov = (const T*)d->lo;
+    hiv = (const T*)d->hi;
+    rtype = d->rowtype;
+    beta = d->beta;
+    tau = d->tau;
+    sigma = d->sigma;
+    two = PASS == 1 && pv.kkt && !pv.eval;
+  }
+
+  __device__ __forceinline__ T gather(const T* gv, int i) const {
+    if constexpr (COH) return ldc(gv, i);
+    return gv[i];
+  }
+  __device__ __forceinline__ T ld(const T* p, int i, bool c) const {
+    if constexpr (COH) {
+      if (c) return ldc(p, i);
+    }
+    return p[i];
+  }
+  __device__ __forceinline__ void st(T* p, int i, T x, bool c) const {
+    if constexpr (COH) {
+      if (c) {
+        stc(p, i, x);
+        return;
+      }
+    }
+    p[i] = x;
+  }
+
+  // ---- epilogue, part 1: loads ----
+  __device__ __forceinline__ void load_row(int r, RowIn<T, MT>& in, bool row_coh) const {
+    const int e = PASS == 0 ? r : n + r;
+    // iterates are always written at agent scope in the loop kernel (other
+    // workgroups gather them), so they are read back the same way
+    in.u = ld(ucur, e, true);
+    in.cq = cq[r];
+    if (PASS == 0) {
+      in.lo = lov[r];
+      in.hi = hiv[r];
+    } else {
+      in.ge = rtype[r];
+    }
+    if (v.hist_on) {
+      in.up = ld(unext, e, true);
+      in.gp = ld(gprev, e, row_coh);
+      in.dh = dhat[e];
+#pragma unroll
+      for (int t = 0; t < MT; ++t)
+        if (t < v.nl && !(t == 0 && v.skip0)) in.hv[t] = ld(dG + (size_t)v.live[t] * N, e, row_coh);
+    }
+  }
+
+  // ---- epilogue, part 2: eq. pdhg update, residual, history, dots, KKT sums ----
+  __device__ __forceinline__ void finish_row(int r, const RowIn<T, MT>& in, double s1, double s2, double* accv,
+                                             bool row_coh) const {
+    const int e = PASS == 0 ? r : n + r;
+    T g = (T)0;
+    if (!v.eval) {
+      T nx;
+      if (PASS == 0) {
+        // x_hat = P_X(x - tau (c - K^T y)), x_bar = 2 x_hat - x
+        nx = clampT((T)((double)in.u - tau * ((double)in.cq - s1)), in.lo, in.hi);
+        st(xbar, r, (T)(2.0 * (double)nx - (double)in.u), true);
+      } else {
+        // y_hat = P_Y(y + sigma (q - K x_bar))
+        nx = (T)((double)in.u + sigma * ((double)in.cq - s1));
+        if (in.ge && nx < (T)0) nx = (T)0;
+      }
+      g = (T)((double)nx - (double)in.u);
+      st(gcur, e, g, row_coh);
+      st(unext, e, nx, true);
+      accv[DT::GG] += (double)g * (double)g;
+    }
+    if (v.hist_on) {
+      // memory pair of this pass: dg = g^k - g^{k-1}, du = u^k - u^{k-1}
+      const T dgT = (T)((double)g - (double)in.gp);
+      const T duT = (T)((double)in.u - (double)in.up);
+      const double dg = (double)dgT, du = (double)duT, gd = (double)g;
+      st(dG + (size_t)v.s_new * N, e, dgT, row_coh);
+      st(W + (size_t)v.s_new * N, e, (T)(du + beta * (double)in.dh * dg), row_coh);
+      accv[DT::DGDG] += dg * dg;
+      accv[DT::DGG] += dg * gd;
+      accv[DT::DU2] += du * du;
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+        if (t < v.nl && !(t == 0 && v.skip0)) {
+          const double hv = (double)in.hv[t];
+          accv[DT::G + t] += dg * hv;
+          accv[DT::R + t] += gd * hv;
+        }
+      }
+    }
+    if (v.kkt) {
+      if (PASS == 0) {
+        const bool lf = isfinite((double)in.lo), uf = isfinite((double)in.hi);
+        const double cj = (double)in.cq;
+        const double lamv = proj_lambda(cj - s1, lf, uf);
+        accv[DT::KA0] += cj * (double)in.u;
+        accv[DT::KA1] += (lf ? (double)in.lo * fmax(lamv, 0.0) : 0.0) - (uf ? (double)in.hi * fmax(-lamv, 0.0) : 0.0);
+        const double rd = cj - s1 - lamv;
+        accv[DT::KA2] += rd * rd;
+        if (v.eval) ((T*)dp->lam)[r] = (T)lamv;
+      } else {
+        const double kx = v.eval ? s1 : s2;  // (K x^k)_i
+        const double qi = (double)in.cq;
+        accv[DT::KB0] += qi * (double)in.u;
+        double res = qi - kx;
+        if (in.ge && res < 0.0) res = 0.0;
+        accv[DT::KB1] += res * res;
+      }
+    }
+  }
+
+  // ---- multi-row chunk: stage products in LDS, reduce rows, epilogue ----
+  __device__ __forceinline__ void multi_chunk(const Chunk& ch, double* acc, double* s_prod, double* s_tmp) const {
+    constexpr int UNR = CHUNK_NNZ / BLOCK;  // staged entries per thread
+    const int tid = threadIdx.x;
+    const int r0 = ch.r0, r1 = ch.r1, kb = ch.k0, ke = ch.k1, tpr = ch.tpr;
+    const bool blockmode = tpr == BLOCK;
+    const int grp = blockmode ? 0 : tid / tpr;
+    const int lane_r = blockmode ? tid : tid % tpr;
+    const int r = r0 + grp;  // this thread group's position (at most one)
+    const bool has_row = r < r1 && (!blockmode || tid == 0);
+    const int row = has_row ? rmap[r] : 0;  // its original row
+    int ci[UNR];
+    T vv[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int q = kb + tid + u * BLOCK;
+      ci[u] = 0;
+      vv[u] = (T)0;
+      if (q < ke) {
+        ci[u] = idx[q];
+        vv[u] = val[q];
+      }
+    }
+    int a0 = 0, a1 = 0;
+    RowIn<T, MT> rin;
+    if (r < r1) {
+      a0 = ptr[r] - kb;
+      a1 = ptr[r + 1] - kb;
+      if (has_row && lane_r == 0) load_row(row, rin, false);
+    }
+    double sum1 = 0.0, sum2 = 0.0;
+    const int nsweep = two ? 2 : 1;
+    for (int sw = 0; sw < nsweep; ++sw) {
+      const T* gv = sw == 0 ? gv1 : gv2;
+      T gg[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) gg[u] = (kb + tid + u * BLOCK < ke) ? gather(gv, ci[u]) : (T)0;
+      __syncthreads();  // s_prod is free
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int q = tid + u * BLOCK;
+        if (kb + q < ke) s_prod[q] = (double)vv[u] * (double)gg[u];
+      }
+      __syncthreads();
+      double sres;
+      if (blockmode) {
+        double s = 0.0;
+        for (int q = a0 + tid; q < a1; q += BLOCK) s += s_prod[q];
+        sres = block_sum(s, s_tmp);
+      } else {
+        double s = 0.0;
+        for (int q = a0 + lane_r; q < a1; q += tpr) s += s_prod[q];
+        for (int off = 1; off < tpr; off <<= 1) s += __shfl_xor(s, off, 64);
+        sres = s;
+      }
+      if (sw == 0) sum1 = sres; else sum2 = sres;
+    }
+    if (has_row && lane_r == 0) finish_row(row, rin, sum1, sum2, acc, false);
+  }
+
+  // ---- one part of a split row: partial sums; the last part to arrive
+  // finishes the row and writes its record.  True in that workgroup.
+  __device__ __forceinline__ bool split_part(const Chunk& ch, const SplitRow* splits, double* splitpart,
+                                             unsigned int* splitcnt, double* rec, double* s_tmp, double* s_racc,
+                                             int* s_own) const {
+    constexpr int UNR = CHUNK_NNZ / BLOCK;
+    const int tid = threadIdx.x;
+    const SplitRow sr = splits[ch.split];
+    const int kb = ch.k0, ke = ch.k1, part = ch.tpr;
+    double s1 = 0.0, s2 = 0.0;
+    for (int base = kb; base < ke; base += UNR * BLOCK) {
+      int ci[UNR];
+      T vv[UNR], g1[UNR], g2[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int q = base + tid + u * BLOCK;
+        ci[u] = 0;
+        vv[u] = (T)0;
+        if (q < ke) {
+          ci[u] = idx[q];
+          vv[u] = val[q];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const bool ok = base + tid + u * BLOCK < ke;
+        g1[u] = ok ? gather(gv1, ci[u]) : (T)0;
+        g2[u] = (ok && two) ? gather(gv2, ci[u]) : (T)0;
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        s1 += (double)vv[u] * (double)g1[u];
+        s2 += (double)vv[u] * (double)g2[u];
+      }
+    }
+    s1 = block_sum(s1, s_tmp);
+    s2 = block_sum(s2, s_tmp);
+    if (tid == 0) {
+      st_agent(&splitpart[2 * (sr.part0 + part) + 0], s1);
+      st_agent(&splitpart[2 * (sr.part0 + part) + 1], s2);
+      *s_own = arrive(&splitcnt[ch.split], (unsigned)sr.nparts);
+    }
+    __syncthreads();
+    if (!*s_own) return false;
+    if (tid == 0) {
+      reset_counter(&splitcnt[ch.split]);
+      RowIn<T, MT> in;
+      const int row = rmap[sr.row];
+      load_row(row, in, true);
+      double t1 = 0.0, t2 = 0.0;
+      for (int p = 0; p < sr.nparts; ++p) {
+        t1 += ld_coh(splitpart, 2 * (sr.part0 + p) + 0);
+        t2 += ld_coh(splitpart, 2 * (sr.part0 + p) + 1);
+      }
+      for (int q = 0; q < DT::COUNT; ++q) s_racc[q] = 0.0;
+      finish_row(row, in, t1, t2, s_racc, true);
+      double* rp = rec + (size_t)sr.leaf * NDOT;
+      for (int q = 0; q < DT::COUNT; ++q) st_agent(&rp[q], s_racc[q]);
+    }
+    return true;
+  }
+};
+
+// The record of one workgroup: its threads' sums, added per wave (DPP) and
+// then over the four waves in order.
+template <int MT>
+__device__ __forceinline__ void write_record(double* acc, double (*s_red)[NDOT], double* out) {
+  constexpr int C = Dot<MT>::COUNT;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+  for (int q = 0; q < C; ++q) acc[q] = wave_sum(acc[q]);
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < C; ++q) s_red[wv][q] = acc[q];
+  }
+  __syncthreads();
+  if (tid < C) st_agent(&out[tid], ((s_red[0][tid] + s_red[1][tid]) + s_red[2][tid]) + s_red[3][tid]);
+}
+
 template <typename T, int MT, int PASS>
 __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
   using DT = Dot<MT>;
-  constexpr int UNR = CHUNK_NNZ / BLOCK;  // staged entries per thread
-  constexpr int RPT = ROWS_PER_THREAD;    // rows per thread in a multi-row chunk
   __shared__ double s_prod[CHUNK_NNZ];
   __shared__ double s_red[BLOCK / 64][NDOT];
   __shared__ double s_fin[NDOT];
@@ -462,127 +811,10 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
   Scalars* sc = dp->sc;
   const bool eval = a.mode == MODE_EVAL;
   if (!eval && sc->status != ST_RUNNING) return;
-
-  const long long k = sc->k;
-  const int nl = sc->nlive;
-  const int s_new = sc->newslot;
-  const int live0 = sc->live[0];
   if (tid < MAXM) s_live[tid] = sc->live[tid];
-  const bool skip0 = nl > 0 && live0 == s_new;
-  const int kkt_every = dp->kkt_every;
-  const bool init = !eval && k == 0;
-  const bool kkt = eval || (!init && kkt_every > 0 && (k % kkt_every) == 0);
-  const bool hist_on = !eval && !init;
-
-  const int n = dp->n, N = dp->N;
-  const int par = (int)(k & 1);
-  const T* __restrict__ ucur = (const T*)dp->u[par];
-  T* __restrict__ unext = (T*)dp->u[par ^ 1];  // u^{k-1} on entry, u_hat^{k+1} on exit
-  T* __restrict__ gcur = (T*)dp->g[par];
-  const T* __restrict__ gprev = (const T*)dp->g[par ^ 1];
-  T* __restrict__ dG = (T*)dp->dG;
-  T* __restrict__ W = (T*)dp->W;
-  const T* __restrict__ dhat = (const T*)dp->dhat;
-  const double beta = dp->beta, tau = dp->tau, sigma = dp->sigma;
-  const int* __restrict__ ptr = PASS == 0 ? dp->colptr : dp->rowptr;
-  const int* __restrict__ idx = PASS == 0 ? dp->rowidx : dp->colidx;
-  const T* __restrict__ val = (const T*)(PASS == 0 ? dp->valT : dp->val);
-  const int* __restrict__ rmap = PASS == 0 ? dp->rmapA : dp->rmapB;
-  // gathered vectors: pass A gathers y^k; pass B gathers x_bar (and x^k for KKT)
-  const T* gv1 = PASS == 0 ? ucur + n : (eval ? ucur : (const T*)dp->xbar);
-  const T* gv2 = ucur;
-  const T* __restrict__ cq = (const T*)(PASS == 0 ? dp->c : dp->q);
-  const T* __restrict__ lov = (const T*)dp->lo;
-  const T* __restrict__ hiv = (const T*)dp->hi;
-  const unsigned char* __restrict__ rtype = dp->rowtype;
-  const bool two = PASS == 1 && kkt && !eval;
-
-  double acc[DT::COUNT];
-#pragma unroll
-  for (int q = 0; q < DT::COUNT; ++q) acc[q] = 0.0;
-
-  __syncthreads();  // s_live
-
-  // ---- epilogue, part 1: loads ----
-  auto load_row = [&](int r, RowIn<T, MT>& in) {
-    const int e = PASS == 0 ? r : n + r;
-    in.u = ucur[e];
-    in.cq = cq[r];
-    if (PASS == 0) {
-      in.lo = lov[r];
-      in.hi = hiv[r];
-    } else {
-      in.ge = rtype[r];
-    }
-    if (hist_on) {
-      in.up = unext[e];
-      in.gp = gprev[e];
-      in.dh = dhat[e];
-#pragma unroll
-      for (int t = 0; t < MT; ++t)
-        if (t < nl && !(t == 0 && skip0)) in.hv[t] = dG[(size_t)s_live[t] * N + e];
-    }
-  };
-
-  // ---- epilogue, part 2: eq. pdhg update, residual, history, dots, KKT sums ----
-  auto finish_row = [&](int r, const RowIn<T, MT>& in, double s1, double s2, auto* accv) {
-    const int e = PASS == 0 ? r : n + r;
-    T g = (T)0;
-    if (!eval) {
-      T nx;
-      if (PASS == 0) {
-        // x_hat = P_X(x - tau (c - K^T y)), x_bar = 2 x_hat - x
-        nx = clampT((T)((double)in.u - tau * ((double)in.cq - s1)), in.lo, in.hi);
-        ((T*)dp->xbar)[r] = (T)(2.0 * (double)nx - (double)in.u);
-      } else {
-        // y_hat = P_Y(y + sigma (q - K x_bar))
-        nx = (T)((double)in.u + sigma * ((double)in.cq - s1));
-        if (in.ge && nx < (T)0) nx = (T)0;
-      }
-      g = (T)((double)nx - (double)in.u);
-      gcur[e] = g;
-      unext[e] = nx;
-      accv[DT::GG] += (double)g * (double)g;
-    }
-    if (hist_on) {
-      // memory pair of this pass: dg = g^k - g^{k-1}, du = u^k - u^{k-1}
-      const T dgT = (T)((double)g - (double)in.gp);
-      const T duT = (T)((double)in.u - (double)in.up);
-      const double dg = (double)dgT, du = (double)duT, gd = (double)g;
-      dG[(size_t)s_new * N + e] = dgT;
-      W[(size_t)s_new * N + e] = (T)(du + beta * (double)in.dh * dg);
-      accv[DT::DGDG] += dg * dg;
-      accv[DT::DGG] += dg * gd;
-      accv[DT::DU2] += du * du;
-#pragma unroll
-      for (int t = 0; t < MT; ++t) {
-        if (t < nl && !(t == 0 && skip0)) {
-          const double v = (double)in.hv[t];
-          accv[DT::G + t] += dg * v;
-          accv[DT::R + t] += gd * v;
-        }
-      }
-    }
-    if (kkt) {
-      if (PASS == 0) {
-        const bool lf = isfinite((double)in.lo), uf = isfinite((double)in.hi);
-        const double cj = (double)in.cq;
-        const double lamv = proj_lambda(cj - s1, lf, uf);
-        accv[DT::KA0] += cj * (double)in.u;
-        accv[DT::KA1] += (lf ? (double)in.lo * fmax(lamv, 0.0) : 0.0) - (uf ? (double)in.hi * fmax(-lamv, 0.0) : 0.0);
-        const double rd = cj - s1 - lamv;
-        accv[DT::KA2] += rd * rd;
-        if (eval) ((T*)dp->lam)[r] = (T)lamv;
-      } else {
-        const double kx = eval ? s1 : s2;  // (K x^k)_i
-        const double qi = (double)in.cq;
-        accv[DT::KB0] += qi * (double)in.u;
-        double res = qi - kx;
-        if (in.ge && res < 0.0) res = 0.0;
-        accv[DT::KB1] += res * res;
-      }
-    }
-  };
+  __syncthreads();
+  const PassView v = make_view(*dp, sc->k, sc->nlive, sc->newslot, s_live, eval);
+  const PassCtx<T, MT, PASS, false> P(dp, v);
 
   // ---- reduction tree: the last child of a node adds the children in order.
   // Every thread calls it; returns true in the block that completed the root.
@@ -632,140 +864,332 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
     unsigned long long* lsc = reinterpret_cast<unsigned long long*>(&s_sc);
     for (int q = tid; q < SW; q += BLOCK) lsc[q] = gsc[q];
     __syncthreads();
-    if (wv == 0) final_step<MT>(*dp, &s_sc, s_fin, eval, kkt, init, &s_work, lane);
+    if (wv == 0) final_step<MT>(*dp, &s_sc, s_fin, eval, v.kkt, v.init, &s_work, lane);
     __syncthreads();
     for (int q = tid; q < SW; q += BLOCK) gsc[q] = lsc[q];
   };
 
   if (bw.kind == 1) {
-    // ---- one part of a split row: partial sums; the last part finishes ----
     const Chunk ch = a.chunks[bw.c0];
-    const SplitRow sr = a.splits[ch.split];
-    const int kb = ch.k0, ke = ch.k1, part = ch.tpr;
-    double s1 = 0.0, s2 = 0.0;
-    for (int base = kb; base < ke; base += UNR * BLOCK) {
-      int ci[UNR];
-      T vv[UNR], g1[UNR], g2[UNR];
-#pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        const int q = base + tid + u * BLOCK;
-        ci[u] = 0;
-        vv[u] = (T)0;
-        if (q < ke) {
-          ci[u] = idx[q];
-          vv[u] = val[q];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        const bool ok = base + tid + u * BLOCK < ke;
-        g1[u] = ok ? gv1[ci[u]] : (T)0;
-        g2[u] = (ok && two) ? gv2[ci[u]] : (T)0;
-      }
-#pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        s1 += (double)vv[u] * (double)g1[u];
-        s2 += (double)vv[u] * (double)g2[u];
-      }
+    if (P.split_part(ch, a.splits, a.splitpart, a.splitcnt, a.rec, s_tmp, s_racc, &s_own)) {
+      if (PASS == 1 && climb(a.splits[ch.split].parent)) finish_lp();
     }
-    s1 = block_sum(s1, s_tmp);
-    s2 = block_sum(s2, s_tmp);
-    if (tid == 0) {
-      st_agent(&a.splitpart[2 * (sr.part0 + part) + 0], s1);
-      st_agent(&a.splitpart[2 * (sr.part0 + part) + 1], s2);
-      s_own = arrive(&a.splitcnt[ch.split], (unsigned)sr.nparts);
-    }
-    __syncthreads();
-    if (!s_own) return;
-    if (tid == 0) {
-      reset_counter(&a.splitcnt[ch.split]);
-      RowIn<T, MT> in;
-      const int row = rmap[sr.row];
-      load_row(row, in);
-      double t1 = 0.0, t2 = 0.0;
-      for (int p = 0; p < sr.nparts; ++p) {
-        t1 += ld_coh(a.splitpart, 2 * (sr.part0 + p) + 0);
-        t2 += ld_coh(a.splitpart, 2 * (sr.part0 + p) + 1);
-      }
-      for (int q = 0; q < DT::COUNT; ++q) s_racc[q] = 0.0;
-      finish_row(row, in, t1, t2, s_racc);
-      double* rp = a.rec + (size_t)sr.leaf * NDOT;
-      for (int q = 0; q < DT::COUNT; ++q) st_agent(&rp[q], s_racc[q]);
-    }
-    if (PASS == 1 && climb(sr.parent)) finish_lp();
     return;
   }
 
-  for (int c = bw.c0; c < bw.c1; ++c) {
-    // ---- multi-row chunk: stage products in LDS, reduce rows, epilogue ----
-    const Chunk ch = a.chunks[c];
-    const int r0 = ch.r0, r1 = ch.r1, kb = ch.k0, ke = ch.k1, tpr = ch.tpr;
-    const bool blockmode = tpr == BLOCK;
-    const int grp = blockmode ? 0 : tid / tpr;
-    const int lane_r = blockmode ? tid : tid % tpr;
-    const int r = r0 + grp;  // this thread group's position (at most one)
-    const bool has_row = r < r1 && (!blockmode || tid == 0);
-    const int row = has_row ? rmap[r] : 0;  // its original row
-    int ci[UNR];
-    T vv[UNR];
+  double acc[DT::COUNT];
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      const int q = kb + tid + u * BLOCK;
-      ci[u] = 0;
-      vv[u] = (T)0;
-      if (q < ke) {
-        ci[u] = idx[q];
-        vv[u] = val[q];
-      }
-    }
-    int a0 = 0, a1 = 0;
-    RowIn<T, MT> rin;
-    if (r < r1) {
-      a0 = ptr[r] - kb;
-      a1 = ptr[r + 1] - kb;
-      if (has_row && lane_r == 0) load_row(row, rin);
-    }
-    double sum1 = 0.0, sum2 = 0.0;
-    const int nsweep = two ? 2 : 1;
-    for (int sw = 0; sw < nsweep; ++sw) {
-      const T* gv = sw == 0 ? gv1 : gv2;
-      T gg[UNR];
-#pragma unroll
-      for (int u = 0; u < UNR; ++u) gg[u] = (kb + tid + u * BLOCK < ke) ? gv[ci[u]] : (T)0;
-      __syncthreads();  // s_prod is free
-#pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        const int q = tid + u * BLOCK;
-        if (kb + q < ke) s_prod[q] = (double)vv[u] * (double)gg[u];
-      }
-      __syncthreads();
-      double sres;
-      if (blockmode) {
-        double s = 0.0;
-        for (int q = a0 + tid; q < a1; q += BLOCK) s += s_prod[q];
-        sres = block_sum(s, s_tmp);
-      } else {
-        double s = 0.0;
-        for (int q = a0 + lane_r; q < a1; q += tpr) s += s_prod[q];
-        for (int off = 1; off < tpr; off <<= 1) s += __shfl_xor(s, off, 64);
-        sres = s;
-      }
-      if (sw == 0) sum1 = sres; else sum2 = sres;
-    }
-    if (has_row && lane_r == 0) finish_row(row, rin, sum1, sum2, acc);
-  }
+  for (int q = 0; q < DT::COUNT; ++q) acc[q] = 0.0;
+  for (int c = bw.c0; c < bw.c1; ++c) P.multi_chunk(a.chunks[c], acc, s_prod, s_tmp);
+  write_record<MT>(acc, s_red, a.rec + (size_t)bw.leaf * NDOT);
+  if (PASS == 1 && climb(bw.parent)) finish_lp();
+}
 
-  // ---- this workgroup's record, then (dual pass) up the tree ----
+// ---------------------------------------------------------------------------
+// persistent loop kernel: many loop passes of Alg 2 / Alg 3 in one launch
+// ---------------------------------------------------------------------------
+//
+// Every LP of the launch owns a group of workgroups (all resident: the launch
+// is cooperative).  A workgroup always works on the same units of the CSC and
+// CSR passes, so the rows it finishes (iterate, residual, history) stay its
+// own from pass to pass; only the gathered vectors, x_bar, the records and
+// the decisions cross workgroups, at agent scope.  Per pass:
+//   phase A over the workgroup's CSC units, group barrier,
+//   phase B over its CSR units, arrival;
+//   rank 0 of the group adds the records of both phases in a fixed order,
+//   takes the decisions (final_step) and publishes them;
+//   on Anderson steps every workgroup mixes the entries it owns, then a group
+//   barrier (the next phase A gathers the new y).
+// Every wait is bounded: after about four seconds, or once another
+// workgroup of the LP has given up, it returns false, the group leaves the
+// loop and the launch reports the failure in *err.
+
+__device__ __forceinline__ unsigned int ld_u32(const unsigned int* p) {
+  return __hip_atomic_load(const_cast<unsigned int*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0 only: wait until *p >= target.
+__device__ bool wait_geq(const unsigned int* p, unsigned int target, unsigned int* abortw, unsigned long long ticks) {
+  const unsigned long long t0 = wall_clock64();
+  for (unsigned int it = 0;; ++it) {
+    if (ld_u32(p) >= target) return true;
+    if ((it & 15u) == 15u) {
+      if (ld_u32(abortw) != 0u) return false;
+      if (wall_clock64() - t0 > ticks) {
+        __hip_atomic_store(abortw, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+      }
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+// Wave 0 only: wait until the NSUB sub-counters at `sub` add up to at least
+// `target` (lane q < NSUB reads sub-counter q).
+__device__ bool wait_sum_geq(const unsigned int* sub, unsigned int target, unsigned int* abortw,
+                             unsigned long long ticks) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long t0 = wall_clock64();
+  for (unsigned int it = 0;; ++it) {
+    unsigned int v = lane < NSUB ? ld_u32(sub + lane * SUB_STRIDE) : 0u;
 #pragma unroll
-  for (int q = 0; q < DT::COUNT; ++q) acc[q] = wave_sum(acc[q]);
-  if (lane == 0) {
-#pragma unroll
-    for (int q = 0; q < DT::COUNT; ++q) s_red[wv][q] = acc[q];
+    for (int off = 1; off < NSUB; off <<= 1) v += __shfl_xor(v, off, 64);
+    if (__shfl(v, 0, 64) >= target) return true;
+    if ((it & 15u) == 15u) {
+      const unsigned int ab = __shfl(lane == 0 ? ld_u32(abortw) : 0u, 0, 64);
+      if (ab != 0u) return false;
+      if (wall_clock64() - t0 > ticks) {
+        if (lane == 0) __hip_atomic_store(abortw, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+      }
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+// Count this workgroup's arrival on its sub-counter (thread 0 only).
+__device__ __forceinline__ void arrive_sub(unsigned int* sub, int rank) {
+  __hip_atomic_fetch_add(sub + (rank % NSUB) * SUB_STRIDE, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Group barrier: every wave's stores complete, one arrival per workgroup,
+// wait for `target` arrivals.  Every thread calls it.
+__device__ __forceinline__ bool group_barrier(unsigned int* sub, int rank, unsigned int target, unsigned int* abortw,
+                                              unsigned long long ticks, int* s_ok) {
+  wait_stores();
+  __syncthreads();
+  if (threadIdx.x == 0) arrive_sub(sub, rank);
+  if (threadIdx.x < 64) {
+    const bool ok = wait_sum_geq(sub, target, abortw, ticks);
+    if (threadIdx.x == 0) *s_ok = ok ? 1 : 0;
   }
   __syncthreads();
-  if (tid < DT::COUNT)
-    st_agent(&a.rec[(size_t)bw.leaf * NDOT + tid], ((s_red[0][tid] + s_red[1][tid]) + s_red[2][tid]) + s_red[3][tid]);
-  if (PASS == 1 && climb(bw.parent)) finish_lp();
+  return *s_ok != 0;
+}
+
+// Fixed-order sum of records: thread (q, s) adds records s, s + S, ... of
+// slot q; the S partial sums are then added in order (and, with `add`, to
+// what s_fin holds).
+template <int MT>
+__device__ __forceinline__ void reduce_records(const double* rec, int nrec, double* s_part, double* s_fin,
+                                               bool add) {
+  constexpr int C = Dot<MT>::COUNT;
+  constexpr int QW = C <= 32 ? 32 : 64;
+  constexpr int S = BLOCK / QW;
+  const int tid = threadIdx.x, q = tid % QW, s = tid / QW;
+  double sum = 0.0;
+  if (q < C) {
+#pragma unroll 8
+    for (int r = s; r < nrec; r += S) sum += ld_coh(rec, r * NDOT + q);
+  }
+  s_part[tid] = sum;
+  __syncthreads();
+  if (tid < C) {
+    double f = 0.0;
+    for (int t = 0; t < S; ++t) f += s_part[t * QW + tid];
+    s_fin[tid] = add ? s_fin[tid] + f : f;
+  }
+  __syncthreads();
+}
+
+// Anderson mix (Alg 2: u^{k+1} = P(u^k + beta D-hat g^k - sum_t gamma_t W_t))
+// of the entries this workgroup owns: the columns of its CSC units, the rows
+// of its CSR units, and the split rows whose part 0 it holds (at agent scope).
+template <typename T>
+__device__ __forceinline__ void mix_owned(const LoopArgs& a, const LoopWG& wg, const LPDesc* dp, const Bcast& bc) {
+  const int par = (int)((bc.k - 1) & 1);  // the pass that decided was k-1
+  const T* ucur = (const T*)dp->u[par];
+  T* unext = (T*)dp->u[par ^ 1];
+  const T* g = (const T*)dp->g[par];
+  const T* W = (const T*)dp->W;
+  const T* dhat = (const T*)dp->dhat;
+  const T* lov = (const T*)dp->lo;
+  const T* hiv = (const T*)dp->hi;
+  const int n = dp->n, N = dp->N, nmix = bc.nmix;
+  const double beta = dp->beta;
+  auto mix1 = [&](int e, bool c) {
+    double v = (double)ldc(ucur, e) + beta * (double)dhat[e] * (double)(c ? ldc(g, e) : g[e]);
+    for (int t = 0; t < nmix; ++t) {
+      const T* wc = W + (size_t)bc.mixslot[t] * N;
+      v -= bc.gamma[t] * (double)(c ? ldc(wc, e) : wc[e]);
+    }
+    T r = (T)v;
+    if (e < n) {
+      r = clampT(r, lov[e], hiv[e]);
+    } else if (dp->rowtype[e - n] != 0 && r < (T)0) {
+      r = (T)0;
+    }
+    stc(unext, e, r);
+  };
+  for (int pass = 0; pass < 2; ++pass) {
+    const BlockWork* bws = pass == 0 ? a.blocksA : a.blocksB;
+    const int u0 = pass == 0 ? wg.a0 : wg.b0, u1 = pass == 0 ? wg.a1 : wg.b1;
+    const int* rmap = pass == 0 ? dp->rmapA : dp->rmapB;
+    const int off = pass == 0 ? 0 : n;
+    for (int u = u0; u < u1; ++u) {
+      const BlockWork bw = bws[u];
+      if (bw.kind == 1) {
+        const Chunk ch = a.chunks[bw.c0];
+        if (ch.tpr == 0 && threadIdx.x == 0) mix1(off + rmap[a.splits[ch.split].row], true);
+        continue;
+      }
+      for (int c = bw.c0; c < bw.c1; ++c) {
+        const Chunk ch = a.chunks[c];
+        for (int pos = ch.r0 + (int)threadIdx.x; pos < ch.r1; pos += BLOCK) mix1(off + rmap[pos], false);
+      }
+    }
+  }
+}
+
+template <typename T, int MT, int PASS>
+__device__ __forceinline__ void loop_units(const LoopArgs& a, const LPDesc* dp, const PassView& v, int u0, int u1,
+                                           double* s_prod, double (*s_red)[NDOT], double* s_tmp, double* s_racc,
+                                           int* s_own) {
+  using DT = Dot<MT>;
+  const PassCtx<T, MT, PASS, true> P(dp, v);
+  const BlockWork* bws = PASS == 0 ? a.blocksA : a.blocksB;
+  for (int u = u0; u < u1; ++u) {
+    const BlockWork bw = bws[u];
+    if (bw.kind == 1) {
+      P.split_part(a.chunks[bw.c0], a.splits, a.splitpart, a.splitcnt, a.rec, s_tmp, s_racc, s_own);
+      __syncthreads();  // s_own, s_racc and s_tmp are reused
+      continue;
+    }
+    double acc[DT::COUNT];
+#pragma unroll
+    for (int q = 0; q < DT::COUNT; ++q) acc[q] = 0.0;
+    for (int c = bw.c0; c < bw.c1; ++c) P.multi_chunk(a.chunks[c], acc, s_prod, s_tmp);
+    write_record<MT>(acc, s_red, a.rec + (size_t)bw.leaf * NDOT);
+  }
+}
+
+template <typename T, int MT>
+__global__ __launch_bounds__(BLOCK) void k_loop(LoopArgs a) {
+  __shared__ double s_prod[CHUNK_NNZ];
+  __shared__ double s_red[BLOCK / 64][NDOT];
+  __shared__ double s_fin[NDOT];
+  __shared__ double s_racc[NDOT];
+  __shared__ double s_tmp[4];
+  __shared__ double s_part[BLOCK];
+  __shared__ int s_own;
+  __shared__ int s_ok;
+  __shared__ Bcast s_bc;
+  __shared__ SolveWork s_work;
+  __shared__ Scalars s_sc;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const LoopWG wg = a.wgs[blockIdx.x];
+  const LPDesc* dp = a.lps + wg.lp;
+  const LoopLP L = a.llp[wg.lp];
+  LoopSync* sy = a.sync + wg.lp;
+  Scalars* sc = dp->sc;
+  // Scalars change only at the end of the launch (rank 0 writes them back
+  // after every workgroup of the group has passed the first barrier).
+  if (sc->status != ST_RUNNING || sc->k < 1) return;
+  const bool root = wg.rank == 0;
+  if (tid == 0) {
+    s_bc.k = sc->k;
+    s_bc.status = sc->status;
+    s_bc.branch = sc->branch;
+    s_bc.nmix = 0;
+    s_bc.nlive = sc->nlive;
+    s_bc.newslot = sc->newslot;
+  }
+  if (tid < MAXM) s_bc.live[tid] = sc->live[tid];
+  constexpr int SW = sizeof(Scalars) / 8;
+  unsigned long long* gsc = reinterpret_cast<unsigned long long*>(sc);
+  unsigned long long* lsc = reinterpret_cast<unsigned long long*>(&s_sc);
+  if (root)
+    for (int q = tid; q < SW; q += BLOCK) lsc[q] = gsc[q];
+  __syncthreads();
+
+  constexpr int BCW = sizeof(Bcast) / 8;
+  double* bcw_l = reinterpret_cast<double*>(&s_bc);
+  double* bcw_g = reinterpret_cast<double*>(a.bc + wg.lp);
+  const unsigned long long ticks = a.timeout_ticks;
+  unsigned int nbar = 0;
+  bool ok = true;
+  for (long long it = 0; it < a.max_passes; ++it) {
+    const PassView v = make_view(*dp, s_bc.k, s_bc.nlive, s_bc.newslot, s_bc.live, false);
+    // ---- phase A: K^T y and the primal update ----
+    loop_units<T, MT, 0>(a, dp, v, wg.a0, wg.a1, s_prod, s_red, s_tmp, s_racc, &s_own);
+    ++nbar;
+    if (!group_barrier(sy->bar, wg.rank, nbar * (unsigned)L.nwg, &sy->abort, ticks, &s_ok)) {
+      ok = false;
+      break;
+    }
+    // ---- phase B: K x_bar and the dual update ----
+    loop_units<T, MT, 1>(a, dp, v, wg.b0, wg.b1, s_prod, s_red, s_tmp, s_racc, &s_own);
+    wait_stores();
+    __syncthreads();
+    if (tid == 0) arrive_sub(sy->arr, wg.rank);
+    const unsigned int done = (unsigned int)(it + 1);
+    if (root) {
+      // ---- decisions of the pass ----
+      // the CSC records are complete since the barrier: add them while the
+      // CSR phase finishes elsewhere
+      reduce_records<MT>(a.rec + (size_t)L.leaf0 * NDOT, L.nleafA, s_part, s_fin, false);
+      if (tid < 64) {
+        const bool okw = wait_sum_geq(sy->arr, done * (unsigned)L.nwg, &sy->abort, ticks);
+        if (tid == 0) s_ok = okw ? 1 : 0;
+      }
+      __syncthreads();
+      if (!s_ok) {
+        ok = false;
+        break;
+      }
+      reduce_records<MT>(a.rec + (size_t)(L.leaf0 + L.nleafA) * NDOT, L.nleaf - L.nleafA, s_part, s_fin, true);
+      if (wv == 0) final_step<MT>(*dp, &s_sc, s_fin, false, v.kkt, false, &s_work, lane);
+      __syncthreads();
+      if (tid == 0) {
+        s_bc.k = s_sc.k;
+        s_bc.status = s_sc.status;
+        s_bc.branch = s_sc.branch;
+        s_bc.nmix = s_sc.nmix;
+        s_bc.nlive = s_sc.nlive;
+        s_bc.newslot = s_sc.newslot;
+      }
+      if (tid < MAXM) {
+        s_bc.live[tid] = s_sc.live[tid];
+        s_bc.mixslot[tid] = s_sc.mixslot[tid];
+        s_bc.gamma[tid] = s_sc.gamma[tid];
+      }
+      __syncthreads();
+      if (tid < BCW) stc(bcw_g, tid, bcw_l[tid]);
+      wait_stores();
+      __syncthreads();
+      if (tid == 0) __hip_atomic_store(&sy->flag, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      if (tid == 0) s_ok = wait_geq(&sy->flag, done, &sy->abort, ticks) ? 1 : 0;
+      __syncthreads();
+      if (!s_ok) {
+        ok = false;
+        break;
+      }
+      if (tid < BCW) bcw_l[tid] = ldc(bcw_g, tid);
+      __syncthreads();
+    }
+    if (s_bc.status != ST_RUNNING) break;
+    if (s_bc.branch == BR_AA) {
+      mix_owned<T>(a, wg, dp, s_bc);
+      ++nbar;
+      if (!group_barrier(sy->bar, wg.rank, nbar * (unsigned)L.nwg, &sy->abort, ticks, &s_ok)) {
+        ok = false;
+        break;
+      }
+    }
+  }
+  if (!ok && tid == 0) __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (root) {
+    __syncthreads();
+    if (!ok && tid == 0) {
+      s_sc.status = ST_NUMERICAL;
+      s_sc.branch = BR_NONE;
+    }
+    __syncthreads();
+    for (int q = tid; q < SW; q += BLOCK) gsc[q] = lsc[q];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -930,6 +1354,56 @@ static hipError_t launch_passes_t(const LaunchTables& t, hipStream_t st, int mod
 
 hipError_t launch_loop_pass(const LaunchTables& t, hipStream_t st, int mode, hipEvent_t* ev) {
   return t.fp64 ? launch_passes_t<double>(t, st, mode, ev) : launch_passes_t<float>(t, st, mode, ev);
+}
+
+template <typename T, int MT>
+static const void* loop_kernel() {
+  return reinterpret_cast<const void*>(&k_loop<T, MT>);
+}
+
+static const void* loop_kernel_for(bool fp64, int mt) {
+  if (fp64) {
+    if (mt <= 4) return loop_kernel<double, 4>();
+    if (mt <= 8) return loop_kernel<double, 8>();
+    if (mt <= 10) return loop_kernel<double, 10>();
+    return loop_kernel<double, 16>();
+  }
+  if (mt <= 4) return loop_kernel<float, 4>();
+  if (mt <= 8) return loop_kernel<float, 8>();
+  if (mt <= 10) return loop_kernel<float, 10>();
+  return loop_kernel<float, 16>();
+}
+
+int loop_capacity(bool fp64, int mt) {
+  int dev = 0, cus = 0, coop = 0, nb = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loop_kernel_for(fp64, mt), BLOCK, 0) != hipSuccess) return 0;
+  return nb * cus;
+}
+
+hipError_t launch_loop(const LaunchTables& t, hipStream_t st, long long passes) {
+  LoopArgs la{};
+  la.lps = t.lps;
+  la.llp = t.looplps;
+  la.wgs = t.wgs;
+  la.blocksA = t.blocksA;
+  la.blocksB = t.blocksB;
+  la.chunks = t.chunks;
+  la.splits = t.splits;
+  la.rec = t.rec;
+  la.splitpart = t.splitpart;
+  la.splitcnt = t.splitcnt;
+  la.sync = t.sync;
+  la.bc = t.bc;
+  la.err = t.err;
+  la.max_passes = passes;
+  la.timeout_ticks = t.timeout_ticks;
+  hipError_t e = hipMemsetAsync(t.sync, 0, sizeof(LoopSync) * (size_t)t.nlps, st);
+  if (e != hipSuccess) return e;
+  void* args[] = {&la};
+  return hipLaunchCooperativeKernel(loop_kernel_for(t.fp64, t.mt), dim3(t.nwgs), dim3(BLOCK), args, 0, st);
 }
 
 hipError_t launch_start_point(const LPDesc& d, bool fp64, hipStream_t st) {

@@ -42,17 +42,21 @@ struct Problem;
 // The device work tables of a set of LPs that advance in the same launches.
 struct LaunchSet {
   static constexpr int MAX_STATUS = 65536;
+  static constexpr int64_t MAX_LOOP_PASSES = 65536;  // per launch of the persistent loop kernel
   std::vector<Problem*> members;
   LaunchTables t;
   DevBuf d_lps, d_llp, d_chunks, d_blocksA, d_blocksB, d_nodes, d_splits, d_rec, d_ncnt, d_splitpart,
-      d_splitcnt, d_tiles, d_status;
+      d_splitcnt, d_tiles, d_status, d_wgs, d_looplps, d_sync, d_bc, d_err;
   int* h_status = nullptr;  // pinned, 2 x MAX_STATUS
   int64_t last_epochs = 0;
   ~LaunchSet();
   void build(const std::vector<Problem*>& lps);
   void enqueue_passes(hipStream_t st, int64_t iters);
-  // enqueue passes with events around each launch; wait; mean ms of A, B, C
-  void timed_passes(hipStream_t st, int64_t iters, double* ms3);
+  // enqueue passes with events around the launches and wait.  Persistent
+  // kernel: ms4 = {1, ms of the one launch, passes, 1}; three launches per
+  // pass: ms4 = {0, mean ms of A, of B, of C}.
+  void timed_passes(hipStream_t st, int64_t iters, double* ms4);
+  void check_loop_error(hipStream_t st);
   void enqueue_eval(hipStream_t st);
   double run_to_completion(hipStream_t st, int epoch, double time_limit_s);
   size_t device_bytes() const;
@@ -64,6 +68,7 @@ struct Problem {
   int m = 0, n = 0, N = 0, nnz = 0;
   bool fp64 = false;
   bool started = false;
+  bool pending_init = false;  // start point set, init step (k = 0) not yet enqueued
   bool in_batch = false;
   double qnorm = 0.0, cnorm = 0.0, norm_est = 0.0;
   double last_solve_seconds = 0.0;
@@ -92,6 +97,7 @@ struct Problem {
   double power_norm();
   void reset_host_state();
   void enqueue_reset(hipStream_t st);
+  void enqueue_init(hipStream_t st);
   void read_scalars(Scalars& s);
   void download(const void* dev, size_t len, double* host, hipStream_t st);
   void upload_vec(void* dev, const double* host, size_t len, hipStream_t st);

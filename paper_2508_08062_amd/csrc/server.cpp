@@ -126,6 +126,7 @@ void aapdhg_server::run() {
           r->prob->create(r->m, r->n, r->nnz, r->rowptr.data(), r->colidx.data(), r->val.data(), r->c.data(),
                           r->q.data(), r->l.data(), r->u.data(), r->rowtype.data(), &opt);
           r->prob->enqueue_reset(st);
+          r->prob->enqueue_init(st);
         } catch (const Error& e) {
           r->prob.reset();
           err = e.status;

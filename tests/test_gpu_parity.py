@@ -35,9 +35,10 @@ def _trajectories(lp, steps, precision, variant=1, memory=5, **kw):
     Po = oracle.Problem.from_lpdata(lp)
     nrm = oracle.power_norm(Po)
     tau = sigma = 0.9 / nrm
+    loop_kernel = kw.pop("loop_kernel", 0)
     common = dict(variant=variant, memory=memory, tau=tau, sigma=sigma, kkt_every=kw.pop("kkt_every", 1),
                   tol=kw.pop("tol", 0.0), max_iter=10 ** 6, **kw)
-    g = _gpu(lp, precision=precision, **common)
+    g = _gpu(lp, precision=precision, loop_kernel=loop_kernel, **common)
     o = _oracle(lp, **common)
     o.start()
     g.iterate(1)
@@ -74,20 +75,22 @@ def test_toy_lp_hand_trace_on_gpu():
     np.testing.assert_allclose(np.r_[r["x"], r["y"]], gld["optimum"], atol=1e-9)
 
 
+@pytest.mark.parametrize("loop_kernel", [0, 1])
 @pytest.mark.parametrize("seed", [0, 1])
-def test_tiny_fp64_trajectory_50(seed):
+def test_tiny_fp64_trajectory_50(seed, loop_kernel):
     lp = lpgen.tiny_lp(seed)
-    ug, uo, ctr, _, _ = _trajectories(lp, 50, precision=1, memory=5)
+    ug, uo, ctr, _, _ = _trajectories(lp, 50, precision=1, memory=5, loop_kernel=loop_kernel)
     errs = [_rel(a, b) for a, b in zip(ug, uo)]
     assert max(errs) < 1e-9, errs
     for (gi, oi) in ctr:
         assert gi == oi
 
 
+@pytest.mark.parametrize("loop_kernel", [0, 1])
 @pytest.mark.parametrize("variant", [0, 1, 2])
-def test_mip_like_fp32_trajectory_50(variant):
+def test_mip_like_fp32_trajectory_50(variant, loop_kernel):
     lp = lpgen.mip_like_lp(11, m=2000, n=5000, nnz=25000)
-    ug, uo, ctr, _, _ = _trajectories(lp, 50, precision=0, variant=variant, memory=10)
+    ug, uo, ctr, _, _ = _trajectories(lp, 50, precision=0, variant=variant, memory=10, loop_kernel=loop_kernel)
     errs = [_rel(a, b) for a, b in zip(ug, uo)]
     assert max(errs) < 1e-5, (max(errs), int(np.argmax(errs)))
     assert ctr[-1][0] == ctr[-1][1]
@@ -222,3 +225,47 @@ def test_batch_member_equals_solo_run():
         r2 = g.result()
         assert r2["status"] == res["status"] and r2["kkt"] == res["kkt"]
     b.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_loop_kernels_agree_over_many_passes(precision):
+    """The persistent loop kernel and the three-launch passes take the same
+    steps (same branches and counters) and reach the same iterate up to
+    summation order, over passes that run many AA steps in one launch."""
+    lp = lpgen.mip_like_lp(13, m=3000, n=7000, nnz=40000)
+    out = []
+    for lk in (0, 1):
+        g = _gpu(lp, precision=precision, memory=10, kkt_every=16, tol=0.0, max_iter=10 ** 6, loop_kernel=lk)
+        g.iterate(1)
+        g.iterate(150)
+        out.append(g.get_state())
+        g.close()
+    a, b = out
+    assert a["k"] == b["k"] == 151
+    assert (a["i"], a["j"]) == (b["i"], b["j"])
+    assert _rel(a["u"], b["u"]) < (1e-4 if precision == 0 else 1e-9)
+
+
+@pytest.mark.parametrize("tol", [1e-4, 1e-6])
+def test_fp64_solve_objective_matches_oracle(tol):
+    """Float64 solves to relative KKT `tol` on both sides reach the same
+    objective.  The iteration is chaotic at this scale: perturbing the
+    oracle's own start point by one ulp moves its stopping pass by hundreds of
+    passes and its objective by up to 7e-5 at KKT 1e-4 and 3e-7 at KKT 1e-6
+    (relative to 1 + |obj|), so each side is taken at its own stop and the
+    objectives must agree to 1e-6 at KKT 1e-6 and to the tolerance at 1e-4.
+    Both must lie within the tolerance of the planted optimum."""
+    lp = lpgen.tiny_lp(4)
+    Po = oracle.Problem.from_lpdata(lp)
+    tau = sigma = 0.9 / oracle.power_norm(Po)
+    common = dict(variant=1, memory=5, tau=tau, sigma=sigma, kkt_every=8, tol=tol, max_iter=40000)
+    g = _gpu(lp, precision=1, **common)
+    g.solve()
+    r = g.result()
+    ro = _oracle(lp, **common).solve()
+    assert r["status"] == ro["status"] == "converged"
+    assert r["kkt"] <= tol
+    o_obj = ro["kkt"]["pobj"]
+    assert abs(r["primal_obj"] - o_obj) / (1 + abs(o_obj)) <= (1e-6 if tol <= 1e-6 else tol)
+    pstar = lp.planted["pstar"]
+    assert abs(r["primal_obj"] - pstar) / (1 + abs(pstar)) < 10 * tol
