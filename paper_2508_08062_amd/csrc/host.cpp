@@ -806,6 +806,10 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
   // units of rank j: a contiguous run, cut by cumulative weight
   auto assign = [&](const std::vector<BlockWork>& bw, int u0, int u1, int g, std::vector<int>& first) {
     first.assign(g + 1, u1);
+    if (u1 - u0 <= g) {  // one unit per workgroup
+      for (int q = 0; q <= g; ++q) first[q] = std::min(u1, u0 + q);
+      return;
+    }
     double tot = 0.0;
     for (int u = u0; u < u1; ++u) tot += unit_weight(bw[u]);
     double cum = 0.0;

@@ -652,7 +652,13 @@ struct PassCtx {
   }
 
   // ---- multi-row chunk: stage products in LDS, reduce rows, epilogue ----
-  __device__ __forceinline__ void multi_chunk(const Chunk& ch, double* acc, double* s_prod, double* s_tmp) const {
+  // CACHED: the chunk's column indices (cidx), this thread's original row
+  // (crow) and its row's range in the chunk (ca0, ca1) come from LDS, where
+  // the persistent kernel keeps the one chunk a workgroup owns.
+  template <bool CACHED>
+  __device__ __forceinline__ void multi_chunk(const Chunk& ch, double* acc, double* s_prod, double* s_tmp,
+                                              const int* cidx = nullptr, const int* crow = nullptr,
+                                              const int* ca0 = nullptr, const int* ca1 = nullptr) const {
     constexpr int UNR = CHUNK_NNZ / BLOCK;  // staged entries per thread
     const int tid = threadIdx.x;
     const int r0 = ch.r0, r1 = ch.r1, kb = ch.k0, ke = ch.k1, tpr = ch.tpr;
@@ -661,7 +667,8 @@ struct PassCtx {
     const int lane_r = blockmode ? tid : tid % tpr;
     const int r = r0 + grp;  // this thread group's position (at most one)
     const bool has_row = r < r1 && (!blockmode || tid == 0);
-    const int row = has_row ? rmap[r] : 0;  // its original row
+    int row = 0;  // its original row
+    if (has_row) row = CACHED ? crow[tid] : rmap[r];
     int ci[UNR];
     T vv[UNR];
 #pragma unroll
@@ -670,15 +677,15 @@ struct PassCtx {
       ci[u] = 0;
       vv[u] = (T)0;
       if (q < ke) {
-        ci[u] = idx[q];
+        ci[u] = CACHED ? cidx[tid + u * BLOCK] : idx[q];
         vv[u] = val[q];
       }
     }
     int a0 = 0, a1 = 0;
     RowIn<T, MT> rin;
     if (r < r1) {
-      a0 = ptr[r] - kb;
-      a1 = ptr[r + 1] - kb;
+      a0 = CACHED ? ca0[tid] : ptr[r] - kb;
+      a1 = CACHED ? ca1[tid] : ptr[r + 1] - kb;
       if (has_row && lane_r == 0) load_row(row, rin, false);
     }
     double sum1 = 0.0, sum2 = 0.0;
@@ -701,8 +708,17 @@ struct PassCtx {
         for (int q = a0 + tid; q < a1; q += BLOCK) s += s_prod[q];
         sres = block_sum(s, s_tmp);
       } else {
-        double s = 0.0;
-        for (int q = a0 + lane_r; q < a1; q += tpr) s += s_prod[q];
+        // four independent partial sums keep several LDS reads in flight
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int q = a0 + lane_r;
+        for (; q + 3 * tpr < a1; q += 4 * tpr) {
+          s0 += s_prod[q];
+          s1 += s_prod[q + tpr];
+          s2 += s_prod[q + 2 * tpr];
+          s3 += s_prod[q + 3 * tpr];
+        }
+        for (; q < a1; q += tpr) s0 += s_prod[q];
+        double s = (s0 + s1) + (s2 + s3);
         for (int off = 1; off < tpr; off <<= 1) s += __shfl_xor(s, off, 64);
         sres = s;
       }
@@ -774,17 +790,45 @@ struct PassCtx {
   }
 };
 
-// The record of one workgroup: its threads' sums, added per wave (DPP) and
-// then over the four waves in order.
+// wave_sum of C values at once: each DPP step is applied to every value
+// before the next step, so the steps of different values overlap.  The sums
+// end in lane 63.
+template <int C>
+__device__ __forceinline__ void wave_sum_lane63(double* v) {
+#pragma unroll
+  for (int q = 0; q < C; ++q) v[q] += dpp_mov<0xB1, 0xF>(v[q]);
+#pragma unroll
+  for (int q = 0; q < C; ++q) v[q] += dpp_mov<0x4E, 0xF>(v[q]);
+#pragma unroll
+  for (int q = 0; q < C; ++q) v[q] += dpp_mov<0x141, 0xF>(v[q]);
+#pragma unroll
+  for (int q = 0; q < C; ++q) v[q] += dpp_mov<0x140, 0xF>(v[q]);
+#pragma unroll
+  for (int q = 0; q < C; ++q) v[q] += dpp_mov<0x142, 0xA>(v[q]);
+#pragma unroll
+  for (int q = 0; q < C; ++q) v[q] += dpp_mov<0x143, 0xC>(v[q]);
+}
+
+// The record of one workgroup: its threads' sums, added per wave (DPP, the
+// same steps as wave_sum) and then over the four waves in order.  With
+// lane0_only the caller guarantees that only lane 0 of each wave holds
+// non-zero sums (one row per wave or per workgroup), which are then the wave
+// sums as they stand.
 template <int MT>
-__device__ __forceinline__ void write_record(double* acc, double (*s_red)[NDOT], double* out) {
+__device__ __forceinline__ void write_record(double* acc, double (*s_red)[NDOT], double* out, bool lane0_only) {
   constexpr int C = Dot<MT>::COUNT;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (lane0_only) {
+    if (lane == 0) {
 #pragma unroll
-  for (int q = 0; q < C; ++q) acc[q] = wave_sum(acc[q]);
-  if (lane == 0) {
+      for (int q = 0; q < C; ++q) s_red[wv][q] = acc[q];
+    }
+  } else {
+    wave_sum_lane63<C>(acc);
+    if (lane == 63) {
 #pragma unroll
-    for (int q = 0; q < C; ++q) s_red[wv][q] = acc[q];
+      for (int q = 0; q < C; ++q) s_red[wv][q] = acc[q];
+    }
   }
   __syncthreads();
   if (tid < C) st_agent(&out[tid], ((s_red[0][tid] + s_red[1][tid]) + s_red[2][tid]) + s_red[3][tid]);
@@ -880,8 +924,13 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
   double acc[DT::COUNT];
 #pragma unroll
   for (int q = 0; q < DT::COUNT; ++q) acc[q] = 0.0;
-  for (int c = bw.c0; c < bw.c1; ++c) P.multi_chunk(a.chunks[c], acc, s_prod, s_tmp);
-  write_record<MT>(acc, s_red, a.rec + (size_t)bw.leaf * NDOT);
+  bool lane0 = true;  // every chunk of the unit has one row per wave or workgroup
+  for (int c = bw.c0; c < bw.c1; ++c) {
+    const Chunk ch = a.chunks[c];
+    lane0 &= ch.tpr >= 64;
+    P.template multi_chunk<false>(ch, acc, s_prod, s_tmp);
+  }
+  write_record<MT>(acc, s_red, a.rec + (size_t)bw.leaf * NDOT, lane0);
   if (PASS == 1 && climb(bw.parent)) finish_lp();
 }
 
@@ -976,11 +1025,20 @@ __device__ __forceinline__ void reduce_records(const double* rec, int nrec, doub
   constexpr int C = Dot<MT>::COUNT;
   constexpr int QW = C <= 32 ? 32 : 64;
   constexpr int S = BLOCK / QW;
+  constexpr int BATCH = 32;  // loads of one thread in flight together
   const int tid = threadIdx.x, q = tid % QW, s = tid / QW;
   double sum = 0.0;
   if (q < C) {
-#pragma unroll 8
-    for (int r = s; r < nrec; r += S) sum += ld_coh(rec, r * NDOT + q);
+    for (int r0 = s; r0 < nrec; r0 += S * BATCH) {
+      double v[BATCH];
+#pragma unroll
+      for (int j = 0; j < BATCH; ++j) {
+        const int r = r0 + j * S;
+        v[j] = r < nrec ? ld_coh(rec, r * NDOT + q) : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < BATCH; ++j) sum += v[j];
+    }
   }
   s_part[tid] = sum;
   __syncthreads();
@@ -1041,12 +1099,59 @@ __device__ __forceinline__ void mix_owned(const LoopArgs& a, const LoopWG& wg, c
   }
 }
 
+// A workgroup that owns exactly one multi-row chunk in a pass keeps it in LDS
+// for the whole launch.
+struct ChunkCache {
+  int on;
+  int leaf;
+  Chunk ch;
+  int idx[CHUNK_NNZ];  // column indices of the chunk's entries
+  int row[BLOCK];      // original row of each thread's row group
+  int a0[BLOCK], a1[BLOCK];
+};
+
+template <int PASS>
+__device__ __forceinline__ void fill_cache(const LoopArgs& a, const LPDesc* dp, int u0, int u1, ChunkCache* cc) {
+  const int tid = threadIdx.x;
+  const BlockWork* bws = PASS == 0 ? a.blocksA : a.blocksB;
+  bool on = false;
+  BlockWork bw{};
+  if (u1 - u0 == 1) {
+    bw = bws[u0];
+    on = bw.kind == 0 && bw.c1 - bw.c0 == 1;
+  }
+  if (tid == 0) cc->on = on ? 1 : 0;
+  if (!on) return;
+  const Chunk ch = a.chunks[bw.c0];
+  if (tid == 0) {
+    cc->ch = ch;
+    cc->leaf = bw.leaf;
+  }
+  const int* ptr = PASS == 0 ? dp->colptr : dp->rowptr;
+  const int* idx = PASS == 0 ? dp->rowidx : dp->colidx;
+  const int* rmap = PASS == 0 ? dp->rmapA : dp->rmapB;
+  for (int q = tid; q < ch.k1 - ch.k0; q += BLOCK) cc->idx[q] = idx[ch.k0 + q];
+  const bool blockmode = ch.tpr == BLOCK;
+  const int r = ch.r0 + (blockmode ? 0 : tid / ch.tpr);
+  cc->row[tid] = r < ch.r1 ? rmap[r] : 0;
+  cc->a0[tid] = r < ch.r1 ? ptr[r] - ch.k0 : 0;
+  cc->a1[tid] = r < ch.r1 ? ptr[r + 1] - ch.k0 : 0;
+}
+
 template <typename T, int MT, int PASS>
 __device__ __forceinline__ void loop_units(const LoopArgs& a, const LPDesc* dp, const PassView& v, int u0, int u1,
                                            double* s_prod, double (*s_red)[NDOT], double* s_tmp, double* s_racc,
-                                           int* s_own) {
+                                           int* s_own, const ChunkCache* cc) {
   using DT = Dot<MT>;
   const PassCtx<T, MT, PASS, true> P(dp, v);
+  if (cc->on) {
+    double acc[DT::COUNT];
+#pragma unroll
+    for (int q = 0; q < DT::COUNT; ++q) acc[q] = 0.0;
+    P.template multi_chunk<true>(cc->ch, acc, s_prod, s_tmp, cc->idx, cc->row, cc->a0, cc->a1);
+    write_record<MT>(acc, s_red, a.rec + (size_t)cc->leaf * NDOT, cc->ch.tpr >= 64);
+    return;
+  }
   const BlockWork* bws = PASS == 0 ? a.blocksA : a.blocksB;
   for (int u = u0; u < u1; ++u) {
     const BlockWork bw = bws[u];
@@ -1058,8 +1163,13 @@ __device__ __forceinline__ void loop_units(const LoopArgs& a, const LPDesc* dp, 
     double acc[DT::COUNT];
 #pragma unroll
     for (int q = 0; q < DT::COUNT; ++q) acc[q] = 0.0;
-    for (int c = bw.c0; c < bw.c1; ++c) P.multi_chunk(a.chunks[c], acc, s_prod, s_tmp);
-    write_record<MT>(acc, s_red, a.rec + (size_t)bw.leaf * NDOT);
+    bool lane0 = true;
+    for (int c = bw.c0; c < bw.c1; ++c) {
+      const Chunk ch = a.chunks[c];
+      lane0 &= ch.tpr >= 64;
+      P.template multi_chunk<false>(ch, acc, s_prod, s_tmp);
+    }
+    write_record<MT>(acc, s_red, a.rec + (size_t)bw.leaf * NDOT, lane0);
   }
 }
 
@@ -1076,6 +1186,7 @@ __global__ __launch_bounds__(BLOCK) void k_loop(LoopArgs a) {
   __shared__ Bcast s_bc;
   __shared__ SolveWork s_work;
   __shared__ Scalars s_sc;
+  __shared__ ChunkCache s_cc[2];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
@@ -1102,6 +1213,8 @@ __global__ __launch_bounds__(BLOCK) void k_loop(LoopArgs a) {
   unsigned long long* lsc = reinterpret_cast<unsigned long long*>(&s_sc);
   if (root)
     for (int q = tid; q < SW; q += BLOCK) lsc[q] = gsc[q];
+  fill_cache<0>(a, dp, wg.a0, wg.a1, &s_cc[0]);
+  fill_cache<1>(a, dp, wg.b0, wg.b1, &s_cc[1]);
   __syncthreads();
 
   constexpr int BCW = sizeof(Bcast) / 8;
@@ -1113,14 +1226,14 @@ __global__ __launch_bounds__(BLOCK) void k_loop(LoopArgs a) {
   for (long long it = 0; it < a.max_passes; ++it) {
     const PassView v = make_view(*dp, s_bc.k, s_bc.nlive, s_bc.newslot, s_bc.live, false);
     // ---- phase A: K^T y and the primal update ----
-    loop_units<T, MT, 0>(a, dp, v, wg.a0, wg.a1, s_prod, s_red, s_tmp, s_racc, &s_own);
+    loop_units<T, MT, 0>(a, dp, v, wg.a0, wg.a1, s_prod, s_red, s_tmp, s_racc, &s_own, &s_cc[0]);
     ++nbar;
     if (!group_barrier(sy->bar, wg.rank, nbar * (unsigned)L.nwg, &sy->abort, ticks, &s_ok)) {
       ok = false;
       break;
     }
     // ---- phase B: K x_bar and the dual update ----
-    loop_units<T, MT, 1>(a, dp, v, wg.b0, wg.b1, s_prod, s_red, s_tmp, s_racc, &s_own);
+    loop_units<T, MT, 1>(a, dp, v, wg.b0, wg.b1, s_prod, s_red, s_tmp, s_racc, &s_own, &s_cc[1]);
     wait_stores();
     __syncthreads();
     if (tid == 0) arrive_sub(sy->arr, wg.rank);
