@@ -8,9 +8,15 @@ every 64 passes as in a solve.  The KKT tolerance is set to 0 inside the timed
 region so that no pass is skipped by early termination.
 
 Workloads (synthetic, seeded; see lpgen):
-  mip20k      20k x 50k LP, 250k nonzeros, Zipf(1.8) rows, float32, m_A = 10 (default)
-  powerlaw1m  1M x 2M LP, 20M nonzeros, power-law columns, Ruiz-scaled, FAA-PDHG, m_A = 10
-  batch256    256 LPs of uneven sizes advanced together (batched), m_A = 8
+  mip20k      20k x 50k LP, 250k nonzeros, Zipf(1.8) rows, float32, m_A = 10 (default):
+              loop passes per second
+  powerlaw1m  1M x 2M LP, 20M nonzeros, power-law columns, Ruiz-scaled, FAA-PDHG, m_A = 10:
+              loop passes per second
+  batch256    256 LPs of uneven sizes (rows log-uniform 1k..50k), m_A = 8: LPs solved per
+              second to relative KKT 1e-4 in one batched float32 solve, beside float64
+              single solves of a sample of the same LPs
+  serve       Poisson stream of LP requests (200/s by default) through the continuous-
+              batching server, float32, m_A = 10: LPs solved per second, p50/p99 latency
 
 Prints one JSON line (see the keys below).  --gpus N with N > 1 is refused:
 this build measures one GPU.
@@ -60,7 +66,9 @@ def _traffic(workload, kernel, ppl):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("kernel_source_hash") != _src_hash() or t.get("passes_per_launch") != ppl:
+    if t.get("kernel_source_hash") != _src_hash():
+        return None
+    if kernel == "loop" and t.get("passes_per_launch") != ppl:
         return None
     k = t.get("kernels", {}).get(kernel)
     return None if k is None else k.get("hbm_bytes_per_launch")
@@ -117,12 +125,132 @@ def _cpu_baseline(lps, opts, seconds):
     return k / el, k, el
 
 
+def _line(metric, value, unit, cfg, extra, higher=True, steps=0, warmup=0, ms=0.0, dtype="f32"):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+            "ms_per_step": ms, "higher_is_better": higher, "scaling": "weak", "vs_baseline": None,
+            "dtype": dtype, "data": "synthetic", "config": cfg, **extra}
+
+
+def _batch_solve(args):
+    """256 LPs solved to relative KKT 1e-4 in one batch (float32), and a sample
+    of them solved one at a time in float64."""
+    import numpy as np
+    import torch
+
+    import lpgen
+    import paper_2508_08062_amd as P
+    lps, opts, cfg = _workload("batch256")
+    stream = torch.cuda.Stream()
+    kw = dict(opts, tol=1e-4, max_iter=200000)
+    solvers = [P.Solver(lp, **kw) for lp in lps]
+    batch = P.Batch(solvers)
+    torch.cuda.synchronize()
+    print(f"# created {len(solvers)} LPs", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    batch.solve(stream)
+    el = time.perf_counter() - t0
+    res = batch.results()
+    iters = np.array([r["iters"] for r in res])
+    conv = sum(r["status"] == "converged" for r in res)
+    batch.close()
+    for sv in solvers:
+        sv.close()
+    print(f"# batch solve {el:.2f} s, {conv} converged", file=sys.stderr, flush=True)
+    # float64 single solves of a sample, one after the other
+    rng = np.random.default_rng(5)
+    sample = sorted(rng.choice(len(lps), size=min(args.fp64_sample, len(lps)), replace=False).tolist())
+    t64 = []
+    it64 = []
+    for i in sample:
+        sv = P.Solver(lps[i], **{**kw, "precision": 1})
+        t1 = time.perf_counter()
+        sv.solve(stream)
+        t64.append(time.perf_counter() - t1)
+        it64.append(sv.result()["iters"])
+        sv.close()
+    nnz_all = sum(lp.nnz for lp in lps)
+    nnz_s = sum(lps[i].nnz for i in sample)
+    # the sample's float64 time scaled to the whole batch by nonzeros x iterations
+    work_all = float(sum(lps[i].nnz * r["iters"] for i, r in enumerate(res)))
+    work_s = float(sum(lps[i].nnz * it64[j] for j, i in enumerate(sample)))
+    est64 = sum(t64) * work_all / max(work_s, 1.0)
+    line = _line("LPs solved/s at rel KKT 1e-4 (batched float32)", len(lps) / el, "LPs/s",
+                 {**cfg, "lps": len(lps), "nnz_total": nnz_all},
+                 {"batch_seconds": el, "converged": int(conv), "iters_median": float(np.median(iters)),
+                  "iters_max": int(iters.max()),
+                  "fp64_single": {"sample": sample, "seconds": t64, "iters": it64, "nnz_sample": nnz_s,
+                                  "lps_per_s_estimate": len(lps) / est64,
+                                  "estimate": "sample seconds scaled by nnz x iterations to all LPs"}},
+                 ms=el * 1e3)
+    print(json.dumps(line), flush=True)
+
+
+def _serve(args):
+    """A Poisson stream of LP requests through the server; LPs solved per
+    second and latency from submission to completion."""
+    import numpy as np
+    import torch
+
+    import lpgen
+    import paper_2508_08062_amd as P
+    reqs = lpgen.serving_requests(rate=args.rate, duration=args.serve_seconds, seed=4)
+    pool = [lpgen.mip_like_lp(r[4], m=r[1], n=r[2], nnz=r[3]) for r in reqs[:args.pool]]
+    opts = dict(variant=1, precision=0, memory=10, kkt_every=64, ruiz_iters=10, dhat_mode=0, tol=1e-4,
+                max_iter=200000, epoch=64)
+    torch.cuda.init()
+    free, _ = torch.cuda.mem_get_info()
+    srv = P.Server(hbm_budget_bytes=int(free * 0.8), max_slots=args.slots, **opts)
+    print(f"# {len(reqs)} requests over {args.serve_seconds} s, pool {len(pool)}", file=sys.stderr, flush=True)
+    pending = {}
+    lat = []
+    t0 = time.perf_counter()
+    i = 0
+    last = 0.0
+    while i < len(reqs) or pending:
+        now = time.perf_counter() - t0
+        if now - last >= 10.0:
+            last = now
+            print(f"# t={now:.0f} s submitted {i} finished {len(lat)} pending {len(pending)}", file=sys.stderr,
+                  flush=True)
+        while i < len(reqs) and reqs[i][0] <= now:
+            pending[srv.submit(pool[i % len(pool)])] = reqs[i][0]
+            i += 1
+        for tk in list(pending):
+            r = srv.poll(tk, want_solution=False)
+            if r is not None:
+                lat.append((r["t_done"], r["status"], pending.pop(tk)))
+        if time.perf_counter() - t0 > args.serve_seconds + args.drain_seconds:
+            break  # requests still pending are reported as unfinished
+        time.sleep(0.0005)
+    el = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    d = np.array([x[0] for x in lat])
+    conv = sum(x[1] == "converged" for x in lat)
+    line = _line("LPs solved/s & p99 latency at rel KKT 1e-4 (served float32)", len(lat) / el, "LPs/s",
+                 {"workload": f"Poisson stream {args.rate}/s for {args.serve_seconds} s (serving_requests seed 4), "
+                              f"columns lognormal(ln 20000, 1) in [1k, 500k], rows 0.4 x columns, 5 nnz/column; "
+                              f"{len(pool)} distinct LPs cycled", "variant": "AA-PDHG", "m_A": 10},
+                 {"requests": len(reqs), "finished": len(lat), "unfinished": len(pending), "converged": int(conv),
+                  "seconds": el,
+                  "latency_p50_s": float(np.percentile(d, 50)) if d.size else None,
+                  "latency_p99_s": float(np.percentile(d, 99)) if d.size else None,
+                  "latency_max_s": float(d.max()) if d.size else None, "server": st})
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=300)
-    ap.add_argument("--workload", default="mip20k", choices=["mip20k", "powerlaw1m", "batch256"])
+    ap.add_argument("--workload", default="mip20k", choices=["mip20k", "powerlaw1m", "batch256", "serve"])
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: requests per second")
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="serve: length of the arrival stream")
+    ap.add_argument("--pool", type=int, default=64, help="serve: distinct LPs cycled through the stream")
+    ap.add_argument("--slots", type=int, default=64, help="serve: resident LPs at most")
+    ap.add_argument("--drain-seconds", type=float, default=120.0, help="serve: wait after the last arrival")
+    ap.add_argument("--fp64-sample", type=int, default=8, help="batch256: LPs solved singly in float64")
     ap.add_argument("--passes-per-launch", type=int, default=500,
                     help="loop passes per launch of the persistent loop kernel")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -155,6 +283,10 @@ def main():
 
     import paper_2508_08062_amd as P
 
+    if args.workload == "serve":
+        return _serve(args)
+    if args.workload == "batch256":
+        return _batch_solve(args)
     lps, opts, cfg = _workload(args.workload)
     if args.chunks_per_block:
         opts["chunks_per_block"] = args.chunks_per_block
