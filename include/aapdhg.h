@@ -153,7 +153,7 @@ aapdhg_status aapdhg_iterate(aapdhg_t h, void *stream, int64_t iters);
  * run first and not timed on a fresh or reset handle) with HIP events recorded on `stream`
  * around the launches; waits for completion and fills ms4[0..3]:
  *   persistent loop kernel: {1, duration in ms of its one launch, iters, 1}
- *     (iters <= 65536);
+ *     (iters <= 65535);
  *   three launches per pass: {0, mean ms of the primal CSC launch, of the dual CSR launch
  *     with the float64 decisions, of the mix launch}; the events add a small gap between
  *     launches, so use aapdhg_iterate for throughput. */

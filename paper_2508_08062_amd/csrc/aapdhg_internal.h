@@ -60,8 +60,8 @@ struct alignas(256) Scalars {
   double gamma[MAXM];     // mixing coefficients for mixslot[]
   double pobj, dobj, r_g, r_p, r_d, kkt;
   double qnorm, cnorm;
-  unsigned int lp_cnt;    // last-arriver counter of the dual pass (reset by the last block)
-  unsigned int pad1;
+  double thr;             // safeguard bound for i^k = thr_i - 1 (valid when thr_i == i^k + 1)
+  long long thr_i;
 };
 
 // Per-LP immutable description (device copy).  Vectors of length N = n + m
@@ -212,13 +212,24 @@ struct alignas(256) LoopSync {
   unsigned int pad[62];
 };
 
-// Decisions of a pass, published by rank 0 of the group.
-struct alignas(64) Bcast {
+// Decisions of a pass as every workgroup of the group keeps them (LDS).
+struct Bcast {
   long long k;
   int status, branch, nmix, nlive, newslot, pad;
   int mixslot[MAXM];
   int live[MAXM];
   double gamma[MAXM];
+};
+
+// The decisions as rank 0 publishes them: BC_WORDS 64-bit words, each a
+// 32-bit payload (low half) and the 32-bit tag of the pass (high half), so a
+// reader that sees every tag of its pass has the whole message in one read.
+//   word 0: status | branch << 4 | nmix << 8 | nlive << 16 | newslot << 24
+//   words 1-2: live slots, 4 bits each; words 3-4: mix slots, 4 bits each
+//   words 5 .. 5 + 2 MAXM: gamma, low and high halves
+constexpr int BC_WORDS = 5 + 2 * MAXM;
+struct alignas(256) BcastMsg {
+  unsigned long long w[64];
 };
 
 struct LoopArgs {
@@ -233,9 +244,10 @@ struct LoopArgs {
   double* splitpart;
   unsigned int* splitcnt;
   LoopSync* sync;
-  Bcast* bc;
+  BcastMsg* bc;
   int* err;  // set to 1 when a wait gave up
   long long max_passes;
+  unsigned int tag0;  // tag of pass 0 of this launch (the pass number is added)
   unsigned long long timeout_ticks;  // bound of one wait, in wall-clock ticks
 };
 

@@ -792,8 +792,10 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
   }
   int gsum = 0;
   for (int i = 0; i < count; ++i) {
-    G[i] = need <= cap ? std::max(1, umax[i])
-                       : std::max(1, std::min(umax[i], (int)std::floor((double)cap * wlp[i] / wtot)));
+    // with room, rank 0 (which takes the decisions) gets no CSR unit
+    const int nb = info[2 * i + 1].bend - info[2 * i + 1].b0;
+    G[i] = need + count <= cap ? std::max(1, std::max(umax[i], nb + 1))
+                               : std::max(1, std::min(umax[i], (int)std::floor((double)cap * wlp[i] / wtot)));
     gsum += G[i];
   }
   while (gsum > cap) {  // trim the largest groups
@@ -804,10 +806,10 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
     --gsum;
   }
   // units of rank j: a contiguous run, cut by cumulative weight
-  auto assign = [&](const std::vector<BlockWork>& bw, int u0, int u1, int g, std::vector<int>& first) {
+  auto assign = [&](const std::vector<BlockWork>& bw, int u0, int u1, int g, std::vector<int>& first, int skip) {
     first.assign(g + 1, u1);
-    if (u1 - u0 <= g) {  // one unit per workgroup
-      for (int q = 0; q <= g; ++q) first[q] = std::min(u1, u0 + q);
+    if (u1 - u0 <= g - skip) {  // one unit per workgroup, none for the first `skip` ranks
+      for (int q = 0; q <= g; ++q) first[q] = std::min(u1, u0 + std::max(0, q - skip));
       return;
     }
     double tot = 0.0;
@@ -829,8 +831,8 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
   for (int i = 0; i < count; ++i) {
     const PassInfo& pa = info[2 * i];
     const PassInfo& pb = info[2 * i + 1];
-    assign(bA, pa.b0, pa.bend, G[i], fa);
-    assign(bB, pb.b0, pb.bend, G[i], fb);
+    assign(bA, pa.b0, pa.bend, G[i], fa, 0);
+    assign(bB, pb.b0, pb.bend, G[i], fb, 1);
     for (int j = 0; j < G[i]; ++j) {
       LoopWG w{};
       w.lp = i;
@@ -849,7 +851,8 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
   d_wgs.upload(wgs.data(), wgs.size() * sizeof(LoopWG), "loop workgroups");
   d_looplps.upload(llps.data(), llps.size() * sizeof(LoopLP), "loop groups");
   d_sync.alloc(sizeof(LoopSync) * (size_t)count, "loop counters");
-  d_bc.alloc(sizeof(Bcast) * (size_t)count, "loop decisions");
+  d_bc.alloc(sizeof(BcastMsg) * (size_t)count, "loop decisions");
+  d_bc.zero("loop decisions");
   d_err.alloc(sizeof(int), "loop error word");
   d_err.zero("loop error word");
   int dev = 0, khz = 0;
@@ -860,7 +863,7 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
   t.nwgs = (int)wgs.size();
   t.looplps = (const LoopLP*)d_looplps.p;
   t.sync = (LoopSync*)d_sync.p;
-  t.bc = (Bcast*)d_bc.p;
+  t.bc = (BcastMsg*)d_bc.p;
   t.err = (int*)d_err.p;
   t.persistent = true;
 }
@@ -882,7 +885,7 @@ void LaunchSet::enqueue_passes(hipStream_t st, int64_t iters) {
   if (t.persistent) {
     for (int64_t done = 0; done < iters;) {
       const int64_t np = std::min<int64_t>(iters - done, MAX_LOOP_PASSES);
-      hip_check(launch_loop(t, st, np), "loop launch");
+      hip_check(launch_loop(t, st, np, next_tag()), "loop launch");
       done += np;
     }
     return;
@@ -897,7 +900,7 @@ void LaunchSet::timed_passes(hipStream_t st, int64_t iters, double* ms4) {
     hipEvent_t ev[2];
     for (auto& e : ev) hip_check(hipEventCreate(&e), "event");
     hip_check(hipEventRecord(ev[0], st), "event record");
-    hip_check(launch_loop(t, st, iters), "loop launch");
+    hip_check(launch_loop(t, st, iters, next_tag()), "loop launch");
     hip_check(hipEventRecord(ev[1], st), "event record");
     hip_check(hipStreamSynchronize(st), "timed sync");
     float ms = 0.f;

@@ -35,7 +35,7 @@ struct LaunchTables {
   int nwgs = 0;
   const LoopLP* looplps = nullptr;
   LoopSync* sync = nullptr;
-  Bcast* bc = nullptr;
+  BcastMsg* bc = nullptr;
   int* err = nullptr;
   unsigned long long timeout_ticks = 0;
 };
@@ -46,7 +46,7 @@ struct LaunchTables {
 hipError_t launch_loop_pass(const LaunchTables& t, hipStream_t st, int mode, hipEvent_t* ev = nullptr);
 // `passes` loop passes of every LP of the table in one cooperative launch of
 // the persistent loop kernel (t.persistent must be set).
-hipError_t launch_loop(const LaunchTables& t, hipStream_t st, long long passes);
+hipError_t launch_loop(const LaunchTables& t, hipStream_t st, long long passes, unsigned int tag0);
 // Workgroups of the persistent loop kernel that fit on the device at once.
 int loop_capacity(bool fp64, int mt);
 hipError_t launch_start_point(const LPDesc& d, bool fp64, hipStream_t st);

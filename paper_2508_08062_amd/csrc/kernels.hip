@@ -374,7 +374,16 @@ __device__ void final_step(const LPDesc& d, Scalars* sc, const double* f, bool e
   int nmix = 0;
   if (d.variant != V_PDHG) {
     // safeguard (Alg 2): ||g^k|| <= D ||g^0|| (i^k + 1)^{-(1+eps)}; ties accelerate
-    const double thr = d.D * n0 * pow((double)(i_aa + 1), -(1.0 + d.eps_sg));
+    // the bound changes only with i^k: computed once per Anderson step
+    double thr = sc->thr;
+    if (sc->thr_i != i_aa + 1) {
+      thr = d.D * n0 * pow((double)(i_aa + 1), -(1.0 + d.eps_sg));
+      wave_sync();
+      if (L0) {
+        sc->thr = thr;
+        sc->thr_i = i_aa + 1;
+      }
+    }
     if (gnorm <= thr) {
       if (d.variant == V_AA) {
         if (solve_gamma(sc, w->live, nl, d.eta, w, lane)) {
@@ -957,22 +966,6 @@ __device__ __forceinline__ unsigned int ld_u32(const unsigned int* p) {
   return __hip_atomic_load(const_cast<unsigned int*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Thread 0 only: wait until *p >= target.
-__device__ bool wait_geq(const unsigned int* p, unsigned int target, unsigned int* abortw, unsigned long long ticks) {
-  const unsigned long long t0 = wall_clock64();
-  for (unsigned int it = 0;; ++it) {
-    if (ld_u32(p) >= target) return true;
-    if ((it & 15u) == 15u) {
-      if (ld_u32(abortw) != 0u) return false;
-      if (wall_clock64() - t0 > ticks) {
-        __hip_atomic_store(abortw, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return false;
-      }
-    }
-    __builtin_amdgcn_s_sleep(1);
-  }
-}
-
 // Wave 0 only: wait until the NSUB sub-counters at `sub` add up to at least
 // `target` (lane q < NSUB reads sub-counter q).
 __device__ bool wait_sum_geq(const unsigned int* sub, unsigned int target, unsigned int* abortw,
@@ -1173,6 +1166,73 @@ __device__ __forceinline__ void loop_units(const LoopArgs& a, const LPDesc* dp, 
   }
 }
 
+// Wave 0 of rank 0: publish the decisions of a pass as tagged words (see
+// BcastMsg).
+__device__ __forceinline__ void publish_decisions(const Bcast& b, unsigned long long* msg, unsigned int tag) {
+  const int lane = threadIdx.x & 63;
+  unsigned int pay = 0;
+  if (lane == 0) {
+    pay = (unsigned)b.status | (unsigned)b.branch << 4 | (unsigned)b.nmix << 8 | (unsigned)b.nlive << 16 |
+          (unsigned)b.newslot << 24;
+  } else if (lane <= 4) {
+    const int* src = lane <= 2 ? b.live : b.mixslot;
+    const int base = ((lane - 1) & 1) * 8;
+    for (int t = 0; t < 8; ++t) pay |= ((unsigned)src[base + t] & 15u) << (4 * t);
+  } else if (lane < BC_WORDS) {
+    const int t = (lane - 5) >> 1;
+    const double gv = b.gamma[t];
+    pay = ((lane - 5) & 1) ? (unsigned)__double2hiint(gv) : (unsigned)__double2loint(gv);
+  }
+  if (lane < BC_WORDS) {
+    const unsigned long long wv = (unsigned long long)pay | (unsigned long long)tag << 32;
+    stc(reinterpret_cast<double*>(msg), lane, __builtin_bit_cast(double, wv));
+  }
+}
+
+// Wave 0 of the other ranks: wait until every word carries `tag`, then
+// unpack into b (k becomes k_next).  Bounded like every wait.
+__device__ bool read_decisions(Bcast& b, const unsigned long long* msg, unsigned int tag, long long k_next,
+                               unsigned int* abortw, unsigned long long ticks) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long t0 = wall_clock64();
+  unsigned long long wv = 0;
+  for (unsigned int it = 0;; ++it) {
+    if (lane < BC_WORDS) wv = __builtin_bit_cast(unsigned long long, ldc(reinterpret_cast<const double*>(msg), lane));
+    const bool stale = lane < BC_WORDS && (unsigned int)(wv >> 32) != tag;
+    if (__ballot(stale) == 0ull) break;
+    if ((it & 15u) == 15u) {
+      const unsigned int ab = __shfl(lane == 0 ? ld_u32(abortw) : 0u, 0, 64);
+      if (ab != 0u) return false;
+      if (wall_clock64() - t0 > ticks) {
+        if (lane == 0) __hip_atomic_store(abortw, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+      }
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  const unsigned int pay = (unsigned int)wv;
+  const unsigned int w0 = __shfl(pay, 0, 64);
+  if (lane == 0) {
+    b.k = k_next;
+    b.status = (int)(w0 & 15u);
+    b.branch = (int)((w0 >> 4) & 15u);
+    b.nmix = (int)((w0 >> 8) & 255u);
+    b.nlive = (int)((w0 >> 16) & 255u);
+    b.newslot = (int)(w0 >> 24);
+  }
+  const unsigned int l0 = __shfl(pay, 1, 64), l1 = __shfl(pay, 2, 64);
+  const unsigned int m0 = __shfl(pay, 3, 64), m1 = __shfl(pay, 4, 64);
+  const unsigned int glo = __shfl(pay, 5 + 2 * (lane & (MAXM - 1)), 64);
+  const unsigned int ghi = __shfl(pay, 6 + 2 * (lane & (MAXM - 1)), 64);
+  if (lane < MAXM) {
+    const unsigned int lw = lane < 8 ? l0 : l1, mw = lane < 8 ? m0 : m1;
+    b.live[lane] = (int)((lw >> (4 * (lane & 7))) & 15u);
+    b.mixslot[lane] = (int)((mw >> (4 * (lane & 7))) & 15u);
+    b.gamma[lane] = __hiloint2double((int)ghi, (int)glo);
+  }
+  return true;
+}
+
 template <typename T, int MT>
 __global__ __launch_bounds__(BLOCK) void k_loop(LoopArgs a) {
   __shared__ double s_prod[CHUNK_NNZ];
@@ -1217,9 +1277,7 @@ __global__ __launch_bounds__(BLOCK) void k_loop(LoopArgs a) {
   fill_cache<1>(a, dp, wg.b0, wg.b1, &s_cc[1]);
   __syncthreads();
 
-  constexpr int BCW = sizeof(Bcast) / 8;
-  double* bcw_l = reinterpret_cast<double*>(&s_bc);
-  double* bcw_g = reinterpret_cast<double*>(a.bc + wg.lp);
+  unsigned long long* msg = a.bc[wg.lp].w;
   const unsigned long long ticks = a.timeout_ticks;
   unsigned int nbar = 0;
   bool ok = true;
@@ -1269,19 +1327,17 @@ __global__ __launch_bounds__(BLOCK) void k_loop(LoopArgs a) {
         s_bc.gamma[tid] = s_sc.gamma[tid];
       }
       __syncthreads();
-      if (tid < BCW) stc(bcw_g, tid, bcw_l[tid]);
-      wait_stores();
-      __syncthreads();
-      if (tid == 0) __hip_atomic_store(&sy->flag, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (tid < 64) publish_decisions(s_bc, msg, a.tag0 + done);
     } else {
-      if (tid == 0) s_ok = wait_geq(&sy->flag, done, &sy->abort, ticks) ? 1 : 0;
+      if (tid < 64) {
+        const bool okw = read_decisions(s_bc, msg, a.tag0 + done, s_bc.k + 1, &sy->abort, ticks);
+        if (tid == 0) s_ok = okw ? 1 : 0;
+      }
       __syncthreads();
       if (!s_ok) {
         ok = false;
         break;
       }
-      if (tid < BCW) bcw_l[tid] = ldc(bcw_g, tid);
-      __syncthreads();
     }
     if (s_bc.status != ST_RUNNING) break;
     if (s_bc.branch == BR_AA) {
@@ -1496,7 +1552,7 @@ int loop_capacity(bool fp64, int mt) {
   return nb * cus;
 }
 
-hipError_t launch_loop(const LaunchTables& t, hipStream_t st, long long passes) {
+hipError_t launch_loop(const LaunchTables& t, hipStream_t st, long long passes, unsigned int tag0) {
   LoopArgs la{};
   la.lps = t.lps;
   la.llp = t.looplps;
@@ -1513,6 +1569,7 @@ hipError_t launch_loop(const LaunchTables& t, hipStream_t st, long long passes) 
   la.err = t.err;
   la.max_passes = passes;
   la.timeout_ticks = t.timeout_ticks;
+  la.tag0 = tag0;
   hipError_t e = hipMemsetAsync(t.sync, 0, sizeof(LoopSync) * (size_t)t.nlps, st);
   if (e != hipSuccess) return e;
   void* args[] = {&la};

@@ -42,7 +42,7 @@ struct Problem;
 // The device work tables of a set of LPs that advance in the same launches.
 struct LaunchSet {
   static constexpr int MAX_STATUS = 65536;
-  static constexpr int64_t MAX_LOOP_PASSES = 65536;  // per launch of the persistent loop kernel
+  static constexpr int64_t MAX_LOOP_PASSES = 65535;  // per launch of the persistent loop kernel
   std::vector<Problem*> members;
   LaunchTables t;
   DevBuf d_lps, d_llp, d_chunks, d_blocksA, d_blocksB, d_nodes, d_splits, d_rec, d_ncnt, d_splitpart,
@@ -57,6 +57,11 @@ struct LaunchSet {
   // pass: ms4 = {0, mean ms of A, of B, of C}.
   void timed_passes(hipStream_t st, int64_t iters, double* ms4);
   void check_loop_error(hipStream_t st);
+  // tag base of the next persistent launch: the launch count times 65536, so
+  // that (launch, pass) tags of published decisions never repeat between
+  // consecutive launches (passes per launch stay below 65536)
+  unsigned int launch_seq = 0;
+  unsigned int next_tag() { return (++launch_seq) << 16; }
   void enqueue_eval(hipStream_t st);
   double run_to_completion(hipStream_t st, int epoch, double time_limit_s);
   size_t device_bytes() const;
