@@ -1,0 +1,101 @@
+"""GPU checks at the benchmark's full sizes and launch configurations.
+
+After a benchmark-sized launch (the 20k x 50k LP: one persistent launch of
+500 loop passes; the 1M x 2M LP: 250 passes of the three-launch kernels), the
+device state must agree with the oracle evaluated on the same seeded,
+equilibrated, float32-rounded LP:
+
+  * the last PDHG point: u_prev + g_prev equals the oracle's T(u_prev)
+    (eq. pdhg) element by element, to relative 1e-5 of the vector's norm
+    (the float32 storage of x_hat, x_bar and y_hat; the products are exact
+    in float64);
+  * the history: every Gram entry is the float64 dot product of the stored
+    difference columns, every right-hand side the dot product with the stored
+    residual, and ||g|| the norm of the stored residual (float64 sums of the
+    same float32 values in another order: relative 1e-9);
+  * the counters add up (i + j = k - 1), the iterate lies in X x Y, and the
+    KKT residuals reported at the returned point equal the oracle's there.
+"""
+import numpy as np
+import pytest
+
+import lpgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2508_08062_amd")
+
+
+def _scaled_oracle_problem(lp, ruiz_iters):
+    Po = oracle.Problem.from_lpdata(lp)
+    if ruiz_iters:
+        Po, _, _ = oracle.ruiz(Po, ruiz_iters)
+    return Po.rounded_fp32()
+
+
+def _check_state(lp, Po, g, tau, sigma, st, M):
+    n = lp.n
+    up, gp = st["u_prev"], st["g_prev"]
+    # the last PDHG point
+    xh, yh = oracle.pdhg_map(Po, up[:n], up[n:], tau, sigma)
+    ref = np.r_[xh, yh]
+    got = up + gp
+    err = np.abs(got - ref)
+    scale = np.linalg.norm(ref)
+    assert np.linalg.norm(got - ref) / scale < 1e-5
+    assert err.max() / np.abs(ref).max() < 1e-5
+    # the history and its Gram matrix
+    live = st["live"]
+    assert len(live) <= M
+    G, rhs = st["G"], st["rhs"]
+    for a in live:
+        for b in live:
+            want = float(np.dot(st["dG"][a], st["dG"][b]))
+            tol = 1e-9 * np.sqrt(G[a, a] * G[b, b]) + 1e-300
+            assert abs(G[a, b] - want) <= tol, (a, b, G[a, b], want)
+        want = float(np.dot(st["dG"][a], gp))
+        assert abs(rhs[a] - want) <= 1e-9 * np.sqrt(G[a, a] * float(gp @ gp)) + 1e-300
+    assert st["gnorm"] == pytest.approx(float(np.linalg.norm(gp)), rel=1e-9)
+    # counters and projections
+    assert st["i"] + st["j"] == st["k"] - 1
+    x, y = st["u"][:n], st["u"][n:]
+    # (the bounds of both sides are float32 roundings of the same scaled values)
+    slack = 1e-6 * (1.0 + np.abs(np.where(np.isfinite(Po.l), Po.l, 0.0)) + np.abs(np.where(np.isfinite(Po.u), Po.u, 0.0)))
+    assert np.all(x >= Po.l - slack) and np.all(x <= Po.u + slack)
+    assert np.all(y[Po.rowtype == oracle.ROW_GE] >= 0.0)
+    # KKT at the returned point, measured on the problem as solved
+    r = g.result()
+    ko = oracle.kkt(Po, x, y)
+    for key, gkey in (("r_p", "r_pri"), ("r_d", "r_dual"), ("r_g", "r_gap")):
+        assert r[gkey] == pytest.approx(ko[key], rel=1e-6, abs=1e-9), key
+
+
+def test_mip20k_after_one_persistent_launch_of_500_passes():
+    lp = lpgen.mip_like_lp(1)
+    opts = dict(variant=1, precision=0, memory=10, kkt_every=64, ruiz_iters=10, dhat_mode=0)
+    Po = _scaled_oracle_problem(lp, 10)
+    tau = sigma = 0.9 / oracle.power_norm(Po)
+    g = P.Solver(lp, tol=0.0, max_iter=10 ** 9, tau=tau, sigma=sigma, **opts)
+    g.iterate(1)  # the init step
+    t = g.iterate_timed(500)  # the benchmark's launch: one persistent launch of 500 passes
+    assert t["kernel"] == "persistent" and t["passes"] == 500
+    st = g.get_state()
+    assert st["k"] == 501 and st["status"] == 4
+    _check_state(lp, Po, g, tau, sigma, st, 10)
+    g.close()
+
+
+def test_powerlaw1m_after_250_three_launch_passes():
+    lp = lpgen.powerlaw_lp(2)
+    opts = dict(variant=2, precision=0, memory=10, kkt_every=64, ruiz_iters=10, dhat_mode=0)
+    Po = _scaled_oracle_problem(lp, 10)
+    tau = sigma = 0.9 / oracle.power_norm(Po)
+    g = P.Solver(lp, tol=0.0, max_iter=10 ** 9, tau=tau, sigma=sigma, **opts)
+    g.iterate(1)
+    t = g.iterate_timed(250)
+    assert t["kernel"] == "three"
+    st = g.get_state()
+    assert st["k"] == 251 and st["status"] == 4
+    _check_state(lp, Po, g, tau, sigma, st, 10)
+    g.close()
