@@ -357,15 +357,20 @@ __device__ void final_step(const LPDesc& d, Scalars* sc, const double* f, bool e
       sc->rhs[slot] = f[DT::R + lane];
     }
   }
-  if (L0) {
-    int nl = 0;
-    for (int t = 0; t < nl_old; ++t)
-      if (sc->live[t] != s) w->live[nl++] = sc->live[t];
-    w->live[nl++] = s;
-    w->nl = nl;
-    sc->G[s * MAXM + s] = f[DT::DGDG];
-    sc->rhs[s] = f[DT::DGG];
-    sc->du2[s] = f[DT::DU2];
+  {
+    // live slots without the replaced one, oldest first, then the new pair
+    const int slot = lane < nl_old ? sc->live[lane] : -1;
+    const bool keep = lane < nl_old && slot != s;
+    const unsigned long long bal = __ballot(keep);
+    if (keep) w->live[__popcll(bal & ((1ull << lane) - 1ull))] = slot;
+    if (L0) {
+      const int nk = __popcll(bal);
+      w->live[nk] = s;
+      w->nl = nk + 1;
+      sc->G[s * MAXM + s] = f[DT::DGDG];
+      sc->rhs[s] = f[DT::DGG];
+      sc->du2[s] = f[DT::DU2];
+    }
   }
   wave_sync();
   int nl = w->nl;
@@ -407,6 +412,13 @@ __device__ void final_step(const LPDesc& d, Scalars* sc, const double* f, bool e
     sc->gamma[lane] = w->gam[lane];
   }
   if (lane < nl) sc->live[lane] = w->live[lane];
+  // slot for the next difference pair: the lowest free one, else the oldest
+  unsigned int used = lane < nl ? 1u << w->live[lane] : 0u;
+#pragma unroll
+  for (int off = 1; off < MAXM; off <<= 1) used |= __shfl_xor(used, off, 64);
+  used = __shfl(used, 0, 64);  // lanes 0..MAXM-1 hold every live slot
+  const unsigned int freem = ~used & ((1u << d.M) - 1u);
+  const int ns = (nl < d.M && freem != 0u) ? __ffs(freem) - 1 : w->live[0];
   wave_sync();
   if (L0) {
     sc->nmix = nmix;
@@ -418,18 +430,6 @@ __device__ void final_step(const LPDesc& d, Scalars* sc, const double* f, bool e
       sc->j_pdhg += 1;
     }
     sc->nlive = nl;
-    // slot for the next difference pair: a free one, else the oldest
-    int ns = w->live[0];
-    if (nl < d.M) {
-      for (int cand = 0; cand < d.M; ++cand) {
-        bool used = false;
-        for (int t = 0; t < nl; ++t) used |= (w->live[t] == cand);
-        if (!used) {
-          ns = cand;
-          break;
-        }
-      }
-    }
     sc->newslot = ns;
     sc->k = k + 1;
   }
