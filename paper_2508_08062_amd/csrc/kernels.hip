@@ -34,11 +34,19 @@ namespace aapdhg {
 // ---------------------------------------------------------------------------
 
 // One DPP data-movement step on the two 32-bit halves of a double (VALU only).
+// With every row enabled each lane reads a valid source lane and no old value
+// is kept; with rows masked off (row broadcasts) those lanes return 0.
 template <int CTRL, int ROWMASK>
 __device__ __forceinline__ double dpp_mov(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), CTRL, ROWMASK, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), CTRL, ROWMASK, 0xF, false);
-  return __hiloint2double(hi, lo);
+  if constexpr (ROWMASK == 0xF) {
+    const int lo = __builtin_amdgcn_mov_dpp((int)__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+  } else {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), CTRL, ROWMASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), CTRL, ROWMASK, 0xF, false);
+    return __hiloint2double(hi, lo);
+  }
 }
 
 // Sum over the 64 lanes of a wave, returned to every lane.  A fixed sequence
@@ -799,48 +807,55 @@ struct PassCtx {
   }
 };
 
-// wave_sum of C values at once: each DPP step is applied to every value
-// before the next step, so the steps of different values overlap.  The sums
-// end in lane 63.
-template <int C>
-__device__ __forceinline__ void wave_sum_lane63(double* v) {
-#pragma unroll
-  for (int q = 0; q < C; ++q) v[q] += dpp_mov<0xB1, 0xF>(v[q]);
-#pragma unroll
-  for (int q = 0; q < C; ++q) v[q] += dpp_mov<0x4E, 0xF>(v[q]);
-#pragma unroll
-  for (int q = 0; q < C; ++q) v[q] += dpp_mov<0x141, 0xF>(v[q]);
-#pragma unroll
-  for (int q = 0; q < C; ++q) v[q] += dpp_mov<0x140, 0xF>(v[q]);
-#pragma unroll
-  for (int q = 0; q < C; ++q) v[q] += dpp_mov<0x142, 0xA>(v[q]);
-#pragma unroll
-  for (int q = 0; q < C; ++q) v[q] += dpp_mov<0x143, 0xC>(v[q]);
-}
-
-// The record of one workgroup: its threads' sums, added per wave (DPP, the
-// same steps as wave_sum) and then over the four waves in order.  With
-// lane0_only the caller guarantees that only lane 0 of each wave holds
-// non-zero sums (one row per wave or per workgroup), which are then the wave
-// sums as they stand.
+// The record of one workgroup: the sums of its threads' C values, in a fixed
+// order.  Lanes are first added in groups of GL (DPP: pairs, quads and, for
+// GL = 8, half rows), every group's C sums go to LDS (s_buf, free on entry),
+// then PARTS threads per value add NG / PARTS groups each in order and finish
+// with DPP over their PARTS lanes.  With lane0_only the caller guarantees
+// that only lane 0 of each wave holds non-zero sums (one row per wave or per
+// workgroup): the four wave values are then added in order.
 template <int MT>
-__device__ __forceinline__ void write_record(double* acc, double (*s_red)[NDOT], double* out, bool lane0_only) {
+__device__ __forceinline__ void write_record(double* acc, double (*s_red)[NDOT], double* out, bool lane0_only,
+                                             double* s_buf) {
   constexpr int C = Dot<MT>::COUNT;
+  constexpr int GL = 64 * C <= CHUNK_NNZ ? 4 : 8;  // lanes per group
+  constexpr int NG = BLOCK / GL;                    // groups of the workgroup
+  constexpr int PARTS = 8 * C <= BLOCK ? 8 : 4;     // threads per value in the second stage
+  constexpr int PER = NG / PARTS;                   // groups per thread
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (lane0_only) {
     if (lane == 0) {
 #pragma unroll
       for (int q = 0; q < C; ++q) s_red[wv][q] = acc[q];
     }
-  } else {
-    wave_sum_lane63<C>(acc);
-    if (lane == 63) {
+    __syncthreads();
+    if (tid < C) st_agent(&out[tid], ((s_red[0][tid] + s_red[1][tid]) + s_red[2][tid]) + s_red[3][tid]);
+    return;
+  }
 #pragma unroll
-      for (int q = 0; q < C; ++q) s_red[wv][q] = acc[q];
-    }
+  for (int q = 0; q < C; ++q) acc[q] += dpp_mov<0xB1, 0xF>(acc[q]);  // pairs
+#pragma unroll
+  for (int q = 0; q < C; ++q) acc[q] += dpp_mov<0x4E, 0xF>(acc[q]);  // quads
+  if (GL == 8) {
+#pragma unroll
+    for (int q = 0; q < C; ++q) acc[q] += dpp_mov<0x141, 0xF>(acc[q]);  // half rows
+  }
+  __syncthreads();  // s_buf is free
+  if ((tid & (GL - 1)) == 0) {
+#pragma unroll
+    for (int q = 0; q < C; ++q) s_buf[(tid / GL) * C + q] = acc[q];
   }
   __syncthreads();
-  if (tid < C) st_agent(&out[tid], ((s_red[0][tid] + s_red[1][tid]) + s_red[2][tid]) + s_red[3][tid]);
+  const int q = tid / PARTS, part = tid % PARTS;
+  double v = 0.0;
+  if (q < C) {
+#pragma unroll
+    for (int g = 0; g < PER; ++g) v += s_buf[(part * PER + g) * C + q];
+  }
+  v += dpp_mov<0xB1, 0xF>(v);
+  v += dpp_mov<0x4E, 0xF>(v);
+  if (PARTS == 8) v += dpp_mov<0x141, 0xF>(v);
+  if (q < C && part == 0) st_agent(&out[q], v);
 }
 
 template <typename T, int MT, int PASS>
@@ -939,7 +954,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
     lane0 &= ch.tpr >= 64;
     P.template multi_chunk<false>(ch, acc, s_prod, s_tmp);
   }
-  write_record<MT>(acc, s_red, a.rec + (size_t)bw.leaf * NDOT, lane0);
+  write_record<MT>(acc, s_red, a.rec + (size_t)bw.leaf * NDOT, lane0, s_prod);
   if (PASS == 1 && climb(bw.parent)) finish_lp();
 }
 
@@ -1142,7 +1157,7 @@ __device__ __forceinline__ void loop_units(const LoopArgs& a, const LPDesc* dp, 
 #pragma unroll
     for (int q = 0; q < DT::COUNT; ++q) acc[q] = 0.0;
     P.template multi_chunk<true>(cc->ch, acc, s_prod, s_tmp, cc->idx, cc->row, cc->a0, cc->a1);
-    write_record<MT>(acc, s_red, a.rec + (size_t)cc->leaf * NDOT, cc->ch.tpr >= 64);
+    write_record<MT>(acc, s_red, a.rec + (size_t)cc->leaf * NDOT, cc->ch.tpr >= 64, s_prod);
     return;
   }
   const BlockWork* bws = PASS == 0 ? a.blocksA : a.blocksB;
@@ -1162,7 +1177,7 @@ __device__ __forceinline__ void loop_units(const LoopArgs& a, const LPDesc* dp, 
       lane0 &= ch.tpr >= 64;
       P.template multi_chunk<false>(ch, acc, s_prod, s_tmp);
     }
-    write_record<MT>(acc, s_red, a.rec + (size_t)bw.leaf * NDOT, lane0);
+    write_record<MT>(acc, s_red, a.rec + (size_t)bw.leaf * NDOT, lane0, s_prod);
   }
 }
 
