@@ -19,17 +19,17 @@ constexpr int MIX_TILE = 2048;    // elements per block of the mix pass
 constexpr int NDOT = 2 * MAXM + 16;  // stride of one partial-sum record (doubles)
 
 // Partial-sum record: MT = memory bound of the kernel instantiation.
-//   [0, MT)    <dg_new, dG[live t]>       [MT, 2MT)  <g, dG[live t]>
-//   2MT+0 <dg,dg>  2MT+1 <dg,g>  2MT+2 <g,g>  2MT+3 <du,du>
-//   2MT+4..2MT+6  KKT sums of the primal pass: c.x, l.lam+ - u.lam-, ||c-K^T y-lam||^2
-//   2MT+7..2MT+8  KKT sums of the dual pass: q.y, ||primal residual||^2
+//   [0, MT)  <dg_new, dG[live t]>, the new row of the Gram matrix
+//   MT+0 <dg,dg>  MT+1 <dg,g>  MT+2 <g,g>  MT+3 <du,du>
+//   MT+4..MT+6  KKT sums of the primal pass: c.x, l.lam+ - u.lam-, ||c-K^T y-lam||^2
+//   MT+7..MT+8  KKT sums of the dual pass: q.y, ||primal residual||^2
 // Both passes fill disjoint KKT slots, so the records of a loop pass are
-// simply added.
+// simply added.  The right-hand sides <dG[t], g^k> need no sums of their own:
+// g^k = g^{k-1} + dg_new, so <dG[t], g^k> = <dG[t], g^{k-1}> + <dG[t], dg_new>.
 template <int MT>
 struct Dot {
-  static constexpr int G = 0, R = MT, DGDG = 2 * MT, DGG = 2 * MT + 1, GG = 2 * MT + 2,
-                       DU2 = 2 * MT + 3, KA0 = 2 * MT + 4, KA1 = 2 * MT + 5, KA2 = 2 * MT + 6,
-                       KB0 = 2 * MT + 7, KB1 = 2 * MT + 8, COUNT = 2 * MT + 9;
+  static constexpr int G = 0, DGDG = MT, DGG = MT + 1, GG = MT + 2, DU2 = MT + 3, KA0 = MT + 4,
+                       KA1 = MT + 5, KA2 = MT + 6, KB0 = MT + 7, KB1 = MT + 8, COUNT = MT + 9;
 };
 
 enum Status : int { ST_CONVERGED = 0, ST_ITER_LIMIT = 1, ST_TIME_LIMIT = 2, ST_NUMERICAL = 3, ST_RUNNING = 4 };

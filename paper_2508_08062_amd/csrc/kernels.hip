@@ -362,7 +362,7 @@ __device__ void final_step(const LPDesc& d, Scalars* sc, const double* f, bool e
       const double gv = f[DT::G + lane];
       sc->G[s * MAXM + slot] = gv;
       sc->G[slot * MAXM + s] = gv;
-      sc->rhs[slot] = f[DT::R + lane];
+      sc->rhs[slot] += gv;  // <dG[slot], g^k> = <dG[slot], g^{k-1}> + <dG[slot], dg_new>
     }
   }
   {
@@ -643,7 +643,6 @@ struct PassCtx {
         if (t < v.nl && !(t == 0 && v.skip0)) {
           const double hv = (double)in.hv[t];
           accv[DT::G + t] += dg * hv;
-          accv[DT::R + t] += gd * hv;
         }
       }
     }

@@ -10,9 +10,13 @@ equilibrated, float32-rounded LP:
     (the float32 storage of x_hat, x_bar and y_hat; the products are exact
     in float64);
   * the history: every Gram entry is the float64 dot product of the stored
-    difference columns, every right-hand side the dot product with the stored
-    residual, and ||g|| the norm of the stored residual (float64 sums of the
-    same float32 values in another order: relative 1e-9);
+    difference columns and ||g|| the norm of the stored residual (float64
+    sums of the same float32 values in another order: relative 1e-9); every
+    right-hand side is the dot product with the stored residual up to the
+    rounding of the float32 difference columns it was updated with (the
+    library adds each new Gram row to the right-hand sides, which is exact
+    for exact differences: each update adds at most 2^-24 ||dG_a|| ||dG_s||,
+    allowed for 4 M updates of the largest live column);
   * the counters add up (i + j = k - 1), the iterate lies in X x Y, and the
     KKT residuals reported at the returned point equal the oracle's there.
 """
@@ -34,7 +38,7 @@ def _scaled_oracle_problem(lp, ruiz_iters):
     return Po.rounded_fp32()
 
 
-def _check_state(lp, Po, g, tau, sigma, st, M):
+def _check_state(lp, Po, g, tau, sigma, st, M, fp32=True):
     n = lp.n
     up, gp = st["u_prev"], st["g_prev"]
     # the last PDHG point
@@ -55,7 +59,9 @@ def _check_state(lp, Po, g, tau, sigma, st, M):
             tol = 1e-9 * np.sqrt(G[a, a] * G[b, b]) + 1e-300
             assert abs(G[a, b] - want) <= tol, (a, b, G[a, b], want)
         want = float(np.dot(st["dG"][a], gp))
-        assert abs(rhs[a] - want) <= 1e-9 * np.sqrt(G[a, a] * float(gp @ gp)) + 1e-300
+        big = max(np.sqrt(G[b, b]) for b in live)
+        upd = 4 * M * 2.0 ** -24 * np.sqrt(G[a, a]) * big if fp32 else 0.0
+        assert abs(rhs[a] - want) <= 1e-9 * np.sqrt(G[a, a] * float(gp @ gp)) + upd + 1e-300, (a, rhs[a], want)
     assert st["gnorm"] == pytest.approx(float(np.linalg.norm(gp)), rel=1e-9)
     # counters and projections
     assert st["i"] + st["j"] == st["k"] - 1
