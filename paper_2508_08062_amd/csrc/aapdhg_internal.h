@@ -17,6 +17,8 @@ constexpr int SPLIT_NNZ = 8192;   // nnz per part of a split (very long) row
 constexpr int FAN = 48;           // children per node of the reduction tree
 constexpr int MIX_TILE = 2048;    // elements per block of the mix pass
 constexpr int NDOT = 2 * MAXM + 16;  // stride of one partial-sum record (doubles)
+constexpr int PANELS = 8;         // column panels of the dual product (one per XCD)
+constexpr int PANEL_ROWS = 1024;  // rows of one panel chunk (four per thread)
 
 // Partial-sum record: MT = memory bound of the kernel instantiation.
 //   [0, MT)  <dg_new, dG[live t]>, the new row of the Gram matrix
@@ -92,6 +94,20 @@ struct LPDesc {
   void* W;     // dU + beta D-hat dG, [M][N]
   void* lam;   // reduced costs written by the evaluation pass (length n)
   Scalars* sc;
+  // Column panels of the CSR (large LPs in launches of their own): the
+  // entries of row position r whose column lies in panel p are
+  // [pptr[p (m+1) + r], pptr[p (m+1) + r + 1]) of pidx / pval; part holds the
+  // panel row sums [2][PANELS][m] (x_bar, and x^k on KKT passes).
+  int panels;  // 0 or PANELS
+  const int* pptr;
+  const int* pidx;
+  const void* pval;
+  double* part;
+  // panel p's chunks (<= PANEL_ROWS rows, <= CHUNK_NNZ entries each) start at
+  // the rows pchunk[pcoff[p] + c], c < pcoff[p+1] - pcoff[p] - 1; the list
+  // of each panel ends with m
+  const int* pchunk;
+  int pcoff[PANELS + 1];
 };
 
 // One workgroup's share of an SpMV pass.  "Rows" are columns of K in the

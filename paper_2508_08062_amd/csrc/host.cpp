@@ -129,6 +129,7 @@ static int pow2floor(int v) {
 }
 
 constexpr int LONG_ROW = 128;  // rows above this length leave the multi-row chunks
+constexpr int64_t PANEL_MIN_NNZ = 1 << 22;  // column panels for the dual product from 4M entries
 
 // Order of the rows of one pass on the device: rows of at most LONG_ROW
 // entries keep their original order (their epilogue accesses stay
@@ -464,6 +465,71 @@ void Problem::create(int32_t m_, int32_t n_, int64_t nnz_, const int64_t* row_pt
     upload_as<float>(d_dhat, dhat, "dhat");
   }
   d_rowtype.upload(rowtype.data(), rowtype.size(), "rowtype");
+  // ---- column panels of the dual product for large LPs without split rows:
+  // the workgroups of panel p gather only the 1/PANELS of x_bar it covers,
+  // which stays in the L2 of the XCD that runs them ----
+  panels = (int64_t)nnz >= PANEL_MIN_NNZ && splitsB.empty() && n >= PANELS * 1024;
+  if (panels) {
+    std::vector<int> pptr((size_t)PANELS * (m + 1), 0), pidx(nnz);
+    std::vector<double> pval(nnz);
+    auto panel_of = [&](int col) { return (int)((int64_t)col * PANELS / n); };
+    std::vector<int64_t> cnt(PANELS, 0);
+    for (int q = 0; q < nnz; ++q) cnt[panel_of(idxB[q])]++;
+    std::vector<int64_t> base(PANELS + 1, 0);
+    for (int p = 0; p < PANELS; ++p) base[p + 1] = base[p] + cnt[p];
+    std::vector<int64_t> fill(base.begin(), base.end() - 1);
+    for (int r = 0; r < m; ++r) {
+      for (int p = 0; p < PANELS; ++p) pptr[(size_t)p * (m + 1) + r] = (int)fill[p];
+      for (int q = ptrB[r]; q < ptrB[r + 1]; ++q) {
+        const int p = panel_of(idxB[q]);
+        pidx[fill[p]] = idxB[q];
+        pval[fill[p]] = valB[q];
+        ++fill[p];
+      }
+    }
+    for (int p = 0; p < PANELS; ++p) pptr[(size_t)p * (m + 1) + m] = (int)fill[p];
+    d_pptr.upload(pptr.data(), pptr.size() * 4, "panel pointers");
+    d_pidx.upload(pidx.data(), pidx.size() * 4, "panel indices");
+    if (fp64)
+      upload_as<double>(d_pval, pval, "panel values");
+    else
+      upload_as<float>(d_pval, pval, "panel values");
+    d_part.alloc((size_t)2 * PANELS * m * 8, "panel sums");
+    // chunks of each panel for k_panel: consecutive rows, at most PANEL_ROWS
+    // of them and CHUNK_NNZ entries
+    std::vector<int> pchunk;
+    for (int p = 0; p < PANELS; ++p) {
+      pcoff[p] = (int)pchunk.size();
+      const int* pp = pptr.data() + (size_t)p * (m + 1);
+      int r = 0;
+      while (r < m) {
+        pchunk.push_back(r);
+        int rows = 0, ent = 0;
+        while (r < m && rows < PANEL_ROWS) {
+          const int len = pp[r + 1] - pp[r];
+          if (rows > 0 && ent + len > CHUNK_NNZ) break;
+          ent += len;
+          ++rows;
+          ++r;
+        }
+      }
+      pchunk.push_back(m);
+    }
+    pcoff[PANELS] = (int)pchunk.size();
+    d_pchunk.upload(pchunk.data(), pchunk.size() * 4, "panel chunks");
+    // the dual epilogue then only adds panel sums: chunks of BLOCK rows
+    chunksBp.clear();
+    for (int r = 0; r < m; r += BLOCK) {
+      Chunk c{};
+      c.kind = 0;
+      c.r0 = r;
+      c.r1 = std::min(m, r + BLOCK);
+      c.k0 = ptrB[c.r0];
+      c.k1 = ptrB[c.r1];
+      c.tpr = 1;
+      chunksBp.push_back(c);
+    }
+  }
   for (int p = 0; p < 2; ++p) {
     d_u[p].alloc(N * ts, "u");
     d_u[p].zero("u");
@@ -540,6 +606,13 @@ void Problem::fill_desc() {
   desc.W = d_hist_W.p;
   desc.lam = d_lam.p;
   desc.sc = (Scalars*)d_sc.p;
+  desc.panels = panels ? PANELS : 0;
+  desc.pptr = (const int*)d_pptr.p;
+  desc.pidx = (const int*)d_pidx.p;
+  desc.pval = d_pval.p;
+  desc.part = (double*)d_part.p;
+  desc.pchunk = (const int*)d_pchunk.p;
+  for (int p = 0; p <= PANELS; ++p) desc.pcoff[p] = pcoff[p];
 }
 
 double Problem::power_norm() {
@@ -555,7 +628,8 @@ double Problem::power_norm() {
 
 size_t Problem::device_bytes() const {
   size_t b = 0;
-  const DevBuf* bufs[] = {&d_rowptr, &d_colidx, &d_val, &d_colptr, &d_rowidx, &d_valT, &d_rmapA, &d_rmapB, &d_c, &d_lo, &d_hi,
+  const DevBuf* bufs[] = {&d_pptr, &d_pidx, &d_pval, &d_part, &d_pchunk,
+                          &d_rowptr, &d_colidx, &d_val, &d_colptr, &d_rowidx, &d_valT, &d_rmapA, &d_rmapB, &d_c, &d_lo, &d_hi,
                           &d_q, &d_dhat, &d_rowtype, &d_u[0], &d_u[1], &d_g[0], &d_g[1], &d_xbar, &d_hist_dG,
                           &d_hist_W, &d_lam, &d_sc, &d_desc, &d_xfer};
   for (auto* p : bufs) b += p->bytes;
@@ -649,8 +723,9 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
     if (p->fp64 != t.fp64) throw Error(AAPDHG_E_ARG, "all problems of a batch must share the precision");
     mt = std::max(mt, p->opt.memory);
     descs.push_back(p->desc);
+    if (count > 1) descs.back().panels = 0;  // panels run only in a launch of their own
     for (int pass = 0; pass < 2; ++pass) {
-      const auto& pc = pass == 0 ? p->chunksA : p->chunksB;
+      const auto& pc = pass == 0 ? p->chunksA : (count == 1 && p->panels ? p->chunksBp : p->chunksB);
       const auto& ps = pass == 0 ? p->splitsA : p->splitsB;
       const int np = pass == 0 ? p->npartsA : p->npartsB;
       auto& bw = pass == 0 ? bA : bB;
@@ -734,6 +809,7 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
     }
   }
   t.mt = mt;
+  t.panels = count == 1 && lps[0]->panels;
   t.nlps = count;
   d_lps.upload(descs.data(), descs.size() * sizeof(LPDesc), "lp table");
   d_llp.upload(llp.data(), llp.size() * sizeof(LaunchLP), "lp roots");

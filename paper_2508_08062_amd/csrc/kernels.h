@@ -30,6 +30,7 @@ struct LaunchTables {
   const MixTile* tiles = nullptr;
   int ntiles = 0;
   // persistent loop kernel (when the set fits the resident workgroups)
+  bool panels = false;  // the one LP of the table has column panels for its dual product
   bool persistent = false;
   const LoopWG* wgs = nullptr;
   int nwgs = 0;

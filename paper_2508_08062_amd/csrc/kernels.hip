@@ -685,6 +685,23 @@ struct PassCtx {
     const bool has_row = r < r1 && (!blockmode || tid == 0);
     int row = 0;  // its original row
     if (has_row) row = CACHED ? crow[tid] : rmap[r];
+    if (!COH && PASS == 1 && dp->panels) {
+      // the row sums were formed by k_panel: add the panels in order
+      if (has_row && lane_r == 0) {
+        RowIn<T, MT> rin;
+        load_row(row, rin, false);
+        const int m = dp->m;
+        double sum1 = 0.0, sum2 = 0.0;
+#pragma unroll
+        for (int p = 0; p < PANELS; ++p) sum1 += dp->part[(size_t)p * m + r];
+        if (two) {
+#pragma unroll
+          for (int p = 0; p < PANELS; ++p) sum2 += dp->part[(size_t)(PANELS + p) * m + r];
+        }
+        finish_row(row, rin, sum1, sum2, acc, false);
+      }
+      return;
+    }
     int ci[UNR];
     T vv[UNR];
 #pragma unroll
@@ -1376,6 +1393,91 @@ __global__ __launch_bounds__(BLOCK) void k_loop(LoopArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// column panels of the dual product (large LPs): row sums per panel
+// ---------------------------------------------------------------------------
+
+// Workgroup b works on panel b % PANELS: workgroups are dealt to the XCDs in
+// turn, so each XCD gathers from one 1/PANELS slice of x_bar, which stays in
+// its L2.  A workgroup takes every (gridDim / PANELS)-th chunk of its panel:
+// stages the chunk's products in LDS (eight gathers in flight per thread),
+// then each thread adds the entries of up to four rows in order.  Writes
+// part[0][p][r] (x_bar, or x^k when evaluating) and, on KKT passes,
+// part[1][p][r] (x^k).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_panel(const LPDesc* lps, int mode) {
+  constexpr int UNR = CHUNK_NNZ / BLOCK;
+  constexpr int RPT = PANEL_ROWS / BLOCK;
+  __shared__ double s_p[CHUNK_NNZ];
+  const LPDesc& d = lps[0];
+  const Scalars* sc = d.sc;
+  const bool eval = mode == MODE_EVAL;
+  if (!eval && sc->status != ST_RUNNING) return;
+  const long long k = sc->k;
+  const bool init = !eval && k == 0;
+  const bool kkt = eval || (!init && d.kkt_every > 0 && (k % d.kkt_every) == 0);
+  const T* ucur = (const T*)d.u[(int)(k & 1)];
+  const T* __restrict__ gv1 = eval ? ucur : (const T*)d.xbar;
+  const T* __restrict__ gv2 = ucur;
+  const bool two = kkt && !eval;
+  const int tid = threadIdx.x;
+  const int p = blockIdx.x % PANELS;
+  const int j = blockIdx.x / PANELS, nj = gridDim.x / PANELS;
+  const int m = d.m;
+  const int* __restrict__ ptr = d.pptr + (size_t)p * (m + 1);
+  const int* __restrict__ idx = d.pidx;
+  const T* __restrict__ val = (const T*)d.pval;
+  const int* __restrict__ cst = d.pchunk + d.pcoff[p];
+  const int nch = d.pcoff[p + 1] - d.pcoff[p] - 1;
+  double* __restrict__ out1 = d.part + (size_t)p * m;
+  double* __restrict__ out2 = d.part + (size_t)(PANELS + p) * m;
+  for (int c = j; c < nch; c += nj) {
+    const int r0 = cst[c], r1 = cst[c + 1];
+    const int kb = ptr[r0], ke = ptr[r1];
+    int ra[RPT], rb[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = r0 + tid + i * BLOCK;
+      ra[i] = r < r1 ? ptr[r] - kb : 0;
+      rb[i] = r < r1 ? ptr[r + 1] - kb : 0;
+    }
+    int ci[UNR];
+    T vv[UNR], g1[UNR], g2[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int q = kb + tid + u * BLOCK;
+      ci[u] = q < ke ? idx[q] : 0;
+      vv[u] = q < ke ? val[q] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const bool ok = kb + tid + u * BLOCK < ke;
+      g1[u] = ok ? gv1[ci[u]] : (T)0;
+      g2[u] = (ok && two) ? gv2[ci[u]] : (T)0;
+    }
+    // one sweep per gathered vector (the second only on KKT passes)
+    for (int sw = 0; sw < (two ? 2 : 1); ++sw) {
+      __syncthreads();  // the previous sums are done with the LDS
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int q = tid + u * BLOCK;
+        if (kb + q < ke) s_p[q] = (double)vv[u] * (double)(sw == 0 ? g1[u] : g2[u]);
+      }
+      __syncthreads();
+      double* out = sw == 0 ? out1 : out2;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int r = r0 + tid + i * BLOCK;
+        if (r < r1) {
+          double a = 0.0;
+          for (int q = ra[i]; q < rb[i]; ++q) a += s_p[q];
+          out[r] = a;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // pass C: Anderson mix and projection (Alg 2: u^{k+1} = P(u^k - H^k g^k))
 // ---------------------------------------------------------------------------
 
@@ -1498,6 +1600,8 @@ __global__ void k_convert(const S* src, D* dst, size_t len) {
 // host-side launchers
 // ---------------------------------------------------------------------------
 
+constexpr int PANEL_GROUPS = 256;  // workgroups per panel (8 per CU of an XCD; the LDS allows them)
+
 template <typename T, int MT>
 static hipError_t launch_passes_mt(const LaunchTables& t, hipStream_t st, int mode, hipEvent_t* ev) {
   PassArgs pa{};
@@ -1516,6 +1620,7 @@ static hipError_t launch_passes_mt(const LaunchTables& t, hipStream_t st, int mo
   if (ev) (void)hipEventRecord(ev[0], st);
   if (t.nblocksA > 0) hipLaunchKernelGGL((k_pass<T, MT, 0>), dim3(t.nblocksA), dim3(BLOCK), 0, st, pa);
   if (ev) (void)hipEventRecord(ev[1], st);
+  if (t.panels) hipLaunchKernelGGL((k_panel<T>), dim3(PANELS * PANEL_GROUPS), dim3(BLOCK), 0, st, t.lps, mode);
   pa.blocks = t.blocksB;
   if (t.nblocksB > 0) hipLaunchKernelGGL((k_pass<T, MT, 1>), dim3(t.nblocksB), dim3(BLOCK), 0, st, pa);
   if (ev) (void)hipEventRecord(ev[2], st);

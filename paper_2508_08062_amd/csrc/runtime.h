@@ -90,6 +90,10 @@ struct Problem {
   DevBuf d_rowptr, d_colidx, d_val, d_colptr, d_rowidx, d_valT, d_rmapA, d_rmapB, d_c, d_lo, d_hi, d_q, d_dhat,
       d_rowtype;
   DevBuf d_u[2], d_g[2], d_xbar, d_hist_dG, d_hist_W, d_lam, d_sc, d_desc, d_xfer;
+  DevBuf d_pptr, d_pidx, d_pval, d_part, d_pchunk;  // column panels of the dual product
+  bool panels = false;
+  int pcoff[PANELS + 1] = {};
+  std::vector<Chunk> chunksBp;  // dual pass in a launch of its own with panels: 256-row chunks
   LPDesc desc{};
   Scalars sc_init{};
   std::unique_ptr<LaunchSet> solo;
