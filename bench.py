@@ -70,8 +70,14 @@ def _traffic(workload, kernel, ppl):
         return None
     if kernel == "loop" and t.get("passes_per_launch") != ppl:
         return None
-    k = t.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("hbm_bytes_per_launch")
+    ks = t.get("kernels", {})
+    k = ks.get(kernel)
+    if k is None:
+        return None
+    b = k.get("hbm_bytes_per_launch")
+    if kernel == "dual" and "panel" in ks:  # the dual launch's events bracket the panel kernel too
+        b += ks["panel"]["hbm_bytes_per_launch"]
+    return b
 
 
 def _workload(name):
