@@ -96,7 +96,11 @@ typedef struct {
   int32_t loop_kernel;/* 0: loop passes run in one persistent cooperative launch per epoch
                          when the LPs fit the resident workgroups, else three launches per
                          pass; 1: always three launches per pass                          */
-  int32_t reserved[5];
+  int32_t wait_limit_us; /* bound (microseconds) of every cross-workgroup wait of the
+                         persistent loop kernel; a wait that reaches it stops the LP
+                         (AAPDHG_NUMERICAL) and the solve returns AAPDHG_E_HIP;
+                         0 = 4 s                                                          */
+  int32_t reserved[4];
 } aapdhg_options;
 
 typedef struct {

@@ -33,7 +33,7 @@ class Options(C.Structure):
                 ("tol", C.c_double), ("max_iter", C.c_int64), ("time_limit_s", C.c_double),
                 ("kkt_every", C.c_int32), ("dhat_mode", C.c_int32), ("ruiz_iters", C.c_int32),
                 ("power_iters", C.c_int32), ("epoch", C.c_int32), ("chunks_per_block", C.c_int32),
-                ("loop_kernel", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("loop_kernel", C.c_int32), ("wait_limit_us", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class Info(C.Structure):

@@ -223,9 +223,8 @@ constexpr int SUB_STRIDE = 32;  // unsigned ints between sub-counters
 struct alignas(256) LoopSync {
   unsigned int bar[NSUB * SUB_STRIDE];  // group-barrier arrivals
   unsigned int arr[NSUB * SUB_STRIDE];  // arrivals after the CSR phase
-  unsigned int flag;                    // passes whose decisions are published
   unsigned int abort;                   // set when a wait gave up
-  unsigned int pad[62];
+  unsigned int pad[63];
 };
 
 // Decisions of a pass as every workgroup of the group keeps them (LDS).

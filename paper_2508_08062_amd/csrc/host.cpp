@@ -115,6 +115,7 @@ static void check_options(const aapdhg_options& o) {
   if (o.epoch < 1 || o.epoch > 1000000) throw Error(AAPDHG_E_ARG, "epoch must be in [1, 1e6]");
   if (o.chunks_per_block < 0 || o.chunks_per_block > 4096) throw Error(AAPDHG_E_ARG, "chunks_per_block must be in [0, 4096]");
   if (o.loop_kernel < 0 || o.loop_kernel > 1) throw Error(AAPDHG_E_ARG, "loop_kernel must be 0 or 1");
+  if (o.wait_limit_us < 0) throw Error(AAPDHG_E_ARG, "wait_limit_us must be >= 0");
   if (!std::isfinite(o.tau) || !std::isfinite(o.sigma)) throw Error(AAPDHG_E_ARG, "tau and sigma must be finite");
 }
 
@@ -934,7 +935,11 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
   int dev = 0, khz = 0;
   hip_check(hipGetDevice(&dev), "device");
   hip_check(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev), "wall clock rate");
-  t.timeout_ticks = (unsigned long long)std::max(khz, 1000) * 4000ull;  // about 4 s
+  long long wait_us = 0;
+  for (auto* p : lps) wait_us = std::max<long long>(wait_us, p->opt.wait_limit_us);
+  if (wait_us == 0) wait_us = 4000000;
+  // wall-clock ticks: khz per millisecond
+  t.timeout_ticks = std::max<unsigned long long>(1ull, (unsigned long long)std::max(khz, 1) * (unsigned long long)wait_us / 1000ull);
   t.wgs = (const LoopWG*)d_wgs.p;
   t.nwgs = (int)wgs.size();
   t.looplps = (const LoopLP*)d_looplps.p;

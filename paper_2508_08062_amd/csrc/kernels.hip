@@ -989,7 +989,8 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
 //   takes the decisions (final_step) and publishes them;
 //   on Anderson steps every workgroup mixes the entries it owns, then a group
 //   barrier (the next phase A gathers the new y).
-// Every wait is bounded: after about four seconds, or once another
+// Every wait is bounded: after the wait limit (four seconds unless the
+// options set it), or once another
 // workgroup of the LP has given up, it returns false, the group leaves the
 // loop and the launch reports the failure in *err.
 

@@ -269,3 +269,24 @@ def test_fp64_solve_objective_matches_oracle(tol):
     assert abs(r["primal_obj"] - o_obj) / (1 + abs(o_obj)) <= (1e-6 if tol <= 1e-6 else tol)
     pstar = lp.planted["pstar"]
     assert abs(r["primal_obj"] - pstar) / (1 + abs(pstar)) < 10 * tol
+
+
+def test_bounded_waits_give_up_cleanly():
+    """Failure handling forced from the host: a wait limit of 1 us makes the
+    persistent kernel's waits give up; the launch ends (every wait is
+    bounded), the solve reports the error and stops the LP, and the device
+    runs the next solve normally."""
+    lp = lpgen.tiny_lp(4)
+    kw = dict(precision=1, memory=5, kkt_every=8, tol=1e-4, max_iter=20000)
+    g = _gpu(lp, wait_limit_us=1, **kw)
+    with pytest.raises(P.AAPDHGError) as e:
+        g.solve()
+    assert e.value.status == P.E_HIP
+    assert "timed out" in str(e.value)
+    assert g.result()["status"] == "numerical"
+    g.close()
+    g2 = _gpu(lp, **kw)
+    g2.solve()
+    r = g2.result()
+    assert r["status"] == "converged" and r["kkt"] <= 1e-4
+    g2.close()
