@@ -157,6 +157,7 @@ def _batch_solve(args):
     el = time.perf_counter() - t0
     res = batch.results()
     iters = np.array([r["iters"] for r in res])
+    done_s = np.array([r["solve_seconds"] for r in res])  # per LP: time until seen stopped
     conv = sum(r["status"] == "converged" for r in res)
     batch.close()
     for sv in solvers:
@@ -184,6 +185,9 @@ def _batch_solve(args):
                  {**cfg, "lps": len(lps), "nnz_total": nnz_all},
                  {"batch_seconds": el, "converged": int(conv), "iters_median": float(np.median(iters)),
                   "iters_max": int(iters.max()),
+                  "completion_p50_s": float(np.percentile(done_s, 50)),
+                  "completion_p99_s": float(np.percentile(done_s, 99)),
+                  "lps_done_by_p50_per_s": 0.5 * len(lps) / float(np.percentile(done_s, 50)),
                   "fp64_single": {"sample": sample, "seconds": t64, "iters": it64, "nnz_sample": nnz_s,
                                   "lps_per_s_estimate": len(lps) / est64,
                                   "estimate": "sample seconds scaled by nnz x iterations to all LPs"}},
@@ -191,7 +195,7 @@ def _batch_solve(args):
     print(json.dumps(line), flush=True)
 
 
-def _serve(args):
+def _serve(args, rate=None, seconds=None, pool_size=None, drain=None, emit=True):
     """A Poisson stream of LP requests through the server; LPs solved per
     second and latency from submission to completion."""
     import numpy as np
@@ -199,14 +203,18 @@ def _serve(args):
 
     import lpgen
     import paper_2508_08062_amd as P
-    reqs = lpgen.serving_requests(rate=args.rate, duration=args.serve_seconds, seed=4)
-    pool = [lpgen.mip_like_lp(r[4], m=r[1], n=r[2], nnz=r[3]) for r in reqs[:args.pool]]
+    rate = args.rate if rate is None else rate
+    seconds = args.serve_seconds if seconds is None else seconds
+    pool_size = args.pool if pool_size is None else pool_size
+    drain = args.drain_seconds if drain is None else drain
+    reqs = lpgen.serving_requests(rate=rate, duration=seconds, seed=4)
+    pool = [lpgen.mip_like_lp(r[4], m=r[1], n=r[2], nnz=r[3]) for r in reqs[:pool_size]]
     opts = dict(variant=1, precision=0, memory=10, kkt_every=64, ruiz_iters=10, dhat_mode=0, tol=1e-4,
                 max_iter=200000, epoch=64)
     torch.cuda.init()
     free, _ = torch.cuda.mem_get_info()
     srv = P.Server(hbm_budget_bytes=int(free * 0.8), max_slots=args.slots, **opts)
-    print(f"# {len(reqs)} requests over {args.serve_seconds} s, pool {len(pool)}", file=sys.stderr, flush=True)
+    print(f"# {len(reqs)} requests over {seconds} s, pool {len(pool)}", file=sys.stderr, flush=True)
     pending = {}
     lat = []
     t0 = time.perf_counter()
@@ -225,7 +233,7 @@ def _serve(args):
             r = srv.poll(tk, want_solution=False)
             if r is not None:
                 lat.append((r["t_done"], r["status"], pending.pop(tk)))
-        if time.perf_counter() - t0 > args.serve_seconds + args.drain_seconds:
+        if time.perf_counter() - t0 > seconds + drain:
             break  # requests still pending are reported as unfinished
         time.sleep(0.0005)
     el = time.perf_counter() - t0
@@ -234,7 +242,7 @@ def _serve(args):
     d = np.array([x[0] for x in lat])
     conv = sum(x[1] == "converged" for x in lat)
     line = _line("LPs solved/s & p99 latency at rel KKT 1e-4 (served float32)", len(lat) / el, "LPs/s",
-                 {"workload": f"Poisson stream {args.rate}/s for {args.serve_seconds} s (serving_requests seed 4), "
+                 {"workload": f"Poisson stream {rate}/s for {seconds} s (serving_requests seed 4), "
                               f"columns lognormal(ln 20000, 1) in [1k, 500k], rows 0.4 x columns, 5 nnz/column; "
                               f"{len(pool)} distinct LPs cycled", "variant": "AA-PDHG", "m_A": 10},
                  {"requests": len(reqs), "finished": len(lat), "unfinished": len(pending), "converged": int(conv),
@@ -242,7 +250,9 @@ def _serve(args):
                   "latency_p50_s": float(np.percentile(d, 50)) if d.size else None,
                   "latency_p99_s": float(np.percentile(d, 99)) if d.size else None,
                   "latency_max_s": float(d.max()) if d.size else None, "server": st})
-    print(json.dumps(line), flush=True)
+    if emit:
+        print(json.dumps(line), flush=True)
+    return line
 
 
 def main():
@@ -257,6 +267,10 @@ def main():
     ap.add_argument("--slots", type=int, default=64, help="serve: resident LPs at most")
     ap.add_argument("--drain-seconds", type=float, default=120.0, help="serve: wait after the last arrival")
     ap.add_argument("--fp64-sample", type=int, default=8, help="batch256: LPs solved singly in float64")
+    ap.add_argument("--serve-rate", type=float, default=4.0,
+                    help="single-LP workloads: rate of the short serving leg (0 = none)")
+    ap.add_argument("--serve-leg-seconds", type=float, default=10.0, help="length of the short serving leg")
+    ap.add_argument("--serve-leg-drain", type=float, default=40.0, help="drain of the short serving leg")
     ap.add_argument("--passes-per-launch", type=int, default=500,
                     help="loop passes per launch of the persistent loop kernel")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -384,6 +398,15 @@ def main():
                         "primal_obj": r["primal_obj"], "aa_steps": r["aa_steps"]}
             s.close()
         line.update(res)
+
+    if args.serve_rate > 0 and len(lps) == 1:
+        # a short serving leg: LPs solved per second and latency of a stream the server keeps up with
+        sv = _serve(args, rate=args.serve_rate, seconds=args.serve_leg_seconds, pool_size=16,
+                    drain=args.serve_leg_drain, emit=False)
+        line["serving"] = {k: sv[k] for k in ("value", "unit")}
+        line["serving"].update({k: sv[k] for k in ("requests", "finished", "unfinished", "converged", "seconds",
+                                                   "latency_p50_s", "latency_p99_s", "latency_max_s")})
+        line["serving"]["workload"] = sv["config"]["workload"]
 
     if not args.no_cpu_baseline:
         rate, k, el = _cpu_baseline(lps, opts, args.cpu_seconds)

@@ -114,7 +114,9 @@ typedef struct {
   double r_gap, r_pri, r_dual, kkt; /* relative KKT pieces and their max               */
   double gnorm;            /* ||g^k|| of the last loop pass                                */
   double g0norm;           /* ||g^0||                                                      */
-  double solve_seconds;    /* host wall time of the last solve/iterate call                */
+  double solve_seconds;    /* host wall time of the last solve call; for a batch member, the
+                              time until the member was seen stopped (status read once per
+                              epoch)                                                       */
   double step_tau, step_sigma;
 } aapdhg_info;
 

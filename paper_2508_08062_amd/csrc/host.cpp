@@ -1025,6 +1025,7 @@ double LaunchSet::run_to_completion(hipStream_t st, int epoch, double time_limit
   int pend_slot = 0;
   bool done = false;
   int64_t epochs = 0;
+  finish_s.assign(count, -1.0);
   while (!done) {
     enqueue_passes(st, epoch);
     hip_check(launch_gather_status(t.lps, count, (int*)d_status.p, st), "status gather");
@@ -1034,7 +1035,12 @@ double LaunchSet::run_to_completion(hipStream_t st, int epoch, double time_limit
     if (pending) {
       hip_check(hipEventSynchronize(ev[pend_slot]), "event wait");
       bool any = false;
-      for (int i = 0; i < count; ++i) any |= h_status[pend_slot * MAX_STATUS + i] == ST_RUNNING;
+      const double now = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      for (int i = 0; i < count; ++i) {
+        const bool run = h_status[pend_slot * MAX_STATUS + i] == ST_RUNNING;
+        any |= run;
+        if (!run && finish_s[i] < 0.0) finish_s[i] = now;  // seen stopped at this status read
+      }
       if (!any) done = true;
     }
     pending = true;
@@ -1050,8 +1056,11 @@ double LaunchSet::run_to_completion(hipStream_t st, int epoch, double time_limit
   (void)hipEventDestroy(ev[0]);
   (void)hipEventDestroy(ev[1]);
   last_epochs = epochs;
+  const double total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (auto& f : finish_s)
+    if (f < 0.0) f = total;
   check_loop_error(st);
-  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return total;
 }
 
 // ---------------------------------------------------------------------------
@@ -1385,7 +1394,8 @@ aapdhg_status aapdhg_batch_solve(aapdhg_batch_t b, void* stream) {
       tl = std::max(tl, h->p.opt.time_limit_s);
     }
     const double secs = b->set.run_to_completion(st, epoch, tl);
-    for (auto* h : b->members) h->p.last_solve_seconds = secs;
+    (void)secs;
+    for (size_t i = 0; i < b->members.size(); ++i) b->members[i]->p.last_solve_seconds = b->set.finish_s[i];
   });
 }
 

@@ -49,6 +49,7 @@ struct LaunchSet {
       d_splitcnt, d_tiles, d_status, d_wgs, d_looplps, d_sync, d_bc, d_err;
   int* h_status = nullptr;  // pinned, 2 x MAX_STATUS
   int64_t last_epochs = 0;
+  std::vector<double> finish_s;  // per member: seconds into run_to_completion when seen stopped
   ~LaunchSet();
   void build(const std::vector<Problem*>& lps);
   void enqueue_passes(hipStream_t st, int64_t iters);
