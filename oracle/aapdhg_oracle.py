@@ -40,6 +40,23 @@ where it matters, and the GPU library takes the same reading):
     appended to (Section 5, implemented variant).
   * Infinite bounds contribute nothing to the dual objective; the set Lambda
     forces the matching part of lambda to zero (eq. lambda-case).
+  * Primal-weight update (Alg 7, optional, ``pw_period`` = U_P > 0): it runs
+    at the top of iteration k (k > 0, k % U_P == 0), before T u^k, and
+    measures x^k - x^{k-U_P}, y^k - y^{k-U_P} against the iterate of the
+    previous check (u^0 for the first).  An accepted update resets the memory;
+    the difference pair of iteration k would join residuals of two different
+    maps and is not formed, so iteration k has m_k = 0 and its AA step (if the
+    safeguard lets it through) is u^k + beta D-hat g^k.  The counters i, j and
+    ||g^0|| carry on.  The step sizes are tau = gamma / omega and
+    sigma = gamma * omega with gamma = sqrt(tau_0 sigma_0) and, unless given,
+    omega^0 = sqrt(sigma_0 / tau_0).
+  * D-hat re-blend (remark on the primal-weight form, optional ``pw_dhat``):
+    after an accepted update, at iteration k once g^k is known,
+    rho_k = (||g^{k-1}|| - ||g^k||) / max(||g^{k-1}||, eps_zero); "decreases
+    sufficiently" is rho_k > ``pw_rho`` (default 0), giving alpha = 0.1, else
+    alpha = 0.9; D-hat_1, D-hat_2 in R are those of the D-hat construction.
+  * Iter_AA / c (supplement, update-D-hat study): the safeguard bound uses
+    (i/c + 1) in place of (i + 1), real division; c = ``sg_div`` (default 1).
 """
 from __future__ import annotations
 
@@ -321,6 +338,14 @@ class Options:
     kkt_every: int = 64
     dhat_mode: int = 1
     fpr_stop: bool = False  # Alg 2's literal ||g^k|| < tol test
+    sg_div: float = 1.0  # c of the Iter_AA / c safeguard
+    # primal-weight update (Alg 7) and D-hat re-blend (remark on the primal-weight form)
+    pw_period: int = 0  # U_P; 0 = off
+    pw_theta: float = 0.5  # smoothing theta
+    pw_eps_zero: float = 1e-10  # epsilon_zero
+    pw_omega0: float = 0.0  # omega^0; <= 0: sqrt(sigma / tau)
+    pw_dhat: bool = True  # re-blend D-hat after each accepted update
+    pw_rho: float = 0.0  # rho_k above this: alpha = 0.1, else 0.9
 
 
 @dataclasses.dataclass
@@ -348,6 +373,14 @@ class Solver:
             nrm = power_norm(P)
             self.opt.tau = self.opt.sigma = 0.9 / nrm
         self.Dhat = dhat(P, self.opt.dhat_mode)
+        self.Dhat0 = self.Dhat.copy()  # D-hat_1, D-hat_2 of the construction
+        # primal weight: tau = gamma / omega, sigma = gamma * omega (remark on the primal-weight form)
+        self.step_gamma = math.sqrt(self.opt.tau * self.opt.sigma)
+        self.omega = self.opt.pw_omega0 if self.opt.pw_omega0 > 0.0 else math.sqrt(self.opt.sigma / self.opt.tau)
+        if self.opt.pw_omega0 > 0.0:
+            self.opt.tau = self.step_gamma / self.omega
+            self.opt.sigma = self.step_gamma * self.omega
+        self.pw_log = []  # (k, dx, dy, accepted, omega after, alpha or None)
         self.status = "running"
         self.last_branch = None
         self.last_gamma = None
@@ -365,6 +398,7 @@ class Solver:
         g0 = u1 - u0
         self.state = State(k=1, x=x1, y=y1, u_prev=u0, g_prev=g0, dU=[], dG=[],
                            n0=float(np.linalg.norm(g0)))
+        self.anchor = u0.copy()  # iterate of the last primal-weight check
         if self.state.n0 == 0.0:
             self.state = dataclasses.replace(self.state, k=0, x=x0, y=y0)
             self.status = "converged"
@@ -376,6 +410,7 @@ class Solver:
         P, o, S = self.P, self.opt, self.state
         n = P.n
         u = np.concatenate((S.x, S.y))
+        reset = self._primal_weight(u) if o.pw_period > 0 else False
         xh, yh = pdhg_map(P, S.x, S.y, o.tau, o.sigma)
         u_hat = np.concatenate((xh, yh))
         g = u_hat - u
@@ -394,20 +429,28 @@ class Solver:
             self.status = "converged"
             return self.status
 
-        # memory update (both branches)
-        S.dU.append(u - S.u_prev)
-        S.dG.append(g - S.g_prev)
-        while len(S.dU) > o.memory:
-            S.dU.pop(0)
-            S.dG.pop(0)
+        if reset:
+            if o.pw_dhat:
+                self._reblend_dhat(float(np.linalg.norm(S.g_prev)), gnorm)
+            # the pair (u^k - u^{k-1}, g^k - g^{k-1}) straddles the weight change: not formed
+        else:
+            # memory update (both branches)
+            S.dU.append(u - S.u_prev)
+            S.dG.append(g - S.g_prev)
+            while len(S.dU) > o.memory:
+                S.dU.pop(0)
+                S.dG.pop(0)
 
         u_next = None
         gamma = None
         branch = "pdhg"
-        if o.variant != VARIANT_PDHG and gnorm <= o.D * S.n0 * (S.i + 1) ** (-(1.0 + o.eps_sg)):
-            dU = np.stack(S.dU, axis=1)
-            dG = np.stack(S.dG, axis=1)
-            if o.variant == VARIANT_AA:
+        if o.variant != VARIANT_PDHG and gnorm <= o.D * S.n0 * (S.i / o.sg_div + 1) ** (-(1.0 + o.eps_sg)):
+            N = P.n + P.m
+            dU = np.stack(S.dU, axis=1) if S.dU else np.zeros((N, 0))
+            dG = np.stack(S.dG, axis=1) if S.dG else np.zeros((N, 0))
+            if dG.shape[1] == 0:
+                gamma = np.zeros(0)  # empty memory: H^k = -beta D-hat
+            elif o.variant == VARIANT_AA:
                 gamma = aa_gamma(dG, g, o.eta)
             else:
                 gamma, dU, dG = self._faa(dU, dG, g)
@@ -432,6 +475,37 @@ class Solver:
         S.y = u_next[n:].copy()
         S.k += 1
         return self.status
+
+    # -- Alg 7 (primal-weight update), at the top of iteration k ------------------
+    def _primal_weight(self, u):
+        """Returns True when the weight was updated (and the memory reset)."""
+        P, o, S = self.P, self.opt, self.state
+        if not (S.k > 0 and S.k % o.pw_period == 0):
+            return False
+        n = P.n
+        dx = float(np.linalg.norm(u[:n] - self.anchor[:n]))
+        dy = float(np.linalg.norm(u[n:] - self.anchor[n:]))
+        self.anchor = u.copy()
+        if dx > o.pw_eps_zero and dy > o.pw_eps_zero:
+            S.dU, S.dG = [], []
+            self.omega = math.exp(o.pw_theta * math.log(dy / dx) + (1.0 - o.pw_theta) * math.log(self.omega))
+            o.tau = self.step_gamma / self.omega
+            o.sigma = self.step_gamma * self.omega
+            self.pw_log.append([S.k, dx, dy, True, self.omega, None])
+            return True
+        self.pw_log.append([S.k, dx, dy, False, self.omega, None])
+        return False
+
+    # -- D-hat = (1 - alpha) D_1 + alpha R (remark on the primal-weight form) -----
+    def _reblend_dhat(self, r_prev, r_cur):
+        o, n = self.opt, self.P.n
+        rho = (r_prev - r_cur) / max(r_prev, o.pw_eps_zero)
+        alpha = 0.1 if rho > o.pw_rho else 0.9
+        w = self.omega
+        D1 = np.concatenate((np.full(n, 1.0 / w), np.full(self.P.m, w)))
+        R = np.concatenate((self.Dhat0[:n] / w, self.Dhat0[n:] * w))
+        self.Dhat = (1.0 - alpha) * D1 + alpha * R
+        self.pw_log[-1][5] = alpha
 
     def _faa(self, dU, dG, g):
         """Alg 3 lines Reverse .. QR: filter the memory, then gamma = R^{-1} Q^T g."""
