@@ -277,6 +277,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the solve-to-tolerance leg")
     ap.add_argument("--chunks-per-block", type=int, default=0, help="workgroup size in chunks (0 = automatic)")
+    ap.add_argument("--pw-period", type=int, default=0,
+                    help="primal-weight update every N iterations (Alg 7; 0 = off, as in the headline line)")
     ap.add_argument("--profile-run", action="store_true",
                     help="only the timed loop passes (for rocprofv3 runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -310,6 +312,9 @@ def main():
     lps, opts, cfg = _workload(args.workload)
     if args.chunks_per_block:
         opts["chunks_per_block"] = args.chunks_per_block
+    if args.pw_period:
+        opts["pw_period"] = args.pw_period
+        cfg = {**cfg, "pw_period": args.pw_period}
     torch.cuda.init()
     stream = torch.cuda.Stream()
     solvers = [P.Solver(lp, tol=0.0, max_iter=10 ** 9, **opts) for lp in lps]

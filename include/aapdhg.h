@@ -100,7 +100,25 @@ typedef struct {
                          persistent loop kernel; a wait that reaches it stops the LP
                          (AAPDHG_NUMERICAL) and the solve returns AAPDHG_E_HIP;
                          0 = 4 s                                                          */
-  int32_t reserved[4];
+  /* Primal-weight update (Alg 7 and the remark on the primal-weight form that follows it):
+   * at the top of every iteration k > 0 with k % pw_period == 0 the distances
+   * dx = ||x^k - x^{k-pw_period}||, dy = ||y^k - y^{k-pw_period}|| (to u^0 for the first
+   * check) are measured; if both exceed pw_eps_zero the Anderson memory is reset,
+   * omega = exp(theta log(dy/dx) + (1 - theta) log omega), tau = gamma / omega and
+   * sigma = gamma * omega with gamma = sqrt(tau_0 sigma_0), and (pw_dhat = 1) D-hat becomes
+   * (1 - alpha) diag(1/omega, omega) + alpha diag(D-hat_1 / omega, D-hat_2 omega), alpha = 0.1
+   * when rho_k = (||g^{k-1}|| - ||g^k||) / max(||g^{k-1}||, pw_eps_zero) > pw_rho, else 0.9.
+   * The difference pair of iteration k is not formed (it would join residuals of two
+   * maps): iteration k runs with an empty memory. */
+  int32_t pw_period;  /* U_P; 0 = no primal-weight update                                 */
+  double pw_theta;    /* smoothing theta in [0, 1] (0.5 in Section 5.3)                   */
+  double pw_eps_zero; /* epsilon_zero > 0 of the acceptance test (default 1e-10)          */
+  double pw_omega0;   /* omega^0 > 0; <= 0 takes sqrt(sigma / tau) (1 for tau = sigma)     */
+  double pw_rho;      /* residual-decrease threshold of the D-hat re-blend (default 0)    */
+  double sg_div;      /* c of the Iter_AA / c safeguard (supplement, update-D-hat study):
+                         the bound uses (i^k / c + 1); 1 = Alg 2 as printed               */
+  int32_t pw_dhat;    /* 1: re-blend D-hat at every accepted weight update, 0: keep it    */
+  int32_t reserved[3];
 } aapdhg_options;
 
 typedef struct {
@@ -117,7 +135,9 @@ typedef struct {
   double solve_seconds;    /* host wall time of the last solve call; for a batch member, the
                               time until the member was seen stopped (status read once per
                               epoch)                                                       */
-  double step_tau, step_sigma;
+  double step_tau, step_sigma; /* step sizes in use (they change with the primal weight) */
+  double omega;            /* primal weight (sqrt(step_sigma / step_tau))                  */
+  int64_t pw_updates;      /* accepted primal-weight updates                               */
 } aapdhg_info;
 
 /* Fills *o with the defaults of Section 5.1: AA-PDHG, float32, m_A = 10, D = 10,
@@ -189,7 +209,20 @@ aapdhg_status aapdhg_set_state(aapdhg_t h, const double *u, const double *u_prev
                                const double *g_prev, const double *dG, const double *W,
                                const int64_t *meta, const double *gram);
 
-/* Sizes of the created problem and the step sizes in use. */
+/* Primal-weight state (not part of aapdhg_get_state's checkpoint; aapdhg_set_state resets
+ * it to the start values, so restore it with aapdhg_set_weights after aapdhg_set_state).
+ *   w       double[AAPDHG_WEIGHT_WORDS]: omega, gamma, tau, sigma, D-hat coefficients
+ *           a_x, a_y, b_x, b_y (D-hat in use = a D-hat_0 + b on each part, D-hat_0 that of
+ *           the D-hat construction), accepted updates, and 1 when the weight changed at the
+ *           last check and the next iteration is the first after the reset (else 0).
+ *   anchor  double[n+m]: the iterate of the last check (u^0 before the first); E_STATE
+ *           when pw_period = 0.  Either pointer may be NULL (set_weights needs w). */
+#define AAPDHG_WEIGHT_WORDS 10
+aapdhg_status aapdhg_get_weights(aapdhg_t h, double *anchor, double *w);
+aapdhg_status aapdhg_set_weights(aapdhg_t h, const double *anchor, const double *w);
+
+/* Sizes of the created problem and the step sizes it was created with (before any
+ * primal-weight update; aapdhg_info holds the ones in use). */
 aapdhg_status aapdhg_get_dims(aapdhg_t h, int32_t *m, int32_t *n, int64_t *nnz, double *tau,
                               double *sigma);
 

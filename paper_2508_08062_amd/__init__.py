@@ -19,6 +19,7 @@ import numpy as np
 PKG_DIR = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG_DIR, "libaapdhg.so")
 MAX_MEMORY = 16
+WEIGHT_WORDS = 10
 
 ROW_EQ, ROW_GE = 0, 1
 VARIANT_PDHG, VARIANT_AA, VARIANT_FAA = 0, 1, 2
@@ -33,7 +34,10 @@ class Options(C.Structure):
                 ("tol", C.c_double), ("max_iter", C.c_int64), ("time_limit_s", C.c_double),
                 ("kkt_every", C.c_int32), ("dhat_mode", C.c_int32), ("ruiz_iters", C.c_int32),
                 ("power_iters", C.c_int32), ("epoch", C.c_int32), ("chunks_per_block", C.c_int32),
-                ("loop_kernel", C.c_int32), ("wait_limit_us", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("loop_kernel", C.c_int32), ("wait_limit_us", C.c_int32), ("pw_period", C.c_int32),
+                ("pw_theta", C.c_double), ("pw_eps_zero", C.c_double), ("pw_omega0", C.c_double),
+                ("pw_rho", C.c_double), ("sg_div", C.c_double), ("pw_dhat", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 class Info(C.Structure):
@@ -42,7 +46,7 @@ class Info(C.Structure):
                 ("dual_obj", C.c_double), ("r_gap", C.c_double), ("r_pri", C.c_double),
                 ("r_dual", C.c_double), ("kkt", C.c_double), ("gnorm", C.c_double),
                 ("g0norm", C.c_double), ("solve_seconds", C.c_double), ("step_tau", C.c_double),
-                ("step_sigma", C.c_double)]
+                ("step_sigma", C.c_double), ("omega", C.c_double), ("pw_updates", C.c_int64)]
 
     def to_dict(self):
         d = {name: getattr(self, name) for name, _ in self._fields_ if not name.startswith("reserved")}
@@ -53,7 +57,8 @@ class Info(C.Structure):
 EXPORTS = [
     "aapdhg_default_options", "aapdhg_create", "aapdhg_solve", "aapdhg_iterate", "aapdhg_iterate_timed",
     "aapdhg_reset",
-    "aapdhg_result", "aapdhg_get_state", "aapdhg_set_state", "aapdhg_get_dims", "aapdhg_get_scaling",
+    "aapdhg_result", "aapdhg_get_state", "aapdhg_set_state", "aapdhg_get_weights", "aapdhg_set_weights",
+    "aapdhg_get_dims", "aapdhg_get_scaling",
     "aapdhg_destroy", "aapdhg_last_error", "aapdhg_batch_create", "aapdhg_batch_solve",
     "aapdhg_batch_iterate", "aapdhg_batch_iterate_timed", "aapdhg_batch_destroy", "aapdhg_server_start", "aapdhg_server_submit",
     "aapdhg_server_poll", "aapdhg_server_stats", "aapdhg_server_stop",
@@ -84,6 +89,8 @@ def lib():
     L.aapdhg_result.argtypes = [_P, _dp, _dp, _dp, C.POINTER(Info)]
     L.aapdhg_get_state.argtypes = [_P, _dp, _dp, _dp, _dp, _dp, _i64p, _dp]
     L.aapdhg_set_state.argtypes = [_P, _dp, _dp, _dp, _dp, _dp, _i64p, _dp]
+    L.aapdhg_get_weights.argtypes = [_P, _dp, _dp]
+    L.aapdhg_set_weights.argtypes = [_P, _dp, _dp]
     L.aapdhg_get_dims.argtypes = [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int64), _dp, _dp]
     L.aapdhg_get_scaling.argtypes = [_P, _dp, _dp]
     L.aapdhg_destroy.argtypes = [_P]
@@ -262,6 +269,27 @@ class Solver:
         st["n0"] = float(g[S * S + 2 * S])
         st["gnorm"] = float(g[S * S + 2 * S + 1])
         return st
+
+    def get_weights(self, anchor=True):
+        """Primal-weight state: omega, gamma, tau, sigma, D-hat coefficients
+        (a_x, a_y, b_x, b_y), accepted updates, the reset flag and (when the
+        update is on) the anchor iterate."""
+        w = np.zeros(WEIGHT_WORDS)
+        anc = np.empty(self.m + self.n) if anchor else None
+        _check(lib().aapdhg_get_weights(self.h, _ptr(anc, C.c_double) if anchor else None,
+                                        _ptr(w, C.c_double)), self.h)
+        out = {"omega": w[0], "gamma": w[1], "tau": w[2], "sigma": w[3], "dha": w[4:6].copy(),
+               "dhb": w[6:8].copy(), "updates": int(w[8]), "flag": int(w[9]), "words": w}
+        if anchor:
+            out["anchor"] = anc
+        return out
+
+    def set_weights(self, words, anchor=None):
+        w = _f64(words)
+        anc = _f64(anchor) if anchor is not None else None
+        _check(lib().aapdhg_set_weights(self.h, _ptr(anc, C.c_double) if anc is not None else None,
+                                        _ptr(w, C.c_double)), self.h)
+        return self
 
     def set_state(self, st):
         dG = _f64(st["dG"]).ravel()

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
 
 namespace aapdhg {
@@ -64,6 +65,13 @@ struct alignas(256) Scalars {
   double qnorm, cnorm;
   double thr;             // safeguard bound for i^k = thr_i - 1 (valid when thr_i == i^k + 1)
   long long thr_i;
+  // primal weight (Alg 7): tau = gstep / omega, sigma = gstep * omega
+  double omega, gstep, tau, sigma;
+  // D-hat in use: dha[p] * D-hat_0 + dhb[p] on the x part (p = 0) and the y part (p = 1)
+  double dha[2], dhb[2];
+  long long pw_updates;   // accepted weight updates
+  int pw_flag;            // 1: the weight changed before this pass (memory reset pending)
+  int pw_blend;           // set by the pass that re-blended D-hat: 1 alpha = 0.9, 2 alpha = 0.1
 };
 
 // Per-LP immutable description (device copy).  Vectors of length N = n + m
@@ -73,6 +81,12 @@ struct LPDesc {
   int variant, kkt_every;
   long long max_iter;
   double tau, sigma, beta, D, eps_sg, eta, cs, kappa_bar, tol;
+  double sg_div;  // c of the Iter_AA / c safeguard
+  // primal-weight update (Alg 7): period U_P (0 = off), theta, epsilon_zero,
+  // the residual-decrease threshold of the D-hat re-blend, re-blend on/off
+  int pw_period, pw_dhat;
+  double pw_theta, pw_eps0, pw_rho;
+  void* anchor;  // u at the last weight check (length N), when pw_period > 0
   const int* rowptr;  // CSR of K, rows in the order rmapB
   const int* colidx;
   const void* val;
@@ -168,7 +182,8 @@ struct LaunchLP {
 struct MixTile {
   int lp;
   int e0, e1;
-  int pad;
+  int t0, nt;  // the LP's tiles: [t0, t0 + nt)
+  int pad[3];
 };
 
 // Everything a pass kernel needs; passed by value.
@@ -190,6 +205,8 @@ struct PassArgs {
 struct MixArgs {
   const LPDesc* lps;
   const MixTile* tiles;
+  double* pwpart;        // [tiles][2]: squared distances to the anchor (weight checks)
+  unsigned int* pwcnt;   // [LPs] arrivals of the weight check
 };
 
 // ---- persistent loop kernel ----
@@ -212,6 +229,8 @@ struct LoopLP {
   int leaf0;
   int nleaf;   // records of both passes
   int nleafA;  // of which the CSC pass's come first
+  int wg0;     // the group's workgroups are [wg0, wg0 + nwg)
+  int pad[3];
 };
 
 // Per-LP counters of one launch (zeroed before the launch).  Arrivals are
@@ -230,11 +249,17 @@ struct alignas(256) LoopSync {
 // Decisions of a pass as every workgroup of the group keeps them (LDS).
 struct Bcast {
   long long k;
-  int status, branch, nmix, nlive, newslot, pad;
+  int status, branch, nmix, nlive, newslot, blend;
   int mixslot[MAXM];
   int live[MAXM];
   double gamma[MAXM];
+  double omega, tau, sigma;  // step sizes in use (primal weight)
+  double dha[2], dhb[2];     // D-hat in use
 };
+// The passes read tau, sigma, dha and dhb as six consecutive doubles from
+// either struct.
+static_assert(offsetof(Bcast, dhb) == offsetof(Bcast, tau) + 4 * sizeof(double), "step words");
+static_assert(offsetof(Scalars, dhb) == offsetof(Scalars, tau) + 4 * sizeof(double), "step words");
 
 // The decisions as rank 0 publishes them: BC_WORDS 64-bit words, each a
 // 32-bit payload (low half) and the 32-bit tag of the pass (high half), so a
@@ -242,7 +267,8 @@ struct Bcast {
 //   word 0: status | branch << 4 | nmix << 8 | nlive << 16 | newslot << 24
 //   words 1-2: live slots, 4 bits each; words 3-4: mix slots, 4 bits each
 //   words 5 .. 5 + 2 MAXM: gamma, low and high halves
-constexpr int BC_WORDS = 5 + 2 * MAXM;
+//   word 5 + 2 MAXM: D-hat re-blend of the pass (0 none, 1 alpha = 0.9, 2 alpha = 0.1)
+constexpr int BC_WORDS = 6 + 2 * MAXM;
 struct alignas(256) BcastMsg {
   unsigned long long w[64];
 };
@@ -258,6 +284,7 @@ struct LoopArgs {
   double* rec;
   double* splitpart;
   unsigned int* splitcnt;
+  double* pwrec;  // [workgroups][2]: squared distances to the anchor (weight checks)
   LoopSync* sync;
   BcastMsg* bc;
   int* err;  // set to 1 when a wait gave up

@@ -94,6 +94,13 @@ void default_options(aapdhg_options* o) {
   o->epoch = 256;
   o->chunks_per_block = 0;
   o->loop_kernel = 0;
+  o->pw_period = 0;
+  o->pw_theta = 0.5;
+  o->pw_eps_zero = 1e-10;
+  o->pw_omega0 = 0.0;
+  o->pw_rho = 0.0;
+  o->sg_div = 1.0;
+  o->pw_dhat = 1;
 }
 
 static void check_options(const aapdhg_options& o) {
@@ -117,6 +124,13 @@ static void check_options(const aapdhg_options& o) {
   if (o.loop_kernel < 0 || o.loop_kernel > 1) throw Error(AAPDHG_E_ARG, "loop_kernel must be 0 or 1");
   if (o.wait_limit_us < 0) throw Error(AAPDHG_E_ARG, "wait_limit_us must be >= 0");
   if (!std::isfinite(o.tau) || !std::isfinite(o.sigma)) throw Error(AAPDHG_E_ARG, "tau and sigma must be finite");
+  if (o.pw_period < 0) throw Error(AAPDHG_E_ARG, "pw_period must be >= 0");
+  if (!(o.pw_theta >= 0.0 && o.pw_theta <= 1.0)) throw Error(AAPDHG_E_ARG, "pw_theta must be in [0, 1]");
+  if (!(o.pw_eps_zero > 0.0) || !std::isfinite(o.pw_eps_zero)) throw Error(AAPDHG_E_ARG, "pw_eps_zero must be > 0");
+  if (!std::isfinite(o.pw_omega0)) throw Error(AAPDHG_E_ARG, "pw_omega0 must be finite");
+  if (!std::isfinite(o.pw_rho)) throw Error(AAPDHG_E_ARG, "pw_rho must be finite");
+  if (o.pw_dhat != 0 && o.pw_dhat != 1) throw Error(AAPDHG_E_ARG, "pw_dhat must be 0 or 1");
+  if (!(o.sg_div > 0.0) || !std::isfinite(o.sg_div)) throw Error(AAPDHG_E_ARG, "sg_div must be > 0");
 }
 
 // ---------------------------------------------------------------------------
@@ -545,6 +559,7 @@ void Problem::create(int32_t m_, int32_t n_, int64_t nnz_, const int64_t* row_pt
   d_lam.alloc(n * ts, "lambda");
   d_sc.alloc(sizeof(Scalars), "scalars");
   d_xfer.alloc((size_t)N * 8, "transfer buffer");
+  if (opt.pw_period > 0) d_anchor.alloc(N * ts, "primal-weight anchor");
   fill_desc();
   // ---- step size (Section 5.1): tau = sigma = 0.9 / ||K||_2 by power iteration ----
   norm_est = power_norm();
@@ -577,6 +592,12 @@ void Problem::fill_desc() {
   desc.max_iter = opt.max_iter;
   desc.tau = opt.tau;
   desc.sigma = opt.sigma;
+  if (opt.pw_omega0 > 0.0 && opt.tau > 0.0 && opt.sigma > 0.0) {
+    // tau = gamma / omega^0, sigma = gamma omega^0 with gamma = sqrt(tau sigma)
+    const double gam = std::sqrt(opt.tau * opt.sigma);
+    desc.tau = gam / opt.pw_omega0;
+    desc.sigma = gam * opt.pw_omega0;
+  }
   desc.beta = opt.beta;
   desc.D = opt.D;
   desc.eps_sg = opt.eps_sg;
@@ -584,6 +605,13 @@ void Problem::fill_desc() {
   desc.cs = opt.cs;
   desc.kappa_bar = opt.kappa_bar;
   desc.tol = opt.tol;
+  desc.sg_div = opt.sg_div;
+  desc.pw_period = opt.pw_period;
+  desc.pw_dhat = opt.pw_dhat;
+  desc.pw_theta = opt.pw_theta;
+  desc.pw_eps0 = opt.pw_eps_zero;
+  desc.pw_rho = opt.pw_rho;
+  desc.anchor = d_anchor.p;
   desc.rowptr = (const int*)d_rowptr.p;
   desc.colidx = (const int*)d_colidx.p;
   desc.val = d_val.p;
@@ -632,7 +660,7 @@ size_t Problem::device_bytes() const {
   const DevBuf* bufs[] = {&d_pptr, &d_pidx, &d_pval, &d_part, &d_pchunk,
                           &d_rowptr, &d_colidx, &d_val, &d_colptr, &d_rowidx, &d_valT, &d_rmapA, &d_rmapB, &d_c, &d_lo, &d_hi,
                           &d_q, &d_dhat, &d_rowtype, &d_u[0], &d_u[1], &d_g[0], &d_g[1], &d_xbar, &d_hist_dG,
-                          &d_hist_W, &d_lam, &d_sc, &d_desc, &d_xfer};
+                          &d_hist_W, &d_lam, &d_sc, &d_desc, &d_xfer, &d_anchor};
   for (auto* p : bufs) b += p->bytes;
   if (solo) b += solo->device_bytes();
   return b;
@@ -647,6 +675,17 @@ void Problem::reset_host_state() {
   sc_init.newslot = 0;
   sc_init.qnorm = qnorm;
   sc_init.cnorm = cnorm;
+  // primal weight (Alg 7): tau = gstep / omega, sigma = gstep * omega; the
+  // given (or estimated) steps are used as they are until the first update
+  sc_init.gstep = std::sqrt(opt.tau * opt.sigma);
+  sc_init.omega = opt.pw_omega0 > 0.0 ? opt.pw_omega0 : std::sqrt(opt.sigma / opt.tau);
+  sc_init.tau = opt.pw_omega0 > 0.0 ? sc_init.gstep / sc_init.omega : opt.tau;
+  sc_init.sigma = opt.pw_omega0 > 0.0 ? sc_init.gstep * sc_init.omega : opt.sigma;
+  sc_init.dha[0] = sc_init.dha[1] = 1.0;
+  sc_init.dhb[0] = sc_init.dhb[1] = 0.0;
+  sc_init.pw_updates = 0;
+  sc_init.pw_flag = 0;
+  sc_init.pw_blend = 0;
 }
 
 void Problem::enqueue_reset(hipStream_t st) {
@@ -676,7 +715,7 @@ size_t LaunchSet::device_bytes() const {
   size_t b = 0;
   const DevBuf* bufs[] = {&d_lps, &d_llp, &d_chunks, &d_blocksA, &d_blocksB, &d_nodes, &d_splits, &d_rec,
                           &d_ncnt, &d_splitpart, &d_splitcnt, &d_tiles, &d_status, &d_wgs, &d_looplps,
-                          &d_sync, &d_bc, &d_err};
+                          &d_sync, &d_bc, &d_err, &d_pwpart, &d_pwcnt, &d_pwrec};
   for (auto* p : bufs) b += p->bytes;
   return b;
 }
@@ -706,7 +745,9 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
     want &= p->opt.loop_kernel == 0;
     need += (long long)std::max(p->chunksA.size(), p->chunksB.size());
   }
-  const int cap = want ? loop_capacity(lps[0]->fp64, mt) : 0;
+  bool pw = false;
+  for (auto* p : lps) pw |= p->opt.pw_period > 0;
+  const int cap = want ? loop_capacity(lps[0]->fp64, mt, pw) : 0;
   const bool persist = cap >= count && need <= 2LL * cap;
   int parts = 0;
   // per LP and pass: chunks, split rows, workgroups; leaves are the
@@ -780,8 +821,11 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
       pi.leaf0 = nleaves;
       nleaves += pi.nb + pi.ns;
     }
+    const int t0 = (int)tl.size();
     for (auto x : p->tiles) {
       x.lp = i;
+      x.t0 = t0;
+      x.nt = (int)p->tiles.size();
       tl.push_back(x);
     }
   }
@@ -810,6 +854,7 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
     }
   }
   t.mt = mt;
+  t.pw = pw;
   t.panels = count == 1 && lps[0]->panels;
   t.nlps = count;
   d_lps.upload(descs.data(), descs.size() * sizeof(LPDesc), "lp table");
@@ -827,6 +872,9 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
   d_splitcnt.alloc(std::max<size_t>(splits.size(), 1) * 4, "split counters");
   d_splitcnt.zero("split counters");
   d_tiles.upload(tl.data(), tl.size() * sizeof(MixTile), "mix tiles");
+  d_pwpart.alloc(std::max<size_t>(tl.size(), 1) * 2 * 8, "weight-check partials");
+  d_pwcnt.alloc((size_t)count * 4, "weight-check counters");
+  d_pwcnt.zero("weight-check counters");
   d_status.alloc(count * 4, "status");
   if (!h_status) hip_check(hipHostMalloc((void**)&h_status, sizeof(int) * 2 * MAX_STATUS, hipHostMallocDefault), "pinned status");
   t.lps = (const LPDesc*)d_lps.p;
@@ -846,6 +894,8 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
   t.splitcnt = (unsigned int*)d_splitcnt.p;
   t.tiles = (const MixTile*)d_tiles.p;
   t.ntiles = (int)tl.size();
+  t.pwpart = (double*)d_pwpart.p;
+  t.pwcnt = (unsigned int*)d_pwcnt.p;
 
   // ---- persistent loop kernel: a group of resident workgroups per LP ----
   t.persistent = false;
@@ -921,6 +971,7 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
       wgs.push_back(w);
     }
     llps[i].nwg = G[i];
+    llps[i].wg0 = (int)wgs.size() - G[i];
     llps[i].leaf0 = pa.leaf0;
     llps[i].nleafA = pa.nb + pa.ns;
     llps[i].nleaf = pb.leaf0 + pb.nb + pb.ns - pa.leaf0;
@@ -932,6 +983,7 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
   d_bc.zero("loop decisions");
   d_err.alloc(sizeof(int), "loop error word");
   d_err.zero("loop error word");
+  d_pwrec.alloc(wgs.size() * 2 * 8, "loop weight-check partials");
   int dev = 0, khz = 0;
   hip_check(hipGetDevice(&dev), "device");
   hip_check(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev), "wall clock rate");
@@ -945,6 +997,7 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
   t.looplps = (const LoopLP*)d_looplps.p;
   t.sync = (LoopSync*)d_sync.p;
   t.bc = (BcastMsg*)d_bc.p;
+  t.pwrec = (double*)d_pwrec.p;
   t.err = (int*)d_err.p;
   t.persistent = true;
 }
@@ -1121,9 +1174,52 @@ void Problem::result(double* x, double* y, double* lam, aapdhg_info* info, bool 
     info->gnorm = s.gnorm;
     info->g0norm = s.n0;
     info->solve_seconds = last_solve_seconds;
-    info->step_tau = opt.tau;
-    info->step_sigma = opt.sigma;
+    info->step_tau = s.tau;
+    info->step_sigma = s.sigma;
+    info->omega = s.omega;
+    info->pw_updates = s.pw_updates;
   }
+}
+
+// primal-weight state: see aapdhg_get_weights in aapdhg.h
+void Problem::get_weights(double* anchor, double* w) {
+  hip_check(hipDeviceSynchronize(), "weight sync");
+  Scalars s;
+  read_scalars(s);
+  if (w) {
+    const double v[AAPDHG_WEIGHT_WORDS] = {s.omega,  s.gstep,  s.tau,    s.sigma,   s.dha[0],
+                                           s.dha[1], s.dhb[0], s.dhb[1], (double)s.pw_updates, (double)s.pw_flag};
+    std::memcpy(w, v, sizeof v);
+  }
+  if (anchor) {
+    if (!d_anchor.p) throw Error(AAPDHG_E_STATE, "the primal-weight update is off (pw_period = 0): no anchor");
+    download(d_anchor.p, N, anchor, nullptr);
+  }
+}
+
+void Problem::set_weights(const double* anchor, const double* w) {
+  if (!w) throw Error(AAPDHG_E_ARG, "set_weights needs the weight words");
+  if (!(w[0] > 0.0) || !(w[1] > 0.0) || !(w[2] > 0.0) || !(w[3] > 0.0) || !(w[8] >= 0.0) ||
+      (w[9] != 0.0 && w[9] != 1.0))
+    throw Error(AAPDHG_E_ARG, "invalid primal-weight state");
+  hip_check(hipDeviceSynchronize(), "weight sync");
+  if (anchor) {
+    if (!d_anchor.p) throw Error(AAPDHG_E_STATE, "the primal-weight update is off (pw_period = 0): no anchor");
+    upload_vec(d_anchor.p, anchor, N, nullptr);
+  }
+  Scalars s;
+  read_scalars(s);
+  s.omega = w[0];
+  s.gstep = w[1];
+  s.tau = w[2];
+  s.sigma = w[3];
+  s.dha[0] = w[4];
+  s.dha[1] = w[5];
+  s.dhb[0] = w[6];
+  s.dhb[1] = w[7];
+  s.pw_updates = (long long)w[8];
+  s.pw_flag = (int)w[9];
+  hip_check(hipMemcpy(d_sc.p, &s, sizeof s, hipMemcpyHostToDevice), "write scalars");
 }
 
 // checkpoint layout: see aapdhg_get_state in aapdhg.h
@@ -1321,6 +1417,16 @@ aapdhg_status aapdhg_set_state(aapdhg_t h, const double* u, const double* u_prev
                                const double* dG, const double* W, const int64_t* meta, const double* gram) {
   if (!h) return AAPDHG_E_ARG;
   return guard(&h->err, [&] { h->p.set_state(u, u_prev, g_prev, dG, W, meta, gram); });
+}
+
+aapdhg_status aapdhg_get_weights(aapdhg_t h, double* anchor, double* w) {
+  if (!h) return AAPDHG_E_ARG;
+  return guard(&h->err, [&] { h->p.get_weights(anchor, w); });
+}
+
+aapdhg_status aapdhg_set_weights(aapdhg_t h, const double* anchor, const double* w) {
+  if (!h) return AAPDHG_E_ARG;
+  return guard(&h->err, [&] { h->p.set_weights(anchor, w); });
 }
 
 aapdhg_status aapdhg_get_dims(aapdhg_t h, int32_t* m, int32_t* n, int64_t* nnz, double* tau, double* sigma) {

@@ -299,6 +299,30 @@ __device__ int faa_filter(const LPDesc& d, const Scalars* sc, int nl, SolveWork*
 // Decisions of loop pass k, on the summed records f: KKT test, memory update,
 // safeguard, Anderson coefficients (Alg 2) or filters (Alg 3).  Every lane of
 // one wave calls it; sc points at an LDS copy of the LP's scalars.
+// D-hat after a primal-weight update (remark on the primal-weight form):
+// (1 - alpha) diag(1/omega, omega) + alpha diag(D-hat_1 / omega, D-hat_2 omega),
+// kept as coefficients of the construction's D-hat: dha[p] D-hat_0 + dhb[p]
+// on the x part (p = 0) and the y part (p = 1).
+__device__ __forceinline__ void dhat_coeffs(double alpha, double omega, double* dha, double* dhb) {
+  dha[0] = alpha / omega;
+  dhb[0] = (1.0 - alpha) / omega;
+  dha[1] = alpha * omega;
+  dhb[1] = (1.0 - alpha) * omega;
+}
+
+// Alg 7 from the squared distances of x^k and y^k to the iterate of the last
+// check: true when both exceed epsilon_zero; then omega is smoothed in log
+// space and tau = gstep / omega, sigma = gstep * omega.
+__device__ __forceinline__ bool pw_decide(const LPDesc& d, double dx2, double dy2, double gstep, double& omega,
+                                          double& tau, double& sigma) {
+  const double dx = sqrt(dx2), dy = sqrt(dy2);
+  if (!(dx > d.pw_eps0 && dy > d.pw_eps0)) return false;
+  omega = exp(d.pw_theta * log(dy / dx) + (1.0 - d.pw_theta) * log(omega));
+  tau = gstep / omega;
+  sigma = gstep * omega;
+  return true;
+}
+
 template <int MT>
 __device__ void final_step(const LPDesc& d, Scalars* sc, const double* f, bool eval, bool kkt, bool init,
                            SolveWork* w, int lane) {
@@ -325,9 +349,11 @@ __device__ void final_step(const LPDesc& d, Scalars* sc, const double* f, bool e
   }
   if (eval) return;
   const double gnorm = sqrt(f[DT::GG]);
+  const double gprev = sc->gnorm;  // ||g^{k-1}||
   const long long k = sc->k;
   const double n0 = sc->n0;
   const long long i_aa = sc->i_aa;
+  wave_sync();
   if (L0) sc->gnorm = gnorm;
   if (init) {  // Alg 2 set-up: g^0 = u^1 - u^0
     if (L0) {
@@ -355,8 +381,25 @@ __device__ void final_step(const LPDesc& d, Scalars* sc, const double* f, bool e
   // memory update (both branches): the pair written this pass goes to newslot
   const int s = sc->newslot;
   const int nl_old = sc->nlive;
+  const bool pw_reset = sc->pw_flag != 0;
   wave_sync();
-  if (lane < nl_old) {
+  if (L0) sc->pw_blend = 0;
+  if (pw_reset) {
+    // the weight changed before this pass (Alg 7): the memory was reset and
+    // the pair of this pass, which joins residuals of two maps, is not kept;
+    // D-hat is re-blended with alpha from the residual decrease
+    if (L0) {
+      w->nl = 0;
+      sc->pw_flag = 0;
+      if (d.pw_dhat) {
+        const double rho = (gprev - gnorm) / fmax(gprev, d.pw_eps0);
+        const bool dec = rho > d.pw_rho;
+        dhat_coeffs(dec ? 0.1 : 0.9, sc->omega, sc->dha, sc->dhb);
+        sc->pw_blend = dec ? 2 : 1;
+      }
+    }
+  }
+  if (!pw_reset && lane < nl_old) {
     const int slot = sc->live[lane];
     if (slot != s) {  // the oldest column is replaced
       const double gv = f[DT::G + lane];
@@ -365,7 +408,7 @@ __device__ void final_step(const LPDesc& d, Scalars* sc, const double* f, bool e
       sc->rhs[slot] += gv;  // <dG[slot], g^k> = <dG[slot], g^{k-1}> + <dG[slot], dg_new>
     }
   }
-  {
+  if (!pw_reset) {
     // live slots without the replaced one, oldest first, then the new pair
     const int slot = lane < nl_old ? sc->live[lane] : -1;
     const bool keep = lane < nl_old && slot != s;
@@ -386,11 +429,12 @@ __device__ void final_step(const LPDesc& d, Scalars* sc, const double* f, bool e
   bool aa = false;
   int nmix = 0;
   if (d.variant != V_PDHG) {
-    // safeguard (Alg 2): ||g^k|| <= D ||g^0|| (i^k + 1)^{-(1+eps)}; ties accelerate
-    // the bound changes only with i^k: computed once per Anderson step
+    // safeguard (Alg 2): ||g^k|| <= D ||g^0|| (i^k / c + 1)^{-(1+eps)}, c = 1 in
+    // Alg 2 (Iter_AA / c otherwise); ties accelerate.  The bound changes only
+    // with i^k: computed once per Anderson step
     double thr = sc->thr;
     if (sc->thr_i != i_aa + 1) {
-      thr = d.D * n0 * pow((double)(i_aa + 1), -(1.0 + d.eps_sg));
+      thr = d.D * n0 * pow((double)i_aa / d.sg_div + 1.0, -(1.0 + d.eps_sg));
       wave_sync();
       if (L0) {
         sc->thr = thr;
@@ -399,7 +443,9 @@ __device__ void final_step(const LPDesc& d, Scalars* sc, const double* f, bool e
     }
     if (gnorm <= thr) {
       if (d.variant == V_AA) {
-        if (solve_gamma(sc, w->live, nl, d.eta, w, lane)) {
+        if (nl == 0) {
+          aa = true;  // empty memory (after a weight update): u_AA = u^k + beta D-hat g^k
+        } else if (solve_gamma(sc, w->live, nl, d.eta, w, lane)) {
           aa = true;
           nmix = nl;
         }
@@ -485,11 +531,15 @@ struct PassView {
   int nl, s_new;
   const int* live;  // live history slots, oldest first (LDS)
   bool eval, init, kkt, hist_on, skip0;
+  // tau, sigma (primal weight) and the D-hat coefficients a_x, a_y, b_x, b_y
+  // of this pass, six consecutive doubles (LDS in the loop kernel)
+  const double* steps;
 };
 
 __device__ __forceinline__ PassView make_view(const LPDesc& d, long long k, int nl, int s_new, const int* live,
-                                              bool eval) {
+                                              bool eval, const double* steps) {
   PassView v;
+  v.steps = steps;
   v.k = k;
   v.nl = nl;
   v.s_new = s_new;
@@ -508,8 +558,10 @@ __device__ __forceinline__ PassView make_view(const LPDesc& d, long long k, int 
 // x_bar are written and read at agent scope.  Everything else of a row is
 // read and written only by the workgroup that owns the row, except for split
 // rows, which are finished by whichever part arrives last: their epilogue
-// (row_coh) reads and writes everything of the row at agent scope.
-template <typename T, int MT, int PASS, bool COH>
+// (row_coh) reads and writes everything of the row at agent scope.  PW: the
+// step sizes and the D-hat blend may change during the solve (primal-weight
+// update on); without it they are the LP's fixed tau, sigma and D-hat.
+template <typename T, int MT, int PASS, bool COH, bool PW>
 struct PassCtx {
   using DT = Dot<MT>;
   const LPDesc* dp;
@@ -534,6 +586,7 @@ struct PassCtx {
   const T* hiv;
   const unsigned char* rtype;
   double beta, tau, sigma;
+  double dh_a, dh_b;  // D-hat of this pass's part: dh_a D-hat_0 + dh_b
   bool two;
 
   __device__ __forceinline__ PassCtx(const LPDesc* d, const PassView& pv) : dp(d), v(pv) {
@@ -559,8 +612,17 @@ struct PassCtx {
     hiv = (const T*)d->hi;
     rtype = d->rowtype;
     beta = d->beta;
-    tau = d->tau;
-    sigma = d->sigma;
+    if constexpr (PW) {
+      tau = pv.steps[0];
+      sigma = pv.steps[1];
+      dh_a = pv.steps[2 + PASS];
+      dh_b = pv.steps[4 + PASS];
+    } else {
+      tau = d->tau;
+      sigma = d->sigma;
+      dh_a = 1.0;
+      dh_b = 0.0;
+    }
     two = PASS == 1 && pv.kkt && !pv.eval;
   }
 
@@ -634,7 +696,8 @@ struct PassCtx {
       const T duT = (T)((double)in.u - (double)in.up);
       const double dg = (double)dgT, du = (double)duT, gd = (double)g;
       st(dG + (size_t)v.s_new * N, e, dgT, row_coh);
-      st(W + (size_t)v.s_new * N, e, (T)(du + beta * (double)in.dh * dg), row_coh);
+      const double dh = PW ? dh_a * (double)in.dh + dh_b : (double)in.dh;
+      st(W + (size_t)v.s_new * N, e, (T)(du + beta * dh * dg), row_coh);
       accv[DT::DGDG] += dg * dg;
       accv[DT::DGG] += dg * gd;
       accv[DT::DU2] += du * du;
@@ -897,8 +960,8 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
   if (!eval && sc->status != ST_RUNNING) return;
   if (tid < MAXM) s_live[tid] = sc->live[tid];
   __syncthreads();
-  const PassView v = make_view(*dp, sc->k, sc->nlive, sc->newslot, s_live, eval);
-  const PassCtx<T, MT, PASS, false> P(dp, v);
+  const PassView v = make_view(*dp, sc->k, sc->nlive, sc->newslot, s_live, eval, &sc->tau);
+  const PassCtx<T, MT, PASS, false, true> P(dp, v);
 
   // ---- reduction tree: the last child of a node adds the children in order.
   // Every thread calls it; returns true in the block that completed the root.
@@ -1075,35 +1138,13 @@ __device__ __forceinline__ void reduce_records(const double* rec, int nrec, doub
   __syncthreads();
 }
 
-// Anderson mix (Alg 2: u^{k+1} = P(u^k + beta D-hat g^k - sum_t gamma_t W_t))
-// of the entries this workgroup owns: the columns of its CSC units, the rows
-// of its CSR units, and the split rows whose part 0 it holds (at agent scope).
-template <typename T>
-__device__ __forceinline__ void mix_owned(const LoopArgs& a, const LoopWG& wg, const LPDesc* dp, const Bcast& bc) {
-  const int par = (int)((bc.k - 1) & 1);  // the pass that decided was k-1
-  const T* ucur = (const T*)dp->u[par];
-  T* unext = (T*)dp->u[par ^ 1];
-  const T* g = (const T*)dp->g[par];
-  const T* W = (const T*)dp->W;
-  const T* dhat = (const T*)dp->dhat;
-  const T* lov = (const T*)dp->lo;
-  const T* hiv = (const T*)dp->hi;
-  const int n = dp->n, N = dp->N, nmix = bc.nmix;
-  const double beta = dp->beta;
-  auto mix1 = [&](int e, bool c) {
-    double v = (double)ldc(ucur, e) + beta * (double)dhat[e] * (double)(c ? ldc(g, e) : g[e]);
-    for (int t = 0; t < nmix; ++t) {
-      const T* wc = W + (size_t)bc.mixslot[t] * N;
-      v -= bc.gamma[t] * (double)(c ? ldc(wc, e) : wc[e]);
-    }
-    T r = (T)v;
-    if (e < n) {
-      r = clampT(r, lov[e], hiv[e]);
-    } else if (dp->rowtype[e - n] != 0 && r < (T)0) {
-      r = (T)0;
-    }
-    stc(unext, e, r);
-  };
+// The entries of u a workgroup of the loop kernel owns: the columns of its
+// CSC units, the rows of its CSR units (threads stride over them) and the
+// split rows whose part 0 it holds (thread 0).  f(e, coh): coh is set for
+// split rows, whose row data another workgroup may have written.
+template <typename F>
+__device__ __forceinline__ void for_owned(const LoopArgs& a, const LoopWG& wg, const LPDesc* dp, F&& f) {
+  const int n = dp->n;
   for (int pass = 0; pass < 2; ++pass) {
     const BlockWork* bws = pass == 0 ? a.blocksA : a.blocksB;
     const int u0 = pass == 0 ? wg.a0 : wg.b0, u1 = pass == 0 ? wg.a1 : wg.b1;
@@ -1113,15 +1154,69 @@ __device__ __forceinline__ void mix_owned(const LoopArgs& a, const LoopWG& wg, c
       const BlockWork bw = bws[u];
       if (bw.kind == 1) {
         const Chunk ch = a.chunks[bw.c0];
-        if (ch.tpr == 0 && threadIdx.x == 0) mix1(off + rmap[a.splits[ch.split].row], true);
+        if (ch.tpr == 0 && threadIdx.x == 0) f(off + rmap[a.splits[ch.split].row], true);
         continue;
       }
       for (int c = bw.c0; c < bw.c1; ++c) {
         const Chunk ch = a.chunks[c];
-        for (int pos = ch.r0 + (int)threadIdx.x; pos < ch.r1; pos += BLOCK) mix1(off + rmap[pos], false);
+        for (int pos = ch.r0 + (int)threadIdx.x; pos < ch.r1; pos += BLOCK) f(off + rmap[pos], false);
       }
     }
   }
+}
+
+// One traversal of the entries this workgroup owns after the decisions of a
+// pass (iterates at agent scope).  With `mix`: the Anderson mix of Alg 2,
+// u^{k+1} = P(u^k + beta D-hat g^k - sum_t gamma_t W_t).  With `check` (Alg 7
+// at the top of the next iteration): the squared distances of the new iterate
+// to the anchor, x part in *sx and y part in *sy (per thread); the anchor then
+// takes the new iterate.
+template <typename T, bool PW>
+__device__ __forceinline__ void mix_owned(const LoopArgs& a, const LoopWG& wg, const LPDesc* dp, const Bcast& bc,
+                                          bool mix, bool check, double* sx, double* sy) {
+  const int par = (int)((bc.k - 1) & 1);  // the pass that decided was k-1
+  const T* ucur = (const T*)dp->u[par];
+  T* unext = (T*)dp->u[par ^ 1];
+  const T* g = (const T*)dp->g[par];
+  const T* W = (const T*)dp->W;
+  const T* dhat = (const T*)dp->dhat;
+  const T* lov = (const T*)dp->lo;
+  const T* hiv = (const T*)dp->hi;
+  T* anc = (T*)dp->anchor;
+  const int n = dp->n, N = dp->N, nmix = bc.nmix;
+  const double beta = dp->beta;
+  double x2 = 0.0, y2 = 0.0;
+  for_owned(a, wg, dp, [&](int e, bool c) {
+    T r;
+    if (mix) {
+      double dh = (double)dhat[e];
+      if constexpr (PW) {
+        const int p = e < n ? 0 : 1;
+        dh = bc.dha[p] * dh + bc.dhb[p];
+      }
+      double v = (double)ldc(ucur, e) + beta * dh * (double)(c ? ldc(g, e) : g[e]);
+      for (int t = 0; t < nmix; ++t) {
+        const T* wc = W + (size_t)bc.mixslot[t] * N;
+        v -= bc.gamma[t] * (double)(c ? ldc(wc, e) : wc[e]);
+      }
+      r = (T)v;
+      if (e < n) {
+        r = clampT(r, lov[e], hiv[e]);
+      } else if (dp->rowtype[e - n] != 0 && r < (T)0) {
+        r = (T)0;
+      }
+      stc(unext, e, r);
+    } else {
+      r = ldc((const T*)unext, e);  // a PDHG step: the new iterate is the PDHG point already written
+    }
+    if (PW && check) {
+      const double dd = (double)r - (double)anc[e];
+      if (e < n) x2 += dd * dd; else y2 += dd * dd;
+      anc[e] = r;
+    }
+  });
+  *sx = x2;
+  *sy = y2;
 }
 
 // A workgroup that owns exactly one multi-row chunk in a pass keeps it in LDS
@@ -1163,12 +1258,12 @@ __device__ __forceinline__ void fill_cache(const LoopArgs& a, const LPDesc* dp, 
   cc->a1[tid] = r < ch.r1 ? ptr[r + 1] - ch.k0 : 0;
 }
 
-template <typename T, int MT, int PASS>
+template <typename T, int MT, int PASS, bool PW>
 __device__ __forceinline__ void loop_units(const LoopArgs& a, const LPDesc* dp, const PassView& v, int u0, int u1,
                                            double* s_prod, double (*s_red)[NDOT], double* s_tmp, double* s_racc,
                                            int* s_own, const ChunkCache* cc) {
   using DT = Dot<MT>;
-  const PassCtx<T, MT, PASS, true> P(dp, v);
+  const PassCtx<T, MT, PASS, true, PW> P(dp, v);
   if (cc->on) {
     double acc[DT::COUNT];
 #pragma unroll
@@ -1210,10 +1305,12 @@ __device__ __forceinline__ void publish_decisions(const Bcast& b, unsigned long 
     const int* src = lane <= 2 ? b.live : b.mixslot;
     const int base = ((lane - 1) & 1) * 8;
     for (int t = 0; t < 8; ++t) pay |= ((unsigned)src[base + t] & 15u) << (4 * t);
-  } else if (lane < BC_WORDS) {
+  } else if (lane < 5 + 2 * MAXM) {
     const int t = (lane - 5) >> 1;
     const double gv = b.gamma[t];
     pay = ((lane - 5) & 1) ? (unsigned)__double2hiint(gv) : (unsigned)__double2loint(gv);
+  } else if (lane == 5 + 2 * MAXM) {
+    pay = (unsigned)b.blend;
   }
   if (lane < BC_WORDS) {
     const unsigned long long wv = (unsigned long long)pay | (unsigned long long)tag << 32;
@@ -1256,6 +1353,8 @@ __device__ bool read_decisions(Bcast& b, const unsigned long long* msg, unsigned
   const unsigned int m0 = __shfl(pay, 3, 64), m1 = __shfl(pay, 4, 64);
   const unsigned int glo = __shfl(pay, 5 + 2 * (lane & (MAXM - 1)), 64);
   const unsigned int ghi = __shfl(pay, 6 + 2 * (lane & (MAXM - 1)), 64);
+  const unsigned int bl = __shfl(pay, 5 + 2 * MAXM, 64);
+  if (lane == 0) b.blend = (int)bl;
   if (lane < MAXM) {
     const unsigned int lw = lane < 8 ? l0 : l1, mw = lane < 8 ? m0 : m1;
     b.live[lane] = (int)((lw >> (4 * (lane & 7))) & 15u);
@@ -1265,7 +1364,7 @@ __device__ bool read_decisions(Bcast& b, const unsigned long long* msg, unsigned
   return true;
 }
 
-template <typename T, int MT>
+template <typename T, int MT, bool PW>
 __global__ __launch_bounds__(BLOCK) void k_loop(LoopArgs a) {
   __shared__ double s_prod[CHUNK_NNZ];
   __shared__ double s_red[BLOCK / 64][NDOT];
@@ -1298,6 +1397,14 @@ __global__ __launch_bounds__(BLOCK) void k_loop(LoopArgs a) {
     s_bc.nmix = 0;
     s_bc.nlive = sc->nlive;
     s_bc.newslot = sc->newslot;
+    s_bc.blend = 0;
+    s_bc.omega = sc->omega;
+    s_bc.tau = sc->tau;
+    s_bc.sigma = sc->sigma;
+    s_bc.dha[0] = sc->dha[0];
+    s_bc.dha[1] = sc->dha[1];
+    s_bc.dhb[0] = sc->dhb[0];
+    s_bc.dhb[1] = sc->dhb[1];
   }
   if (tid < MAXM) s_bc.live[tid] = sc->live[tid];
   constexpr int SW = sizeof(Scalars) / 8;
@@ -1314,16 +1421,16 @@ __global__ __launch_bounds__(BLOCK) void k_loop(LoopArgs a) {
   unsigned int nbar = 0;
   bool ok = true;
   for (long long it = 0; it < a.max_passes; ++it) {
-    const PassView v = make_view(*dp, s_bc.k, s_bc.nlive, s_bc.newslot, s_bc.live, false);
+    const PassView v = make_view(*dp, s_bc.k, s_bc.nlive, s_bc.newslot, s_bc.live, false, &s_bc.tau);
     // ---- phase A: K^T y and the primal update ----
-    loop_units<T, MT, 0>(a, dp, v, wg.a0, wg.a1, s_prod, s_red, s_tmp, s_racc, &s_own, &s_cc[0]);
+    loop_units<T, MT, 0, PW>(a, dp, v, wg.a0, wg.a1, s_prod, s_red, s_tmp, s_racc, &s_own, &s_cc[0]);
     ++nbar;
     if (!group_barrier(sy->bar, wg.rank, nbar * (unsigned)L.nwg, &sy->abort, ticks, &s_ok)) {
       ok = false;
       break;
     }
     // ---- phase B: K x_bar and the dual update ----
-    loop_units<T, MT, 1>(a, dp, v, wg.b0, wg.b1, s_prod, s_red, s_tmp, s_racc, &s_own, &s_cc[1]);
+    loop_units<T, MT, 1, PW>(a, dp, v, wg.b0, wg.b1, s_prod, s_red, s_tmp, s_racc, &s_own, &s_cc[1]);
     wait_stores();
     __syncthreads();
     if (tid == 0) arrive_sub(sy->arr, wg.rank);
@@ -1352,6 +1459,13 @@ __global__ __launch_bounds__(BLOCK) void k_loop(LoopArgs a) {
         s_bc.nmix = s_sc.nmix;
         s_bc.nlive = s_sc.nlive;
         s_bc.newslot = s_sc.newslot;
+        if (PW) {
+          s_bc.blend = s_sc.pw_blend;
+          for (int p = 0; p < 2; ++p) {
+            s_bc.dha[p] = s_sc.dha[p];
+            s_bc.dhb[p] = s_sc.dhb[p];
+          }
+        }
       }
       if (tid < MAXM) {
         s_bc.live[tid] = s_sc.live[tid];
@@ -1365,6 +1479,8 @@ __global__ __launch_bounds__(BLOCK) void k_loop(LoopArgs a) {
         const bool okw = read_decisions(s_bc, msg, a.tag0 + done, s_bc.k + 1, &sy->abort, ticks);
         if (tid == 0) s_ok = okw ? 1 : 0;
       }
+      if (PW && tid == 0 && s_ok && s_bc.blend != 0)  // the D-hat re-blend rank 0 made in final_step
+        dhat_coeffs(s_bc.blend == 2 ? 0.1 : 0.9, s_bc.omega, s_bc.dha, s_bc.dhb);
       __syncthreads();
       if (!s_ok) {
         ok = false;
@@ -1372,12 +1488,59 @@ __global__ __launch_bounds__(BLOCK) void k_loop(LoopArgs a) {
       }
     }
     if (s_bc.status != ST_RUNNING) break;
-    if (s_bc.branch == BR_AA) {
-      mix_owned<T>(a, wg, dp, s_bc);
+    const bool mix = s_bc.branch == BR_AA;
+    const bool check = PW && dp->pw_period > 0 && s_bc.k % dp->pw_period == 0;
+    if (mix || check) {
+      // the mix of an AA step and/or the distances of Alg 7's check, then a
+      // group barrier (the next phase A gathers the new y; the check's sums
+      // are complete)
+      double sx, sy2;
+      mix_owned<T, PW>(a, wg, dp, s_bc, mix, check, &sx, &sy2);
+      if (check) {
+        sx = block_sum(sx, s_tmp);
+        sy2 = block_sum(sy2, s_tmp);
+        if (tid == 0) {
+          st_agent(&a.pwrec[2 * blockIdx.x], sx);
+          st_agent(&a.pwrec[2 * blockIdx.x + 1], sy2);
+        }
+      }
       ++nbar;
       if (!group_barrier(sy->bar, wg.rank, nbar * (unsigned)L.nwg, &sy->abort, ticks, &s_ok)) {
         ok = false;
         break;
+      }
+      if (check) {
+        // every workgroup adds the group's sums in the same order and takes
+        // the same decision; rank 0 keeps it in the LP's scalars
+        if (tid < 64) {
+          double px = 0.0, py = 0.0;
+          for (int r = lane; r < L.nwg; r += 64) {
+            px += ld_coh(a.pwrec, 2 * (L.wg0 + r));
+            py += ld_coh(a.pwrec, 2 * (L.wg0 + r) + 1);
+          }
+          px = wave_sum(px);
+          py = wave_sum(py);
+          if (tid == 0) {
+            double om = s_bc.omega, ta = s_bc.tau, si = s_bc.sigma;
+            if (pw_decide(*dp, px, py, sc->gstep, om, ta, si)) {
+              s_bc.omega = om;
+              s_bc.tau = ta;
+              s_bc.sigma = si;
+              s_bc.nlive = 0;
+              s_bc.newslot = 0;
+              if (root) {
+                s_sc.omega = om;
+                s_sc.tau = ta;
+                s_sc.sigma = si;
+                s_sc.nlive = 0;
+                s_sc.newslot = 0;
+                s_sc.pw_flag = 1;
+                s_sc.pw_updates += 1;
+              }
+            }
+          }
+        }
+        __syncthreads();
       }
     }
   }
@@ -1482,37 +1645,91 @@ __global__ __launch_bounds__(BLOCK) void k_panel(const LPDesc* lps, int mode) {
 // pass C: Anderson mix and projection (Alg 2: u^{k+1} = P(u^k - H^k g^k))
 // ---------------------------------------------------------------------------
 
+// Pass C: the Anderson mix of Alg 2 on AA steps, and the weight check of
+// Alg 7 when the next iteration k is a multiple of U_P: every tile adds the
+// squared distances of its entries of u^k to the anchor (which then takes
+// u^k); the last tile of the LP to arrive adds the tiles' sums in order and
+// updates the weight, the step sizes and the memory in the LP's scalars.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_mix(MixArgs a) {
   __shared__ double s_gam[MAXM];
   __shared__ int s_slot[MAXM];
+  __shared__ double s_tmp[4];
+  __shared__ int s_last;
   const MixTile tl = a.tiles[blockIdx.x];
   const LPDesc& d = a.lps[tl.lp];
-  const Scalars* sc = d.sc;
-  if (sc->status != ST_RUNNING || sc->branch != BR_AA) return;
-  const int nmix = sc->nmix;
-  if (threadIdx.x < MAXM) {
-    s_gam[threadIdx.x] = sc->gamma[threadIdx.x];
-    s_slot[threadIdx.x] = sc->mixslot[threadIdx.x];
-  }
-  __syncthreads();
+  Scalars* sc = d.sc;
+  if (sc->status != ST_RUNNING) return;
+  const bool mix = sc->branch == BR_AA;
+  const bool check = d.pw_period > 0 && sc->k % d.pw_period == 0;
+  if (!mix && !check) return;
   const int par = (int)((sc->k - 1) & 1);  // the pass that decided was k-1
   const T* ucur = (const T*)d.u[par];
-  T* unext = (T*)d.u[par ^ 1];
-  const T* g = (const T*)d.g[par];
-  const T* W = (const T*)d.W;
-  const T* dhat = (const T*)d.dhat;
+  T* unext = (T*)d.u[par ^ 1];  // u^k once the mix is done
   const int n = d.n, N = d.N;
-  for (int e = tl.e0 + threadIdx.x; e < tl.e1; e += BLOCK) {
-    double v = (double)ucur[e] + d.beta * (double)dhat[e] * (double)g[e];
-    for (int t = 0; t < nmix; ++t) v -= s_gam[t] * (double)W[(size_t)s_slot[t] * N + e];
-    T r = (T)v;
-    if (e < n) {
-      r = clampT(r, ((const T*)d.lo)[e], ((const T*)d.hi)[e]);
-    } else if (d.rowtype[e - n] != 0 && r < (T)0) {
-      r = (T)0;
+  if (mix) {
+    const int nmix = sc->nmix;
+    if (threadIdx.x < MAXM) {
+      s_gam[threadIdx.x] = sc->gamma[threadIdx.x];
+      s_slot[threadIdx.x] = sc->mixslot[threadIdx.x];
     }
-    unext[e] = r;
+    __syncthreads();
+    const T* g = (const T*)d.g[par];
+    const T* W = (const T*)d.W;
+    const T* dhat = (const T*)d.dhat;
+    const double dha[2] = {sc->dha[0], sc->dha[1]}, dhb[2] = {sc->dhb[0], sc->dhb[1]};
+    for (int e = tl.e0 + threadIdx.x; e < tl.e1; e += BLOCK) {
+      const int p = e < n ? 0 : 1;
+      const double dh = dha[p] * (double)dhat[e] + dhb[p];
+      double v = (double)ucur[e] + d.beta * dh * (double)g[e];
+      for (int t = 0; t < nmix; ++t) v -= s_gam[t] * (double)W[(size_t)s_slot[t] * N + e];
+      T r = (T)v;
+      if (e < n) {
+        r = clampT(r, ((const T*)d.lo)[e], ((const T*)d.hi)[e]);
+      } else if (d.rowtype[e - n] != 0 && r < (T)0) {
+        r = (T)0;
+      }
+      unext[e] = r;
+    }
+  }
+  if (!check) return;
+  T* anc = (T*)d.anchor;
+  double x2 = 0.0, y2 = 0.0;
+  for (int e = tl.e0 + threadIdx.x; e < tl.e1; e += BLOCK) {
+    const T v = unext[e];
+    const double dd = (double)v - (double)anc[e];
+    if (e < n) x2 += dd * dd; else y2 += dd * dd;
+    anc[e] = v;
+  }
+  x2 = block_sum(x2, s_tmp);
+  y2 = block_sum(y2, s_tmp);
+  if (threadIdx.x == 0) {
+    st_agent(&a.pwpart[2 * blockIdx.x], x2);
+    st_agent(&a.pwpart[2 * blockIdx.x + 1], y2);
+    s_last = arrive(&a.pwcnt[tl.lp], (unsigned)tl.nt) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!s_last || threadIdx.x >= 64) return;
+  const int lane = threadIdx.x;
+  if (lane == 0) reset_counter(&a.pwcnt[tl.lp]);
+  double px = 0.0, py = 0.0;
+  for (int t = lane; t < tl.nt; t += 64) {
+    px += ld_coh(a.pwpart, 2 * (tl.t0 + t));
+    py += ld_coh(a.pwpart, 2 * (tl.t0 + t) + 1);
+  }
+  px = wave_sum(px);
+  py = wave_sum(py);
+  if (lane == 0) {
+    double om = sc->omega, ta = sc->tau, si = sc->sigma;
+    if (pw_decide(d, px, py, sc->gstep, om, ta, si)) {
+      sc->omega = om;
+      sc->tau = ta;
+      sc->sigma = si;
+      sc->nlive = 0;
+      sc->newslot = 0;
+      sc->pw_flag = 1;
+      sc->pw_updates += 1;
+    }
   }
 }
 
@@ -1520,16 +1737,15 @@ __global__ __launch_bounds__(BLOCK) void k_mix(MixArgs a) {
 // set-up kernels
 // ---------------------------------------------------------------------------
 
-// u^0 = (clip(0, l, u), 0)
+// u^0 = (clip(0, l, u), 0); the weight check's anchor starts at u^0
 template <typename T>
 __global__ void k_start_point(LPDesc d) {
   T* u0 = (T*)d.u[0];
+  T* anc = (T*)d.anchor;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < d.N; e += gridDim.x * blockDim.x) {
-    if (e < d.n) {
-      u0[e] = clampT((T)0, ((const T*)d.lo)[e], ((const T*)d.hi)[e]);
-    } else {
-      u0[e] = (T)0;
-    }
+    const T v = e < d.n ? clampT((T)0, ((const T*)d.lo)[e], ((const T*)d.hi)[e]) : (T)0;
+    u0[e] = v;
+    if (anc) anc[e] = v;
   }
 }
 
@@ -1626,7 +1842,7 @@ static hipError_t launch_passes_mt(const LaunchTables& t, hipStream_t st, int mo
   if (t.nblocksB > 0) hipLaunchKernelGGL((k_pass<T, MT, 1>), dim3(t.nblocksB), dim3(BLOCK), 0, st, pa);
   if (ev) (void)hipEventRecord(ev[2], st);
   if (mode == MODE_ITER && t.ntiles > 0) {
-    MixArgs ma{t.lps, t.tiles};
+    MixArgs ma{t.lps, t.tiles, t.pwpart, t.pwcnt};
     hipLaunchKernelGGL((k_mix<T>), dim3(t.ntiles), dim3(BLOCK), 0, st, ma);
   }
   if (ev) (void)hipEventRecord(ev[3], st);
@@ -1645,30 +1861,26 @@ hipError_t launch_loop_pass(const LaunchTables& t, hipStream_t st, int mode, hip
   return t.fp64 ? launch_passes_t<double>(t, st, mode, ev) : launch_passes_t<float>(t, st, mode, ev);
 }
 
-template <typename T, int MT>
-static const void* loop_kernel() {
-  return reinterpret_cast<const void*>(&k_loop<T, MT>);
+template <typename T, bool PW>
+static const void* loop_kernel_mt(int mt) {
+  if (mt <= 4) return reinterpret_cast<const void*>(&k_loop<T, 4, PW>);
+  if (mt <= 8) return reinterpret_cast<const void*>(&k_loop<T, 8, PW>);
+  if (mt <= 10) return reinterpret_cast<const void*>(&k_loop<T, 10, PW>);
+  return reinterpret_cast<const void*>(&k_loop<T, 16, PW>);
 }
 
-static const void* loop_kernel_for(bool fp64, int mt) {
-  if (fp64) {
-    if (mt <= 4) return loop_kernel<double, 4>();
-    if (mt <= 8) return loop_kernel<double, 8>();
-    if (mt <= 10) return loop_kernel<double, 10>();
-    return loop_kernel<double, 16>();
-  }
-  if (mt <= 4) return loop_kernel<float, 4>();
-  if (mt <= 8) return loop_kernel<float, 8>();
-  if (mt <= 10) return loop_kernel<float, 10>();
-  return loop_kernel<float, 16>();
+static const void* loop_kernel_for(bool fp64, int mt, bool pw) {
+  if (fp64) return pw ? loop_kernel_mt<double, true>(mt) : loop_kernel_mt<double, false>(mt);
+  return pw ? loop_kernel_mt<float, true>(mt) : loop_kernel_mt<float, false>(mt);
 }
 
-int loop_capacity(bool fp64, int mt) {
+int loop_capacity(bool fp64, int mt, bool pw) {
   int dev = 0, cus = 0, coop = 0, nb = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loop_kernel_for(fp64, mt), BLOCK, 0) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loop_kernel_for(fp64, mt, pw), BLOCK, 0) != hipSuccess)
+    return 0;
   return nb * cus;
 }
 
@@ -1686,6 +1898,7 @@ hipError_t launch_loop(const LaunchTables& t, hipStream_t st, long long passes, 
   la.splitcnt = t.splitcnt;
   la.sync = t.sync;
   la.bc = t.bc;
+  la.pwrec = t.pwrec;
   la.err = t.err;
   la.max_passes = passes;
   la.timeout_ticks = t.timeout_ticks;
@@ -1693,7 +1906,7 @@ hipError_t launch_loop(const LaunchTables& t, hipStream_t st, long long passes, 
   hipError_t e = hipMemsetAsync(t.sync, 0, sizeof(LoopSync) * (size_t)t.nlps, st);
   if (e != hipSuccess) return e;
   void* args[] = {&la};
-  return hipLaunchCooperativeKernel(loop_kernel_for(t.fp64, t.mt), dim3(t.nwgs), dim3(BLOCK), args, 0, st);
+  return hipLaunchCooperativeKernel(loop_kernel_for(t.fp64, t.mt, t.pw), dim3(t.nwgs), dim3(BLOCK), args, 0, st);
 }
 
 hipError_t launch_start_point(const LPDesc& d, bool fp64, hipStream_t st) {

@@ -46,7 +46,7 @@ struct LaunchSet {
   std::vector<Problem*> members;
   LaunchTables t;
   DevBuf d_lps, d_llp, d_chunks, d_blocksA, d_blocksB, d_nodes, d_splits, d_rec, d_ncnt, d_splitpart,
-      d_splitcnt, d_tiles, d_status, d_wgs, d_looplps, d_sync, d_bc, d_err;
+      d_splitcnt, d_tiles, d_status, d_wgs, d_looplps, d_sync, d_bc, d_err, d_pwpart, d_pwcnt, d_pwrec;
   int* h_status = nullptr;  // pinned, 2 x MAX_STATUS
   int64_t last_epochs = 0;
   std::vector<double> finish_s;  // per member: seconds into run_to_completion when seen stopped
@@ -91,6 +91,7 @@ struct Problem {
   DevBuf d_rowptr, d_colidx, d_val, d_colptr, d_rowidx, d_valT, d_rmapA, d_rmapB, d_c, d_lo, d_hi, d_q, d_dhat,
       d_rowtype;
   DevBuf d_u[2], d_g[2], d_xbar, d_hist_dG, d_hist_W, d_lam, d_sc, d_desc, d_xfer;
+  DevBuf d_anchor;  // iterate of the last primal-weight check (when the update is on)
   DevBuf d_pptr, d_pidx, d_pval, d_part, d_pchunk;  // column panels of the dual product
   bool panels = false;
   int pcoff[PANELS + 1] = {};
@@ -113,6 +114,8 @@ struct Problem {
   void upload_vec(void* dev, const double* host, size_t len, hipStream_t st);
   void result(double* x, double* y, double* lam, aapdhg_info* info, bool run_eval);
   void get_state(double* u, double* u_prev, double* g_prev, double* dG, double* W, int64_t* meta, double* gram);
+  void get_weights(double* anchor, double* w);
+  void set_weights(const double* anchor, const double* w);
   void set_state(const double* u, const double* u_prev, const double* g_prev, const double* dG, const double* W,
                  const int64_t* meta, const double* gram);
   size_t device_bytes() const;
