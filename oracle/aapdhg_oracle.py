@@ -57,6 +57,12 @@ where it matters, and the GPU library takes the same reading):
     alpha = 0.9; D-hat_1, D-hat_2 in R are those of the D-hat construction.
   * Iter_AA / c (supplement, update-D-hat study): the safeguard bound uses
     (i/c + 1) in place of (i + 1), real division; c = ``sg_div`` (default 1).
+  * Fixed-frequency restarted PDHG (the toy comparison of Section 5.3, restart
+    length 75): PDHG steps; the iterates u^1, u^2, ... are grouped in epochs of
+    R = ``restart_period`` consecutive iterates, and the last iterate of each
+    epoch is replaced by the epoch's average (the restart point of the cited
+    restarted PDHG); the next epoch starts after it.  The paper names the
+    scheme but not the restart point.
 """
 from __future__ import annotations
 
@@ -73,6 +79,7 @@ ROW_GE = 1
 VARIANT_PDHG = 0
 VARIANT_AA = 1
 VARIANT_FAA = 2
+VARIANT_RPDHG = 3  # fixed-frequency restarted PDHG (Section 5.3, the toy comparison)
 
 
 # ---------------------------------------------------------------------------
@@ -346,6 +353,7 @@ class Options:
     pw_omega0: float = 0.0  # omega^0; <= 0: sqrt(sigma / tau)
     pw_dhat: bool = True  # re-blend D-hat after each accepted update
     pw_rho: float = 0.0  # rho_k above this: alpha = 0.1, else 0.9
+    restart_period: int = 75  # R of the restarted PDHG variant
 
 
 @dataclasses.dataclass
@@ -361,6 +369,8 @@ class State:
     i: int = 0  # AA steps taken
     j: int = 0  # PDHG steps taken
     n0: float = 0.0  # ||g^0||
+    rsum: np.ndarray = None  # restarted PDHG: sum of the epoch's iterates so far
+    rcount: int = 0
 
 
 class Solver:
@@ -399,6 +409,9 @@ class Solver:
         self.state = State(k=1, x=x1, y=y1, u_prev=u0, g_prev=g0, dU=[], dG=[],
                            n0=float(np.linalg.norm(g0)))
         self.anchor = u0.copy()  # iterate of the last primal-weight check
+        if self.opt.variant == VARIANT_RPDHG:
+            u1 = self._restart_point(u1)
+            self.state.x, self.state.y = u1[:P.n].copy(), u1[P.n:].copy()
         if self.state.n0 == 0.0:
             self.state = dataclasses.replace(self.state, k=0, x=x0, y=y0)
             self.status = "converged"
@@ -444,7 +457,7 @@ class Solver:
         u_next = None
         gamma = None
         branch = "pdhg"
-        if o.variant != VARIANT_PDHG and gnorm <= o.D * S.n0 * (S.i / o.sg_div + 1) ** (-(1.0 + o.eps_sg)):
+        if o.variant in (VARIANT_AA, VARIANT_FAA) and gnorm <= o.D * S.n0 * (S.i / o.sg_div + 1) ** (-(1.0 + o.eps_sg)):
             N = P.n + P.m
             dU = np.stack(S.dU, axis=1) if S.dU else np.zeros((N, 0))
             dG = np.stack(S.dG, axis=1) if S.dG else np.zeros((N, 0))
@@ -464,6 +477,8 @@ class Solver:
                 branch = "aa"
         if u_next is None:
             u_next = u_hat
+            if o.variant == VARIANT_RPDHG:
+                u_next = self._restart_point(u_hat)
             S.j += 1
         else:
             S.i += 1
@@ -475,6 +490,19 @@ class Solver:
         S.y = u_next[n:].copy()
         S.k += 1
         return self.status
+
+    # -- restarted PDHG: the epoch's iterates and its restart -------------------
+    def _restart_point(self, u_new):
+        """Adds the new iterate to the epoch; returns it, or the epoch's
+        average when it completes the epoch of restart_period iterates."""
+        S, R = self.state, self.opt.restart_period
+        S.rsum = u_new.copy() if S.rcount == 0 else S.rsum + u_new
+        S.rcount += 1
+        if S.rcount < R:
+            return u_new
+        avg = S.rsum / R
+        S.rsum, S.rcount = None, 0
+        return avg
 
     # -- Alg 7 (primal-weight update), at the top of iteration k ------------------
     def _primal_weight(self, u):
