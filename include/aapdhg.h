@@ -68,10 +68,20 @@ typedef enum {
   AAPDHG_RUNNING = 4     /* not finished (only seen before a solve completes) */
 } aapdhg_term;
 
-typedef enum { AAPDHG_VARIANT_PDHG = 0, AAPDHG_VARIANT_AA = 1, AAPDHG_VARIANT_FAA = 2 } aapdhg_variant;
+/* AAPDHG_VARIANT_RPDHG: fixed-frequency restarted PDHG, the comparison method of Section 5.3
+ * (its toy example restarts every 75 iterations): PDHG steps, and every restart_period-th
+ * iterate u^{eR} is replaced by the average of its epoch u^{(e-1)R+1}, ..., u^{eR} (the
+ * restart point of the cited restarted PDHG; the paper does not name one). */
+typedef enum {
+  AAPDHG_VARIANT_PDHG = 0,
+  AAPDHG_VARIANT_AA = 1,
+  AAPDHG_VARIANT_FAA = 2,
+  AAPDHG_VARIANT_RPDHG = 3
+} aapdhg_variant;
 
 typedef struct {
-  int32_t variant;    /* aapdhg_variant: PDHG, AA-PDHG (Alg 2) or FAA-PDHG (Alg 3)        */
+  int32_t variant;    /* aapdhg_variant: PDHG, AA-PDHG (Alg 2), FAA-PDHG (Alg 3) or
+                         restarted PDHG                                                   */
   int32_t precision;  /* 0: float32 data and iterates, float64 reductions, Gram, solve
                          and KKT; 1: float64 throughout                                  */
   int32_t memory;     /* Anderson memory m_A, 1..AAPDHG_MAX_MEMORY                        */
@@ -118,7 +128,8 @@ typedef struct {
   double sg_div;      /* c of the Iter_AA / c safeguard (supplement, update-D-hat study):
                          the bound uses (i^k / c + 1); 1 = Alg 2 as printed               */
   int32_t pw_dhat;    /* 1: re-blend D-hat at every accepted weight update, 0: keep it    */
-  int32_t reserved[3];
+  int32_t restart_period; /* epoch length R of AAPDHG_VARIANT_RPDHG (>= 1; default 75)     */
+  int32_t reserved[2];
 } aapdhg_options;
 
 typedef struct {

@@ -22,7 +22,7 @@ MAX_MEMORY = 16
 WEIGHT_WORDS = 10
 
 ROW_EQ, ROW_GE = 0, 1
-VARIANT_PDHG, VARIANT_AA, VARIANT_FAA = 0, 1, 2
+VARIANT_PDHG, VARIANT_AA, VARIANT_FAA, VARIANT_RPDHG = 0, 1, 2, 3
 TERM_NAMES = {0: "converged", 1: "iter_limit", 2: "time_limit", 3: "numerical", 4: "running"}
 OK, E_ARG, E_NOMEM, E_HIP, E_STATE, PENDING = 0, -1, -2, -3, -4, 1
 
@@ -37,7 +37,7 @@ class Options(C.Structure):
                 ("loop_kernel", C.c_int32), ("wait_limit_us", C.c_int32), ("pw_period", C.c_int32),
                 ("pw_theta", C.c_double), ("pw_eps_zero", C.c_double), ("pw_omega0", C.c_double),
                 ("pw_rho", C.c_double), ("sg_div", C.c_double), ("pw_dhat", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("restart_period", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class Info(C.Structure):

@@ -37,7 +37,7 @@ struct Dot {
 
 enum Status : int { ST_CONVERGED = 0, ST_ITER_LIMIT = 1, ST_TIME_LIMIT = 2, ST_NUMERICAL = 3, ST_RUNNING = 4 };
 enum Branch : int { BR_NONE = 0, BR_PDHG = 1, BR_AA = 2 };
-enum Variant : int { V_PDHG = 0, V_AA = 1, V_FAA = 2 };
+enum Variant : int { V_PDHG = 0, V_AA = 1, V_FAA = 2, V_RPDHG = 3 };
 enum Mode : int { MODE_ITER = 0, MODE_EVAL = 1 };
 
 // Per-LP iteration state, written only by the single block that finishes a
@@ -87,6 +87,10 @@ struct LPDesc {
   int pw_period, pw_dhat;
   double pw_theta, pw_eps0, pw_rho;
   void* anchor;  // u at the last weight check (length N), when pw_period > 0
+  // restarted PDHG: epoch length R (0 = no restarts) and the sum of the
+  // epoch's iterates so far (length N, float64)
+  int restart;
+  double* rsum;
   const int* rowptr;  // CSR of K, rows in the order rmapB
   const int* colidx;
   const void* val;

@@ -101,10 +101,13 @@ void default_options(aapdhg_options* o) {
   o->pw_rho = 0.0;
   o->sg_div = 1.0;
   o->pw_dhat = 1;
+  o->restart_period = 75;
 }
 
 static void check_options(const aapdhg_options& o) {
-  if (o.variant < 0 || o.variant > 2) throw Error(AAPDHG_E_ARG, "variant must be 0, 1 or 2");
+  if (o.variant < 0 || o.variant > 3) throw Error(AAPDHG_E_ARG, "variant must be 0, 1, 2 or 3");
+  if (o.variant == AAPDHG_VARIANT_RPDHG && o.restart_period < 1)
+    throw Error(AAPDHG_E_ARG, "restart_period must be >= 1 for restarted PDHG");
   if (o.precision != 0 && o.precision != 1) throw Error(AAPDHG_E_ARG, "precision must be 0 or 1");
   if (o.memory < 1 || o.memory > MAXM) throw Error(AAPDHG_E_ARG, "memory must be in [1, %d]", MAXM);
   if (!(o.D >= 0.0)) throw Error(AAPDHG_E_ARG, "D must be >= 0");
@@ -560,6 +563,7 @@ void Problem::create(int32_t m_, int32_t n_, int64_t nnz_, const int64_t* row_pt
   d_sc.alloc(sizeof(Scalars), "scalars");
   d_xfer.alloc((size_t)N * 8, "transfer buffer");
   if (opt.pw_period > 0) d_anchor.alloc(N * ts, "primal-weight anchor");
+  if (opt.variant == AAPDHG_VARIANT_RPDHG) d_rsum.alloc(N * 8, "restart epoch sum");
   fill_desc();
   // ---- step size (Section 5.1): tau = sigma = 0.9 / ||K||_2 by power iteration ----
   norm_est = power_norm();
@@ -612,6 +616,8 @@ void Problem::fill_desc() {
   desc.pw_eps0 = opt.pw_eps_zero;
   desc.pw_rho = opt.pw_rho;
   desc.anchor = d_anchor.p;
+  desc.restart = opt.variant == AAPDHG_VARIANT_RPDHG ? opt.restart_period : 0;
+  desc.rsum = (double*)d_rsum.p;
   desc.rowptr = (const int*)d_rowptr.p;
   desc.colidx = (const int*)d_colidx.p;
   desc.val = d_val.p;
@@ -660,7 +666,7 @@ size_t Problem::device_bytes() const {
   const DevBuf* bufs[] = {&d_pptr, &d_pidx, &d_pval, &d_part, &d_pchunk,
                           &d_rowptr, &d_colidx, &d_val, &d_colptr, &d_rowidx, &d_valT, &d_rmapA, &d_rmapB, &d_c, &d_lo, &d_hi,
                           &d_q, &d_dhat, &d_rowtype, &d_u[0], &d_u[1], &d_g[0], &d_g[1], &d_xbar, &d_hist_dG,
-                          &d_hist_W, &d_lam, &d_sc, &d_desc, &d_xfer, &d_anchor};
+                          &d_hist_W, &d_lam, &d_sc, &d_desc, &d_xfer, &d_anchor, &d_rsum};
   for (auto* p : bufs) b += p->bytes;
   if (solo) b += solo->device_bytes();
   return b;
@@ -745,9 +751,9 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
     want &= p->opt.loop_kernel == 0;
     need += (long long)std::max(p->chunksA.size(), p->chunksB.size());
   }
-  bool pw = false;
-  for (auto* p : lps) pw |= p->opt.pw_period > 0;
-  const int cap = want ? loop_capacity(lps[0]->fp64, mt, pw) : 0;
+  bool ext = false;
+  for (auto* p : lps) ext |= p->opt.pw_period > 0 || p->opt.variant == AAPDHG_VARIANT_RPDHG;
+  const int cap = want ? loop_capacity(lps[0]->fp64, mt, ext) : 0;
   const bool persist = cap >= count && need <= 2LL * cap;
   int parts = 0;
   // per LP and pass: chunks, split rows, workgroups; leaves are the
@@ -854,7 +860,7 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
     }
   }
   t.mt = mt;
-  t.pw = pw;
+  t.ext = ext;
   t.panels = count == 1 && lps[0]->panels;
   t.nlps = count;
   d_lps.upload(descs.data(), descs.size() * sizeof(LPDesc), "lp table");

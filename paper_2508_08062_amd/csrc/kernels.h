@@ -34,7 +34,7 @@ struct LaunchTables {
   // persistent loop kernel (when the set fits the resident workgroups)
   bool panels = false;  // the one LP of the table has column panels for its dual product
   bool persistent = false;
-  bool pw = false;  // some LP of the table has the primal-weight update on
+  bool ext = false;  // some LP of the table uses the primal-weight update or restarts
   const LoopWG* wgs = nullptr;
   int nwgs = 0;
   const LoopLP* looplps = nullptr;
@@ -53,7 +53,7 @@ hipError_t launch_loop_pass(const LaunchTables& t, hipStream_t st, int mode, hip
 // the persistent loop kernel (t.persistent must be set).
 hipError_t launch_loop(const LaunchTables& t, hipStream_t st, long long passes, unsigned int tag0);
 // Workgroups of the persistent loop kernel that fit on the device at once.
-int loop_capacity(bool fp64, int mt, bool pw);
+int loop_capacity(bool fp64, int mt, bool ext);
 hipError_t launch_start_point(const LPDesc& d, bool fp64, hipStream_t st);
 // Power iteration on K^T K from the all-ones vector; est[0..iters] receives
 // ||K^T K v|| of each step (the square of the ||K|| estimate).  work holds

@@ -428,7 +428,7 @@ __device__ void final_step(const LPDesc& d, Scalars* sc, const double* f, bool e
 
   bool aa = false;
   int nmix = 0;
-  if (d.variant != V_PDHG) {
+  if (d.variant == V_AA || d.variant == V_FAA) {
     // safeguard (Alg 2): ||g^k|| <= D ||g^0|| (i^k / c + 1)^{-(1+eps)}, c = 1 in
     // Alg 2 (Iter_AA / c otherwise); ties accelerate.  The bound changes only
     // with i^k: computed once per Anderson step
@@ -531,6 +531,7 @@ struct PassView {
   int nl, s_new;
   const int* live;  // live history slots, oldest first (LDS)
   bool eval, init, kkt, hist_on, skip0;
+  bool restart_now;  // restarted PDHG: this pass ends an epoch
   // tau, sigma (primal weight) and the D-hat coefficients a_x, a_y, b_x, b_y
   // of this pass, six consecutive doubles (LDS in the loop kernel)
   const double* steps;
@@ -548,6 +549,7 @@ __device__ __forceinline__ PassView make_view(const LPDesc& d, long long k, int 
   v.init = !eval && k == 0;
   v.kkt = eval || (!v.init && d.kkt_every > 0 && (k % d.kkt_every) == 0);
   v.hist_on = !eval && !v.init;
+  v.restart_now = !eval && d.restart > 0 && (k + 1) % d.restart == 0;
   // a full memory replaces its oldest column: that column takes no dots
   v.skip0 = nl > 0 && live[0] == s_new;
   return v;
@@ -558,10 +560,11 @@ __device__ __forceinline__ PassView make_view(const LPDesc& d, long long k, int 
 // x_bar are written and read at agent scope.  Everything else of a row is
 // read and written only by the workgroup that owns the row, except for split
 // rows, which are finished by whichever part arrives last: their epilogue
-// (row_coh) reads and writes everything of the row at agent scope.  PW: the
-// step sizes and the D-hat blend may change during the solve (primal-weight
-// update on); without it they are the LP's fixed tau, sigma and D-hat.
-template <typename T, int MT, int PASS, bool COH, bool PW>
+// (row_coh) reads and writes everything of the row at agent scope.  EXT: the
+// extended loop features may be on: step sizes and D-hat that change during
+// the solve (primal-weight update) and restarts (restarted PDHG); without it
+// tau, sigma and D-hat are the LP's fixed values and there are no restarts.
+template <typename T, int MT, int PASS, bool COH, bool EXT>
 struct PassCtx {
   using DT = Dot<MT>;
   const LPDesc* dp;
@@ -612,7 +615,7 @@ struct PassCtx {
     hiv = (const T*)d->hi;
     rtype = d->rowtype;
     beta = d->beta;
-    if constexpr (PW) {
+    if constexpr (EXT) {
       tau = pv.steps[0];
       sigma = pv.steps[1];
       dh_a = pv.steps[2 + PASS];
@@ -687,7 +690,23 @@ struct PassCtx {
       }
       g = (T)((double)nx - (double)in.u);
       st(gcur, e, g, row_coh);
-      st(unext, e, nx, true);
+      T nu = nx;  // the next iterate
+      if constexpr (EXT) {
+        if (dp->restart > 0) {
+          // restarted PDHG: add the PDHG point to the epoch's sum; the last
+          // pass of an epoch moves to the epoch's average and clears the sum
+          double* rs = dp->rsum;
+          const bool rc = COH && row_coh;
+          const double sum = (rc ? ldc((const double*)rs, e) : rs[e]) + (double)nx;
+          double keep = sum;
+          if (v.restart_now) {
+            nu = (T)(sum / (double)dp->restart);
+            keep = 0.0;
+          }
+          if (rc) stc(rs, e, keep); else rs[e] = keep;
+        }
+      }
+      st(unext, e, nu, true);
       accv[DT::GG] += (double)g * (double)g;
     }
     if (v.hist_on) {
@@ -696,7 +715,7 @@ struct PassCtx {
       const T duT = (T)((double)in.u - (double)in.up);
       const double dg = (double)dgT, du = (double)duT, gd = (double)g;
       st(dG + (size_t)v.s_new * N, e, dgT, row_coh);
-      const double dh = PW ? dh_a * (double)in.dh + dh_b : (double)in.dh;
+      const double dh = EXT ? dh_a * (double)in.dh + dh_b : (double)in.dh;
       st(W + (size_t)v.s_new * N, e, (T)(du + beta * dh * dg), row_coh);
       accv[DT::DGDG] += dg * dg;
       accv[DT::DGG] += dg * gd;
@@ -1171,7 +1190,7 @@ __device__ __forceinline__ void for_owned(const LoopArgs& a, const LoopWG& wg, c
 // at the top of the next iteration): the squared distances of the new iterate
 // to the anchor, x part in *sx and y part in *sy (per thread); the anchor then
 // takes the new iterate.
-template <typename T, bool PW>
+template <typename T, bool EXT>
 __device__ __forceinline__ void mix_owned(const LoopArgs& a, const LoopWG& wg, const LPDesc* dp, const Bcast& bc,
                                           bool mix, bool check, double* sx, double* sy) {
   const int par = (int)((bc.k - 1) & 1);  // the pass that decided was k-1
@@ -1190,7 +1209,7 @@ __device__ __forceinline__ void mix_owned(const LoopArgs& a, const LoopWG& wg, c
     T r;
     if (mix) {
       double dh = (double)dhat[e];
-      if constexpr (PW) {
+      if constexpr (EXT) {
         const int p = e < n ? 0 : 1;
         dh = bc.dha[p] * dh + bc.dhb[p];
       }
@@ -1209,7 +1228,7 @@ __device__ __forceinline__ void mix_owned(const LoopArgs& a, const LoopWG& wg, c
     } else {
       r = ldc((const T*)unext, e);  // a PDHG step: the new iterate is the PDHG point already written
     }
-    if (PW && check) {
+    if (EXT && check) {
       const double dd = (double)r - (double)anc[e];
       if (e < n) x2 += dd * dd; else y2 += dd * dd;
       anc[e] = r;
@@ -1258,12 +1277,12 @@ __device__ __forceinline__ void fill_cache(const LoopArgs& a, const LPDesc* dp, 
   cc->a1[tid] = r < ch.r1 ? ptr[r + 1] - ch.k0 : 0;
 }
 
-template <typename T, int MT, int PASS, bool PW>
+template <typename T, int MT, int PASS, bool EXT>
 __device__ __forceinline__ void loop_units(const LoopArgs& a, const LPDesc* dp, const PassView& v, int u0, int u1,
                                            double* s_prod, double (*s_red)[NDOT], double* s_tmp, double* s_racc,
                                            int* s_own, const ChunkCache* cc) {
   using DT = Dot<MT>;
-  const PassCtx<T, MT, PASS, true, PW> P(dp, v);
+  const PassCtx<T, MT, PASS, true, EXT> P(dp, v);
   if (cc->on) {
     double acc[DT::COUNT];
 #pragma unroll
@@ -1364,7 +1383,7 @@ __device__ bool read_decisions(Bcast& b, const unsigned long long* msg, unsigned
   return true;
 }
 
-template <typename T, int MT, bool PW>
+template <typename T, int MT, bool EXT>
 __global__ __launch_bounds__(BLOCK) void k_loop(LoopArgs a) {
   __shared__ double s_prod[CHUNK_NNZ];
   __shared__ double s_red[BLOCK / 64][NDOT];
@@ -1423,14 +1442,14 @@ __global__ __launch_bounds__(BLOCK) void k_loop(LoopArgs a) {
   for (long long it = 0; it < a.max_passes; ++it) {
     const PassView v = make_view(*dp, s_bc.k, s_bc.nlive, s_bc.newslot, s_bc.live, false, &s_bc.tau);
     // ---- phase A: K^T y and the primal update ----
-    loop_units<T, MT, 0, PW>(a, dp, v, wg.a0, wg.a1, s_prod, s_red, s_tmp, s_racc, &s_own, &s_cc[0]);
+    loop_units<T, MT, 0, EXT>(a, dp, v, wg.a0, wg.a1, s_prod, s_red, s_tmp, s_racc, &s_own, &s_cc[0]);
     ++nbar;
     if (!group_barrier(sy->bar, wg.rank, nbar * (unsigned)L.nwg, &sy->abort, ticks, &s_ok)) {
       ok = false;
       break;
     }
     // ---- phase B: K x_bar and the dual update ----
-    loop_units<T, MT, 1, PW>(a, dp, v, wg.b0, wg.b1, s_prod, s_red, s_tmp, s_racc, &s_own, &s_cc[1]);
+    loop_units<T, MT, 1, EXT>(a, dp, v, wg.b0, wg.b1, s_prod, s_red, s_tmp, s_racc, &s_own, &s_cc[1]);
     wait_stores();
     __syncthreads();
     if (tid == 0) arrive_sub(sy->arr, wg.rank);
@@ -1459,7 +1478,7 @@ __global__ __launch_bounds__(BLOCK) void k_loop(LoopArgs a) {
         s_bc.nmix = s_sc.nmix;
         s_bc.nlive = s_sc.nlive;
         s_bc.newslot = s_sc.newslot;
-        if (PW) {
+        if (EXT) {
           s_bc.blend = s_sc.pw_blend;
           for (int p = 0; p < 2; ++p) {
             s_bc.dha[p] = s_sc.dha[p];
@@ -1479,7 +1498,7 @@ __global__ __launch_bounds__(BLOCK) void k_loop(LoopArgs a) {
         const bool okw = read_decisions(s_bc, msg, a.tag0 + done, s_bc.k + 1, &sy->abort, ticks);
         if (tid == 0) s_ok = okw ? 1 : 0;
       }
-      if (PW && tid == 0 && s_ok && s_bc.blend != 0)  // the D-hat re-blend rank 0 made in final_step
+      if (EXT && tid == 0 && s_ok && s_bc.blend != 0)  // the D-hat re-blend rank 0 made in final_step
         dhat_coeffs(s_bc.blend == 2 ? 0.1 : 0.9, s_bc.omega, s_bc.dha, s_bc.dhb);
       __syncthreads();
       if (!s_ok) {
@@ -1489,13 +1508,13 @@ __global__ __launch_bounds__(BLOCK) void k_loop(LoopArgs a) {
     }
     if (s_bc.status != ST_RUNNING) break;
     const bool mix = s_bc.branch == BR_AA;
-    const bool check = PW && dp->pw_period > 0 && s_bc.k % dp->pw_period == 0;
+    const bool check = EXT && dp->pw_period > 0 && s_bc.k % dp->pw_period == 0;
     if (mix || check) {
       // the mix of an AA step and/or the distances of Alg 7's check, then a
       // group barrier (the next phase A gathers the new y; the check's sums
       // are complete)
       double sx, sy2;
-      mix_owned<T, PW>(a, wg, dp, s_bc, mix, check, &sx, &sy2);
+      mix_owned<T, EXT>(a, wg, dp, s_bc, mix, check, &sx, &sy2);
       if (check) {
         sx = block_sum(sx, s_tmp);
         sy2 = block_sum(sy2, s_tmp);
@@ -1737,7 +1756,8 @@ __global__ __launch_bounds__(BLOCK) void k_mix(MixArgs a) {
 // set-up kernels
 // ---------------------------------------------------------------------------
 
-// u^0 = (clip(0, l, u), 0); the weight check's anchor starts at u^0
+// u^0 = (clip(0, l, u), 0); the weight check's anchor starts at u^0 and the
+// restart epoch's sum at 0
 template <typename T>
 __global__ void k_start_point(LPDesc d) {
   T* u0 = (T*)d.u[0];
@@ -1746,6 +1766,7 @@ __global__ void k_start_point(LPDesc d) {
     const T v = e < d.n ? clampT((T)0, ((const T*)d.lo)[e], ((const T*)d.hi)[e]) : (T)0;
     u0[e] = v;
     if (anc) anc[e] = v;
+    if (d.rsum) d.rsum[e] = 0.0;
   }
 }
 
@@ -1861,25 +1882,25 @@ hipError_t launch_loop_pass(const LaunchTables& t, hipStream_t st, int mode, hip
   return t.fp64 ? launch_passes_t<double>(t, st, mode, ev) : launch_passes_t<float>(t, st, mode, ev);
 }
 
-template <typename T, bool PW>
+template <typename T, bool EXT>
 static const void* loop_kernel_mt(int mt) {
-  if (mt <= 4) return reinterpret_cast<const void*>(&k_loop<T, 4, PW>);
-  if (mt <= 8) return reinterpret_cast<const void*>(&k_loop<T, 8, PW>);
-  if (mt <= 10) return reinterpret_cast<const void*>(&k_loop<T, 10, PW>);
-  return reinterpret_cast<const void*>(&k_loop<T, 16, PW>);
+  if (mt <= 4) return reinterpret_cast<const void*>(&k_loop<T, 4, EXT>);
+  if (mt <= 8) return reinterpret_cast<const void*>(&k_loop<T, 8, EXT>);
+  if (mt <= 10) return reinterpret_cast<const void*>(&k_loop<T, 10, EXT>);
+  return reinterpret_cast<const void*>(&k_loop<T, 16, EXT>);
 }
 
-static const void* loop_kernel_for(bool fp64, int mt, bool pw) {
-  if (fp64) return pw ? loop_kernel_mt<double, true>(mt) : loop_kernel_mt<double, false>(mt);
-  return pw ? loop_kernel_mt<float, true>(mt) : loop_kernel_mt<float, false>(mt);
+static const void* loop_kernel_for(bool fp64, int mt, bool ext) {
+  if (fp64) return ext ? loop_kernel_mt<double, true>(mt) : loop_kernel_mt<double, false>(mt);
+  return ext ? loop_kernel_mt<float, true>(mt) : loop_kernel_mt<float, false>(mt);
 }
 
-int loop_capacity(bool fp64, int mt, bool pw) {
+int loop_capacity(bool fp64, int mt, bool ext) {
   int dev = 0, cus = 0, coop = 0, nb = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loop_kernel_for(fp64, mt, pw), BLOCK, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, loop_kernel_for(fp64, mt, ext), BLOCK, 0) != hipSuccess)
     return 0;
   return nb * cus;
 }
@@ -1906,7 +1927,7 @@ hipError_t launch_loop(const LaunchTables& t, hipStream_t st, long long passes, 
   hipError_t e = hipMemsetAsync(t.sync, 0, sizeof(LoopSync) * (size_t)t.nlps, st);
   if (e != hipSuccess) return e;
   void* args[] = {&la};
-  return hipLaunchCooperativeKernel(loop_kernel_for(t.fp64, t.mt, t.pw), dim3(t.nwgs), dim3(BLOCK), args, 0, st);
+  return hipLaunchCooperativeKernel(loop_kernel_for(t.fp64, t.mt, t.ext), dim3(t.nwgs), dim3(BLOCK), args, 0, st);
 }
 
 hipError_t launch_start_point(const LPDesc& d, bool fp64, hipStream_t st) {

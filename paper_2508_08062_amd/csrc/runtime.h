@@ -92,6 +92,7 @@ struct Problem {
       d_rowtype;
   DevBuf d_u[2], d_g[2], d_xbar, d_hist_dG, d_hist_W, d_lam, d_sc, d_desc, d_xfer;
   DevBuf d_anchor;  // iterate of the last primal-weight check (when the update is on)
+  DevBuf d_rsum;    // restarted PDHG: sum of the epoch's iterates
   DevBuf d_pptr, d_pidx, d_pval, d_part, d_pchunk;  // column panels of the dual product
   bool panels = false;
   int pcoff[PANELS + 1] = {};

@@ -59,6 +59,7 @@ size_t estimate_bytes(const aapdhg_options& o, int32_t m, int32_t n, int64_t nnz
   b += ts * (4 * N + 2 * (size_t)n + 2 * (size_t)o.memory * N);         // iterates, residuals, x_bar, lambda, history
   b += 8 * N + sizeof(Scalars) + 64 * 1024;                             // transfer buffer, scalars, tables
   if (o.pw_period > 0) b += ts * N;                                     // primal-weight anchor
+  if (o.variant == AAPDHG_VARIANT_RPDHG) b += 8 * N;                     // restart epoch sum
   b += (size_t)NDOT * 8 * (2 + ((size_t)nnz + 4 * N) / CHUNK_NNZ);      // partial records
   return b;
 }
