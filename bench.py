@@ -17,6 +17,8 @@ Workloads (synthetic, seeded; see lpgen):
               single solves of a sample of the same LPs
   serve       Poisson stream of LP requests (200/s by default) through the continuous-
               batching server, float32, m_A = 10: LPs solved per second, p50/p99 latency
+  compare     the 20k x 50k LP solved to relative KKT 1e-4 by PDHG, AA-PDHG, FAA-PDHG,
+              AA-PDHG with primal weights and restarted PDHG: passes and seconds
 
 Prints one JSON line (see the keys below).  --gpus N with N > 1 is refused:
 this build measures one GPU.
@@ -195,6 +197,46 @@ def _batch_solve(args):
     print(json.dumps(line), flush=True)
 
 
+def _compare(args):
+    """The paper's comparison on one LP: vanilla PDHG, AA-PDHG, FAA-PDHG and
+    fixed-frequency restarted PDHG solving the 20k x 50k LP to relative KKT
+    1e-4 in float32, plus AA-PDHG in the configuration of Section 5.3
+    (m_A = 5, primal-weight update every 3000 iterations with theta = 0.5,
+    Iter_AA / 3 safeguard)."""
+    import torch
+
+    import paper_2508_08062_amd as P
+    lps, opts, cfg = _workload("mip20k")
+    stream = torch.cuda.Stream()
+    methods = [
+        ("PDHG", dict(variant=0)),
+        ("AA-PDHG m_A=10", dict(variant=1)),
+        ("FAA-PDHG m_A=10", dict(variant=2)),
+        ("AA-PDHG m_A=5, primal weight U_P=3000, Iter_AA/3", dict(variant=1, memory=5, pw_period=3000,
+                                                                 pw_theta=0.5, sg_div=3.0)),
+        ("restarted PDHG R=75", dict(variant=3, restart_period=75)),
+        ("restarted PDHG R=500", dict(variant=3, restart_period=500)),
+        ("restarted PDHG R=3000", dict(variant=3, restart_period=3000)),
+    ]
+    out = []
+    for name, m in methods:
+        s = P.Solver(lps[0], tol=1e-4, max_iter=args.compare_max_iter, **{**opts, **m})
+        t0 = time.perf_counter()
+        s.solve(stream)
+        el = time.perf_counter() - t0
+        r = s.result()
+        out.append({"method": name, "status": r["status"], "iters": r["iters"], "seconds": el, "kkt": r["kkt"],
+                    "aa_steps": r["aa_steps"], "primal_obj": r["primal_obj"]})
+        s.close()
+        print(f"# {name}: {r['status']} after {r['iters']} passes, {el:.2f} s", file=sys.stderr, flush=True)
+    best = min((o for o in out if o["status"] == "converged"), key=lambda o: o["seconds"], default=None)
+    line = _line("LP solved to rel KKT 1e-4 (float32): passes and seconds by method",
+                 best["seconds"] if best else None, "s", {**cfg, "max_iter": args.compare_max_iter},
+                 {"methods": out, "fastest": best["method"] if best else None}, higher=False,
+                 ms=(best["seconds"] * 1e3) if best else 0.0)
+    print(json.dumps(line), flush=True)
+
+
 def _serve(args, rate=None, seconds=None, pool_size=None, drain=None, emit=True):
     """A Poisson stream of LP requests through the server; LPs solved per
     second and latency from submission to completion."""
@@ -260,7 +302,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=300)
-    ap.add_argument("--workload", default="mip20k", choices=["mip20k", "powerlaw1m", "batch256", "serve"])
+    ap.add_argument("--workload", default="mip20k", choices=["mip20k", "powerlaw1m", "batch256", "serve", "compare"])
+    ap.add_argument("--compare-max-iter", type=int, default=300000, help="compare: pass limit per method")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: requests per second")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="serve: length of the arrival stream")
     ap.add_argument("--pool", type=int, default=64, help="serve: distinct LPs cycled through the stream")
@@ -309,6 +352,8 @@ def main():
         return _serve(args)
     if args.workload == "batch256":
         return _batch_solve(args)
+    if args.workload == "compare":
+        return _compare(args)
     lps, opts, cfg = _workload(args.workload)
     if args.chunks_per_block:
         opts["chunks_per_block"] = args.chunks_per_block
@@ -357,7 +402,8 @@ def main():
         launch_ms = sum(k["launch_ms"] for k in kt) / len(kt)
         per_pass = bm["primal"] + bm["dual"] + aa_frac * bm["mix"]
         dom, dom_bytes, dom_ms = "loop", per_pass * ppl, launch_ms
-        kernel_name = f"k_loop<float, {10 if M > 8 else 8}>"
+        ext = bool(opts.get("pw_period")) or opts.get("variant") == 3
+        kernel_name = f"k_loop<float, {10 if M > 8 else 8}, {'true' if ext else 'false'}>"
         spmv_gbs = bm["spmv"] * ppl / (launch_ms * 1e-3) / 1e9
         launch = {"kernel": kernel_name, "passes_per_launch": ppl, "launch_ms": launch_ms,
                   "ms_per_pass": launch_ms / ppl, "aa_fraction": aa_frac}
