@@ -19,6 +19,8 @@ Workloads (synthetic, seeded; see lpgen):
               batching server, float32, m_A = 10: LPs solved per second, p50/p99 latency
   compare     the 20k x 50k LP solved to relative KKT 1e-4 by PDHG, AA-PDHG, FAA-PDHG,
               AA-PDHG with primal weights and restarted PDHG: passes and seconds
+  sweep       AA-PDHG hyperparameters (m_A, eta, Iter_AA / c) as members of one batch on
+              the 20k x 50k LP: passes to relative KKT 1e-4 per configuration
 
 Prints one JSON line (see the keys below).  --gpus N with N > 1 is refused:
 this build measures one GPU.
@@ -237,6 +239,50 @@ def _compare(args):
     print(json.dumps(line), flush=True)
 
 
+def _sweep(args):
+    """The supplement's tuning study on synthetic LPs: AA-PDHG with
+    m_A in {3, 5, 7} x eta in {1e-6, 1e-8, 1e-10} x safeguard Iter_AA / c with
+    c in {1, 3}, every configuration a member of one batched float32 solve of
+    the same LP (relative KKT 1e-4)."""
+    import itertools
+
+    import numpy as np
+    import torch
+
+    import lpgen
+    import paper_2508_08062_amd as P
+    lp = lpgen.mip_like_lp(args.sweep_seed, m=args.sweep_m, n=int(2.5 * args.sweep_m), nnz=int(12.5 * args.sweep_m))
+    grid = list(itertools.product((3, 5, 7), (1e-6, 1e-8, 1e-10), (1.0, 3.0)))
+    base = dict(variant=1, precision=0, kkt_every=64, ruiz_iters=10, dhat_mode=0, tol=1e-4,
+                max_iter=args.sweep_max_iter)
+    solvers = [P.Solver(lp, memory=mA, eta=eta, sg_div=c, **base) for mA, eta, c in grid]
+    batch = P.Batch(solvers)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.solve(stream)
+    el = time.perf_counter() - t0
+    res = batch.results()
+    rows = [{"m_A": mA, "eta": eta, "sg_div": c, "status": r["status"], "iters": r["iters"],
+             "aa_steps": r["aa_steps"], "kkt": r["kkt"], "seconds_to_stop": r["solve_seconds"]}
+            for (mA, eta, c), r in zip(grid, res)]
+    batch.close()
+    for sv in solvers:
+        sv.close()
+    conv = [r for r in rows if r["status"] == "converged"]
+    best = min(conv, key=lambda r: r["iters"], default=None)
+    for r in rows:
+        print(f"# m_A={r['m_A']} eta={r['eta']:.0e} c={r['sg_div']:.0f}: {r['status']} {r['iters']} passes",
+              file=sys.stderr, flush=True)
+    line = _line("AA-PDHG hyperparameter sweep: passes to rel KKT 1e-4 (batched float32)",
+                 len(rows) / el, "configurations/s",
+                 {"workload": f"one LP {lp.m}x{lp.n}, {lp.nnz} nnz (mip_like_lp seed {args.sweep_seed}), "
+                              f"{len(rows)} configurations in one batch", "variant": "AA-PDHG"},
+                 {"batch_seconds": el, "configurations": rows, "fewest_passes": best,
+                  "median_passes": float(np.median([r["iters"] for r in rows]))}, ms=el * 1e3)
+    print(json.dumps(line), flush=True)
+
+
 def _serve(args, rate=None, seconds=None, pool_size=None, drain=None, emit=True):
     """A Poisson stream of LP requests through the server; LPs solved per
     second and latency from submission to completion."""
@@ -302,8 +348,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=300)
-    ap.add_argument("--workload", default="mip20k", choices=["mip20k", "powerlaw1m", "batch256", "serve", "compare"])
+    ap.add_argument("--workload", default="mip20k", choices=["mip20k", "powerlaw1m", "batch256", "serve", "compare", "sweep"])
     ap.add_argument("--compare-max-iter", type=int, default=300000, help="compare: pass limit per method")
+    ap.add_argument("--sweep-m", type=int, default=20000, help="sweep: rows of the LP (columns 2.5x, 12.5 nnz/row)")
+    ap.add_argument("--sweep-seed", type=int, default=1)
+    ap.add_argument("--sweep-max-iter", type=int, default=100000)
     ap.add_argument("--rate", type=float, default=200.0, help="serve: requests per second")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="serve: length of the arrival stream")
     ap.add_argument("--pool", type=int, default=64, help="serve: distinct LPs cycled through the stream")
@@ -354,6 +403,8 @@ def main():
         return _batch_solve(args)
     if args.workload == "compare":
         return _compare(args)
+    if args.workload == "sweep":
+        return _sweep(args)
     lps, opts, cfg = _workload(args.workload)
     if args.chunks_per_block:
         opts["chunks_per_block"] = args.chunks_per_block

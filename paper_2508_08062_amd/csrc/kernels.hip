@@ -1793,13 +1793,16 @@ __global__ void k_sqnorm_part(const double* x, int len, double* part) {
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// x = z / ||z|| with ||z||^2 = sum of nparts partials (every block adds them in
-// the same order); block 0 records ||z|| in est[slot].
+// x = z / ||z|| with ||z||^2 = sum of nparts partials: thread t adds partials
+// t, t + BLOCK, ... in order, then the block's fixed butterfly, so every block
+// gets the same value; block 0 records ||z|| in est[slot].
 __global__ void k_normalize(const double* z, double* x, int len, const double* part, int nparts, double* est, int slot) {
   __shared__ double s_norm;
+  __shared__ double s_tmp[4];
+  double s = 0.0;
+  for (int p = threadIdx.x; p < nparts; p += BLOCK) s += part[p];
+  s = block_sum(s, s_tmp);
   if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int p = 0; p < nparts; ++p) s += part[p];
     s_norm = sqrt(s);
     if (blockIdx.x == 0) est[slot] = s_norm;
   }
