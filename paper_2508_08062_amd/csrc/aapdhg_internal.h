@@ -121,9 +121,10 @@ struct LPDesc {
   const int* pidx;
   const void* pval;
   double* part;
-  // panel p's chunks (<= PANEL_ROWS rows, <= CHUNK_NNZ entries each) start at
-  // the rows pchunk[pcoff[p] + c], c < pcoff[p+1] - pcoff[p] - 1; the list
-  // of each panel ends with m
+  // panel p's chunks (<= PANEL_ROWS rows, <= CHUNK_NNZ entries each): chunk
+  // c < pcoff[p+1] - pcoff[p] - 1 starts at row pchunk[2 (pcoff[p] + c)] and
+  // entry pchunk[2 (pcoff[p] + c) + 1]; the list of each panel ends with
+  // (m, the panel's last entry + 1)
   const int* pchunk;
   int pcoff[PANELS + 1];
 };

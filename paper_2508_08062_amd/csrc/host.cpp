@@ -514,14 +514,18 @@ void Problem::create(int32_t m_, int32_t n_, int64_t nnz_, const int64_t* row_pt
       upload_as<float>(d_pval, pval, "panel values");
     d_part.alloc((size_t)2 * PANELS * m * 8, "panel sums");
     // chunks of each panel for k_panel: consecutive rows, at most PANEL_ROWS
-    // of them and CHUNK_NNZ entries
+    // of them and CHUNK_NNZ entries; each listed as (first row, first entry),
+    // the list of a panel closed by (m, the panel's end)
     std::vector<int> pchunk;
+    int nlist = 0;
     for (int p = 0; p < PANELS; ++p) {
-      pcoff[p] = (int)pchunk.size();
+      pcoff[p] = nlist;
       const int* pp = pptr.data() + (size_t)p * (m + 1);
       int r = 0;
       while (r < m) {
         pchunk.push_back(r);
+        pchunk.push_back(pp[r]);
+        ++nlist;
         int rows = 0, ent = 0;
         while (r < m && rows < PANEL_ROWS) {
           const int len = pp[r + 1] - pp[r];
@@ -532,8 +536,10 @@ void Problem::create(int32_t m_, int32_t n_, int64_t nnz_, const int64_t* row_pt
         }
       }
       pchunk.push_back(m);
+      pchunk.push_back(pp[m]);
+      ++nlist;
     }
-    pcoff[PANELS] = (int)pchunk.size();
+    pcoff[PANELS] = nlist;
     d_pchunk.upload(pchunk.data(), pchunk.size() * 4, "panel chunks");
     // the dual epilogue then only adds panel sums: chunks of BLOCK rows
     chunksBp.clear();

@@ -1585,7 +1585,10 @@ __global__ __launch_bounds__(BLOCK) void k_loop(LoopArgs a) {
 // stages the chunk's products in LDS (eight gathers in flight per thread),
 // then each thread adds the entries of up to four rows in order.  Writes
 // part[0][p][r] (x_bar, or x^k when evaluating) and, on KKT passes,
-// part[1][p][r] (x^k).
+// part[1][p][r] (x^k).  The chunk table holds each chunk's first row and
+// first entry, so a chunk's loads depend on one table read; the indices,
+// values and row ranges of the next chunk are loaded while the current one
+// is summed.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_panel(const LPDesc* lps, int mode) {
   constexpr int UNR = CHUNK_NNZ / BLOCK;
@@ -1609,41 +1612,64 @@ __global__ __launch_bounds__(BLOCK) void k_panel(const LPDesc* lps, int mode) {
   const int* __restrict__ ptr = d.pptr + (size_t)p * (m + 1);
   const int* __restrict__ idx = d.pidx;
   const T* __restrict__ val = (const T*)d.pval;
-  const int* __restrict__ cst = d.pchunk + d.pcoff[p];
+  const int* __restrict__ cst = d.pchunk + 2 * d.pcoff[p];  // (first row, first entry) per chunk
   const int nch = d.pcoff[p + 1] - d.pcoff[p] - 1;
   double* __restrict__ out1 = d.part + (size_t)p * m;
   double* __restrict__ out2 = d.part + (size_t)(PANELS + p) * m;
-  for (int c = j; c < nch; c += nj) {
-    const int r0 = cst[c], r1 = cst[c + 1];
-    const int kb = ptr[r0], ke = ptr[r1];
-    int ra[RPT], rb[RPT];
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-      const int r = r0 + tid + i * BLOCK;
-      ra[i] = r < r1 ? ptr[r] - kb : 0;
-      rb[i] = r < r1 ? ptr[r + 1] - kb : 0;
-    }
-    int ci[UNR];
-    T vv[UNR], g1[UNR], g2[UNR];
+  // the chunk's loads: column indices, values and this thread's row ranges
+  int ci[UNR], ra[RPT], rb[RPT];
+  T vv[UNR];
+  auto load = [&](int c, int* lci, T* lvv, int* lra, int* lrb) {
+    const int r0 = cst[2 * c], kb = cst[2 * c + 1];
+    const int r1 = cst[2 * c + 2], ke = cst[2 * c + 3];
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
       const int q = kb + tid + u * BLOCK;
-      ci[u] = q < ke ? idx[q] : 0;
-      vv[u] = q < ke ? val[q] : (T)0;
+      lci[u] = q < ke ? idx[q] : 0;
+      lvv[u] = q < ke ? val[q] : (T)0;
     }
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = r0 + tid + i * BLOCK;
+      lra[i] = r < r1 ? ptr[r] - kb : 0;
+      lrb[i] = r < r1 ? ptr[r + 1] - kb : 0;
+    }
+  };
+  int c = j;
+  if (c >= nch) return;
+  load(c, ci, vv, ra, rb);
+  for (;;) {
+    const int r0 = cst[2 * c], kb = cst[2 * c + 1];
+    const int r1 = cst[2 * c + 2], ke = cst[2 * c + 3];
+    T g1[UNR], g2[UNR];
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
       const bool ok = kb + tid + u * BLOCK < ke;
       g1[u] = ok ? gv1[ci[u]] : (T)0;
       g2[u] = (ok && two) ? gv2[ci[u]] : (T)0;
     }
+    // products of this chunk into registers, then the next chunk's loads
+    double pr1[UNR], pr2[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      pr1[u] = (double)vv[u] * (double)g1[u];
+      pr2[u] = (double)vv[u] * (double)g2[u];
+    }
+    int sra[RPT], srb[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      sra[i] = ra[i];
+      srb[i] = rb[i];
+    }
+    const int cn = c + nj;
+    if (cn < nch) load(cn, ci, vv, ra, rb);
     // one sweep per gathered vector (the second only on KKT passes)
     for (int sw = 0; sw < (two ? 2 : 1); ++sw) {
       __syncthreads();  // the previous sums are done with the LDS
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
         const int q = tid + u * BLOCK;
-        if (kb + q < ke) s_p[q] = (double)vv[u] * (double)(sw == 0 ? g1[u] : g2[u]);
+        if (kb + q < ke) s_p[q] = sw == 0 ? pr1[u] : pr2[u];
       }
       __syncthreads();
       double* out = sw == 0 ? out1 : out2;
@@ -1652,17 +1678,15 @@ __global__ __launch_bounds__(BLOCK) void k_panel(const LPDesc* lps, int mode) {
         const int r = r0 + tid + i * BLOCK;
         if (r < r1) {
           double a = 0.0;
-          for (int q = ra[i]; q < rb[i]; ++q) a += s_p[q];
+          for (int q = sra[i]; q < srb[i]; ++q) a += s_p[q];
           out[r] = a;
         }
       }
     }
+    if (cn >= nch) break;
+    c = cn;
   }
 }
-
-// ---------------------------------------------------------------------------
-// pass C: Anderson mix and projection (Alg 2: u^{k+1} = P(u^k - H^k g^k))
-// ---------------------------------------------------------------------------
 
 // Pass C: the Anderson mix of Alg 2 on AA steps, and the weight check of
 // Alg 7 when the next iteration k is a multiple of U_P: every tile adds the
@@ -1841,7 +1865,7 @@ __global__ void k_convert(const S* src, D* dst, size_t len) {
 // host-side launchers
 // ---------------------------------------------------------------------------
 
-constexpr int PANEL_GROUPS = 256;  // workgroups per panel (8 per CU of an XCD; the LDS allows them)
+constexpr int PANEL_GROUPS = 128;  // workgroups per panel (4 per CU of an XCD: every one resident)
 
 template <typename T, int MT>
 static hipError_t launch_passes_mt(const LaunchTables& t, hipStream_t st, int mode, hipEvent_t* ev) {
