@@ -250,6 +250,29 @@ def ruiz(P: Problem, iters: int = 10):
     return scaled, d_row, d_col
 
 
+def pock_chambolle(P: Problem, alpha: float = 1.0):
+    """Diagonal Pock-Chambolle scaling with parameter alpha (the
+    preconditioning of Section 5.3 together with Ruiz): row i is divided by
+    sqrt(sum_j |K_ij|^alpha) and column j by sqrt(sum_i |K_ij|^(2 - alpha))
+    (zero sums replaced by one), both measured on the matrix as given.
+    Returns the scaled problem and (d_row, d_col) as ruiz does."""
+    K = P.K.copy().astype(np.float64)
+    rows = np.repeat(np.arange(P.m), np.diff(K.indptr))
+    a = np.abs(K.data)
+    rsum = np.zeros(P.m)
+    csum = np.zeros(P.n)
+    np.add.at(rsum, rows, a ** alpha)
+    np.add.at(csum, K.indices, a ** (2.0 - alpha))
+    r = np.sqrt(np.where(rsum > 0.0, rsum, 1.0))
+    s = np.sqrt(np.where(csum > 0.0, csum, 1.0))
+    K.data = K.data / (r[rows] * s[K.indices])
+    d_row = 1.0 / r
+    d_col = 1.0 / s
+    scaled = Problem(P.m, P.n, K.indptr, K.indices, K.data, P.c * d_col, P.q * d_row,
+                     P.l / d_col, P.u / d_col, P.rowtype)
+    return scaled, d_row, d_col
+
+
 # ---------------------------------------------------------------------------
 # Anderson pieces
 # ---------------------------------------------------------------------------

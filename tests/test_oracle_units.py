@@ -371,3 +371,38 @@ def test_ruiz_equilibrates_and_preserves_the_lp():
     r = oracle.kkt(S, lp.planted["x"] / dc, lp.planted["y"] / dr)
     assert r["kkt"] < 1e-12
     assert r["pobj"] == pytest.approx(lp.planted["pstar"], rel=1e-12)
+
+
+@pytest.mark.parametrize("seed", [2, 3])
+def test_pock_chambolle_bounds_the_norm_and_preserves_the_lp(seed):
+    """With alpha = 1 the scaled matrix has ||K~||_2 <= 1: the Schur test with
+    weights sqrt(row sums) and sqrt(column sums) bounds it by the product of
+    two quantities that are both 1.  The planted optimum stays a KKT point of
+    the scaled LP with the same objective (the scaling is a change of
+    variables)."""
+    lp = lpgen.mip_like_lp(seed, m=80, n=160, nnz=900, fp32=False)
+    P = oracle.Problem.from_lpdata(lp)
+    S, dr, dc = oracle.pock_chambolle(P, 1.0)
+    Kd = lpgen.to_dense(lp)
+    Ks = S.K.toarray()
+    np.testing.assert_allclose(Ks, dr[:, None] * Kd * dc[None, :], rtol=1e-13, atol=1e-15)
+    # the factors are the plain row and column 1-norms
+    np.testing.assert_allclose(1.0 / dr ** 2, np.where(np.abs(Kd).sum(1) > 0, np.abs(Kd).sum(1), 1.0), rtol=1e-13)
+    np.testing.assert_allclose(1.0 / dc ** 2, np.where(np.abs(Kd).sum(0) > 0, np.abs(Kd).sum(0), 1.0), rtol=1e-13)
+    assert np.linalg.norm(Ks, 2) <= 1.0 + 1e-12
+    assert np.linalg.norm(Kd, 2) > 1.5  # the bound is not trivially true before scaling
+    r = oracle.kkt(S, lp.planted["x"] / dc, lp.planted["y"] / dr)
+    assert r["kkt"] < 1e-12
+    assert r["pobj"] == pytest.approx(lp.planted["pstar"], rel=1e-12)
+
+
+def test_ruiz_then_pock_chambolle_composes():
+    """Ruiz sweeps followed by the Pock-Chambolle step (the preconditioning of
+    Section 5.3): the factors multiply and the norm bound holds after both."""
+    lp = lpgen.mip_like_lp(4, m=80, n=160, nnz=900, fp32=False)
+    P = oracle.Problem.from_lpdata(lp)
+    S1, r1, c1 = oracle.ruiz(P, 10)
+    S2, r2, c2 = oracle.pock_chambolle(S1, 1.0)
+    Kd = lpgen.to_dense(lp)
+    np.testing.assert_allclose(S2.K.toarray(), (r1 * r2)[:, None] * Kd * (c1 * c2)[None, :], rtol=1e-12, atol=1e-15)
+    assert np.linalg.norm(S2.K.toarray(), 2) <= 1.0 + 1e-12
