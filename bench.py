@@ -202,7 +202,7 @@ def _batch_solve(args):
 def _compare(args):
     """The paper's comparison on one LP: vanilla PDHG, AA-PDHG, FAA-PDHG and
     fixed-frequency restarted PDHG solving the 20k x 50k LP to relative KKT
-    1e-4 in float32, plus AA-PDHG in the configuration of Section 5.3
+    1e-4 in float32, plus AA-PDHG in the configuration of Section 5.2
     (m_A = 5, primal-weight update every 3000 iterations with theta = 0.5,
     Iter_AA / 3 safeguard)."""
     import torch

@@ -68,7 +68,7 @@ typedef enum {
   AAPDHG_RUNNING = 4     /* not finished (only seen before a solve completes) */
 } aapdhg_term;
 
-/* AAPDHG_VARIANT_RPDHG: fixed-frequency restarted PDHG, the comparison method of Section 5.3
+/* AAPDHG_VARIANT_RPDHG: fixed-frequency restarted PDHG, the comparison method of Section 5.2
  * (its toy example restarts every 75 iterations): PDHG steps, and every restart_period-th
  * iterate u^{eR} is replaced by the average of its epoch u^{(e-1)R+1}, ..., u^{eR} (the
  * restart point of the cited restarted PDHG; the paper does not name one). */
@@ -121,7 +121,7 @@ typedef struct {
    * The difference pair of iteration k is not formed (it would join residuals of two
    * maps): iteration k runs with an empty memory. */
   int32_t pw_period;  /* U_P; 0 = no primal-weight update                                 */
-  double pw_theta;    /* smoothing theta in [0, 1] (0.5 in Section 5.3)                   */
+  double pw_theta;    /* smoothing theta in [0, 1] (0.5 in Section 5.2)                   */
   double pw_eps_zero; /* epsilon_zero > 0 of the acceptance test (default 1e-10)          */
   double pw_omega0;   /* omega^0 > 0; <= 0 takes sqrt(sigma / tau) (1 for tau = sigma)     */
   double pw_rho;      /* residual-decrease threshold of the D-hat re-blend (default 0)    */
@@ -129,7 +129,12 @@ typedef struct {
                          the bound uses (i^k / c + 1); 1 = Alg 2 as printed               */
   int32_t pw_dhat;    /* 1: re-blend D-hat at every accepted weight update, 0: keep it    */
   int32_t restart_period; /* epoch length R of AAPDHG_VARIANT_RPDHG (>= 1; default 75)     */
-  int32_t reserved[2];
+  int32_t prep_device;    /* where the Ruiz and Pock-Chambolle scaling run: 0 host, 1 device,
+                             2 (default) the device from 2^20 entries, else the host.  Ruiz
+                             gives the same bits either way                               */
+  int32_t pock_chambolle; /* 1: after the Ruiz sweeps, one Pock-Chambolle step with alpha = 1
+                             (rows and columns divided by the square roots of their absolute
+                             sums), the preconditioning of Section 5.2 together with Ruiz */
 } aapdhg_options;
 
 typedef struct {

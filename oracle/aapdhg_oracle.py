@@ -57,7 +57,7 @@ where it matters, and the GPU library takes the same reading):
     alpha = 0.9; D-hat_1, D-hat_2 in R are those of the D-hat construction.
   * Iter_AA / c (supplement, update-D-hat study): the safeguard bound uses
     (i/c + 1) in place of (i + 1), real division; c = ``sg_div`` (default 1).
-  * Fixed-frequency restarted PDHG (the toy comparison of Section 5.3, restart
+  * Fixed-frequency restarted PDHG (the toy comparison of Section 5.2, restart
     length 75): PDHG steps; the iterates u^1, u^2, ... are grouped in epochs of
     R = ``restart_period`` consecutive iterates, and the last iterate of each
     epoch is replaced by the epoch's average (the restart point of the cited
@@ -79,7 +79,7 @@ ROW_GE = 1
 VARIANT_PDHG = 0
 VARIANT_AA = 1
 VARIANT_FAA = 2
-VARIANT_RPDHG = 3  # fixed-frequency restarted PDHG (Section 5.3, the toy comparison)
+VARIANT_RPDHG = 3  # fixed-frequency restarted PDHG (Section 5.2, the toy comparison)
 
 
 # ---------------------------------------------------------------------------
@@ -252,7 +252,7 @@ def ruiz(P: Problem, iters: int = 10):
 
 def pock_chambolle(P: Problem, alpha: float = 1.0):
     """Diagonal Pock-Chambolle scaling with parameter alpha (the
-    preconditioning of Section 5.3 together with Ruiz): row i is divided by
+    preconditioning of Section 5.2 together with Ruiz): row i is divided by
     sqrt(sum_j |K_ij|^alpha) and column j by sqrt(sum_i |K_ij|^(2 - alpha))
     (zero sums replaced by one), both measured on the matrix as given.
     Returns the scaled problem and (d_row, d_col) as ruiz does."""

@@ -102,10 +102,14 @@ void default_options(aapdhg_options* o) {
   o->sg_div = 1.0;
   o->pw_dhat = 1;
   o->restart_period = 75;
+  o->prep_device = 2;
+  o->pock_chambolle = 0;
 }
 
 static void check_options(const aapdhg_options& o) {
   if (o.variant < 0 || o.variant > 3) throw Error(AAPDHG_E_ARG, "variant must be 0, 1, 2 or 3");
+  if (o.prep_device < 0 || o.prep_device > 2) throw Error(AAPDHG_E_ARG, "prep_device must be 0, 1 or 2");
+  if (o.pock_chambolle != 0 && o.pock_chambolle != 1) throw Error(AAPDHG_E_ARG, "pock_chambolle must be 0 or 1");
   if (o.variant == AAPDHG_VARIANT_RPDHG && o.restart_period < 1)
     throw Error(AAPDHG_E_ARG, "restart_period must be >= 1 for restarted PDHG");
   if (o.precision != 0 && o.precision != 1) throw Error(AAPDHG_E_ARG, "precision must be 0 or 1");
@@ -148,6 +152,7 @@ static int pow2floor(int v) {
 
 constexpr int LONG_ROW = 128;  // rows above this length leave the multi-row chunks
 constexpr int64_t PANEL_MIN_NNZ = 1 << 22;  // column panels for the dual product from 4M entries
+constexpr int64_t PREP_DEVICE_NNZ = 1 << 20;  // automatic scaling on the device from 1M entries
 
 // Order of the rows of one pass on the device: rows of at most LONG_ROW
 // entries keep their original order (their epilogue accesses stay
@@ -368,10 +373,17 @@ void Problem::create(int32_t m_, int32_t n_, int64_t nnz_, const int64_t* row_pt
     if (!std::isfinite(q[i])) throw Error(AAPDHG_E_ARG, "non-finite q[%d]", i);
     if (rowtype[i] > 1) throw Error(AAPDHG_E_ARG, "row_type[%d] must be 0 or 1", i);
   }
-  // ---- Ruiz equilibration (Section 5.2 preprocessing) ----
+  // ---- Ruiz equilibration and the Pock-Chambolle step (preconditioning of
+  // Section 5.2): on the device or the host (prep_device; automatic: the
+  // device from PREP_DEVICE_NNZ entries, where its set-up pays off); both
+  // apply the same operations in the same order to every entry ----
   d_row.assign(m, 1.0);
   d_col.assign(n, 1.0);
-  if (opt.ruiz_iters > 0) {
+  const bool scale = opt.ruiz_iters > 0 || opt.pock_chambolle;
+  const bool on_device = opt.prep_device == 1 || (opt.prep_device == 2 && (int64_t)nnz >= PREP_DEVICE_NNZ);
+  if (scale && on_device) {
+    scale_on_device();
+  } else if (scale) {
     std::vector<double> rmax(m), cmax(n), r(m), s(n);
     for (int it = 0; it < opt.ruiz_iters; ++it) {
       std::fill(rmax.begin(), rmax.end(), 0.0);
@@ -389,6 +401,23 @@ void Problem::create(int32_t m_, int32_t n_, int64_t nnz_, const int64_t* row_pt
       for (int i = 0; i < m; ++i) d_row[i] = d_row[i] / r[i];
       for (int j = 0; j < n; ++j) d_col[j] = d_col[j] / s[j];
     }
+    if (opt.pock_chambolle) {
+      // alpha = 1: row and column absolute sums, rows in index order
+      std::vector<double> rs(m, 0.0), cs(n, 0.0);
+      for (int i = 0; i < m; ++i)
+        for (int qq = rowptr[i]; qq < rowptr[i + 1]; ++qq) {
+          rs[i] += std::fabs(val[qq]);
+          cs[colidx[qq]] += std::fabs(val[qq]);
+        }
+      for (int i = 0; i < m; ++i) r[i] = std::sqrt(rs[i] > 0.0 ? rs[i] : 1.0);
+      for (int j = 0; j < n; ++j) s[j] = std::sqrt(cs[j] > 0.0 ? cs[j] : 1.0);
+      for (int i = 0; i < m; ++i)
+        for (int qq = rowptr[i]; qq < rowptr[i + 1]; ++qq) val[qq] = val[qq] / (r[i] * s[colidx[qq]]);
+      for (int i = 0; i < m; ++i) d_row[i] = d_row[i] / r[i];
+      for (int j = 0; j < n; ++j) d_col[j] = d_col[j] / s[j];
+    }
+  }
+  if (scale) {
     for (int j = 0; j < n; ++j) {
       c[j] = c[j] * d_col[j];
       lo[j] = lo[j] / d_col[j];
@@ -654,6 +683,50 @@ void Problem::fill_desc() {
   desc.part = (double*)d_part.p;
   desc.pchunk = (const int*)d_pchunk.p;
   for (int p = 0; p <= PANELS; ++p) desc.pcoff[p] = pcoff[p];
+}
+
+// The scaling loops of create() on the device: the CSR (float64 values) and
+// the CSC order of its entries go up, the scaled values and the factors come
+// back.
+void Problem::scale_on_device() {
+  std::vector<int> cptr(n + 1, 0), cperm(nnz);
+  for (int qq = 0; qq < nnz; ++qq) cptr[colidx[qq] + 1]++;
+  for (int j = 0; j < n; ++j) cptr[j + 1] += cptr[j];
+  {
+    std::vector<int> fill(cptr.begin(), cptr.end() - 1);
+    for (int i = 0; i < m; ++i)
+      for (int qq = rowptr[i]; qq < rowptr[i + 1]; ++qq) cperm[fill[colidx[qq]]++] = qq;
+  }
+  DevBuf b_rowptr, b_colidx, b_val, b_cptr, b_cperm, b_rfac, b_cfac, b_cmax, b_drow, b_dcol;
+  b_rowptr.upload(rowptr.data(), rowptr.size() * 4, "scaling rowptr");
+  b_colidx.upload(colidx.data(), std::max<size_t>(colidx.size(), 1) * 4, "scaling colidx");
+  b_val.upload(val.data(), std::max<size_t>(val.size(), 1) * 8, "scaling values");
+  b_cptr.upload(cptr.data(), cptr.size() * 4, "scaling column pointers");
+  b_cperm.upload(cperm.data(), std::max<size_t>(cperm.size(), 1) * 4, "scaling column order");
+  b_rfac.alloc((size_t)m * 8, "row factors");
+  b_cfac.alloc((size_t)n * 8, "column factors");
+  b_cmax.alloc((size_t)n * 8, "column maxima");
+  b_drow.upload(d_row.data(), (size_t)m * 8, "d_row");
+  b_dcol.upload(d_col.data(), (size_t)n * 8, "d_col");
+  ScalingArgs a;
+  a.m = m;
+  a.n = n;
+  a.rowptr = (const int*)b_rowptr.p;
+  a.colidx = (const int*)b_colidx.p;
+  a.val = (double*)b_val.p;
+  a.cptr = (const int*)b_cptr.p;
+  a.cperm = (const int*)b_cperm.p;
+  a.rfac = (double*)b_rfac.p;
+  a.cfac = (double*)b_cfac.p;
+  a.cmax = (unsigned long long*)b_cmax.p;
+  a.drow = (double*)b_drow.p;
+  a.dcol = (double*)b_dcol.p;
+  a.ruiz_iters = opt.ruiz_iters;
+  a.pock_chambolle = opt.pock_chambolle != 0;
+  hip_check(launch_scaling(a, nullptr), "scaling launch");
+  if (nnz > 0) hip_check(hipMemcpy(val.data(), b_val.p, (size_t)nnz * 8, hipMemcpyDeviceToHost), "scaled values");
+  hip_check(hipMemcpy(d_row.data(), b_drow.p, (size_t)m * 8, hipMemcpyDeviceToHost), "d_row");
+  hip_check(hipMemcpy(d_col.data(), b_dcol.p, (size_t)n * 8, hipMemcpyDeviceToHost), "d_col");
 }
 
 double Problem::power_norm() {

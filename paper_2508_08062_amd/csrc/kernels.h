@@ -55,6 +55,28 @@ hipError_t launch_loop(const LaunchTables& t, hipStream_t st, long long passes, 
 // Workgroups of the persistent loop kernel that fit on the device at once.
 int loop_capacity(bool fp64, int mt, bool ext);
 hipError_t launch_start_point(const LPDesc& d, bool fp64, hipStream_t st);
+
+// Scaling of K before the solve: ruiz_iters Ruiz sweeps, then (pock_chambolle)
+// one Pock-Chambolle step with alpha = 1, on the float64 CSR values `val`;
+// the factors are divided into drow[m] and dcol[n].  cptr/cperm: the CSC
+// order of the entries (positions in the CSR), for the column sums.
+// Work: rfac[m], cfac[n], cmax[n].
+struct ScalingArgs {
+  int m = 0, n = 0;
+  const int* rowptr = nullptr;
+  const int* colidx = nullptr;
+  double* val = nullptr;
+  const int* cptr = nullptr;
+  const int* cperm = nullptr;
+  double* rfac = nullptr;
+  double* cfac = nullptr;
+  unsigned long long* cmax = nullptr;
+  double* drow = nullptr;
+  double* dcol = nullptr;
+  int ruiz_iters = 0;
+  bool pock_chambolle = false;
+};
+hipError_t launch_scaling(const ScalingArgs& s, hipStream_t st);
 // Power iteration on K^T K from the all-ones vector; est[0..iters] receives
 // ||K^T K v|| of each step (the square of the ||K|| estimate).  work holds
 // 2n + m + 1024 doubles.

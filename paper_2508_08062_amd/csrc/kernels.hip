@@ -1966,6 +1966,97 @@ hipError_t launch_start_point(const LPDesc& d, bool fp64, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// scaling of K before the solve (Ruiz sweeps, Pock-Chambolle step), float64
+// CSR values in place; d_row and d_col collect the factors
+// ---------------------------------------------------------------------------
+
+// Row i: r_i = sqrt(max_j |K_ij|) and the column maxima by 64-bit atomic max
+// of the absolute values' bit patterns (non-negative doubles order like their
+// bits, so the maxima are exact whatever the order).
+__global__ void k_ruiz_max(const int* rowptr, const int* colidx, const double* val, int m, double* rfac,
+                           unsigned long long* cmax) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+    double rm = 0.0;
+    for (int q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+      const double a = fabs(val[q]);
+      rm = fmax(rm, a);
+      atomicMax(&cmax[colidx[q]], (unsigned long long)__double_as_longlong(a));
+    }
+    rfac[i] = sqrt(rm > 0.0 ? rm : 1.0);
+  }
+}
+
+__global__ void k_max_to_fac(const unsigned long long* cmax, int n, double* cfac) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    const double c = __longlong_as_double((long long)cmax[j]);
+    cfac[j] = sqrt(c > 0.0 ? c : 1.0);
+  }
+}
+
+// Pock-Chambolle with alpha = 1: the factor of row i (of column j) is the
+// square root of its absolute sum, one wave per row (per column, through the
+// CSC order cperm), lanes strided then the fixed butterfly.
+__global__ void k_pc_rows(const int* rowptr, const double* val, int m, double* rfac) {
+  const int lane = threadIdx.x & 63;
+  const int w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
+  for (int i = w; i < m; i += nw) {
+    double s = 0.0;
+    for (int q = rowptr[i] + lane; q < rowptr[i + 1]; q += 64) s += fabs(val[q]);
+    s = wave_sum(s);
+    if (lane == 0) rfac[i] = sqrt(s > 0.0 ? s : 1.0);
+  }
+}
+
+__global__ void k_pc_cols(const int* cptr, const int* cperm, const double* val, int n, double* cfac) {
+  const int lane = threadIdx.x & 63;
+  const int w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
+  for (int j = w; j < n; j += nw) {
+    double s = 0.0;
+    for (int q = cptr[j] + lane; q < cptr[j + 1]; q += 64) s += fabs(val[cperm[q]]);
+    s = wave_sum(s);
+    if (lane == 0) cfac[j] = sqrt(s > 0.0 ? s : 1.0);
+  }
+}
+
+// K_ij / (r_i s_j) and d_row /= r (thread per row), d_col /= s.
+__global__ void k_apply_scale(const int* rowptr, const int* colidx, double* val, int m, const double* rfac,
+                              const double* cfac, double* drow) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+    const double r = rfac[i];
+    for (int q = rowptr[i]; q < rowptr[i + 1]; ++q) val[q] = val[q] / (r * cfac[colidx[q]]);
+    drow[i] = drow[i] / r;
+  }
+}
+
+__global__ void k_div_by(double* d, const double* f, int len) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < len; e += gridDim.x * blockDim.x) d[e] = d[e] / f[e];
+}
+
+hipError_t launch_scaling(const ScalingArgs& s, hipStream_t st) {
+  const int gr = std::min(4096, (s.m + BLOCK - 1) / BLOCK);
+  const int gc = std::min(4096, (s.n + BLOCK - 1) / BLOCK);
+  for (int it = 0; it < s.ruiz_iters; ++it) {
+    hipError_t e = hipMemsetAsync(s.cmax, 0, (size_t)s.n * 8, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ruiz_max, dim3(gr), dim3(BLOCK), 0, st, s.rowptr, s.colidx, (const double*)s.val, s.m,
+                       s.rfac, s.cmax);
+    hipLaunchKernelGGL(k_max_to_fac, dim3(gc), dim3(BLOCK), 0, st, (const unsigned long long*)s.cmax, s.n, s.cfac);
+    hipLaunchKernelGGL(k_apply_scale, dim3(gr), dim3(BLOCK), 0, st, s.rowptr, s.colidx, s.val, s.m,
+                       (const double*)s.rfac, (const double*)s.cfac, s.drow);
+    hipLaunchKernelGGL(k_div_by, dim3(gc), dim3(BLOCK), 0, st, s.dcol, (const double*)s.cfac, s.n);
+  }
+  if (s.pock_chambolle) {
+    const int wr = std::min(4096, (s.m + 3) / 4), wc = std::min(4096, (s.n + 3) / 4);  // 4 waves per block
+    hipLaunchKernelGGL(k_pc_rows, dim3(wr), dim3(BLOCK), 0, st, s.rowptr, (const double*)s.val, s.m, s.rfac);
+    hipLaunchKernelGGL(k_pc_cols, dim3(wc), dim3(BLOCK), 0, st, s.cptr, s.cperm, (const double*)s.val, s.n, s.cfac);
+    hipLaunchKernelGGL(k_apply_scale, dim3(gr), dim3(BLOCK), 0, st, s.rowptr, s.colidx, s.val, s.m,
+                       (const double*)s.rfac, (const double*)s.cfac, s.drow);
+    hipLaunchKernelGGL(k_div_by, dim3(gc), dim3(BLOCK), 0, st, s.dcol, (const double*)s.cfac, s.n);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_power_iteration(const LPDesc& d, bool fp64, int iters, double* work, double* est,
                                   hipStream_t st) {
   // work: v[n], z[n], w[m], part[1024]

@@ -116,6 +116,7 @@ struct Problem {
   void result(double* x, double* y, double* lam, aapdhg_info* info, bool run_eval);
   void get_state(double* u, double* u_prev, double* g_prev, double* dG, double* W, int64_t* meta, double* gram);
   void get_weights(double* anchor, double* w);
+  void scale_on_device();
   void set_weights(const double* anchor, const double* w);
   void set_state(const double* u, const double* u_prev, const double* g_prev, const double* dG, const double* W,
                  const int64_t* meta, const double* gram);

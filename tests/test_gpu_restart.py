@@ -1,5 +1,5 @@
 """GPU parity of fixed-frequency restarted PDHG (the comparison method of
-Section 5.3) against the oracle, through the C ABI: tiny LPs in float64
+Section 5.2) against the oracle, through the C ABI: tiny LPs in float64
 (iterates to 1e-9), the 2k x 5k LP in float32 (1e-5) over several epochs in
 both loop kernels, the toy LP with the paper's restart length 75, an LP with
 split rows and columns (the coherent epilogue path), restarts inside one

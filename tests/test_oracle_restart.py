@@ -1,5 +1,5 @@
 """Pins of the oracle's fixed-frequency restarted PDHG (the toy comparison
-of Section 5.3): special cases that reduce to vanilla PDHG, the epoch
+of Section 5.2): special cases that reduce to vanilla PDHG, the epoch
 averages on the toy LP in closed form (its PDHG map is affine while x > 0),
 and the toy behaviour the paper describes (restarts move the iterate to the
 solution far faster than vanilla PDHG)."""

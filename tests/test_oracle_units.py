@@ -398,7 +398,7 @@ def test_pock_chambolle_bounds_the_norm_and_preserves_the_lp(seed):
 
 def test_ruiz_then_pock_chambolle_composes():
     """Ruiz sweeps followed by the Pock-Chambolle step (the preconditioning of
-    Section 5.3): the factors multiply and the norm bound holds after both."""
+    Section 5.2): the factors multiply and the norm bound holds after both."""
     lp = lpgen.mip_like_lp(4, m=80, n=160, nnz=900, fp32=False)
     P = oracle.Problem.from_lpdata(lp)
     S1, r1, c1 = oracle.ruiz(P, 10)
