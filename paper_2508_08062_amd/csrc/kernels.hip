@@ -792,8 +792,15 @@ struct PassCtx {
       ci[u] = 0;
       vv[u] = (T)0;
       if (q < ke) {
-        ci[u] = CACHED ? cidx[tid + u * BLOCK] : idx[q];
-        vv[u] = val[q];
+        if constexpr (COH) {
+          ci[u] = CACHED ? cidx[tid + u * BLOCK] : idx[q];
+          vv[u] = val[q];
+        } else {
+          // a launch streams the matrix once: non-temporal, so the gathered
+          // vector keeps its place in L2
+          ci[u] = __builtin_nontemporal_load(&idx[q]);
+          vv[u] = __builtin_nontemporal_load(&val[q]);
+        }
       }
     }
     int a0 = 0, a1 = 0;
@@ -861,8 +868,8 @@ struct PassCtx {
         ci[u] = 0;
         vv[u] = (T)0;
         if (q < ke) {
-          ci[u] = idx[q];
-          vv[u] = val[q];
+          ci[u] = COH ? idx[q] : __builtin_nontemporal_load(&idx[q]);
+          vv[u] = COH ? val[q] : __builtin_nontemporal_load(&val[q]);
         }
       }
 #pragma unroll

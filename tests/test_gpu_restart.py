@@ -117,3 +117,34 @@ def test_restarted_solve_matches_the_oracle_and_the_planted_optimum():
 def test_restart_period_must_be_positive():
     with pytest.raises(P.AAPDHGError, match="restart_period"):
         P.Solver(lpgen.tiny_lp(1), variant=RP, restart_period=0)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_mixing_methods_equals_solo_runs(precision):
+    """A batch whose members use AA-PDHG, restarted PDHG, AA-PDHG with primal
+    weights and vanilla PDHG runs every member in the extended loop kernel;
+    each member's iterate after 60 batch passes equals its solo run's bit for
+    bit (the plain AA member's solo run uses the unextended kernel: with the
+    LP's fixed steps and D-hat both compute the same values)."""
+    specs = [(lpgen.tiny_lp(0), dict(variant=1)),
+             (lpgen.tiny_lp(1), dict(variant=RP, restart_period=7)),
+             (lpgen.tiny_lp(2), dict(variant=1, pw_period=8)),
+             (lpgen.tiny_lp(3), dict(variant=0))]
+    base = dict(precision=precision, memory=5, kkt_every=8, tol=0.0, max_iter=10 ** 6)
+    solo = []
+    for lp, kw in specs:
+        s = P.Solver(lp, **base, **kw)
+        s.iterate(1)
+        s.iterate(60)
+        solo.append(s.get_state()["u"])
+        s.close()
+    members = [P.Solver(lp, **base, **kw) for lp, kw in specs]
+    b = P.Batch(members)
+    b.iterate(60)  # a batch takes the members' init step before the 60 passes
+    for g, ref in zip(members, solo):
+        st = g.get_state()
+        assert st["k"] == 61
+        np.testing.assert_array_equal(st["u"], ref)
+    b.close()
+    for g in members:
+        g.close()
