@@ -1152,8 +1152,10 @@ void LaunchSet::enqueue_eval(hipStream_t st) { hip_check(launch_loop_pass(t, st,
 
 // Run epochs until every member has stopped.  The status of epoch e is read
 // while epoch e+1 is already queued, so the device does not wait for the host.
-double LaunchSet::run_to_completion(hipStream_t st, int epoch, double time_limit_s) {
-  const auto t0 = std::chrono::steady_clock::now();
+double LaunchSet::run_to_completion(hipStream_t st, int epoch, double time_limit_s, int compact_below,
+                                    const std::chrono::steady_clock::time_point* t0p) {
+  const auto t0 = t0p ? *t0p : std::chrono::steady_clock::now();
+  compacted = false;
   const int count = t.nlps;
   hipEvent_t ev[2];
   hip_check(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming), "event");
@@ -1172,14 +1174,18 @@ double LaunchSet::run_to_completion(hipStream_t st, int epoch, double time_limit
     ++epochs;
     if (pending) {
       hip_check(hipEventSynchronize(ev[pend_slot]), "event wait");
-      bool any = false;
+      int nrun = 0;
       const double now = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
       for (int i = 0; i < count; ++i) {
         const bool run = h_status[pend_slot * MAX_STATUS + i] == ST_RUNNING;
-        any |= run;
+        nrun += run ? 1 : 0;
         if (!run && finish_s[i] < 0.0) finish_s[i] = now;  // seen stopped at this status read
       }
-      if (!any) done = true;
+      if (nrun == 0) done = true;
+      if (nrun > 0 && nrun <= compact_below) {
+        compacted = true;  // the caller continues with the running members only
+        done = true;
+      }
     }
     pending = true;
     pend_slot = slot;
@@ -1195,8 +1201,9 @@ double LaunchSet::run_to_completion(hipStream_t st, int epoch, double time_limit
   (void)hipEventDestroy(ev[1]);
   last_epochs = epochs;
   const double total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  for (auto& f : finish_s)
-    if (f < 0.0) f = total;
+  if (!compacted)
+    for (auto& f : finish_s)
+      if (f < 0.0) f = total;
   check_loop_error(st);
   return total;
 }
@@ -1584,9 +1591,42 @@ aapdhg_status aapdhg_batch_solve(aapdhg_batch_t b, void* stream) {
       epoch = std::min(epoch, h->p.opt.epoch);
       tl = std::max(tl, h->p.opt.time_limit_s);
     }
-    const double secs = b->set.run_to_completion(st, epoch, tl);
-    (void)secs;
-    for (size_t i = 0; i < b->members.size(); ++i) b->members[i]->p.last_solve_seconds = b->set.finish_s[i];
+    // Members stop at different passes: once at most half of a set of 8 or
+    // more is still running, the running members continue in a launch set of
+    // their own (a small set fits the persistent loop kernel), so the passes
+    // of the last stragglers do not pay for the launches of finished LPs.
+    const auto t0 = std::chrono::steady_clock::now();
+    const size_t nm = b->members.size();
+    std::vector<double> fin(nm, -1.0);
+    std::vector<size_t> idx(nm);
+    for (size_t i = 0; i < nm; ++i) idx[i] = i;
+    LaunchSet* cur = &b->set;
+    std::unique_ptr<LaunchSet> sub;
+    double total = 0.0;
+    for (;;) {
+      const int count = cur->t.nlps;
+      const int below = count >= 8 ? count / 2 : 0;
+      double left = 0.0;
+      if (tl > 0.0) left = std::max(1e-9, tl - std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+      total = cur->run_to_completion(st, epoch, left, below, &t0);
+      std::vector<Problem*> running;
+      std::vector<size_t> ridx;
+      for (int j = 0; j < count; ++j) {
+        if (cur->finish_s[j] >= 0.0) {
+          fin[idx[j]] = cur->finish_s[j];
+        } else {
+          running.push_back(&b->members[idx[j]]->p);
+          ridx.push_back(idx[j]);
+        }
+      }
+      if (!cur->compacted || running.empty()) break;
+      auto next = std::make_unique<LaunchSet>();
+      next->build(running);
+      sub = std::move(next);
+      cur = sub.get();
+      idx = ridx;
+    }
+    for (size_t i = 0; i < nm; ++i) b->members[i]->p.last_solve_seconds = fin[i] >= 0.0 ? fin[i] : total;
   });
 }
 

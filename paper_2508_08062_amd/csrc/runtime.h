@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <memory>
 #include <string>
 #include <vector>
@@ -64,7 +65,13 @@ struct LaunchSet {
   unsigned int launch_seq = 0;
   unsigned int next_tag() { return (++launch_seq) << 16; }
   void enqueue_eval(hipStream_t st);
-  double run_to_completion(hipStream_t st, int epoch, double time_limit_s);
+  // Epochs of loop passes until every member has stopped (or the time
+  // limit).  With compact_below > 0 it returns as soon as at most that many
+  // members are still running (compacted is then set and the others' finish
+  // times stay -1).  Times count from *t0 when given.
+  double run_to_completion(hipStream_t st, int epoch, double time_limit_s, int compact_below = 0,
+                           const std::chrono::steady_clock::time_point* t0 = nullptr);
+  bool compacted = false;
   size_t device_bytes() const;
 };
 
