@@ -1,0 +1,76 @@
+"""GPU parity at the edges of the input space, against the oracle:
+  * the smallest and the largest Anderson memory (m_A = 1 and 16, the widest
+    kernel instantiation), AA-PDHG and FAA-PDHG, both loop kernels;
+  * an LP whose matrix has no entries (K = 0): the map reduces to projected
+    gradient steps on c and the dual stays at its fixed point; the solve
+    reaches the box minimum of c^T x."""
+import numpy as np
+import pytest
+
+import lpgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2508_08062_amd")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _pair(lp, steps, tau, loop_kernel, **kw):
+    common = dict(tau=tau, sigma=tau, kkt_every=1, tol=0.0, max_iter=10 ** 6, **kw)
+    g = P.Solver(lp, precision=1, loop_kernel=loop_kernel, **common)
+    o = oracle.Solver(oracle.Problem.from_lpdata(lp), oracle.Options(**common))
+    o.start()
+    g.iterate(1)
+    errs = []
+    for _ in range(steps):
+        o.step()
+        g.iterate(1)
+        st = g.get_state()
+        errs.append(_rel(st["u"], np.r_[o.state.x, o.state.y]))
+        assert (st["i"], st["j"]) == (o.state.i, o.state.j)
+    return errs, g
+
+
+@pytest.mark.parametrize("loop_kernel", [0, 1])
+@pytest.mark.parametrize("variant,memory", [(1, 1), (1, 16), (2, 16)])
+def test_memory_extremes_fp64(variant, memory, loop_kernel):
+    lp = lpgen.tiny_lp(5)
+    tau = 0.9 / oracle.power_norm(oracle.Problem.from_lpdata(lp))
+    errs, g = _pair(lp, 50, tau, loop_kernel, variant=variant, memory=memory)
+    assert max(errs) < 1e-9, (max(errs), int(np.argmax(errs)))
+    g.close()
+
+
+def _empty_matrix_lp():
+    m, n = 3, 5
+    return lpgen.LPData(m=m, n=n, rowptr=np.zeros(m + 1, dtype=np.int64), colidx=np.zeros(0, dtype=np.int32),
+                        val=np.zeros(0), c=np.array([1.0, -2.0, 0.5, -0.25, 0.0]),
+                        q=np.array([0.0, 0.0, -1.0]),
+                        l=np.array([-1.0, -np.inf, 0.0, -3.0, -np.inf]),
+                        u=np.array([2.0, 4.0, np.inf, 1.0, np.inf]),
+                        rowtype=np.array([0, 0, 1], dtype=np.uint8))
+
+
+@pytest.mark.parametrize("loop_kernel", [0, 1])
+def test_matrix_without_entries(loop_kernel):
+    """The PDHG trajectory is compared pass by pass (AA on this LP solves
+    nearly singular systems: its difference columns are collinear, x walks to
+    its bounds in equal steps and y never moves, so rounding is amplified by
+    1/eta); the AA solve must reach the box minimum."""
+    lp = _empty_matrix_lp()
+    errs, g = _pair(lp, 30, 0.5, loop_kernel, variant=0, memory=4)
+    assert max(errs) < 1e-14, errs
+    g.close()
+    # the solve: x at the bound c pushes it to, y = 0, objective sum_j min over the box
+    s = P.Solver(lp, precision=1, tol=1e-9, kkt_every=1, max_iter=1000, loop_kernel=loop_kernel)
+    s.solve()
+    r = s.result()
+    assert r["status"] == "converged"
+    np.testing.assert_allclose(r["x"][:4], [-1.0, 4.0, 0.0, 1.0], atol=1e-9)
+    assert r["primal_obj"] == pytest.approx(-1.0 - 8.0 + 0.0 - 0.25, abs=1e-9)
+    np.testing.assert_allclose(r["y"], 0.0, atol=1e-12)
+    s.close()
