@@ -1077,11 +1077,16 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
 //   rank 0 of the group adds the records of both phases in a fixed order,
 //   takes the decisions (final_step) and publishes them;
 //   on Anderson steps every workgroup mixes the entries it owns, then a group
-//   barrier (the next phase A gathers the new y).
+//   barrier (the next phase A gathers the new y); with EXT, when the next
+//   iteration is a primal-weight check (Alg 7), the same traversal adds the
+//   distances to the anchor and every workgroup takes the weight decision
+//   from the group's sums after that barrier.
+// EXT = false compiles the primal-weight and restart paths out: the kernel of
+// plain AA-PDHG / FAA-PDHG / PDHG sets keeps its registers for the passes.
 // Every wait is bounded: after the wait limit (four seconds unless the
-// options set it), or once another
-// workgroup of the LP has given up, it returns false, the group leaves the
-// loop and the launch reports the failure in *err.
+// options set it), or once another workgroup of the LP has given up, it
+// returns false, the group leaves the loop and the launch reports the failure
+// in *err.
 
 __device__ __forceinline__ unsigned int ld_u32(const unsigned int* p) {
   return __hip_atomic_load(const_cast<unsigned int*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
