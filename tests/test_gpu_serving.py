@@ -23,18 +23,20 @@ def _lps(count, seed0):
     return out
 
 
-def _solo(lp):
-    s = P.Solver(lp, **OPTS)
+def _solo(lp, **extra):
+    s = P.Solver(lp, **{**OPTS, **extra})
     s.solve()
     r = s.result()
     s.close()
     return r
 
 
-def test_served_results_equal_solo_results():
+@pytest.mark.parametrize("extra", [{}, {"variant": 3, "restart_period": 50}, {"pw_period": 64, "sg_div": 3.0}],
+                         ids=["aa", "restarted", "primal-weight"])
+def test_served_results_equal_solo_results(extra):
     lps = _lps(10, 7)
-    solo = [_solo(lp) for lp in lps]
-    srv = P.Server(hbm_budget_bytes=1 << 30, max_slots=4, **OPTS)
+    solo = [_solo(lp, **extra) for lp in lps]
+    srv = P.Server(hbm_budget_bytes=1 << 30, max_slots=4, **{**OPTS, **extra})
     tickets = []
     for i, lp in enumerate(lps):  # staggered arrivals: some join while others run
         tickets.append(srv.submit(lp))
