@@ -196,7 +196,9 @@ class Solver:
             lib().aapdhg_destroy(self.h)
             self.h = None
 
-    __del__ = close
+    def __del__(self):
+        if lib is not None:  # module globals are gone during interpreter teardown
+            self.close()
 
     def __enter__(self):
         return self
@@ -334,7 +336,9 @@ class Batch:
             lib().aapdhg_batch_destroy(self.h)
             self.h = None
 
-    __del__ = close
+    def __del__(self):
+        if lib is not None:  # module globals are gone during interpreter teardown
+            self.close()
 
 
 class Server:
@@ -386,4 +390,6 @@ class Server:
             lib().aapdhg_server_stop(self.h)
             self.h = None
 
-    __del__ = close
+    def __del__(self):
+        if lib is not None:  # module globals are gone during interpreter teardown
+            self.close()
