@@ -17,6 +17,7 @@ Workloads (synthetic, seeded; see lpgen):
               single solves of a sample of the same LPs
   serve       Poisson stream of LP requests (200/s by default) through the continuous-
               batching server, float32, m_A = 10: LPs solved per second, p50/p99 latency
+  serve_curve the serving mix at rising arrival rates: LPs/s and p50/p99 latency per rate
   compare     the 20k x 50k LP solved to relative KKT 1e-4 by PDHG, AA-PDHG, FAA-PDHG,
               AA-PDHG with primal weights and restarted PDHG: passes and seconds
   sweep       AA-PDHG hyperparameters (m_A, eta, Iter_AA / c) as members of one batch on
@@ -307,6 +308,28 @@ def _sweep(args):
     print(json.dumps(line), flush=True)
 
 
+def _serve_curve(args):
+    """Latency against throughput of the server: Poisson streams at rising
+    rates (each 10 s with up to 40 s of drain), the knee of the curve beside
+    the overloaded 200/s point of the serve workload."""
+    pts = []
+    for rate in args.curve_rates:
+        sv = _serve(args, rate=rate, seconds=args.serve_leg_seconds, pool_size=16, drain=args.serve_leg_drain,
+                    emit=False)
+        pts.append({"rate_per_s": rate, "lps_per_s": sv["value"], "finished": sv["finished"],
+                    "unfinished": sv["unfinished"], "latency_p50_s": sv["latency_p50_s"],
+                    "latency_p99_s": sv["latency_p99_s"]})
+        print(f"# rate {rate}/s: {sv['value']:.2f} LPs/s, p50 {sv['latency_p50_s']}, p99 {sv['latency_p99_s']}",
+              file=sys.stderr, flush=True)
+    best = max(pts, key=lambda q: q["lps_per_s"])
+    line = _line("LPs solved/s & p99 latency at rel KKT 1e-4 (served float32), by arrival rate",
+                 best["lps_per_s"], "LPs/s",
+                 {"workload": "Poisson streams of the serving mix (serving_requests seed 4), 16 distinct LPs cycled, "
+                              f"{args.serve_leg_seconds} s each", "variant": "AA-PDHG", "m_A": 10},
+                 {"curve": pts})
+    print(json.dumps(line), flush=True)
+
+
 def _serve(args, rate=None, seconds=None, pool_size=None, drain=None, emit=True):
     """A Poisson stream of LP requests through the server; LPs solved per
     second and latency from submission to completion."""
@@ -372,7 +395,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=300)
-    ap.add_argument("--workload", default="mip20k", choices=["mip20k", "powerlaw1m", "batch256", "serve", "compare", "sweep"])
+    ap.add_argument("--workload", default="mip20k", choices=["mip20k", "powerlaw1m", "batch256", "serve", "serve_curve", "compare", "sweep"])
     ap.add_argument("--compare-max-iter", type=int, default=300000, help="compare: pass limit per method")
     ap.add_argument("--sweep-m", type=int, default=20000, help="sweep: rows of the LP (columns 2.5x, 12.5 nnz/row)")
     ap.add_argument("--sweep-seed", type=int, default=1)
@@ -387,6 +410,8 @@ def main():
                     help="single-LP workloads: rate of the short serving leg (0 = none)")
     ap.add_argument("--serve-leg-seconds", type=float, default=10.0, help="length of the short serving leg")
     ap.add_argument("--serve-leg-drain", type=float, default=40.0, help="drain of the short serving leg")
+    ap.add_argument("--curve-rates", type=float, nargs="+", default=[1.0, 2.0, 4.0, 8.0, 16.0],
+                    help="serve_curve: arrival rates (requests per second)")
     ap.add_argument("--passes-per-launch", type=int, default=500,
                     help="loop passes per launch of the persistent loop kernel")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -424,6 +449,8 @@ def main():
 
     if args.workload == "serve":
         return _serve(args)
+    if args.workload == "serve_curve":
+        return _serve_curve(args)
     if args.workload == "batch256":
         return _batch_solve(args)
     if args.workload == "compare":
