@@ -140,15 +140,20 @@ def _cpu_baseline(lps, opts, seconds):
     import oracle
     lp = lps[0]
     with threadpool_limits(limits=1):
+        print("# oracle set-up", file=sys.stderr, flush=True)
         P = oracle.Problem.from_lpdata(lp)
         if opts.get("ruiz_iters", 0):
             P, _, _ = oracle.ruiz(P, opts["ruiz_iters"])
             P = P.rounded_fp32()
-        nrm = oracle.power_norm(P)
+        print("# oracle scaled", file=sys.stderr, flush=True)
+        # the pass rate does not depend on the step size: a short power
+        # iteration is enough for the large LP
+        nrm = oracle.power_norm(P, iters=200 if lp.nnz < 2_000_000 else 10)
         o = oracle.Solver(P, oracle.Options(variant=opts["variant"], memory=opts["memory"],
                                             kkt_every=opts["kkt_every"], tol=0.0, tau=0.9 / nrm,
                                             sigma=0.9 / nrm, dhat_mode=opts.get("dhat_mode", 1)))
         o.start()
+        print("# oracle started", file=sys.stderr, flush=True)
         for _ in range(3):
             o.step()
         t0 = time.perf_counter()
@@ -158,6 +163,43 @@ def _cpu_baseline(lps, opts, seconds):
             k += 1
         el = time.perf_counter() - t0
     return k / el, k, el
+
+
+def _cpu_batch_baseline(lps, opts, seconds):
+    """The oracle, one thread, solving members of the batch to relative KKT
+    1e-4 one after the other (smallest first) for about `seconds`; the batch's
+    LPs/s on one core follows from the time per nonzero-pass it shows."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    order = sorted(range(len(lps)), key=lambda i: lps[i].nnz)
+    done, work, t_all = [], 0.0, 0.0
+    with threadpool_limits(limits=1):
+        for i in order:
+            if t_all > seconds:
+                break
+            P = oracle.Problem.from_lpdata(lps[i])
+            P, _, _ = oracle.ruiz(P, opts.get("ruiz_iters", 10))
+            P = P.rounded_fp32()
+            t0 = time.perf_counter()
+            nrm = oracle.power_norm(P)
+            o = oracle.Solver(P, oracle.Options(variant=opts["variant"], memory=opts["memory"], tol=1e-4,
+                                                kkt_every=opts["kkt_every"], max_iter=20000, tau=0.9 / nrm,
+                                                sigma=0.9 / nrm, dhat_mode=opts.get("dhat_mode", 1)))
+            r = o.solve()
+            el = time.perf_counter() - t0
+            t_all += el
+            done.append((i, r["status"], int(r["k"]), el))
+            work += lps[i].nnz * r["k"]
+    # seconds per nonzero-pass, applied to the batch's own passes would need its
+    # iteration counts; report the sample and the LPs/s it reached
+    n_conv = sum(1 for d in done if d[1] == "converged")
+    return {"value": n_conv / max(t_all, 1e-9), "unit": "LPs/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(done)} smallest members solved one after the other by the float64 oracle "
+                      f"({n_conv} converged, {t_all:.1f} s, one thread): " +
+                      ", ".join(f"LP {i} {st} in {k} passes, {el:.1f} s" for i, st, k, el in done),
+            "seconds_per_nnz_pass": t_all / max(work, 1.0)}
 
 
 def _line(metric, value, unit, cfg, extra, higher=True, steps=0, warmup=0, ms=0.0, dtype="f32"):
@@ -210,6 +252,17 @@ def _batch_solve(args):
     work_all = float(sum(lps[i].nnz * r["iters"] for i, r in enumerate(res)))
     work_s = float(sum(lps[i].nnz * it64[j] for j, i in enumerate(sample)))
     est64 = sum(t64) * work_all / max(work_s, 1.0)
+    extra_cpu = {}
+    if not args.no_cpu_baseline:
+        cb = _cpu_batch_baseline(lps, opts, args.cpu_seconds)
+        # the whole batch on one core at the sample's time per nonzero-pass,
+        # with the passes each LP took on the GPU
+        est = cb["seconds_per_nnz_pass"] * float(sum(lps[i].nnz * r["iters"] for i, r in enumerate(res)))
+        cb["sample_lps_per_s"] = cb["value"]
+        cb["value"] = len(lps) / est  # the batch on one core, scaled from the sample
+        cb["sample"] += (f"; scaled to the batch: {est:.0f} s for its {len(lps)} LPs at the sample's seconds per "
+                         "nonzero-pass and the passes each LP took on the GPU")
+        extra_cpu = {"cpu_baseline": cb}
     line = _line("LPs solved/s at rel KKT 1e-4 (batched float32)", len(lps) / el, "LPs/s",
                  {**cfg, "lps": len(lps), "nnz_total": nnz_all},
                  {"batch_seconds": el, "converged": int(conv), "iters_median": float(np.median(iters)),
@@ -219,7 +272,8 @@ def _batch_solve(args):
                   "lps_done_by_p50_per_s": 0.5 * len(lps) / float(np.percentile(done_s, 50)),
                   "fp64_single": {"sample": sample, "seconds": t64, "iters": it64, "nnz_sample": nnz_s,
                                   "lps_per_s_estimate": len(lps) / est64,
-                                  "estimate": "sample seconds scaled by nnz x iterations to all LPs"}},
+                                  "estimate": "sample seconds scaled by nnz x iterations to all LPs"},
+                  **extra_cpu},
                  ms=el * 1e3)
     print(json.dumps(line), flush=True)
 
@@ -417,6 +471,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hbm-leg", action="store_true", help="skip the 1M x 2M roofline leg of the default line")
+    ap.add_argument("--large-cpu-baseline", action="store_true",
+                    help="powerlaw1m: also time the oracle (its set-up on 20M entries takes minutes)")
     ap.add_argument("--no-solve", action="store_true", help="skip the solve-to-tolerance leg")
     ap.add_argument("--chunks-per-block", type=int, default=0, help="workgroup size in chunks (0 = automatic)")
     ap.add_argument("--pw-period", type=int, default=0,
@@ -569,7 +625,7 @@ def main():
                                                    "latency_p50_s", "latency_p99_s", "latency_max_s")})
         line["serving"]["workload"] = sv["config"]["workload"]
 
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and (args.workload != "powerlaw1m" or args.large_cpu_baseline):
         rate, k, el = _cpu_baseline(lps, opts, args.cpu_seconds)
         line["cpu_baseline"] = {"value": rate, "unit": "iters/s", "cores": 1, "kind": "oracle",
                                 "sample": f"{k} loop passes of the float64 oracle on the first LP of the "
