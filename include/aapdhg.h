@@ -15,7 +15,10 @@
  * safeguard (Alg 2, AA-PDHG) or with angle and length filtering (Alg 3-6,
  * FAA-PDHG), terminated on the relative KKT residual of Remark
  * re:constrcution-termi-con.  Vanilla PDHG is the same iteration with the
- * Anderson step switched off.
+ * Anderson step switched off.  Options add the primal-weight update of Alg 7
+ * (with the D-hat re-blend that follows it and the Iter_AA / c safeguard),
+ * the fixed-frequency restarted PDHG that Section 5.2 compares against, and
+ * the Ruiz + Pock-Chambolle preconditioning of Section 5.2.
  *
  * Conventions for every entry point:
  *   - Every call returns an aapdhg_status; nothing is thrown across the ABI.
