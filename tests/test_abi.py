@@ -77,3 +77,31 @@ def test_invalid_input_is_rejected_without_a_gpu_call():
     assert "out of range" in str(e.value)
     with pytest.raises(P.AAPDHGError):
         P.Solver(lp, memory=17)
+
+
+@pytest.mark.parametrize("opts,needle", [
+    (dict(pw_period=-1), "pw_period"),
+    (dict(pw_period=10, pw_theta=1.5), "pw_theta"),
+    (dict(pw_period=10, pw_eps_zero=0.0), "pw_eps_zero"),
+    (dict(pw_dhat=2), "pw_dhat"),
+    (dict(sg_div=0.0), "sg_div"),
+    (dict(variant=3, restart_period=0), "restart_period"),
+    (dict(variant=4), "variant"),
+    (dict(prep_device=3), "prep_device"),
+    (dict(pock_chambolle=2), "pock_chambolle"),
+])
+def test_invalid_method_options_are_rejected_without_a_gpu_call(opts, needle):
+    """The options of the primal-weight update, the Iter_AA / c safeguard,
+    restarted PDHG and the scaling are validated before any device work."""
+    import lpgen
+    import paper_2508_08062_amd as P
+    with pytest.raises(P.AAPDHGError) as e:
+        P.Solver(lpgen.tiny_lp(0), precision=1, **opts)
+    assert e.value.status == P.E_ARG and needle in str(e.value)
+
+
+def test_method_option_defaults():
+    import paper_2508_08062_amd as P
+    o = P.default_options()
+    assert (o.pw_period, o.pw_theta, o.pw_eps_zero, o.pw_omega0, o.pw_rho, o.pw_dhat) == (0, 0.5, 1e-10, 0.0, 0.0, 1)
+    assert (o.sg_div, o.restart_period, o.prep_device, o.pock_chambolle) == (1.0, 75, 2, 0)
