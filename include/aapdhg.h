@@ -190,6 +190,32 @@ aapdhg_status aapdhg_create(int32_t m, int32_t n, int64_t nnz, const int64_t *ro
  * in epochs; the call returns when the solve has finished (it waits on the stream). */
 aapdhg_status aapdhg_solve(aapdhg_t h, void *stream);
 
+/* Device-memory variants, for callers whose data already lives on the GPU (say in torch
+ * tensors).  The LP is the one of Section 2 (the standard form the method solves), stored as
+ * for aapdhg_create.
+ *
+ * aapdhg_create_device: the same arguments, sizes and layouts as aapdhg_create, with every
+ * array in device memory of the current device.  It copies them to the host on `stream`
+ * (NULL = the default stream), waits for the copies, and then creates exactly as
+ * aapdhg_create does: the two give the same problem, bit for bit.  Each array must lie
+ * inside one device allocation, checked with hipMemGetAddressRange; a host pointer, or a
+ * buffer shorter than m, n and nnz imply, is AAPDHG_E_ARG.  Other errors as aapdhg_create.
+ *
+ * aapdhg_result_device: waits for the handle's work, runs the evaluation pass at the current
+ * iterate (the relative KKT quantities of the termination remark) and enqueues on `stream`,
+ * without waiting, a kernel that writes x double[n], y double[m] and lambda double[n] into
+ * the caller's device memory, unscaled as aapdhg_result gives them (the same float64 operations, so the same
+ * bits).  Any of the three may be NULL; info is host memory (may be NULL), filled before
+ * return.  AAPDHG_E_STATE before any solve or iterate.  The caller owns every buffer in
+ * both calls. */
+aapdhg_status aapdhg_create_device(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr,
+                                   const int32_t *col_idx, const double *val, const double *c,
+                                   const double *q, const double *l, const double *u,
+                                   const uint8_t *row_type, const aapdhg_options *opt, void *stream,
+                                   aapdhg_t *out);
+aapdhg_status aapdhg_result_device(aapdhg_t h, double *x, double *y, double *lambda, aapdhg_info *info,
+                                   void *stream);
+
 /* Enqueue `iters` loop passes on `stream` without waiting (asynchronous).  On a fresh or
  * reset handle the first pass is the init step.  Passes after termination do nothing. */
 aapdhg_status aapdhg_iterate(aapdhg_t h, void *stream, int64_t iters);

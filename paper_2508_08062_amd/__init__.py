@@ -57,7 +57,8 @@ class Info(C.Structure):
 EXPORTS = [
     "aapdhg_default_options", "aapdhg_create", "aapdhg_solve", "aapdhg_iterate", "aapdhg_iterate_timed",
     "aapdhg_reset",
-    "aapdhg_result", "aapdhg_get_state", "aapdhg_set_state", "aapdhg_get_weights", "aapdhg_set_weights",
+    "aapdhg_result", "aapdhg_create_device", "aapdhg_result_device", "aapdhg_get_state", "aapdhg_set_state",
+    "aapdhg_get_weights", "aapdhg_set_weights",
     "aapdhg_get_dims", "aapdhg_get_scaling",
     "aapdhg_destroy", "aapdhg_last_error", "aapdhg_batch_create", "aapdhg_batch_solve",
     "aapdhg_batch_iterate", "aapdhg_batch_iterate_timed", "aapdhg_batch_destroy", "aapdhg_server_start", "aapdhg_server_submit",
@@ -87,6 +88,9 @@ def lib():
     L.aapdhg_iterate_timed.argtypes = [_P, _P, C.c_int64, _dp]
     L.aapdhg_reset.argtypes = [_P, _P]
     L.aapdhg_result.argtypes = [_P, _dp, _dp, _dp, C.POINTER(Info)]
+    L.aapdhg_create_device.argtypes = [C.c_int32, C.c_int32, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P,
+                                       C.POINTER(Options), _P, C.POINTER(_P)]
+    L.aapdhg_result_device.argtypes = [_P, _P, _P, _P, C.POINTER(Info), _P]
     L.aapdhg_get_state.argtypes = [_P, _dp, _dp, _dp, _dp, _dp, _i64p, _dp]
     L.aapdhg_set_state.argtypes = [_P, _dp, _dp, _dp, _dp, _dp, _i64p, _dp]
     L.aapdhg_get_weights.argtypes = [_P, _dp, _dp]
@@ -190,6 +194,47 @@ class Solver:
         self.h = h
         self.options = opt
         self.memory = int(opt.memory)
+
+    @classmethod
+    def from_device(cls, m, n, rowptr, colidx, val, c, q, l, u, rowtype, stream=None,
+                    options: Options | None = None, **kw):
+        """Create from device tensors (torch, contiguous): rowptr int64[m+1],
+        colidx int32[nnz], val/c/q/l/u float64, rowtype uint8[m]
+        (aapdhg_create_device)."""
+        import torch
+        L = lib()
+        opt = options if options is not None else default_options(**kw)
+        ts = (rowptr, colidx, val, c, q, l, u, rowtype)
+        want = (torch.int64, torch.int32, torch.float64, torch.float64, torch.float64, torch.float64,
+                torch.float64, torch.uint8)
+        for t, dt in zip(ts, want):
+            if not (t.is_cuda and t.dtype == dt and t.is_contiguous()):
+                raise ValueError("device inputs must be contiguous CUDA tensors of the documented dtypes")
+        sizes = (m + 1, colidx.numel(), colidx.numel(), n, m, n, n, m)
+        if any(t.numel() != k for t, k in zip(ts, sizes)):
+            raise ValueError("device input lengths do not match m, n and nnz")
+        self = cls.__new__(cls)
+        self.m, self.n = int(m), int(n)
+        self._keep = ts
+        h = C.c_void_p()
+        _check(L.aapdhg_create_device(self.m, self.n, int(colidx.numel()), *[C.c_void_p(t.data_ptr()) for t in ts],
+                                      C.byref(opt), _stream(stream), C.byref(h)), None)
+        self.h = h
+        self.options = opt
+        self.memory = int(opt.memory)
+        return self
+
+    def result_device(self, stream=None):
+        """x, y, lambda as float64 CUDA tensors written by the library
+        (aapdhg_result_device), and the info dictionary."""
+        import torch
+        x = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        y = torch.empty(self.m, dtype=torch.float64, device="cuda")
+        lam = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        info = Info()
+        _check(lib().aapdhg_result_device(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                          C.c_void_p(lam.data_ptr()), C.byref(info), _stream(stream)), self.h)
+        return {"x": x, "y": y, "lam": lam, **info.to_dict()}
 
     def close(self):
         if getattr(self, "h", None):

@@ -745,7 +745,7 @@ size_t Problem::device_bytes() const {
   const DevBuf* bufs[] = {&d_pptr, &d_pidx, &d_pval, &d_part, &d_pchunk,
                           &d_rowptr, &d_colidx, &d_val, &d_colptr, &d_rowidx, &d_valT, &d_rmapA, &d_rmapB, &d_c, &d_lo, &d_hi,
                           &d_q, &d_dhat, &d_rowtype, &d_u[0], &d_u[1], &d_g[0], &d_g[1], &d_xbar, &d_hist_dG,
-                          &d_hist_W, &d_lam, &d_sc, &d_desc, &d_xfer, &d_anchor, &d_rsum};
+                          &d_hist_W, &d_lam, &d_sc, &d_desc, &d_xfer, &d_anchor, &d_rsum, &d_scale};
   for (auto* p : bufs) b += p->bytes;
   if (solo) b += solo->device_bytes();
   return b;
@@ -1228,6 +1228,47 @@ void Problem::upload_vec(void* dev, const double* host, size_t len, hipStream_t 
   hip_check(hipStreamSynchronize(st), "upload sync");
 }
 
+static void fill_info(const Scalars& s, double secs, aapdhg_info* info) {
+  std::memset(info, 0, sizeof *info);
+  info->term = s.status;
+  info->iters = s.k;
+  info->aa_steps = s.i_aa;
+  info->pdhg_steps = s.j_pdhg;
+  info->primal_obj = s.pobj;
+  info->dual_obj = s.dobj;
+  info->r_gap = s.r_g;
+  info->r_pri = s.r_p;
+  info->r_dual = s.r_d;
+  info->kkt = s.kkt;
+  info->gnorm = s.gnorm;
+  info->g0norm = s.n0;
+  info->solve_seconds = secs;
+  info->step_tau = s.tau;
+  info->step_sigma = s.sigma;
+  info->omega = s.omega;
+  info->pw_updates = s.pw_updates;
+}
+
+// Results into caller device memory: the evaluation pass at the current
+// iterate, then x, y, lambda unscaled and converted to float64 on `st`.
+void Problem::result_device(double* x, double* y, double* lam, aapdhg_info* info, hipStream_t st) {
+  hip_check(hipDeviceSynchronize(), "result sync");
+  if (!started) throw Error(AAPDHG_E_STATE, "no solve has been run on this handle");
+  solo->enqueue_eval(nullptr);
+  hip_check(hipStreamSynchronize(nullptr), "evaluation sync");
+  Scalars s;
+  read_scalars(s);
+  if (!d_scale.p) {
+    std::vector<double> sc(N);
+    std::copy(d_col.begin(), d_col.end(), sc.begin());
+    std::copy(d_row.begin(), d_row.end(), sc.begin() + n);
+    d_scale.upload(sc.data(), sc.size() * 8, "scaling factors");
+  }
+  hip_check(launch_unscale(d_u[(int)(s.k & 1)].p, d_lam.p, (const double*)d_scale.p, fp64, n, m, x, y, lam, st),
+            "unscale launch");
+  if (info) fill_info(s, last_solve_seconds, info);
+}
+
 void Problem::result(double* x, double* y, double* lam, aapdhg_info* info, bool run_eval) {
   hip_check(hipDeviceSynchronize(), "result sync");
   if (!started) throw Error(AAPDHG_E_STATE, "no solve has been run on this handle");
@@ -1251,26 +1292,7 @@ void Problem::result(double* x, double* y, double* lam, aapdhg_info* info, bool 
     for (int j = 0; j < n; ++j) lam[j] = l[j] / d_col[j];
   }
   (void)ts;
-  if (info) {
-    std::memset(info, 0, sizeof *info);
-    info->term = s.status;
-    info->iters = s.k;
-    info->aa_steps = s.i_aa;
-    info->pdhg_steps = s.j_pdhg;
-    info->primal_obj = s.pobj;
-    info->dual_obj = s.dobj;
-    info->r_gap = s.r_g;
-    info->r_pri = s.r_p;
-    info->r_dual = s.r_d;
-    info->kkt = s.kkt;
-    info->gnorm = s.gnorm;
-    info->g0norm = s.n0;
-    info->solve_seconds = last_solve_seconds;
-    info->step_tau = s.tau;
-    info->step_sigma = s.sigma;
-    info->omega = s.omega;
-    info->pw_updates = s.pw_updates;
-  }
+  if (info) fill_info(s, last_solve_seconds, info);
 }
 
 // primal-weight state: see aapdhg_get_weights in aapdhg.h
@@ -1450,6 +1472,80 @@ aapdhg_status aapdhg_create(int32_t m, int32_t n, int64_t nnz, const int64_t* ro
   }
   *out = h;
   return AAPDHG_OK;
+}
+
+aapdhg_status aapdhg_create_device(int32_t m, int32_t n, int64_t nnz, const int64_t* row_ptr,
+                                   const int32_t* col_idx, const double* val, const double* c, const double* q,
+                                   const double* l, const double* u, const uint8_t* row_type,
+                                   const aapdhg_options* opt, void* stream, aapdhg_t* out) {
+  if (!out) {
+    g_thread_error = "out is NULL";
+    return AAPDHG_E_ARG;
+  }
+  *out = nullptr;
+  std::vector<int64_t> hp;
+  std::vector<int32_t> hi;
+  std::vector<double> hv, hc, hq, hl, hu;
+  std::vector<uint8_t> ht;
+  const aapdhg_status st0 = guard(nullptr, [&] {
+    if (m < 1 || n < 1) throw Error(AAPDHG_E_ARG, "m and n must be >= 1 (m=%d n=%d)", m, n);
+    if (nnz < 0 || nnz >= (int64_t)1 << 31) throw Error(AAPDHG_E_ARG, "nnz must be in [0, 2^31)");
+    if (!row_ptr || (!col_idx && nnz) || (!val && nnz) || !c || !q || !l || !u || !row_type)
+      throw Error(AAPDHG_E_ARG, "null input array");
+    hipStream_t s = (hipStream_t)stream;
+    // every range must lie inside one device allocation (checked before any
+    // host buffer is sized): a short buffer is an argument error here rather
+    // than a read past its end
+    auto in_range = [&](const void* src, size_t bytes, const char* what) {
+      if (!bytes) return;
+      hipDeviceptr_t base = nullptr;
+      size_t size = 0;
+      if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)src) != hipSuccess || !base) {
+        (void)hipGetLastError();
+        throw Error(AAPDHG_E_ARG, "%s: not device memory", what);
+      }
+      if ((const char*)src + bytes > (const char*)base + size)
+        throw Error(AAPDHG_E_ARG, "%s: the allocation ends before the %zu bytes the sizes imply", what, bytes);
+    };
+    const size_t M = m, Nn = n, Z = (size_t)nnz;
+    in_range(row_ptr, (M + 1) * 8, "row_ptr");
+    in_range(col_idx, Z * 4, "col_idx");
+    in_range(val, Z * 8, "val");
+    in_range(c, Nn * 8, "c");
+    in_range(q, M * 8, "q");
+    in_range(l, Nn * 8, "l");
+    in_range(u, Nn * 8, "u");
+    in_range(row_type, M, "row_type");
+    hp.resize(M + 1);
+    hi.resize(Z);
+    hv.resize(Z);
+    hc.resize(Nn);
+    hl.resize(Nn);
+    hu.resize(Nn);
+    hq.resize(M);
+    ht.resize(M);
+    auto get = [&](void* dst, const void* src, size_t bytes, const char* what) {
+      if (bytes) hip_check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s), what);
+    };
+    get(hp.data(), row_ptr, hp.size() * 8, "row_ptr from device");
+    get(hi.data(), col_idx, hi.size() * 4, "col_idx from device");
+    get(hv.data(), val, hv.size() * 8, "val from device");
+    get(hc.data(), c, hc.size() * 8, "c from device");
+    get(hq.data(), q, hq.size() * 8, "q from device");
+    get(hl.data(), l, hl.size() * 8, "l from device");
+    get(hu.data(), u, hu.size() * 8, "u from device");
+    get(ht.data(), row_type, ht.size(), "row_type from device");
+    hip_check(hipStreamSynchronize(s), "device input sync");
+  });
+  if (st0 != AAPDHG_OK) return st0;
+  return aapdhg_create(m, n, nnz, hp.data(), hi.data(), hv.data(), hc.data(), hq.data(), hl.data(), hu.data(),
+                       ht.data(), opt, out);
+}
+
+aapdhg_status aapdhg_result_device(aapdhg_t h, double* x, double* y, double* lambda, aapdhg_info* info,
+                                   void* stream) {
+  if (!h) return AAPDHG_E_ARG;
+  return guard(&h->err, [&] { h->p.result_device(x, y, lambda, info, (hipStream_t)stream); });
 }
 
 aapdhg_status aapdhg_solve(aapdhg_t h, void* stream) {

@@ -77,6 +77,11 @@ struct ScalingArgs {
   bool pock_chambolle = false;
 };
 hipError_t launch_scaling(const ScalingArgs& s, hipStream_t st);
+// x[n], y[m], lambda[n] (float64, device; any may be null) from the iterate u
+// and the reduced costs lam of type T (fp64: double, else float), unscaled by
+// scale = (d_col[n], d_row[m]).
+hipError_t launch_unscale(const void* u, const void* lam, const double* scale, bool fp64, int n, int m, double* x,
+                          double* y, double* lo, hipStream_t st);
 // Power iteration on K^T K from the all-ones vector; est[0..iters] receives
 // ||K^T K v|| of each step (the square of the ||K|| estimate).  work holds
 // 2n + m + 1024 doubles.

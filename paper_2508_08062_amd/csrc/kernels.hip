@@ -2045,6 +2045,33 @@ __global__ void k_div_by(double* d, const double* f, int len) {
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < len; e += gridDim.x * blockDim.x) d[e] = d[e] / f[e];
 }
 
+// Results in the caller's variables, float64: x = d_col x_s, y = d_row y_s,
+// lambda = lambda_s / d_col (scale = d_col then d_row); any output may be null.
+template <typename T>
+__global__ void k_unscale(const T* u, const T* lam, const double* scale, int n, int m, double* x, double* y,
+                          double* lo) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n + m; e += gridDim.x * blockDim.x) {
+    if (e < n) {
+      if (x) x[e] = (double)u[e] * scale[e];
+      if (lo) lo[e] = (double)lam[e] / scale[e];
+    } else if (y) {
+      y[e - n] = (double)u[e] * scale[e];
+    }
+  }
+}
+
+hipError_t launch_unscale(const void* u, const void* lam, const double* scale, bool fp64, int n, int m, double* x,
+                          double* y, double* lo, hipStream_t st) {
+  const int grid = std::min(4096, (n + m + BLOCK - 1) / BLOCK);
+  if (fp64)
+    hipLaunchKernelGGL(k_unscale<double>, dim3(grid), dim3(BLOCK), 0, st, (const double*)u, (const double*)lam,
+                       scale, n, m, x, y, lo);
+  else
+    hipLaunchKernelGGL(k_unscale<float>, dim3(grid), dim3(BLOCK), 0, st, (const float*)u, (const float*)lam,
+                       scale, n, m, x, y, lo);
+  return hipGetLastError();
+}
+
 hipError_t launch_scaling(const ScalingArgs& s, hipStream_t st) {
   const int gr = std::min(4096, (s.m + BLOCK - 1) / BLOCK);
   const int gc = std::min(4096, (s.n + BLOCK - 1) / BLOCK);

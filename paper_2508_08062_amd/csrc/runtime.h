@@ -100,6 +100,7 @@ struct Problem {
   DevBuf d_u[2], d_g[2], d_xbar, d_hist_dG, d_hist_W, d_lam, d_sc, d_desc, d_xfer;
   DevBuf d_anchor;  // iterate of the last primal-weight check (when the update is on)
   DevBuf d_rsum;    // restarted PDHG: sum of the epoch's iterates
+  DevBuf d_scale;   // d_col then d_row, for results written to device memory (made on first use)
   DevBuf d_pptr, d_pidx, d_pval, d_part, d_pchunk;  // column panels of the dual product
   bool panels = false;
   int pcoff[PANELS + 1] = {};
@@ -124,6 +125,7 @@ struct Problem {
   void get_state(double* u, double* u_prev, double* g_prev, double* dG, double* W, int64_t* meta, double* gram);
   void get_weights(double* anchor, double* w);
   void scale_on_device();
+  void result_device(double* x, double* y, double* lam, aapdhg_info* info, hipStream_t st);
   void set_weights(const double* anchor, const double* w);
   void set_state(const double* u, const double* u_prev, const double* g_prev, const double* dG, const double* W,
                  const int64_t* meta, const double* gram);
