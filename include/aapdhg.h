@@ -138,6 +138,10 @@ typedef struct {
   int32_t pock_chambolle; /* 1: after the Ruiz sweeps, one Pock-Chambolle step with alpha = 1
                              (rows and columns divided by the square roots of their absolute
                              sums), the preconditioning of Section 5.2 together with Ruiz */
+  int32_t angle_mode;     /* FAA AngleFilter (Alg 4): 0 (default) judges every column against
+                             one factorisation of the reversed history, as printed; 1 judges
+                             column i against the columns kept so far (the factor refreshed
+                             after each removal), which keeps every column mode 0 keeps   */
 } aapdhg_options;
 
 typedef struct {

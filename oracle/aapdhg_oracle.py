@@ -295,11 +295,25 @@ def reverse(E, F):
     return E[:, ::-1], F[:, ::-1]
 
 
-def angle_filter(E, F, cs):
+def angle_filter(E, F, cs, sequential=False):
     """Alg 4 on matrices whose first column is the newest.  One economy QR of
     F; column i >= 2 is removed when |r_ii| / ||f_i|| < cs.  Returns the kept
-    column indices (into the input order)."""
+    column indices (into the input order).
+
+    ``sequential``: the factor is refreshed after every removal, so column i
+    is judged by its distance from the span of the columns kept so far (the
+    last diagonal entry of the QR of those columns followed by f_i)."""
     m = F.shape[1]
+    if sequential:
+        keep = [0]
+        for i in range(1, m):
+            fn = float(np.linalg.norm(F[:, i]))
+            if fn == 0.0 or len(keep) >= F.shape[0]:
+                continue
+            _, Ri = np.linalg.qr(F[:, keep + [i]], mode="reduced")
+            if abs(Ri[-1, -1]) / fn >= cs:
+                keep.append(i)
+        return keep
     _, R = np.linalg.qr(F, mode="reduced")
     keep = [0]
     for i in range(1, m):
@@ -361,6 +375,7 @@ class Options:
     eta: float = 1e-10
     cs: float = 0.2
     kappa_bar: float = 1e8
+    angle_mode: int = 0  # 0: Alg 4 with one factorisation; 1: refreshed after each removal
     tau: float = 0.0  # <= 0: 0.9 / ||K|| by power iteration
     sigma: float = 0.0
     tol: float = 1e-4
@@ -562,7 +577,7 @@ class Solver:
         """Alg 3 lines Reverse .. QR: filter the memory, then gamma = R^{-1} Q^T g."""
         o, S = self.opt, self.state
         E, F = reverse(dU, dG)  # newest first
-        keep = angle_filter(E, F, o.cs)
+        keep = angle_filter(E, F, o.cs, sequential=o.angle_mode == 1)
         E, F = E[:, keep], F[:, keep]
         mbar = length_filter(np.linalg.norm(E, axis=0), np.linalg.norm(F, axis=0), o.cs, o.kappa_bar)
         E, F = E[:, :mbar], F[:, :mbar]

@@ -90,6 +90,7 @@ struct LPDesc {
   // restarted PDHG: epoch length R (0 = no restarts) and the sum of the
   // epoch's iterates so far (length N, float64)
   int restart;
+  int angle_mode;  // FAA angle filter: 0 one factorisation, 1 refreshed after each removal
   double* rsum;
   const int* rowptr;  // CSR of K, rows in the order rmapB
   const int* colidx;

@@ -104,12 +104,14 @@ void default_options(aapdhg_options* o) {
   o->restart_period = 75;
   o->prep_device = 2;
   o->pock_chambolle = 0;
+  o->angle_mode = 0;
 }
 
 static void check_options(const aapdhg_options& o) {
   if (o.variant < 0 || o.variant > 3) throw Error(AAPDHG_E_ARG, "variant must be 0, 1, 2 or 3");
   if (o.prep_device < 0 || o.prep_device > 2) throw Error(AAPDHG_E_ARG, "prep_device must be 0, 1 or 2");
   if (o.pock_chambolle != 0 && o.pock_chambolle != 1) throw Error(AAPDHG_E_ARG, "pock_chambolle must be 0 or 1");
+  if (o.angle_mode != 0 && o.angle_mode != 1) throw Error(AAPDHG_E_ARG, "angle_mode must be 0 or 1");
   if (o.variant == AAPDHG_VARIANT_RPDHG && o.restart_period < 1)
     throw Error(AAPDHG_E_ARG, "restart_period must be >= 1 for restarted PDHG");
   if (o.precision != 0 && o.precision != 1) throw Error(AAPDHG_E_ARG, "precision must be 0 or 1");
@@ -643,6 +645,7 @@ void Problem::fill_desc() {
   desc.eta = opt.eta;
   desc.cs = opt.cs;
   desc.kappa_bar = opt.kappa_bar;
+  desc.angle_mode = opt.angle_mode;
   desc.tol = opt.tol;
   desc.sg_div = opt.sg_div;
   desc.pw_period = opt.pw_period;

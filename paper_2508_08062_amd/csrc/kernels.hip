@@ -154,13 +154,18 @@ struct SolveWork {
 // triangle, so every entry receives its updates in the order of a
 // column-by-column factorisation.  With gdiag != nullptr a pivot that is not
 // above 1e-28 gdiag[j] marks column j dependent (zero column, dep[j] = true)
-// and the factorisation continues; without it such a pivot fails.
-__device__ bool wave_chol(double* A, int n, int lane, const double* gdiag, bool* dep) {
+// and the factorisation continues; without it such a pivot fails.  With
+// seq_cs > 0 (and gdiag, fn) a column j >= 1 whose r_jj / fn[j] is below
+// seq_cs is marked dependent as well, so later columns are measured against
+// the columns kept so far only.
+__device__ bool wave_chol(double* A, int n, int lane, const double* gdiag, bool* dep, double seq_cs = 0.0,
+                          const double* fn = nullptr) {
   for (int j = 0; j < n; ++j) {
     const double piv = A[j * MAXM + j];
     bool isdep = false;
     if (gdiag) {
       isdep = !(piv > 1e-28 * gdiag[j]) || !isfinite(piv);
+      if (!isdep && seq_cs > 0.0 && j > 0) isdep = !(sqrt(piv) / fn[j] >= seq_cs);
     } else if (!(piv > 0.0) || !isfinite(piv)) {
       return false;
     }
@@ -241,9 +246,11 @@ __device__ int faa_filter(const LPDesc& d, const Scalars* sc, int nl, SolveWork*
     }
   }
   wave_sync();
-  wave_chol(w->A, nl, lane, w->gdiag, w->dep);
+  wave_chol(w->A, nl, lane, w->gdiag, w->dep, d.angle_mode ? d.cs : 0.0, w->fn);
   // AngleFilter: the newest column is always kept; column i >= 2 is removed
   // when |r_ii| / ||f_i|| < c_s (a zero or dependent column is removed).
+  // With angle_mode 1 the factorisation above already skipped the removed
+  // columns, so r_ii is the distance from the span of the kept ones.
   bool keepme = false;
   if (lane < nl) {
     const double rii = w->dep[lane] ? 0.0 : w->A[lane * MAXM + lane];

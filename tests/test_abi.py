@@ -89,6 +89,7 @@ def test_invalid_input_is_rejected_without_a_gpu_call():
     (dict(variant=4), "variant"),
     (dict(prep_device=3), "prep_device"),
     (dict(pock_chambolle=2), "pock_chambolle"),
+    (dict(angle_mode=2), "angle_mode"),
 ])
 def test_invalid_method_options_are_rejected_without_a_gpu_call(opts, needle):
     """The options of the primal-weight update, the Iter_AA / c safeguard,
@@ -104,4 +105,4 @@ def test_method_option_defaults():
     import paper_2508_08062_amd as P
     o = P.default_options()
     assert (o.pw_period, o.pw_theta, o.pw_eps_zero, o.pw_omega0, o.pw_rho, o.pw_dhat) == (0, 0.5, 1e-10, 0.0, 0.0, 1)
-    assert (o.sg_div, o.restart_period, o.prep_device, o.pock_chambolle) == (1.0, 75, 2, 0)
+    assert (o.sg_div, o.restart_period, o.prep_device, o.pock_chambolle, o.angle_mode) == (1.0, 75, 2, 0, 0)

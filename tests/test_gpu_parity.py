@@ -104,6 +104,34 @@ def test_mip_like_fp64_trajectory_faa():
     assert ctr[-1][0] == ctr[-1][1]
 
 
+@pytest.mark.parametrize("angle_mode", [0, 1])
+def test_faa_filters_removing_columns_on_most_steps_fp64(angle_mode):
+    """c_s = 0.8 with every step on the AA branch (D = 1e6): the angle filter
+    removes columns on most steps (under both readings of Alg 4, which here
+    give different trajectories); the GPU keeps the oracle's memory length
+    and iterate pass for pass."""
+    lp = lpgen.mip_like_lp(12, m=1500, n=3500, nnz=20000, fp32=False)
+    tau = 0.9 / oracle.power_norm(oracle.Problem.from_lpdata(lp))
+    common = dict(variant=2, memory=10, tau=tau, sigma=tau, kkt_every=1, tol=0.0, max_iter=10 ** 6, cs=0.8,
+                  D=1e6, angle_mode=angle_mode)
+    g = _gpu(lp, precision=1, **common)
+    o = _oracle(lp, **common)
+    o.start()
+    g.iterate(1)
+    errs, lens = [], []
+    for _ in range(50):
+        o.step()
+        g.iterate(1)
+        st = g.get_state()
+        errs.append(_rel(st["u"], np.r_[o.state.x, o.state.y]))
+        lens.append((len(st["live"]), len(o.state.dG)))
+        assert (st["i"], st["j"]) == (o.state.i, o.state.j)
+    assert all(a == b for a, b in lens), lens
+    assert sum(1 for a, _ in lens[10:] if a < 10) >= 5, lens  # the filter did remove columns
+    assert max(errs) < 1e-8, errs
+    g.close()
+
+
 def _teacher_forced(lp, g, o, steps, tol):
     """For `steps` loop passes: load the GPU's state into the oracle, let both
     take one pass, compare the next iterates.  Isolates the rounding of one

@@ -305,6 +305,62 @@ def test_length_filter_output_is_conditioned(seed):
     assert oracle.length_filter(en, fn, cs, 1e300) == 6
 
 
+def _dist_to_span(F, cols, v):
+    """Distance of v from the span of F[:, cols], by least squares (a routine
+    other than the QR the filter uses)."""
+    if not cols:
+        return float(np.linalg.norm(v))
+    coef, *_ = np.linalg.lstsq(F[:, cols], v, rcond=None)
+    return float(np.linalg.norm(v - F[:, cols] @ coef))
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_sequential_angle_filter_definition_and_superset(seed):
+    """angle_mode 1: every column is kept exactly when its sine against the
+    columns kept before it is >= cs (checked by least squares), and every
+    column the one-factorisation filter keeps is kept too (its distance from
+    a subset of the earlier columns is at least its distance from all of
+    them)."""
+    rng = np.random.default_rng(300 + seed)
+    N, m, cs = 25, 9, 0.3
+    F = rng.standard_normal((N, m)) * rng.uniform(0.1, 10, m)
+    F[:, 2] = F[:, 1] + 0.05 * rng.standard_normal(N)
+    F[:, 5] = F[:, 0] - 0.5 * F[:, 3] + 0.02 * rng.standard_normal(N)
+    F[:, 7] = 0.0
+    E = rng.standard_normal((N, m))
+    seq = oracle.angle_filter(E, F, cs, sequential=True)
+    once = oracle.angle_filter(E, F, cs)
+    assert set(once) <= set(seq)
+    kept = [0]
+    for i in range(1, m):
+        fn = np.linalg.norm(F[:, i])
+        if fn > 0 and _dist_to_span(F, kept, F[:, i]) / fn >= cs:
+            kept.append(i)
+    assert seq == kept
+    assert 7 not in seq
+
+
+def test_sequential_angle_filter_keeps_a_column_the_single_factorisation_drops():
+    """f1 is nearly parallel to f0 (dropped by both); f2 = e2 lies in the span
+    of f0 and f1 (dropped by the single factorisation) but is orthogonal to
+    f0, the only column kept before it (kept by the sequential reading)."""
+    F = np.zeros((4, 3))
+    F[0, 0] = 1.0
+    F[:, 1] = [1.0, 0.01, 0.0, 0.0]
+    F[1, 2] = 1.0
+    E = np.eye(4)[:, :3]
+    assert oracle.angle_filter(E, F, 0.2) == [0]
+    assert oracle.angle_filter(E, F, 0.2, sequential=True) == [0, 2]
+
+
+def test_angle_filter_modes_agree_on_well_separated_columns():
+    rng = np.random.default_rng(7)
+    F = _angled_columns(rng, 30, 7, 0.5)
+    E = rng.standard_normal((30, 7))
+    assert oracle.angle_filter(E, F, 0.4) == list(range(7))
+    assert oracle.angle_filter(E, F, 0.4, sequential=True) == list(range(7))
+
+
 def test_reverse_is_involution():
     E = np.arange(12.0).reshape(3, 4)
     F = -E
