@@ -95,7 +95,9 @@ typedef struct {
   double cs;          /* angle-filter threshold c_s in (0, 1] (Alg 4), FAA only           */
   double kappa_bar;   /* length-filter bound kappa-bar > 0 (Alg 5), FAA only              */
   double tau, sigma;  /* step sizes; if either is <= 0 both are set to 0.9 / ||K||_2
-                         with ||K||_2 estimated by power iteration (Section 5.1)          */
+                         with ||K||_2 estimated by power iteration (Section 5.1; `seed`
+                         gives the start vector; a zero estimate for a nonzero K falls
+                         back to the Frobenius norm, an upper bound)                      */
   double tol;         /* relative KKT tolerance (Remark re:constrcution-termi-con)        */
   int64_t max_iter;   /* loop passes before AAPDHG_ITER_LIMIT                             */
   double time_limit_s;/* wall-clock limit per solve call, <= 0 for none                   */
@@ -142,6 +144,10 @@ typedef struct {
                              one factorisation of the reversed history, as printed; 1 judges
                              column i against the columns kept so far (the factor refreshed
                              after each removal), which keeps every column mode 0 keeps   */
+  uint64_t seed;          /* start vector of the power iteration for ||K||_2: entry j is 2u - 1,
+                             u the top 53 bits of output j of SplitMix64 started at `seed`, as
+                             a fraction of 2^53 (a random start; a constant one is orthogonal
+                             to the dominant singular vector when the rows of K sum to zero) */
 } aapdhg_options;
 
 typedef struct {

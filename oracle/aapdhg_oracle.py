@@ -202,10 +202,35 @@ def kkt(P: Problem, x, y):
 # step size by power iteration (Section 5.1)
 # ---------------------------------------------------------------------------
 
-def power_norm(P: Problem, iters: int = 200, rtol: float = 1e-8, v0=None):
+_SM_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+
+
+def splitmix64(seed: int, count: int):
+    """The first ``count`` outputs of SplitMix64 (Steele, Lea and Flood,
+    OOPSLA 2014) started at state ``seed``: output j mixes the state
+    seed + (j + 1) * 0x9E3779B97F4A7C15 with two xor-shift-multiply rounds and
+    a final xor-shift.  uint64 arithmetic wraps modulo 2^64."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (np.arange(1, count + 1, dtype=np.uint64) * _SM_GAMMA)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def power_start(n: int, seed: int = 0):
+    """Start vector of the power iteration: entry j is 2u - 1 with u the top
+    53 bits of SplitMix64 output j as a fraction in [0, 1).  A random start
+    reaches the dominant singular vector whatever the sign pattern of K (a
+    constant start is orthogonal to it when, say, every row of K sums to
+    zero)."""
+    u = (splitmix64(seed, n) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    return 2.0 * u - 1.0
+
+
+def power_norm(P: Problem, iters: int = 200, rtol: float = 1e-8, v0=None, seed: int = 0):
     """Estimate ||K||_2 as sqrt of the dominant eigenvalue of K^T K by power
-    iteration.  The start vector is v0 (default: all ones)."""
-    v = np.ones(P.n) if v0 is None else np.asarray(v0, dtype=np.float64).copy()
+    iteration.  The start vector is v0 (default: power_start(n, seed))."""
+    v = power_start(P.n, seed) if v0 is None else np.asarray(v0, dtype=np.float64).copy()
     v /= np.linalg.norm(v)
     est = 0.0
     for _ in range(iters):
@@ -392,6 +417,7 @@ class Options:
     pw_dhat: bool = True  # re-blend D-hat after each accepted update
     pw_rho: float = 0.0  # rho_k above this: alpha = 0.1, else 0.9
     restart_period: int = 75  # R of the restarted PDHG variant
+    seed: int = 0  # power-iteration start vector (power_start)
 
 
 @dataclasses.dataclass
@@ -418,8 +444,8 @@ class Solver:
         self.P = P
         self.opt = dataclasses.replace(opt)
         if self.opt.tau <= 0.0 or self.opt.sigma <= 0.0:
-            nrm = power_norm(P)
-            self.opt.tau = self.opt.sigma = 0.9 / nrm
+            nrm = power_norm(P, seed=self.opt.seed)
+            self.opt.tau = self.opt.sigma = 0.9 / nrm if nrm > 0.0 else 1.0
         self.Dhat = dhat(P, self.opt.dhat_mode)
         self.Dhat0 = self.Dhat.copy()  # D-hat_1, D-hat_2 of the construction
         # primal weight: tau = gamma / omega, sigma = gamma * omega (remark on the primal-weight form)

@@ -38,7 +38,7 @@ class Options(C.Structure):
                 ("pw_theta", C.c_double), ("pw_eps_zero", C.c_double), ("pw_omega0", C.c_double),
                 ("pw_rho", C.c_double), ("sg_div", C.c_double), ("pw_dhat", C.c_int32),
                 ("restart_period", C.c_int32), ("prep_device", C.c_int32), ("pock_chambolle", C.c_int32),
-                ("angle_mode", C.c_int32)]
+                ("angle_mode", C.c_int32), ("seed", C.c_uint64)]
 
 
 class Info(C.Structure):

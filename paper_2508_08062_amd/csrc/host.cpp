@@ -105,6 +105,7 @@ void default_options(aapdhg_options* o) {
   o->prep_device = 2;
   o->pock_chambolle = 0;
   o->angle_mode = 0;
+  o->seed = 0;
 }
 
 static void check_options(const aapdhg_options& o) {
@@ -604,6 +605,13 @@ void Problem::create(int32_t m_, int32_t n_, int64_t nnz_, const int64_t* row_pt
   fill_desc();
   // ---- step size (Section 5.1): tau = sigma = 0.9 / ||K||_2 by power iteration ----
   norm_est = power_norm();
+  if (!(norm_est > 0.0)) {
+    // the iteration found nothing: K = 0, or (measure zero for a random start)
+    // a start in the null space of K; the Frobenius norm bounds ||K||_2 above
+    double f2 = 0.0;
+    for (const double v : val) f2 += v * v;
+    norm_est = std::sqrt(f2);
+  }
   if (opt.tau <= 0.0 || opt.sigma <= 0.0) {
     if (!(norm_est > 0.0)) {
       opt.tau = opt.sigma = 1.0;  // K = 0: any step satisfies the assumption
@@ -736,7 +744,7 @@ double Problem::power_norm() {
   DevBuf work, est;
   work.alloc(((size_t)2 * n + m + 1024) * 8, "power iteration work");
   est.alloc(((size_t)opt.power_iters + 1) * 8, "power iteration estimates");
-  hip_check(launch_power_iteration(desc, fp64, opt.power_iters, (double*)work.p, (double*)est.p, nullptr),
+  hip_check(launch_power_iteration(desc, fp64, opt.power_iters, opt.seed, (double*)work.p, (double*)est.p, nullptr),
             "power iteration launch");
   std::vector<double> e(opt.power_iters + 1);
   hip_check(hipMemcpy(e.data(), est.p, e.size() * 8, hipMemcpyDeviceToHost), "power iteration result");

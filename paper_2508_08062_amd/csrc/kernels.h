@@ -82,11 +82,11 @@ hipError_t launch_scaling(const ScalingArgs& s, hipStream_t st);
 // scale = (d_col[n], d_row[m]).
 hipError_t launch_unscale(const void* u, const void* lam, const double* scale, bool fp64, int n, int m, double* x,
                           double* y, double* lo, hipStream_t st);
-// Power iteration on K^T K from the all-ones vector; est[0..iters] receives
-// ||K^T K v|| of each step (the square of the ||K|| estimate).  work holds
-// 2n + m + 1024 doubles.
-hipError_t launch_power_iteration(const LPDesc& d, bool fp64, int iters, double* work, double* est,
-                                  hipStream_t st);
+// Power iteration on K^T K from the SplitMix64 start vector of `seed`;
+// est[0..iters] receives ||K^T K v|| of each step (the square of the ||K||
+// estimate).  work holds 2n + m + 1024 doubles.
+hipError_t launch_power_iteration(const LPDesc& d, bool fp64, int iters, unsigned long long seed, double* work,
+                                  double* est, hipStream_t st);
 hipError_t launch_gather_status(const LPDesc* lps, int count, int* out, hipStream_t st);
 hipError_t launch_time_limit(const LPDesc* lps, int count, hipStream_t st);
 hipError_t launch_to_f64(const void* src, bool fp64, double* dst, size_t len, hipStream_t st);

@@ -1854,8 +1854,18 @@ __global__ void k_normalize(const double* z, double* x, int len, const double* p
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < len; e += gridDim.x * blockDim.x) x[e] = nz > 0.0 ? z[e] / nz : 0.0;
 }
 
-__global__ void k_fill(double* x, int len, double v) {
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < len; e += gridDim.x * blockDim.x) x[e] = v;
+// Start vector of the power iteration: x[j] = 2u - 1 with u the top 53 bits
+// of output j of SplitMix64 (Steele, Lea and Flood, 2014) started at state
+// `seed`, i.e. the mix of seed + (j + 1) * 0x9E3779B97F4A7C15, as a fraction
+// of 2^53.
+__global__ void k_fill_start(double* x, int len, unsigned long long seed) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < len; e += gridDim.x * blockDim.x) {
+    unsigned long long z = seed + ((unsigned long long)e + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    x[e] = 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
+  }
 }
 
 // Copy the status word of every LP of a launch table into out[].
@@ -2103,8 +2113,8 @@ hipError_t launch_scaling(const ScalingArgs& s, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_power_iteration(const LPDesc& d, bool fp64, int iters, double* work, double* est,
-                                  hipStream_t st) {
+hipError_t launch_power_iteration(const LPDesc& d, bool fp64, int iters, unsigned long long seed, double* work,
+                                  double* est, hipStream_t st) {
   // work: v[n], z[n], w[m], part[1024]
   const int n = d.n, m = d.m;
   double* v = work;
@@ -2114,7 +2124,7 @@ hipError_t launch_power_iteration(const LPDesc& d, bool fp64, int iters, double*
   const int nparts = 1024;
   const int gridv = 1024;
   const int gridr = 2048;
-  hipLaunchKernelGGL(k_fill, dim3(gridv), dim3(BLOCK), 0, st, v, n, 1.0);
+  hipLaunchKernelGGL(k_fill_start, dim3(gridv), dim3(BLOCK), 0, st, v, n, seed);
   hipLaunchKernelGGL(k_sqnorm_part, dim3(nparts), dim3(BLOCK), 0, st, (const double*)v, n, part);
   hipLaunchKernelGGL(k_normalize, dim3(gridv), dim3(BLOCK), 0, st, (const double*)v, v, n, (const double*)part, nparts, est, 0);
   for (int it = 0; it < iters; ++it) {

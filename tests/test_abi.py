@@ -105,4 +105,4 @@ def test_method_option_defaults():
     import paper_2508_08062_amd as P
     o = P.default_options()
     assert (o.pw_period, o.pw_theta, o.pw_eps_zero, o.pw_omega0, o.pw_rho, o.pw_dhat) == (0, 0.5, 1e-10, 0.0, 0.0, 1)
-    assert (o.sg_div, o.restart_period, o.prep_device, o.pock_chambolle, o.angle_mode) == (1.0, 75, 2, 0, 0)
+    assert (o.sg_div, o.restart_period, o.prep_device, o.pock_chambolle, o.angle_mode, o.seed) == (1.0, 75, 2, 0, 0, 0)

@@ -74,3 +74,40 @@ def test_matrix_without_entries(loop_kernel):
     assert r["primal_obj"] == pytest.approx(-1.0 - 8.0 + 0.0 - 0.25, abs=1e-9)
     np.testing.assert_allclose(r["y"], 0.0, atol=1e-12)
     s.close()
+
+
+def _cycle_difference_lp(m, c):
+    # rows x_i - x_{i+1 mod m} = 0: every row sums to zero (K 1 = 0), ||K||_2 = 2 for even m
+    K = np.eye(m) - np.roll(np.eye(m), 1, axis=1)
+    rows, cols = np.nonzero(K)
+    rowptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=m), out=rowptr[1:])
+    return lpgen.LPData(m=m, n=m, rowptr=rowptr, colidx=cols.astype(np.int32), val=K[rows, cols],
+                        c=np.asarray(c, float), q=np.zeros(m), l=np.zeros(m), u=np.full(m, 10.0),
+                        rowtype=np.zeros(m, dtype=np.uint8))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_step_size_when_the_rows_of_K_sum_to_zero(precision):
+    """The power iteration starts from the SplitMix64 vector, not a constant
+    one (orthogonal to every singular vector of this K with a nonzero
+    singular value): tau = 0.9 / ||K||_2 = 0.45, and the solve reaches the
+    closed-form optimum (all x_i equal, at the bound the cost pushes them to)."""
+    m = 16  # 200 power steps reach ||K|| to 1e-8 here (the gap closes as m grows)
+    for c, xstar in ((np.ones(m), 0.0), (-np.ones(m), 10.0)):
+        s = P.Solver(_cycle_difference_lp(m, c), precision=precision, tol=1e-6, kkt_every=8, max_iter=20000)
+        assert s.dims()["tau"] == pytest.approx(0.45, rel=1e-5)
+        s.solve()
+        r = s.result()
+        assert r["status"] == "converged"
+        np.testing.assert_allclose(r["x"], xstar, atol=1e-3)
+        s.close()
+
+
+def test_power_iteration_seed():
+    lp = lpgen.tiny_lp(3)
+    nrm = oracle.power_norm(oracle.Problem.from_lpdata(lp), iters=5000, rtol=1e-14)
+    for seed in (0, 12345):
+        s = P.Solver(lp, precision=1, seed=seed, power_iters=2000)
+        assert s.dims()["tau"] == pytest.approx(0.9 / nrm, rel=1e-6)
+        s.close()

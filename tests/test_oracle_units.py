@@ -462,3 +462,40 @@ def test_ruiz_then_pock_chambolle_composes():
     Kd = lpgen.to_dense(lp)
     np.testing.assert_allclose(S2.K.toarray(), (r1 * r2)[:, None] * Kd * (c1 * c2)[None, :], rtol=1e-12, atol=1e-15)
     assert np.linalg.norm(S2.K.toarray(), 2) <= 1.0 + 1e-12
+
+
+# ---------------------------------------------------------------------------
+# power-iteration start vector (step size 0.9 / ||K||_2, Section 5.1)
+# ---------------------------------------------------------------------------
+
+def test_splitmix64_published_outputs():
+    g = golden("splitmix64.json")
+    want = [int(h, 16) for h in g["outputs_hex"]]
+    got = [int(v) for v in oracle.splitmix64(g["seed"], len(want))]
+    assert got == want
+
+
+def test_power_start_is_uniform_on_minus_one_one():
+    v = oracle.power_start(200000, seed=7)
+    assert v.min() >= -1.0 and v.max() < 1.0
+    assert abs(v.mean()) < 0.01 and abs(v.var() - 1.0 / 3.0) < 0.01
+    assert not np.array_equal(v, oracle.power_start(200000, seed=8))
+
+
+def _cycle_difference_lp(m, c):
+    """Rows x_i - x_{i+1 mod m} = 0: every row of K sums to zero, so the
+    constant vector is in its null space; K = I - P (P the cyclic shift) has
+    eigenvalues 1 - w^k, so ||K||_2 = 2 for even m."""
+    K = np.eye(m) - np.roll(np.eye(m), 1, axis=1)
+    return lp_from_dense(K, np.zeros(m), c, [0.0] * m, [10.0] * m, [0] * m)
+
+
+def test_power_norm_finds_the_norm_where_a_constant_start_sees_nothing():
+    Po = oracle.Problem.from_lpdata(_cycle_difference_lp(6, np.ones(6)))
+    assert oracle.power_norm(Po, v0=np.ones(6)) == 0.0  # K 1 = 0
+    assert oracle.power_norm(Po) == pytest.approx(2.0, rel=1e-8)
+    s = oracle.Solver(Po, oracle.Options(tol=1e-8, max_iter=20000, kkt_every=1))
+    assert s.opt.tau == pytest.approx(0.45, rel=1e-8)
+    r = s.solve()
+    assert r["status"] == "converged"
+    np.testing.assert_allclose(r["x"], 0.0, atol=1e-6)  # all equal (K x = 0), at the bound c pushes to
