@@ -94,3 +94,23 @@ def test_batch_of_uneven_lps_equals_solo():
         assert r["status"] == ref["status"] and r["iters"] == ref["iters"]
         assert np.array_equal(r["x"], ref["x"])
     b.close()
+
+
+def test_batch_of_mixed_methods_equals_solo():
+    """Every member of one batch runs its own method and options (each LP has
+    its own descriptor): vanilla PDHG, AA-PDHG, FAA-PDHG under both angle
+    filter readings, restarted PDHG and AA-PDHG with the primal-weight
+    update share the launches, and each result equals the LP's solo run bit
+    for bit."""
+    lps = _lps(6, 11)
+    methods = [dict(variant=0), dict(variant=1), dict(variant=2, cs=0.5), dict(variant=2, cs=0.5, angle_mode=1),
+               dict(variant=3, restart_period=40), dict(variant=1, pw_period=64, sg_div=2.0)]
+    solo = [_solo(lp, **mth) for lp, mth in zip(lps, methods)]
+    members = [P.Solver(lp, **{**OPTS, **mth}) for lp, mth in zip(lps, methods)]
+    b = P.Batch(members)
+    b.solve()
+    for g, ref, mth in zip(members, solo, methods):
+        r = g.result()
+        assert (r["status"], r["iters"], r["aa_steps"]) == (ref["status"], ref["iters"], ref["aa_steps"]), mth
+        assert np.array_equal(r["x"], ref["x"]) and np.array_equal(r["y"], ref["y"]), mth
+    b.close()
