@@ -259,19 +259,19 @@ def _batch_solve(args):
         # with the passes each LP took on the GPU
         est = cb["seconds_per_nnz_pass"] * float(sum(lps[i].nnz * r["iters"] for i, r in enumerate(res)))
         cb["sample_lps_per_s"] = cb["value"]
-        cb["value"] = len(lps) / est  # the batch on one core, scaled from the sample
+        cb["value"] = conv / est  # the batch on one core, scaled from the sample (converged LPs only)
         cb["sample"] += (f"; scaled to the batch: {est:.0f} s for its {len(lps)} LPs at the sample's seconds per "
                          "nonzero-pass and the passes each LP took on the GPU")
         extra_cpu = {"cpu_baseline": cb}
-    line = _line("LPs solved/s at rel KKT 1e-4 (batched float32)", len(lps) / el, "LPs/s",
+    line = _line("LPs solved/s at rel KKT 1e-4 (batched float32)", conv / el, "LPs/s",
                  {**cfg, "lps": len(lps), "nnz_total": nnz_all},
-                 {"batch_seconds": el, "converged": int(conv), "iters_median": float(np.median(iters)),
+                 {"batch_seconds": el, "converged": int(conv), "lps_stopped_per_s": len(lps) / el, "iters_median": float(np.median(iters)),
                   "iters_max": int(iters.max()),
                   "completion_p50_s": float(np.percentile(done_s, 50)),
                   "completion_p99_s": float(np.percentile(done_s, 99)),
                   "lps_done_by_p50_per_s": 0.5 * len(lps) / float(np.percentile(done_s, 50)),
                   "fp64_single": {"sample": sample, "seconds": t64, "iters": it64, "nnz_sample": nnz_s,
-                                  "lps_per_s_estimate": len(lps) / est64,
+                                  "lps_per_s_estimate": conv / est64,
                                   "estimate": "sample seconds scaled by nnz x iterations to all LPs"},
                   **extra_cpu},
                  ms=el * 1e3)
@@ -430,12 +430,12 @@ def _serve(args, rate=None, seconds=None, pool_size=None, drain=None, emit=True)
     srv.close()
     d = np.array([x[0] for x in lat])
     conv = sum(x[1] == "converged" for x in lat)
-    line = _line("LPs solved/s & p99 latency at rel KKT 1e-4 (served float32)", len(lat) / el, "LPs/s",
+    line = _line("LPs solved/s & p99 latency at rel KKT 1e-4 (served float32)", conv / el, "LPs/s",
                  {"workload": f"Poisson stream {rate}/s for {seconds} s (serving_requests seed 4), "
                               f"columns lognormal(ln 20000, 1) in [1k, 500k], rows 0.4 x columns, 5 nnz/column; "
                               f"{len(pool)} distinct LPs cycled", "variant": "AA-PDHG", "m_A": 10},
                  {"requests": len(reqs), "finished": len(lat), "unfinished": len(pending), "converged": int(conv),
-                  "seconds": el,
+                  "seconds": el, "finished_per_s": len(lat) / el,
                   "latency_p50_s": float(np.percentile(d, 50)) if d.size else None,
                   "latency_p99_s": float(np.percentile(d, 99)) if d.size else None,
                   "latency_max_s": float(d.max()) if d.size else None, "server": st})

@@ -302,6 +302,12 @@ aapdhg_status aapdhg_batch_solve(aapdhg_batch_t b, void *stream);
 aapdhg_status aapdhg_batch_iterate(aapdhg_batch_t b, void *stream, int64_t iters);
 /* Measurement variant of aapdhg_batch_iterate (see aapdhg_iterate_timed). */
 aapdhg_status aapdhg_batch_iterate_timed(aapdhg_batch_t b, void *stream, int64_t iters, double *ms4);
+/* Result of member i (0 <= i < count, in the order given to aapdhg_batch_create): the same
+ * as aapdhg_result on that member's handle (waits for the device; caller-owned host buffers
+ * x[n_i], y[m_i], lambda[n_i], any may be NULL).  AAPDHG_E_ARG for an index out of range,
+ * with the text on the calling thread (aapdhg_last_error(NULL)). */
+aapdhg_status aapdhg_batch_result(aapdhg_batch_t b, int32_t i, double *x, double *y, double *lambda,
+                                  aapdhg_info *info);
 aapdhg_status aapdhg_batch_destroy(aapdhg_batch_t b);
 
 /* ---- serving: continuous batching of LP requests ----

@@ -62,7 +62,7 @@ EXPORTS = [
     "aapdhg_get_weights", "aapdhg_set_weights",
     "aapdhg_get_dims", "aapdhg_get_scaling",
     "aapdhg_destroy", "aapdhg_last_error", "aapdhg_batch_create", "aapdhg_batch_solve",
-    "aapdhg_batch_iterate", "aapdhg_batch_iterate_timed", "aapdhg_batch_destroy", "aapdhg_server_start", "aapdhg_server_submit",
+    "aapdhg_batch_iterate", "aapdhg_batch_iterate_timed", "aapdhg_batch_result", "aapdhg_batch_destroy", "aapdhg_server_start", "aapdhg_server_submit",
     "aapdhg_server_poll", "aapdhg_server_stats", "aapdhg_server_stop",
 ]
 
@@ -105,6 +105,7 @@ def lib():
     L.aapdhg_batch_solve.argtypes = [_P, _P]
     L.aapdhg_batch_iterate.argtypes = [_P, _P, C.c_int64]
     L.aapdhg_batch_iterate_timed.argtypes = [_P, _P, C.c_int64, _dp]
+    L.aapdhg_batch_result.argtypes = [_P, C.c_int32, _dp, _dp, _dp, C.POINTER(Info)]
     L.aapdhg_batch_destroy.argtypes = [_P]
     L.aapdhg_server_start.argtypes = [C.c_size_t, C.c_int32, C.POINTER(Options), C.POINTER(_P)]
     L.aapdhg_server_submit.argtypes = [_P, C.c_int32, C.c_int32, C.c_int64, C.POINTER(C.c_int64),
@@ -374,8 +375,18 @@ class Batch:
         _check(lib().aapdhg_batch_iterate_timed(self.h, _stream(stream), int(iters), _ptr(ms, C.c_double)), None)
         return _timing(ms)
 
+    def result(self, i):
+        """Member i's result (aapdhg_batch_result)."""
+        s = self.solvers[i] if 0 <= i < len(self.solvers) else None
+        x, y, lam = (np.empty(s.n), np.empty(s.m), np.empty(s.n)) if s else (None, None, None)
+        info = Info()
+        _check(lib().aapdhg_batch_result(self.h, int(i), _ptr(x, C.c_double) if s else None,
+                                         _ptr(y, C.c_double) if s else None, _ptr(lam, C.c_double) if s else None,
+                                         C.byref(info)), None)
+        return {"x": x, "y": y, "lam": lam, **info.to_dict()}
+
     def results(self):
-        return [s.result() for s in self.solvers]
+        return [self.result(i) for i in range(len(self.solvers))]
 
     def close(self):
         if getattr(self, "h", None):

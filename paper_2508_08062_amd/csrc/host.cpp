@@ -1762,6 +1762,16 @@ aapdhg_status aapdhg_batch_iterate_timed(aapdhg_batch_t b, void* stream, int64_t
   });
 }
 
+aapdhg_status aapdhg_batch_result(aapdhg_batch_t b, int32_t i, double* x, double* y, double* lambda,
+                                  aapdhg_info* info) {
+  if (!b) return AAPDHG_E_ARG;
+  if (i < 0 || i >= (int32_t)b->members.size()) {
+    g_thread_error = "batch member index out of range";
+    return AAPDHG_E_ARG;
+  }
+  return aapdhg_result(b->members[i], x, y, lambda, info);
+}
+
 aapdhg_status aapdhg_batch_destroy(aapdhg_batch_t b) {
   if (!b) return AAPDHG_E_ARG;
   (void)hipDeviceSynchronize();

@@ -109,8 +109,9 @@ def test_batch_of_mixed_methods_equals_solo():
     members = [P.Solver(lp, **{**OPTS, **mth}) for lp, mth in zip(lps, methods)]
     b = P.Batch(members)
     b.solve()
-    for g, ref, mth in zip(members, solo, methods):
-        r = g.result()
+    for r, ref, mth in zip(b.results(), solo, methods):  # aapdhg_batch_result
         assert (r["status"], r["iters"], r["aa_steps"]) == (ref["status"], ref["iters"], ref["aa_steps"]), mth
         assert np.array_equal(r["x"], ref["x"]) and np.array_equal(r["y"], ref["y"]), mth
+    with pytest.raises(P.AAPDHGError, match="out of range"):
+        b.result(len(members))
     b.close()
