@@ -1,9 +1,10 @@
 """GPU checks at the benchmark's full sizes and launch configurations.
 
 After a benchmark-sized launch (the 20k x 50k LP: one persistent launch of
-500 loop passes; the 1M x 2M LP: 250 passes of the three-launch kernels), the
-device state must agree with the oracle evaluated on the same seeded,
-equilibrated, float32-rounded LP:
+500 loop passes; the 1M x 2M LP: 250 passes of the three-launch kernels; the
+256-LP batch: 200 passes of its launch set, sampled members), the device
+state must agree with the oracle evaluated on the same seeded, equilibrated,
+float32-rounded LP:
 
   * the last PDHG point: u_prev + g_prev equals the oracle's T(u_prev)
     (eq. pdhg) element by element, to relative 1e-5 of the vector's norm
@@ -105,3 +106,28 @@ def test_powerlaw1m_after_250_three_launch_passes():
     assert st["k"] == 251 and st["status"] == 4
     _check_state(lp, Po, g, tau, sigma, st, 10)
     g.close()
+
+
+@pytest.mark.timeout(300)
+def test_batch256_after_200_passes_of_the_whole_batch():
+    """The batch workload at full size (256 LPs, 44.6M entries) advanced by
+    the launches of one launch set; the state of sampled members (the
+    first, a middle one, the last and the largest) is checked as above
+    against the oracle on that member's own scaled LP, with the member's
+    own step sizes."""
+    lps = lpgen.batch_lps(256, 3)
+    opts = dict(variant=1, precision=0, memory=8, kkt_every=64, ruiz_iters=10, dhat_mode=0)
+    members = [P.Solver(lp, tol=0.0, max_iter=10 ** 9, **opts) for lp in lps]
+    b = P.Batch(members)
+    b.iterate(200)  # a member that has not started takes its init step first: k = 201
+    big = int(np.argmax([lp.nnz for lp in lps]))
+    for i in sorted({0, 128, 255, big}):
+        g = members[i]
+        st = g.get_state()
+        assert st["k"] == 201 and st["status"] == 4, i
+        d = g.dims()
+        Po = _scaled_oracle_problem(lps[i], 10)
+        _check_state(lps[i], Po, g, d["tau"], d["sigma"], st, 8)
+    b.close()
+    for g in members:
+        g.close()
