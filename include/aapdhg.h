@@ -26,7 +26,9 @@
  *     a message readable with aapdhg_last_error().
  *   - "host" arrays are ordinary CPU memory owned by the caller; the library
  *     copies what it needs before returning and never keeps the pointer.
- *   - Device memory is owned by the library from create to destroy.
+ *     aapdhg_create_device and aapdhg_result_device take caller-owned device
+ *     memory instead (for example torch tensors), under the same rule.
+ *   - The library's own device memory is owned by it from create to destroy.
  *   - A stream argument is a hipStream_t passed as void*; NULL means the
  *     default stream.  A handle is used by one host thread at a time.
  *   - Not converging is not an error: it is reported in aapdhg_info.term.
