@@ -149,6 +149,39 @@ def test_difference_form_equals_alg1_alpha_form():
         assert np.allclose(u_k, us[-2])
 
 
+def test_difference_form_equals_alpha_form_with_dhat_and_damping():
+    """The same equivalence with a mixing matrix: for D-hat != I (literal
+    reading on a dense K with uneven magnitudes) and beta = 0.7, the AA step
+    must equal sum_i alpha_i (u^i + beta D-hat g^i), the type-II Anderson
+    step with mixing beta D-hat written in Alg 1's constrained form."""
+    rng = np.random.default_rng(11)
+    m, n = 5, 8
+    K = rng.standard_normal((m, n)) * rng.uniform(0.1, 10.0, (m, 1)) * rng.uniform(0.1, 10.0, (1, n))
+    lp = lp_from_dense(K, rng.standard_normal(m), rng.standard_normal(n),
+                       ["-inf"] * n, ["inf"] * n, [0] * m)
+    P = oracle.Problem.from_lpdata(lp)
+    nrm = np.linalg.norm(K, 2)
+    mem, beta = 3, 0.7
+    s = oracle.Solver(P, oracle.Options(tau=0.5 / nrm, sigma=0.5 / nrm, memory=mem, D=1e300,
+                                        eta=0.0, dhat_mode=1, beta=beta, kkt_every=0))
+    D = s.Dhat
+    assert np.ptp(D) > 1.0  # a genuinely non-identity D-hat
+    s.start()
+    us = [s.state.u_prev, np.r_[s.state.x, s.state.y]]
+    gs = [s.state.g_prev]
+    for _ in range(6):
+        s.step()
+        assert s.last_branch == "aa"
+        gs.append(s.state.g_prev)
+        mk = min(mem, len(gs) - 1)
+        window = list(range(len(gs) - 1 - mk, len(gs)))
+        alpha = _alg1_alpha([gs[t] for t in window])
+        expect = sum(a * (us[t] + beta * D * gs[t]) for a, t in zip(alpha, window))
+        got = np.r_[s.state.x, s.state.y]
+        np.testing.assert_allclose(got, expect, rtol=1e-7, atol=1e-9)
+        us.append(got)
+
+
 # ---------------------------------------------------------------------------
 # vanilla PDHG: firm non-expansiveness (Thm th:pdhg-residual-0)
 # ---------------------------------------------------------------------------
@@ -264,6 +297,42 @@ def test_length_bounds_dominate_columns_of_R_inverse(seed):
     col_sq = np.sum(Rinv ** 2, axis=0)
     assert np.all(col_sq <= b * (1 + 1e-10))
     assert col_sq[0] == pytest.approx(b[0], rel=1e-10)  # b_1 is exact
+
+
+@pytest.mark.parametrize("cs", [0.2, 0.5])
+def test_length_bounds_hold_on_extremal_angles(cs):
+    """Three unit columns, each at exactly the smallest allowed sine cs from
+    the span of the ones before it, with the off-diagonal part of the third
+    turned by theta: R = [[1, ct, -ct sin t], [0, cs, ct cos t], [0, 0, cs]].
+    The squared norm of column 3 of R^{-1} then reaches 83% (cs = 0.2) and
+    69% (cs = 0.5) of b_3, so the bound is checked where it is close to
+    tight."""
+    ct = math.sqrt(1.0 - cs * cs)
+    worst = 0.0
+    for t in np.linspace(-np.pi, np.pi, 721):
+        F = np.array([[1.0, ct, -ct * math.sin(t)], [0.0, cs, ct * math.cos(t)], [0.0, 0.0, cs]])
+        _, R = np.linalg.qr(F)
+        col_sq = np.sum(np.linalg.inv(R) ** 2, axis=0)
+        b = oracle.length_bounds(np.linalg.norm(F, axis=0), cs)
+        assert np.all(col_sq <= b * (1 + 1e-12))
+        worst = max(worst, col_sq[2] / b[2])
+    assert worst > 0.5  # the construction does press on the bound
+
+
+@pytest.mark.parametrize("cs", [0.2, 0.5, 0.9])
+def test_length_bound_b2_is_attained(cs):
+    """The second bound is tight: with r_11 = ||f_1||, r_12 = ct ||f_2|| and
+    r_22 = cs ||f_2|| (ct = sqrt(1 - cs^2), the largest off-diagonal entry the
+    angle condition allows), column 2 of R^{-1} has squared norm
+    ct^2 / (cs^2 ||f_1||^2) + 1 / (cs^2 ||f_2||^2), which the bound must equal.
+    The inverse is taken numerically from the constructed columns."""
+    f1, f2 = 3.0, 0.25
+    ct = math.sqrt(1.0 - cs * cs)
+    F = np.array([[f1, ct * f2], [0.0, cs * f2], [0.0, 0.0]])
+    _, R = np.linalg.qr(F)
+    col2 = float(np.sum(np.linalg.inv(R)[:, 1] ** 2))
+    b = oracle.length_bounds(np.linalg.norm(F, axis=0), cs)
+    assert b[1] == pytest.approx(col2, rel=1e-12)
 
 
 @pytest.mark.parametrize("seed", range(5))
