@@ -202,9 +202,13 @@ class Solver:
                     options: Options | None = None, **kw):
         """Create from device tensors (torch, contiguous): rowptr int64[m+1],
         colidx int32[nnz], val/c/q/l/u float64, rowtype uint8[m]
-        (aapdhg_create_device)."""
+        (aapdhg_create_device).  The copies run on `stream`, by default
+        torch's current stream, so they follow the work that produced the
+        tensors."""
         import torch
         L = lib()
+        if stream is None:
+            stream = torch.cuda.current_stream()
         opt = options if options is not None else default_options(**kw)
         ts = (rowptr, colidx, val, c, q, l, u, rowtype)
         want = (torch.int64, torch.int32, torch.float64, torch.float64, torch.float64, torch.float64,
@@ -228,8 +232,11 @@ class Solver:
 
     def result_device(self, stream=None):
         """x, y, lambda as float64 CUDA tensors written by the library
-        (aapdhg_result_device), and the info dictionary."""
+        (aapdhg_result_device) on `stream` (by default torch's current
+        stream, where they were allocated), and the info dictionary."""
         import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
         x = torch.empty(self.n, dtype=torch.float64, device="cuda")
         y = torch.empty(self.m, dtype=torch.float64, device="cuda")
         lam = torch.empty(self.n, dtype=torch.float64, device="cuda")
