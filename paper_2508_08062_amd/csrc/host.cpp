@@ -845,6 +845,7 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
   for (auto* p : lps) ext |= p->opt.pw_period > 0 || p->opt.variant == AAPDHG_VARIANT_RPDHG;
   const int cap = want ? loop_capacity(lps[0]->fp64, mt, ext) : 0;
   const bool persist = cap >= count && need <= 2LL * cap;
+
   int parts = 0;
   // per LP and pass: chunks, split rows, workgroups; leaves are the
   // workgroups followed by the split rows
@@ -883,7 +884,15 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
       }
       const int nch = (int)pc.size();
       int cpb = p->opt.chunks_per_block;
-      if (cpb <= 0) cpb = std::max(1, (nch + 1023) / 1024);
+      if (cpb <= 0) {
+        // group the LP's chunks so that its workgroups of the pass fit on the
+        // device at once, in one round (the pass B kernel holds fewer per CU);
+        // the count depends on the LP's own options only, so the LP's
+        // reduction order is the same alone and in any batch
+        int pcap = pass_capacity(p->fp64, p->opt.memory, pass);
+        if (pcap <= 0) pcap = 1024;
+        cpb = std::max(1, (nch + pcap - 1) / pcap);
+      }
       if (persist) cpb = 1;
       // workgroups: runs of up to cpb multi-row chunks (leaves, listed first),
       // then one workgroup per split-row part (no leaf of their own)

@@ -54,6 +54,9 @@ hipError_t launch_loop_pass(const LaunchTables& t, hipStream_t st, int mode, hip
 hipError_t launch_loop(const LaunchTables& t, hipStream_t st, long long passes, unsigned int tag0);
 // Workgroups of the persistent loop kernel that fit on the device at once.
 int loop_capacity(bool fp64, int mt, bool ext);
+// Workgroups of pass A (pass 0) or pass B (pass 1) of the three-launch path
+// that the device holds at once (0 if the query fails).
+int pass_capacity(bool fp64, int mt, int pass);
 hipError_t launch_start_point(const LPDesc& d, bool fp64, hipStream_t st);
 
 // Scaling of K before the solve: ruiz_iters Ruiz sweeps, then (pock_chambolle)

@@ -1951,6 +1951,24 @@ static const void* loop_kernel_for(bool fp64, int mt, bool ext) {
   return ext ? loop_kernel_mt<float, true>(mt) : loop_kernel_mt<float, false>(mt);
 }
 
+template <typename T, int PASS>
+static const void* pass_kernel_mt(int mt) {
+  if (mt <= 4) return reinterpret_cast<const void*>(&k_pass<T, 4, PASS>);
+  if (mt <= 8) return reinterpret_cast<const void*>(&k_pass<T, 8, PASS>);
+  if (mt <= 10) return reinterpret_cast<const void*>(&k_pass<T, 10, PASS>);
+  return reinterpret_cast<const void*>(&k_pass<T, 16, PASS>);
+}
+
+int pass_capacity(bool fp64, int mt, int pass) {
+  int dev = 0, cus = 0, nb = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  const void* k = fp64 ? (pass == 0 ? pass_kernel_mt<double, 0>(mt) : pass_kernel_mt<double, 1>(mt))
+                       : (pass == 0 ? pass_kernel_mt<float, 0>(mt) : pass_kernel_mt<float, 1>(mt));
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, BLOCK, 0) != hipSuccess) return 0;
+  return nb * cus;
+}
+
 int loop_capacity(bool fp64, int mt, bool ext) {
   int dev = 0, cus = 0, coop = 0, nb = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
