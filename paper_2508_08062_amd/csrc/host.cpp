@@ -845,7 +845,6 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
   for (auto* p : lps) ext |= p->opt.pw_period > 0 || p->opt.variant == AAPDHG_VARIANT_RPDHG;
   const int cap = want ? loop_capacity(lps[0]->fp64, mt, ext) : 0;
   const bool persist = cap >= count && need <= 2LL * cap;
-
   int parts = 0;
   // per LP and pass: chunks, split rows, workgroups; leaves are the
   // workgroups followed by the split rows
