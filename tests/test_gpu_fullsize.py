@@ -4,7 +4,8 @@ After a benchmark-sized launch (the 20k x 50k LP: one persistent launch of
 500 loop passes; the 1M x 2M LP: 250 passes of the three-launch kernels; the
 256-LP batch: 200 passes of its launch set, sampled members), the device
 state must agree with the oracle evaluated on the same seeded, equilibrated,
-float32-rounded LP:
+float32-rounded LP (requests of the serving mix are checked at their
+solution instead, after going through the server):
 
   * the last PDHG point: u_prev + g_prev equals the oracle's T(u_prev)
     (eq. pdhg) element by element, to relative 1e-5 of the vector's norm
@@ -21,6 +22,8 @@ float32-rounded LP:
   * the counters add up (i + j = k - 1), the iterate lies in X x Y, and the
     KKT residuals reported at the returned point equal the oracle's there.
 """
+import time
+
 import numpy as np
 import pytest
 
@@ -130,4 +133,47 @@ def test_batch256_after_200_passes_of_the_whole_batch():
         _check_state(lps[i], Po, g, d["tau"], d["sigma"], st, 8)
     b.close()
     for g in members:
+        g.close()
+
+
+@pytest.mark.timeout(300)
+def test_serving_mix_requests_through_the_server():
+    """Requests of the serving workload's pool (Poisson stream seed 4: the
+    largest, 96,675 columns and 483,375 entries, and two typical ones) go
+    through the server with the workload's options, submitted together; each
+    result equals the LP's solo solve bit for bit, and the KKT residuals the
+    server reports equal the oracle's at the returned point on the LP's
+    scaled, float32-rounded problem."""
+    reqs = lpgen.serving_requests(rate=4.0, duration=10.0, seed=4)[:16]
+    pick = [5, 0, 6]
+    lps = [lpgen.mip_like_lp(reqs[i][4], m=reqs[i][1], n=reqs[i][2], nnz=reqs[i][3]) for i in pick]
+    opts = dict(variant=1, precision=0, memory=10, kkt_every=64, ruiz_iters=10, dhat_mode=0, tol=1e-4,
+                max_iter=200000, epoch=64)
+    srv = P.Server(hbm_budget_bytes=8 << 30, max_slots=64, **opts)
+    tickets = [srv.submit(lp) for lp in lps]
+    served = {}
+    deadline = time.monotonic() + 240.0
+    while len(served) < len(tickets):
+        assert time.monotonic() < deadline, "served requests did not finish"
+        for t in tickets:
+            if t not in served:
+                r = srv.poll(t)
+                if r is not None:
+                    served[t] = r
+        time.sleep(0.01)
+    srv.close()
+    for lp, t in zip(lps, tickets):
+        r = served[t]
+        g = P.Solver(lp, **opts)
+        g.solve()
+        ref = g.result()
+        assert r["status"] == ref["status"] == "converged"
+        assert r["iters"] == ref["iters"] and r["kkt"] == ref["kkt"]
+        assert np.array_equal(r["x"], ref["x"]) and np.array_equal(r["y"], ref["y"])
+        d_row, d_col = g.scaling()
+        Po = _scaled_oracle_problem(lp, 10)
+        ko = oracle.kkt(Po, r["x"] / d_col, r["y"] / d_row)
+        for key, gkey in (("r_p", "r_pri"), ("r_d", "r_dual"), ("r_g", "r_gap")):
+            assert ref[gkey] == pytest.approx(ko[key], rel=1e-5, abs=1e-9), key
+        assert ko["kkt"] <= 1.01e-4
         g.close()
