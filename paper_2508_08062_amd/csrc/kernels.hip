@@ -760,6 +760,48 @@ struct PassCtx {
   // CACHED: the chunk's column indices (cidx), this thread's original row
   // (crow) and its row's range in the chunk (ca0, ca1) come from LDS, where
   // the persistent kernel keeps the one chunk a workgroup owns.
+  // Pass B of an LP with column panels (three-launch path): the row sums come
+  // from k_panel, so each chunk of the run is BLOCK rows, one per thread, with
+  // no matrix work.  RB chunks are loaded together (their loads in flight at
+  // once) and then finished in chunk order, so each thread adds its rows'
+  // dots in the same order as one chunk at a time.
+  template <int RB>
+  __device__ __forceinline__ void panel_rows(const Chunk* chunks, int c0, int c1, double* acc) const {
+    const int tid = threadIdx.x;
+    const int m = dp->m;
+    for (int c = c0; c < c1; c += RB) {
+      RowIn<T, MT> rin[RB];
+      double s1[RB], s2[RB];
+      int row[RB];
+      bool has[RB];
+#pragma unroll
+      for (int j = 0; j < RB; ++j) {
+        s1[j] = 0.0;
+        s2[j] = 0.0;
+        row[j] = 0;
+        has[j] = false;
+        if (c + j < c1) {
+          const Chunk ch = chunks[c + j];
+          const int r = ch.r0 + tid;
+          has[j] = r < ch.r1;
+          if (has[j]) {
+            row[j] = rmap[r];
+            load_row(row[j], rin[j], false);
+#pragma unroll
+            for (int p = 0; p < PANELS; ++p) s1[j] += dp->part[(size_t)p * m + r];
+            if (two) {
+#pragma unroll
+              for (int p = 0; p < PANELS; ++p) s2[j] += dp->part[(size_t)(PANELS + p) * m + r];
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < RB; ++j)
+        if (has[j]) finish_row(row[j], rin[j], s1[j], s2[j], acc, false);
+    }
+  }
+
   template <bool CACHED>
   __device__ __forceinline__ void multi_chunk(const Chunk& ch, double* acc, double* s_prod, double* s_tmp,
                                               const int* cidx = nullptr, const int* crow = nullptr,
@@ -1061,10 +1103,15 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
 #pragma unroll
   for (int q = 0; q < DT::COUNT; ++q) acc[q] = 0.0;
   bool lane0 = true;  // every chunk of the unit has one row per wave or workgroup
-  for (int c = bw.c0; c < bw.c1; ++c) {
-    const Chunk ch = a.chunks[c];
-    lane0 &= ch.tpr >= 64;
-    P.template multi_chunk<false>(ch, acc, s_prod, s_tmp);
+  if (PASS == 1 && dp->panels) {
+    P.template panel_rows<2>(a.chunks, bw.c0, bw.c1, acc);
+    lane0 = false;
+  } else {
+    for (int c = bw.c0; c < bw.c1; ++c) {
+      const Chunk ch = a.chunks[c];
+      lane0 &= ch.tpr >= 64;
+      P.template multi_chunk<false>(ch, acc, s_prod, s_tmp);
+    }
   }
   write_record<MT>(acc, s_red, a.rec + (size_t)bw.leaf * NDOT, lane0, s_prod);
   if (PASS == 1 && climb(bw.parent)) finish_lp();
