@@ -57,7 +57,7 @@ def build(verbose: bool = True) -> str:
         _run(cmd)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"])
+    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread", "-lrocprofiler-sdk-roctx"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -323,6 +323,7 @@ Problem::~Problem() = default;
 void Problem::create(int32_t m_, int32_t n_, int64_t nnz_, const int64_t* row_ptr, const int32_t* col_idx,
                      const double* val_, const double* c_, const double* q_, const double* l_, const double* u_,
                      const uint8_t* row_type, const aapdhg_options* opt_) {
+  TraceRange tr("aapdhg create");
   if (opt_) opt = *opt_; else default_options(&opt);
   check_options(opt);
   if (m_ < 1 || n_ < 1) throw Error(AAPDHG_E_ARG, "m and n must be >= 1 (m=%d n=%d)", m_, n_);
@@ -1173,6 +1174,7 @@ void LaunchSet::enqueue_eval(hipStream_t st) { hip_check(launch_loop_pass(t, st,
 // while epoch e+1 is already queued, so the device does not wait for the host.
 double LaunchSet::run_to_completion(hipStream_t st, int epoch, double time_limit_s, int compact_below,
                                     const std::chrono::steady_clock::time_point* t0p) {
+  TraceRange tr("aapdhg solve");
   const auto t0 = t0p ? *t0p : std::chrono::steady_clock::now();
   compacted = false;
   const int count = t.nlps;
@@ -1186,6 +1188,7 @@ double LaunchSet::run_to_completion(hipStream_t st, int epoch, double time_limit
   int64_t epochs = 0;
   finish_s.assign(count, -1.0);
   while (!done) {
+    roctxMark("aapdhg epoch");
     enqueue_passes(st, epoch);
     hip_check(launch_gather_status(t.lps, count, (int*)d_status.p, st), "status gather");
     hip_check(hipMemcpyAsync(h_status + slot * MAX_STATUS, d_status.p, count * 4, hipMemcpyDeviceToHost, st), "status copy");

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <chrono>
 #include <memory>
@@ -39,6 +40,15 @@ struct DevBuf {
 };
 
 struct Problem;
+
+// A named host range for profilers (roctx; seen with rocprofv3 --marker-trace,
+// free when no tool is attached): create, solve and serving epochs.
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePush(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 // The device work tables of a set of LPs that advance in the same launches.
 struct LaunchSet {

@@ -155,6 +155,7 @@ void aapdhg_server::run() {
       }
       if (resident.empty()) continue;
       // ---- one epoch for every resident LP ----
+      TraceRange tr("aapdhg serving epoch");
       if (dirty) {
         std::vector<Problem*> ps;
         for (Request* r : resident) ps.push_back(r->prob.get());
