@@ -115,3 +115,39 @@ def test_batch_of_mixed_methods_equals_solo():
     with pytest.raises(P.AAPDHGError, match="out of range"):
         b.result(len(members))
     b.close()
+
+
+def _infeasible_lp():
+    # x0 + x1 = 1 and x0 + x1 = 3 with 0 <= x <= 10: no feasible point
+    return lpgen.LPData(m=2, n=2, rowptr=np.array([0, 2, 4], dtype=np.int64),
+                        colidx=np.array([0, 1, 0, 1], dtype=np.int32), val=np.ones(4), c=np.ones(2),
+                        q=np.array([1.0, 3.0]), l=np.zeros(2), u=np.full(2, 10.0),
+                        rowtype=np.zeros(2, dtype=np.uint8))
+
+
+def test_a_request_that_cannot_converge_does_not_disturb_the_others():
+    """An infeasible request shares the server's epochs with ordinary ones: it
+    ends at its pass limit while the others finish exactly as alone."""
+    lps = _lps(4, 13)
+    solo = [_solo(lp) for lp in lps]
+    srv = P.Server(hbm_budget_bytes=1 << 30, max_slots=8, **OPTS)
+    bad = srv.submit(_infeasible_lp())
+    tickets = [srv.submit(lp) for lp in lps]
+    results = {}
+    t0 = time.time()
+    while len(results) < len(tickets) + 1:
+        assert time.time() - t0 < 90, srv.stats()
+        for t in [bad] + tickets:
+            if t not in results:
+                r = srv.poll(t)
+                if r is not None:
+                    results[t] = r
+        time.sleep(0.001)
+    srv.close()
+    rb = results[bad]
+    assert rb["status"] == "iter_limit" and rb["iters"] == OPTS["max_iter"] + 1
+    assert np.all(np.isfinite(rb["x"])) and np.all(np.isfinite(rb["y"]))
+    for t, ref in zip(tickets, solo):
+        r = results[t]
+        assert r["status"] == ref["status"] and r["iters"] == ref["iters"]
+        assert np.array_equal(r["x"], ref["x"]) and np.array_equal(r["y"], ref["y"])
