@@ -96,6 +96,18 @@ def test_mip_like_fp32_trajectory_50(variant, loop_kernel):
     assert ctr[-1][0] == ctr[-1][1]
 
 
+@pytest.mark.parametrize("loop_kernel", [0, 1])
+def test_mip_like_fp32_trajectory_faa_refreshed_angle_filter(loop_kernel):
+    """FAA-PDHG in float32 with the refreshed angle filter (angle_mode 1)
+    and every step accelerated, so the filter runs on each pass."""
+    lp = lpgen.mip_like_lp(11, m=2000, n=5000, nnz=25000)
+    ug, uo, ctr, _, _ = _trajectories(lp, 50, precision=0, variant=2, memory=10, loop_kernel=loop_kernel,
+                                      angle_mode=1, cs=0.5, D=1e6)
+    errs = [_rel(a, b) for a, b in zip(ug, uo)]
+    assert max(errs) < 1e-5, (max(errs), int(np.argmax(errs)))
+    assert all(g == o for g, o in ctr), ctr
+
+
 def test_mip_like_fp64_trajectory_faa():
     lp = lpgen.mip_like_lp(12, m=1500, n=3500, nnz=20000, fp32=False)
     ug, uo, ctr, _, _ = _trajectories(lp, 50, precision=1, variant=2, memory=10)
