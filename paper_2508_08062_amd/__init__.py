@@ -6,8 +6,9 @@ this package does not load the library; the first call does, and it raises
 if the library is missing.  There is no CPU fallback.
 
 Entry points mirror include/aapdhg.h:  Solver (aapdhg_create/solve/iterate/
-result/get_state/set_state/destroy), Batch (aapdhg_batch_*), Server
-(aapdhg_server_*).
+result/get_state/set_state/get_weights/set_weights/destroy; from_device and
+result_device for torch CUDA tensors through aapdhg_create_device and
+aapdhg_result_device), Batch (aapdhg_batch_*), Server (aapdhg_server_*).
 """
 from __future__ import annotations
 
