@@ -131,6 +131,21 @@ def _hbm_bound_leg(stream, passes=100):
     return out
 
 
+def _host_cpu():
+    """The host the CPU baseline ran on: processor model and the cores this
+    process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "host_cores_usable": len(os.sched_getaffinity(0))}
+
+
 def _cpu_baseline(lps, opts, seconds):
     """The oracle on the host, one thread, on the first LP of the workload,
     for about `seconds` of loop passes; returns passes per second."""
@@ -195,7 +210,7 @@ def _cpu_batch_baseline(lps, opts, seconds):
     # seconds per nonzero-pass, applied to the batch's own passes would need its
     # iteration counts; report the sample and the LPs/s it reached
     n_conv = sum(1 for d in done if d[1] == "converged")
-    return {"value": n_conv / max(t_all, 1e-9), "unit": "LPs/s", "cores": 1, "kind": "oracle",
+    return {"value": n_conv / max(t_all, 1e-9), "unit": "LPs/s", "cores": 1, "kind": "oracle", **_host_cpu(),
             "sample": f"{len(done)} smallest members solved one after the other by the float64 oracle "
                       f"({n_conv} converged, {t_all:.1f} s, one thread): " +
                       ", ".join(f"LP {i} {st} in {k} passes, {el:.1f} s" for i, st, k, el in done),
@@ -627,7 +642,7 @@ def main():
 
     if not args.no_cpu_baseline and (args.workload != "powerlaw1m" or args.large_cpu_baseline):
         rate, k, el = _cpu_baseline(lps, opts, args.cpu_seconds)
-        line["cpu_baseline"] = {"value": rate, "unit": "iters/s", "cores": 1, "kind": "oracle",
+        line["cpu_baseline"] = {"value": rate, "unit": "iters/s", "cores": 1, "kind": "oracle", **_host_cpu(),
                                 "sample": f"{k} loop passes of the float64 oracle on the first LP of the "
                                           f"workload ({el:.1f} s, one thread)"}
     print(json.dumps(line), flush=True)
