@@ -275,8 +275,11 @@ static_assert(offsetof(Scalars, dhb) == offsetof(Scalars, tau) + 4 * sizeof(doub
 //   words 5 .. 5 + 2 MAXM: gamma, low and high halves
 //   word 5 + 2 MAXM: D-hat re-blend of the pass (0 none, 1 alpha = 0.9, 2 alpha = 0.1)
 constexpr int BC_WORDS = 6 + 2 * MAXM;
+// Rank 0 writes BC_COPIES copies of the message; the other ranks poll copy
+// (rank % BC_COPIES), which spreads their polling over four copies.
+constexpr int BC_COPIES = 4;
 struct alignas(256) BcastMsg {
-  unsigned long long w[64];
+  unsigned long long w[64 * BC_COPIES];
 };
 
 struct LoopArgs {

@@ -1378,8 +1378,8 @@ __device__ __forceinline__ void loop_units(const LoopArgs& a, const LPDesc* dp, 
   }
 }
 
-// Wave 0 of rank 0: publish the decisions of a pass as tagged words (see
-// BcastMsg).
+// Wave 0 of rank 0: publish the decisions of a pass as tagged words, in
+// every copy of the message (see BcastMsg).
 __device__ __forceinline__ void publish_decisions(const Bcast& b, unsigned long long* msg, unsigned int tag) {
   const int lane = threadIdx.x & 63;
   unsigned int pay = 0;
@@ -1399,7 +1399,7 @@ __device__ __forceinline__ void publish_decisions(const Bcast& b, unsigned long 
   }
   if (lane < BC_WORDS) {
     const unsigned long long wv = (unsigned long long)pay | (unsigned long long)tag << 32;
-    stc(reinterpret_cast<double*>(msg), lane, __builtin_bit_cast(double, wv));
+    for (int c = 0; c < BC_COPIES; ++c) stc(reinterpret_cast<double*>(msg + 64 * c), lane, __builtin_bit_cast(double, wv));
   }
 }
 
@@ -1561,7 +1561,7 @@ __global__ __launch_bounds__(BLOCK) void k_loop(LoopArgs a) {
       if (tid < 64) publish_decisions(s_bc, msg, a.tag0 + done);
     } else {
       if (tid < 64) {
-        const bool okw = read_decisions(s_bc, msg, a.tag0 + done, s_bc.k + 1, &sy->abort, ticks);
+        const bool okw = read_decisions(s_bc, msg + 64 * (wg.rank % BC_COPIES), a.tag0 + done, s_bc.k + 1, &sy->abort, ticks);
         if (tid == 0) s_ok = okw ? 1 : 0;
       }
       if (EXT && tid == 0 && s_ok && s_bc.blend != 0)  // the D-hat re-blend rank 0 made in final_step
