@@ -15,9 +15,10 @@ g^k = T u^k - u^k is the fixed-point residual, Delta U / Delta G hold the last
 m_k iterate / residual differences (oldest column first), i and j count AA and
 PDHG steps, D-hat is the diagonal of Remark se:Dhat_construction.
 
-Parity unpinned: in length_bounds (Lemma le:RK-1bound1) the power of
-(ct + cs) for j >= 3, which the tests pin only as an upper bound; and the
-convergence speed under the D-hat and eta readings below.
+Every function below is pinned by tests/test_oracle_*.py and
+tests/test_bruteforce.py against values and properties the paper and the
+mathematics fix.  The paper prints no iteration counts, so the convergence
+speed under the D-hat and eta readings below is not compared with it.
 
 Readings of points where the paper is silent or ambiguous (each is an option
 where it matters, and the GPU library takes the same reading):
@@ -357,9 +358,8 @@ def angle_filter(E, F, cs, sequential=False):
 def length_bounds(fnorm, cs):
     """Upper bounds b_j on ||column j of R^{-1}||^2 (Lemma le:RK-1bound1),
     from the column norms ||f_j|| of F (newest first).  A zero norm gives an
-    infinite bound.  Pinned as an upper bound and exactly at j = 2; for
-    j >= 3 the power of (ct + cs) is parity unpinned (a smaller power still
-    bounds every construction tried)."""
+    infinite bound.  b_j equals the sum over i <= j of the squares of
+    Lemma eq:lemma1.51's bounds on the entries s_ij of that column."""
     ct = math.sqrt(1.0 - cs * cs)
     m = len(fnorm)
     b = np.zeros(m)

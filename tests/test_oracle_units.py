@@ -335,6 +335,106 @@ def test_length_bound_b2_is_attained(cs):
     assert b[1] == pytest.approx(col2, rel=1e-12)
 
 
+def _entry_bounds(fnorm, cs):
+    """The entrywise bounds of Lemma eq:lemma1.51 on |s_ij|, s = R^{-1}, as an
+    upper-triangular table (1-based i <= j in the lemma, 0-based here):
+    s_11 = 1 / ||f_1||; |s_1j| <= ct (ct + cs)^(j-2) / (||f_1|| cs^(j-1)) for
+    j >= 2; s_ii <= 1 / (||f_i|| cs) for i >= 2; and
+    |s_ij| <= ct (ct + cs)^(j-i-1) / (||f_i|| cs^(j-i+1)) for 2 <= i < j."""
+    ct = math.sqrt(1.0 - cs * cs)
+    m = len(fnorm)
+    B = np.zeros((m, m))
+    for i in range(1, m + 1):
+        for j in range(i, m + 1):
+            if i == 1 and j == 1:
+                v = 1.0 / fnorm[0]
+            elif i == 1:
+                v = ct * (ct + cs) ** (j - 2) / (fnorm[0] * cs ** (j - 1))
+            elif i == j:
+                v = 1.0 / (fnorm[i - 1] * cs)
+            else:
+                v = ct * (ct + cs) ** (j - i - 1) / (fnorm[i - 1] * cs ** (j - i + 1))
+            B[i - 1, j - 1] = v
+    return B
+
+
+@pytest.mark.parametrize("cs", [0.05, 0.2, 0.5, 0.9, 1.0])
+def test_length_bounds_are_the_squared_entry_bounds_summed(cs):
+    """Lemma le:RK-1bound1 bounds the squared norm of column j of R^{-1} by
+    b_j; Lemma eq:lemma1.51 bounds each entry s_ij of that column.  The
+    column's squared norm is the sum of its squared entries, so b_j must be
+    the sum over i <= j of the squared entry bounds, for every j (here up to
+    16, the largest memory) and any column norms.  This second formula comes
+    from the entrywise lemma, not from the printed b_j, and fixes every power
+    of ct, (ct + cs) and cs in b_j."""
+    rng = np.random.default_rng(int(cs * 1000))
+    for trial in range(4):
+        fnorm = rng.uniform(0.05, 20.0, size=16)
+        b = oracle.length_bounds(fnorm, cs)
+        B = _entry_bounds(fnorm, cs)
+        ref = np.sum(B ** 2, axis=0)
+        np.testing.assert_allclose(b, ref, rtol=4e-15, atol=0.0)
+
+
+@pytest.mark.parametrize("cs", [0.2, 0.5, 0.9])
+def test_entry_bounds_attained_on_a_bidiagonal_chain(cs):
+    """Columns f_1 = ||f_1|| e_1 and, for i >= 2, f_i = ||f_i|| (ct e_{i-1} +
+    cs e_i) satisfy the hypotheses of Lemma eq:lemma1.51 with equality in the
+    sine condition (each f_i is at sine exactly cs from the span of the ones
+    before it, and its cosines with them are ct cs, ct or 0).  Their R is
+    bidiagonal, and the diagonal and first superdiagonal of R^{-1} (taken
+    numerically) reach the lemma's entry bounds exactly; every other entry
+    stays below its bound.  This fixes the powers of cs and the column norm
+    each entry bound carries where the bound is attained; the sum identity
+    above carries them into b_j."""
+    ct = math.sqrt(1.0 - cs * cs)
+    m = 7
+    fnorm = np.array([3.0, 0.25, 1.5, 0.7, 2.0, 0.4, 1.1])
+    F = np.zeros((m + 2, m))
+    F[0, 0] = fnorm[0]
+    for i in range(1, m):
+        F[i - 1, i] = fnorm[i] * ct
+        F[i, i] = fnorm[i] * cs
+    Q, R = np.linalg.qr(F)
+    # the hypotheses hold: sines from the QR, cosines directly
+    for i in range(1, m):
+        assert abs(R[i, i]) / fnorm[i] >= cs * (1 - 1e-12)
+        for k in range(i):
+            cosik = abs(F[:, i] @ F[:, k]) / (fnorm[i] * fnorm[k])
+            assert cosik <= ct * (1 + 1e-12)
+    S = np.abs(np.linalg.inv(R))
+    B = _entry_bounds(fnorm, cs)
+    iu = np.triu_indices(m)
+    assert np.all(S[iu] <= B[iu] * (1 + 1e-12))
+    for i in range(m):
+        assert S[i, i] == pytest.approx(B[i, i], rel=1e-12)
+        if i + 1 < m:
+            assert S[i, i + 1] == pytest.approx(B[i, i + 1], rel=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_entry_bounds_hold_for_random_angled_columns(seed):
+    """Random columns drawn to satisfy the sine condition with cs, whose
+    cosines with earlier columns happen to stay below ct: every entry of
+    R^{-1} is within the bound of Lemma eq:lemma1.51."""
+    rng = np.random.default_rng(300 + seed)
+    cs = 0.3
+    ct = math.sqrt(1.0 - cs * cs)
+    checked = 0
+    while checked < 5:
+        F = _angled_columns(rng, 12, 6, cs)
+        fn = np.linalg.norm(F, axis=0)
+        C = np.abs(F.T @ F) / np.outer(fn, fn)
+        if np.any(C[np.triu_indices(6, 1)] > ct):
+            continue
+        _, R = np.linalg.qr(F)
+        S = np.abs(np.linalg.inv(R))
+        B = _entry_bounds(fn, cs)
+        iu = np.triu_indices(6)
+        assert np.all(S[iu] <= B[iu] * (1 + 1e-10))
+        checked += 1
+
+
 @pytest.mark.parametrize("seed", range(5))
 def test_angle_filter_survivors_satisfy_angle_condition(seed):
     rng = np.random.default_rng(100 + seed)

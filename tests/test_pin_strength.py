@@ -41,6 +41,12 @@ MUTATIONS = [
     ("length bound: ct for cs in the first term", "/ (fnorm[0] ** 2 * cs ** (2 * (j - 2)))",
      "/ (fnorm[0] ** 2 * ct ** (2 * (j - 2)))"),
     ("length bound: 1 / cs^2 dropped", "b[j - 1] = total / cs ** 2", "b[j - 1] = total"),
+    ("length bound: power of (ct + cs) in the first term one higher", "(ct + cs) ** (2 * (j - 2))",
+     "(ct + cs) ** (2 * (j - 1))"),
+    ("length bound: power of (ct + cs) in the sum one higher", "(ct + cs) ** (2 * (j - i - 1))",
+     "(ct + cs) ** (2 * (j - i))"),
+    ("length bound: power of cs in the sum one lower", "cs ** (2 * (j - i)))", "cs ** (2 * (j - i - 1)))"),
+    ("length bound: norm of the wrong column in the sum", "/ (fnorm[i - 1] ** 2 *", "/ (fnorm[i] ** 2 *"),
     ("length filter: keeps one more", "            k -= 1\n    return k", "            k -= 1\n    return min(k + 1, m)"),
     ("power iteration: eigenvalue for norm", "new = math.sqrt(nz)", "new = nz"),
     ("Ruiz: column factor inverted", "        d_col = d_col / s\n", "        d_col = d_col * s\n"),
