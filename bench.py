@@ -1,17 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the AA-PDHG hot path on one MI355X.
 
-A step is one loop pass of AA-PDHG (Alg 2) over the whole LP: the CSC pass
+A step is one loop pass of the method (Alg 2 for AA-PDHG, Alg 3 for FAA-PDHG)
+over the whole LP: the CSC pass
 (K^T y and the primal update), the CSR pass (K x_bar, the dual update and the
 float64 decisions) and, on Anderson steps, the mix pass; the KKT test runs
 every 64 passes as in a solve.  The KKT tolerance is set to 0 inside the timed
 region so that no pass is skipped by early termination.
 
 Workloads (synthetic, seeded; see lpgen):
-  mip20k      20k x 50k LP, 250k nonzeros, Zipf(1.8) rows, float32, m_A = 10 (default):
-              loop passes per second
-  powerlaw1m  1M x 2M LP, 20M nonzeros, power-law columns, Ruiz-scaled, FAA-PDHG, m_A = 10:
-              loop passes per second
+  powerlaw1m  (default) 1M x 2M LP, 20M nonzeros, power-law columns, Ruiz-scaled, FAA-PDHG,
+              m_A = 10, float32 with float64 reductions and decisions: loop passes per
+              second (value), the longest launch against the HBM roofline, SpMV GB/s, and
+              the LP solved to relative KKT 1e-4; the line also carries the batch leg
+              (batch256 below), a serving leg (Poisson stream at 200 requests/s), the
+              cache-resident 20k x 50k LP, and the oracle on the host (cpu_baseline)
+  mip20k      20k x 50k LP, 250k nonzeros, Zipf(1.8) rows, float32, m_A = 10: loop passes
+              per second in the persistent kernel
   batch256    256 LPs of uneven sizes (rows log-uniform 1k..50k), m_A = 8: LPs solved per
               second to relative KKT 1e-4 in one batched float32 solve, beside float64
               single solves of a sample of the same LPs
@@ -64,8 +69,10 @@ def _src_hash():
 
 
 def _traffic(workload, kernel, ppl):
-    """HBM bytes per launch from the committed counter summary, if it was taken
-    on the current kernel source with the same passes per launch."""
+    """HBM bytes per launch of `ppl` passes from the committed counter summary,
+    if it was taken on the current kernel source (the summary stores bytes per
+    pass: per dispatch for the three launches, per launch / passes for the
+    persistent kernel)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -73,16 +80,14 @@ def _traffic(workload, kernel, ppl):
         t = json.load(f)
     if t.get("kernel_source_hash") != _src_hash():
         return None
-    if kernel == "loop" and t.get("passes_per_launch") != ppl:
-        return None
     ks = t.get("kernels", {})
     k = ks.get(kernel)
-    if k is None:
+    if k is None or "hbm_bytes_per_pass" not in k:
         return None
-    b = k.get("hbm_bytes_per_launch")
+    b = k["hbm_bytes_per_pass"]
     if kernel == "dual" and "panel" in ks:  # the dual launch's events bracket the panel kernel too
-        b += ks["panel"]["hbm_bytes_per_launch"]
-    return b
+        b += ks["panel"]["hbm_bytes_per_pass"]
+    return b * ppl
 
 
 def _workload(name):
@@ -107,27 +112,96 @@ def _workload(name):
     raise ValueError(name)
 
 
-def _hbm_bound_leg(stream, passes=100):
-    """The 1M x 2M LP (working set far beyond the caches): the three launches
-    of a loop pass timed with HIP events, each against the HBM roofline with
-    its algorithmic bytes (and the counter-measured traffic when the committed
-    summary matches the kernel source)."""
+def _timed_passes(runner, stream, steps, warmup, ppl):
+    """W untimed passes, then `steps` passes bracketed by events on the launch
+    stream and device synchronisations; returns (passes, ms)."""
+    import torch
+    runner.iterate(1, stream)  # the init step
+    for _ in range(max(1, warmup // ppl)):
+        runner.iterate(ppl, stream)
+    torch.cuda.synchronize()
+    nlaunch = max(1, steps // ppl)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(nlaunch):
+        runner.iterate(ppl, stream)
+    end.record(stream)
+    torch.cuda.synchronize()
+    return nlaunch * ppl, start.elapsed_time(end)
+
+
+def _launch_roofline(lps, opts, solvers, runner, stream, ppl, workload):
+    """The launch that takes longest per pass, against the HBM roofline: its
+    algorithmic bytes per launch over its average duration measured with HIP
+    events on the launch stream (three timed repetitions), with the counter
+    traffic of the committed summary when it was taken on the current kernel
+    source."""
+    n = sum(lp.n for lp in lps)
+    m = sum(lp.m for lp in lps)
+    Z = sum(lp.nnz for lp in lps)
+    M = opts["memory"]
+    bm = _bytes_model(n, m, Z, M, 1.0 / opts["kkt_every"])
+    def aa_steps():
+        if runner in solvers:
+            return sum(s.result()["aa_steps"] for s in solvers)
+        return sum(runner.result(i)["aa_steps"] for i in range(len(solvers)))
+
+    aa0 = aa_steps()
+    kt = [runner.iterate_timed(ppl, stream) for _ in range(3)]
+    aa1 = aa_steps()
+    aa_frac = (aa1 - aa0) / (3.0 * ppl * len(solvers))
+    if kt[0]["kernel"] == "persistent":
+        launch_ms = sum(k["launch_ms"] for k in kt) / len(kt)
+        per_pass = bm["primal"] + bm["dual"] + aa_frac * bm["mix"]
+        dom, dom_bytes, dom_ms = "loop", per_pass * ppl, launch_ms
+        ext = bool(opts.get("pw_period")) or opts.get("variant") == 3
+        kernel_name = f"k_loop<float, {10 if M > 8 else 8}, {'true' if ext else 'false'}>"
+        spmv_gbs = bm["spmv"] * ppl / (launch_ms * 1e-3) / 1e9
+        launch = {"kernel": kernel_name, "passes_per_launch": ppl, "launch_ms": launch_ms,
+                  "ms_per_pass": launch_ms / ppl, "aa_fraction": aa_frac}
+        traffic = _traffic(workload, "loop", ppl)
+    else:
+        avg = {q: sum(k[q] for k in kt) / len(kt) for q in ("primal", "dual", "mix")}
+        dom = max(avg, key=lambda q: avg[q])
+        dom_bytes, dom_ms = bm[dom], avg[dom]
+        kernel_name = {"primal": f"k_pass<float, {10 if M > 8 else 8}, 0>",
+                       "dual": f"k_pass<float, {10 if M > 8 else 8}, 1>", "mix": "k_mix<float>"}[dom]
+        # SpMV GB/s: the product pair's algorithmic bytes over the two SpMV launches
+        spmv_gbs = bm["spmv"] / ((avg["primal"] + avg["dual"]) * 1e-3) / 1e9
+        launch = {"kernel": "three launches per pass", **avg, "aa_fraction": aa_frac,
+                  "per_launch": {q: {"algorithmic_bytes": bm[q], "ms": avg[q],
+                                     "achieved_gbs": bm[q] / (avg[q] * 1e-3) / 1e9,
+                                     "frac": bm[q] / (avg[q] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                     "traffic": _traffic(workload, q, 1)} for q in ("primal", "dual")}}
+        traffic = _traffic(workload, dom, 1)
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel_name,
+            "algorithmic_bytes_per_launch": dom_bytes, "launch_ms": dom_ms}
+    return roof, launch, {"spmv_gbps": spmv_gbs, "spmv_frac_of_peak": spmv_gbs / HBM_PEAK_GBS,
+                          "bytes_per_pass": bm}
+
+
+def _solve_leg(lp, opts, stream, seconds, tol=1e-4, precision=0):
+    """One LP solved from its start point to relative KKT `tol` (time-limited):
+    passes, seconds, KKT and the objective against the planted optimum."""
     import paper_2508_08062_amd as P
-    lps, opts, cfg = _workload("powerlaw1m")
-    s = P.Solver(lps[0], tol=0.0, max_iter=10 ** 9, **opts)
-    s.iterate(1, stream)
-    s.iterate(20, stream)  # warm-up
-    kt = s.iterate_timed(passes, stream)
-    lp = lps[0]
-    bm = _bytes_model(lp.n, lp.m, lp.nnz, opts["memory"], 1.0 / opts["kkt_every"])
-    out = {"workload": cfg["workload"], "passes": passes, "ms_per_pass": kt["primal"] + kt["dual"] + kt["mix"],
-           "launches": {}}
-    for q in ("primal", "dual"):
-        ach = bm[q] / (kt[q] * 1e-3) / 1e9
-        out["launches"][q] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": ach / HBM_PEAK_GBS, "traffic": _traffic("powerlaw1m", q, 0),
-                              "algorithmic_bytes_per_launch": bm[q], "ms": kt[q]}
+    s = P.Solver(lp, tol=tol, max_iter=10 ** 7, time_limit_s=seconds, **{**opts, "precision": precision})
+    t0 = time.perf_counter()
+    s.solve(stream)
+    el = time.perf_counter() - t0
+    r = s.result()
     s.close()
+    out = {"status": r["status"], "iters": r["iters"], "seconds": el, "kkt": r["kkt"], "r_gap": r["r_gap"],
+           "r_pri": r["r_pri"], "r_dual": r["r_dual"], "primal_obj": r["primal_obj"], "dual_obj": r["dual_obj"],
+           "aa_steps": r["aa_steps"], "lps_per_s": (1.0 / el) if r["status"] == "converged" else 0.0,
+           "tol": tol, "precision": "f64" if precision else "f32"}
+    pstar = lp.planted.get("pstar") if lp.planted else None
+    if pstar is not None:
+        out["planted_pstar"] = pstar
+        out["rel_obj_err_vs_planted"] = abs(r["primal_obj"] - pstar) / (1.0 + abs(pstar))
     return out
 
 
@@ -223,52 +297,70 @@ def _line(metric, value, unit, cfg, extra, higher=True, steps=0, warmup=0, ms=0.
             "dtype": dtype, "data": "synthetic", "config": cfg, **extra}
 
 
-def _batch_solve(args):
-    """256 LPs solved to relative KKT 1e-4 in one batch (float32), and a sample
-    of them solved one at a time in float64."""
+def _batch_leg(args, stream, cpu_baseline=False):
+    """256 LPs of uneven sizes: the aggregate batch iteration against the HBM
+    roofline (all members running, three launches per pass), then the whole
+    batch solved to relative KKT 1e-4 in float32, and a sample of the same LPs
+    solved one at a time in float64 and in float32 (measured, not scaled)."""
     import numpy as np
-    import torch
 
-    import lpgen
     import paper_2508_08062_amd as P
     lps, opts, cfg = _workload("batch256")
-    stream = torch.cuda.Stream()
     kw = dict(opts, tol=1e-4, max_iter=200000)
     solvers = [P.Solver(lp, **kw) for lp in lps]
-    batch = P.Batch(solvers)
-    torch.cuda.synchronize()
     print(f"# created {len(solvers)} LPs", file=sys.stderr, flush=True)
+    # aggregate batch iteration: 64 passes, far from any member's termination
+    batch = P.Batch(solvers)
+    batch.iterate(1, stream)
+    batch.iterate(8, stream)
+    roof, launch, spmv = _launch_roofline(lps, opts, solvers, batch, stream, 64, "batch256")
+    batch.close()
+    for sv in solvers:
+        sv.reset(stream)
+    batch = P.Batch(solvers)
     t0 = time.perf_counter()
     batch.solve(stream)
     el = time.perf_counter() - t0
     res = batch.results()
     iters = np.array([r["iters"] for r in res])
     done_s = np.array([r["solve_seconds"] for r in res])  # per LP: time until seen stopped
-    conv = sum(r["status"] == "converged" for r in res)
+    conv = int(sum(r["status"] == "converged" for r in res))
     batch.close()
     for sv in solvers:
         sv.close()
     print(f"# batch solve {el:.2f} s, {conv} converged", file=sys.stderr, flush=True)
-    # float64 single solves of a sample, one after the other
+    # single solves of a sample, one after the other, float64 and float32
     rng = np.random.default_rng(5)
     sample = sorted(rng.choice(len(lps), size=min(args.fp64_sample, len(lps)), replace=False).tolist())
-    t64 = []
-    it64 = []
-    for i in sample:
-        sv = P.Solver(lps[i], **{**kw, "precision": 1})
-        t1 = time.perf_counter()
-        sv.solve(stream)
-        t64.append(time.perf_counter() - t1)
-        it64.append(sv.result()["iters"])
-        sv.close()
-    nnz_all = sum(lp.nnz for lp in lps)
-    nnz_s = sum(lps[i].nnz for i in sample)
-    # the sample's float64 time scaled to the whole batch by nonzeros x iterations
-    work_all = float(sum(lps[i].nnz * r["iters"] for i, r in enumerate(res)))
-    work_s = float(sum(lps[i].nnz * it64[j] for j, i in enumerate(sample)))
-    est64 = sum(t64) * work_all / max(work_s, 1.0)
-    extra_cpu = {}
-    if not args.no_cpu_baseline:
+    single = {}
+    for prec, key in ((1, "fp64_single"), (0, "fp32_single")):
+        t, it, st = [], [], []
+        for i in sample:
+            sv = P.Solver(lps[i], **{**kw, "precision": prec})
+            t1 = time.perf_counter()
+            sv.solve(stream)
+            t.append(time.perf_counter() - t1)
+            r = sv.result()
+            it.append(r["iters"])
+            st.append(r["status"])
+            sv.close()
+        c = sum(x == "converged" for x in st)
+        single[key] = {"sample": sample, "seconds": t, "iters": it, "status": st,
+                       "lps_per_s": c / sum(t), "latency_p50_s": float(np.percentile(t, 50)),
+                       "latency_p99_s": float(np.percentile(t, 99)),
+                       "measured": "each sampled LP solved alone from create-time state to rel KKT 1e-4"}
+    out = {"workload": cfg["workload"], "lps": len(lps), "nnz_total": sum(lp.nnz for lp in lps),
+           "value": conv / el, "unit": "LPs/s", "batch_seconds": el, "converged": conv,
+           "lps_stopped_per_s": len(lps) / el, "iters_median": float(np.median(iters)),
+           "iters_max": int(iters.max()),
+           "completion_p50_s": float(np.percentile(done_s, 50)),
+           "completion_p99_s": float(np.percentile(done_s, 99)),
+           "lps_done_by_p50_per_s": 0.5 * len(lps) / float(np.percentile(done_s, 50)),
+           "batch_iteration": {"roofline": roof, "launch": launch, **spmv,
+                               "ms_per_batch_iteration": launch.get("primal", 0) + launch.get("dual", 0)
+                               + launch.get("aa_fraction", 0) * launch.get("mix", 0)},
+           **single}
+    if cpu_baseline:
         cb = _cpu_batch_baseline(lps, opts, args.cpu_seconds)
         # the whole batch on one core at the sample's time per nonzero-pass,
         # with the passes each LP took on the GPU
@@ -277,20 +369,21 @@ def _batch_solve(args):
         cb["value"] = conv / est  # the batch on one core, scaled from the sample (converged LPs only)
         cb["sample"] += (f"; scaled to the batch: {est:.0f} s for its {len(lps)} LPs at the sample's seconds per "
                          "nonzero-pass and the passes each LP took on the GPU")
-        extra_cpu = {"cpu_baseline": cb}
-    line = _line("LPs solved/s at rel KKT 1e-4 (batched float32)", conv / el, "LPs/s",
-                 {**cfg, "lps": len(lps), "nnz_total": nnz_all},
-                 {"batch_seconds": el, "converged": int(conv), "lps_stopped_per_s": len(lps) / el, "iters_median": float(np.median(iters)),
-                  "iters_max": int(iters.max()),
-                  "completion_p50_s": float(np.percentile(done_s, 50)),
-                  "completion_p99_s": float(np.percentile(done_s, 99)),
-                  "lps_done_by_p50_per_s": 0.5 * len(lps) / float(np.percentile(done_s, 50)),
-                  "fp64_single": {"sample": sample, "seconds": t64, "iters": it64, "nnz_sample": nnz_s,
-                                  "lps_per_s_estimate": conv / est64,
-                                  "estimate": "sample seconds scaled by nnz x iterations to all LPs"},
-                  **extra_cpu},
-                 ms=el * 1e3)
-    print(json.dumps(line), flush=True)
+        out["cpu_baseline"] = cb
+    return out
+
+
+def _batch_solve(args):
+    import torch
+    stream = torch.cuda.Stream()
+    out = _batch_leg(args, stream, cpu_baseline=not args.no_cpu_baseline)
+    cfg = {"workload": out.pop("workload"), "variant": "AA-PDHG", "m_A": 8, "ruiz_iters": 10, "dhat_mode": 0,
+           "lps": out["lps"], "nnz_total": out["nnz_total"]}
+    value = out.pop("value")
+    out.pop("unit")
+    extra = {k: v for k, v in out.items() if k not in ("lps", "nnz_total")}
+    print(json.dumps(_line("LPs solved/s at rel KKT 1e-4 (batched float32)", value, "LPs/s", cfg, extra,
+                           ms=out["batch_seconds"] * 1e3)), flush=True)
 
 
 def _compare(args):
@@ -444,6 +537,9 @@ def _serve(args, rate=None, seconds=None, pool_size=None, drain=None, emit=True)
     st = srv.stats()
     srv.close()
     d = np.array([x[0] for x in lat])
+    # requests still pending at the end have waited at least this long
+    ages = np.array([el - t_arr for t_arr in pending.values()])
+    d_all = np.concatenate([d, ages])
     conv = sum(x[1] == "converged" for x in lat)
     line = _line("LPs solved/s & p99 latency at rel KKT 1e-4 (served float32)", conv / el, "LPs/s",
                  {"workload": f"Poisson stream {rate}/s for {seconds} s (serving_requests seed 4), "
@@ -453,7 +549,9 @@ def _serve(args, rate=None, seconds=None, pool_size=None, drain=None, emit=True)
                   "seconds": el, "finished_per_s": len(lat) / el,
                   "latency_p50_s": float(np.percentile(d, 50)) if d.size else None,
                   "latency_p99_s": float(np.percentile(d, 99)) if d.size else None,
-                  "latency_max_s": float(d.max()) if d.size else None, "server": st})
+                  "latency_max_s": float(d.max()) if d.size else None,
+                  "latency_p99_with_unfinished_lower_bound_s": float(np.percentile(d_all, 99)) if d_all.size else None,
+                  "server": st})
     if emit:
         print(json.dumps(line), flush=True)
     return line
@@ -462,9 +560,9 @@ def _serve(args, rate=None, seconds=None, pool_size=None, drain=None, emit=True)
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5000)
-    ap.add_argument("--warmup", type=int, default=300)
-    ap.add_argument("--workload", default="mip20k", choices=["mip20k", "powerlaw1m", "batch256", "serve", "serve_curve", "compare", "sweep"])
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="powerlaw1m", choices=["mip20k", "powerlaw1m", "batch256", "serve", "serve_curve", "compare", "sweep"])
     ap.add_argument("--compare-max-iter", type=int, default=300000, help="compare: pass limit per method")
     ap.add_argument("--sweep-m", type=int, default=20000, help="sweep: rows of the LP (columns 2.5x, 12.5 nnz/row)")
     ap.add_argument("--sweep-seed", type=int, default=1)
@@ -476,18 +574,18 @@ def main():
     ap.add_argument("--drain-seconds", type=float, default=120.0, help="serve: wait after the last arrival")
     ap.add_argument("--fp64-sample", type=int, default=8, help="batch256: LPs solved singly in float64")
     ap.add_argument("--serve-rate", type=float, default=4.0,
-                    help="single-LP workloads: rate of the short serving leg (0 = none)")
-    ap.add_argument("--serve-leg-seconds", type=float, default=10.0, help="length of the short serving leg")
-    ap.add_argument("--serve-leg-drain", type=float, default=40.0, help="drain of the short serving leg")
+                    help="mip20k: rate of the short serving leg (0 = none)")
+    ap.add_argument("--serve-leg-seconds", type=float, default=5.0, help="length of the serving leg's stream")
+    ap.add_argument("--serve-leg-drain", type=float, default=25.0, help="drain of the serving leg")
+    ap.add_argument("--solve-seconds", type=float, default=150.0, help="time limit of the solve-to-1e-4 legs")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="powerlaw1m: only the headline passes (no batch, serving and 20k x 50k legs)")
     ap.add_argument("--curve-rates", type=float, nargs="+", default=[1.0, 2.0, 4.0, 8.0, 16.0],
                     help="serve_curve: arrival rates (requests per second)")
     ap.add_argument("--passes-per-launch", type=int, default=500,
                     help="loop passes per launch of the persistent loop kernel")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-hbm-leg", action="store_true", help="skip the 1M x 2M roofline leg of the default line")
-    ap.add_argument("--large-cpu-baseline", action="store_true",
-                    help="powerlaw1m: also time the oracle (its set-up on 20M entries takes minutes)")
     ap.add_argument("--no-solve", action="store_true", help="skip the solve-to-tolerance leg")
     ap.add_argument("--chunks-per-block", type=int, default=0, help="workgroup size in chunks (0 = automatic)")
     ap.add_argument("--pw-period", type=int, default=0,
@@ -541,57 +639,27 @@ def main():
     torch.cuda.synchronize()
     print(f"# created {len(solvers)} LP(s); warmup {args.warmup}", file=sys.stderr, flush=True)
     ppl = max(1, min(args.passes_per_launch, args.steps))
-    runner.iterate(1, stream)  # the init step
-    for _ in range(max(1, args.warmup // ppl)):
-        runner.iterate(ppl, stream)
-    torch.cuda.synchronize()
-    nlaunch = max(1, args.steps // ppl)
-    steps = nlaunch * ppl
-
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record(stream)
-    for _ in range(nlaunch):
-        runner.iterate(ppl, stream)  # one launch of the loop kernel each
-    end.record(stream)
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(end)
+    steps, ms = _timed_passes(runner, stream, args.steps, args.warmup, ppl)
     print(f"# timed {steps} passes in {ms:.1f} ms", file=sys.stderr, flush=True)
     if args.profile_run:
+        # every handle is destroyed, and the device idle, before the program ends
+        if runner is not solvers[0]:
+            runner.close()
+        for sv in solvers:
+            sv.close()
+        torch.cuda.synchronize()
         return
-
+    roof, launch, spmv = _launch_roofline(lps, opts, solvers, runner, stream, ppl, args.workload)
+    if runner is not solvers[0]:
+        runner.close()
+    for sv in solvers:
+        sv.close()
     n = sum(lp.n for lp in lps)
     m = sum(lp.m for lp in lps)
     Z = sum(lp.nnz for lp in lps)
-    M = opts["memory"]
-    bm = _bytes_model(n, m, Z, M, 1.0 / opts["kkt_every"])
-    # Anderson steps among the measured passes (the mix pass runs only on them)
-    aa0 = sum(s.result()["aa_steps"] for s in solvers)
-    kt = [runner.iterate_timed(ppl, stream) for _ in range(3)]
-    aa1 = sum(s.result()["aa_steps"] for s in solvers)
-    aa_frac = (aa1 - aa0) / (3.0 * ppl * len(solvers))
-    value = steps / (ms * 1e-3)
-    if kt[0]["kernel"] == "persistent":
-        launch_ms = sum(k["launch_ms"] for k in kt) / len(kt)
-        per_pass = bm["primal"] + bm["dual"] + aa_frac * bm["mix"]
-        dom, dom_bytes, dom_ms = "loop", per_pass * ppl, launch_ms
-        ext = bool(opts.get("pw_period")) or opts.get("variant") == 3
-        kernel_name = f"k_loop<float, {10 if M > 8 else 8}, {'true' if ext else 'false'}>"
-        spmv_gbs = bm["spmv"] * ppl / (launch_ms * 1e-3) / 1e9
-        launch = {"kernel": kernel_name, "passes_per_launch": ppl, "launch_ms": launch_ms,
-                  "ms_per_pass": launch_ms / ppl, "aa_fraction": aa_frac}
-    else:
-        avg = {q: sum(k[q] for k in kt) / len(kt) for q in ("primal", "dual", "mix")}
-        dom = max(avg, key=lambda q: avg[q])
-        dom_bytes, dom_ms = bm[dom], avg[dom]
-        kernel_name = {"primal": "k_pass<float, MT, 0>", "dual": "k_pass<float, MT, 1>", "mix": "k_mix<float>"}[dom]
-        spmv_gbs = bm["spmv"] / ((avg["primal"] + avg["dual"]) * 1e-3) / 1e9
-        launch = {"kernel": "three launches per pass", **avg, "aa_fraction": aa_frac}
-    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     line = {
         "metric": "PDHG iters/s + SpMV HBM GB/s; LPs solved/s & p99 latency at rel KKT 1e-4",
-        "value": value,
+        "value": steps / (ms * 1e-3),
         "unit": "iters/s" if len(lps) == 1 else "batch iters/s",
         "n_gpus": 1,
         "steps": steps,
@@ -603,49 +671,68 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {**cfg, "m": m, "n": n, "nnz": Z},
-        "spmv_gbps": spmv_gbs,
+        **spmv,
         "launch": launch,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": _traffic(args.workload, dom, ppl),
-                     "kernel": kernel_name, "algorithmic_bytes_per_launch": dom_bytes},
+        "roofline": roof,
     }
+    if args.workload == "mip20k":
+        ws = (16 * Z + 4 * (2 * opts["memory"] + 12) * (n + m)) / 1e6
+        line["roofline"]["note"] = (f"working set about {ws:.0f} MB stays in L2/MALL: the pass is bound by "
+                                    "latency, not HBM")
 
     if not args.no_solve and len(lps) == 1:
-        # solve to relative KKT 1e-4 in float32, and the same LP in float64
-        res = {}
-        for prec, key in ((0, "solve_fp32"), (1, "solve_fp64")):
-            s = P.Solver(lps[0], tol=1e-4, max_iter=200000, **{**opts, "precision": prec})
-            t0 = time.perf_counter()
-            s.solve(stream)
-            el = time.perf_counter() - t0
-            r = s.result()
-            res[key] = {"status": r["status"], "iters": r["iters"], "seconds": el, "kkt": r["kkt"],
-                        "primal_obj": r["primal_obj"], "aa_steps": r["aa_steps"]}
-            s.close()
-        line.update(res)
+        print("# solve to rel KKT 1e-4, float32", file=sys.stderr, flush=True)
+        line["solve_fp32"] = _solve_leg(lps[0], opts, stream, args.solve_seconds)
+        if args.workload == "mip20k":
+            line["solve_fp64"] = _solve_leg(lps[0], opts, stream, args.solve_seconds, precision=1)
 
-    if args.workload == "mip20k":
-        ws = (16 * Z + 4 * (2 * M + 12) * (n + m)) / 1e6
-        line["roofline"]["note"] = (f"working set about {ws:.0f} MB stays in L2/MALL: the pass is bound by latency, "
-                                    "not HBM; roofline_hbm_bound is the HBM-bound 1M x 2M LP")
-        if not args.no_hbm_leg:
-            line["roofline_hbm_bound"] = _hbm_bound_leg(stream)
-
-    if args.serve_rate > 0 and len(lps) == 1:
-        # a short serving leg: LPs solved per second and latency of a stream the server keeps up with
+    if args.workload == "powerlaw1m" and not args.no_legs:
+        print("# batch leg", file=sys.stderr, flush=True)
+        line["batch"] = _batch_leg(args, stream)
+        print("# serving leg", file=sys.stderr, flush=True)
+        sv = _serve(args, rate=args.rate, seconds=args.serve_leg_seconds, pool_size=args.pool,
+                    drain=args.serve_leg_drain, emit=False)
+        line["serving"] = _serving_summary(sv)
+        print("# cache-resident leg", file=sys.stderr, flush=True)
+        line["cache_resident"] = _c1_leg(args, stream)
+    elif args.serve_rate > 0 and len(lps) == 1:
         sv = _serve(args, rate=args.serve_rate, seconds=args.serve_leg_seconds, pool_size=16,
                     drain=args.serve_leg_drain, emit=False)
-        line["serving"] = {k: sv[k] for k in ("value", "unit")}
-        line["serving"].update({k: sv[k] for k in ("requests", "finished", "unfinished", "converged", "seconds",
-                                                   "latency_p50_s", "latency_p99_s", "latency_max_s")})
-        line["serving"]["workload"] = sv["config"]["workload"]
+        line["serving"] = _serving_summary(sv)
 
-    if not args.no_cpu_baseline and (args.workload != "powerlaw1m" or args.large_cpu_baseline):
+    if not args.no_cpu_baseline:
+        print("# oracle on the host", file=sys.stderr, flush=True)
         rate, k, el = _cpu_baseline(lps, opts, args.cpu_seconds)
         line["cpu_baseline"] = {"value": rate, "unit": "iters/s", "cores": 1, "kind": "oracle", **_host_cpu(),
-                                "sample": f"{k} loop passes of the float64 oracle on the first LP of the "
-                                          f"workload ({el:.1f} s, one thread)"}
+                                "sample": f"the first {k} loop passes (after 3 untimed) of the float64 oracle on "
+                                          f"the same LP, Ruiz-scaled and float32-rounded ({el:.1f} s, one thread)"}
     print(json.dumps(line), flush=True)
+
+
+def _serving_summary(sv):
+    out = {k: sv[k] for k in ("value", "unit")}
+    out.update({k: sv[k] for k in ("requests", "finished", "unfinished", "converged", "seconds", "finished_per_s",
+                                   "latency_p50_s", "latency_p99_s", "latency_max_s",
+                                   "latency_p99_with_unfinished_lower_bound_s", "server")})
+    out["workload"] = sv["config"]["workload"]
+    return out
+
+
+def _c1_leg(args, stream):
+    """The 20k x 50k LP (cache-resident): loop passes per second in the
+    persistent kernel, and solves to relative KKT 1e-4 in float32 and float64."""
+    import paper_2508_08062_amd as P
+    lps, opts, cfg = _workload("mip20k")
+    s = P.Solver(lps[0], tol=0.0, max_iter=10 ** 9, **opts)
+    ppl = 500
+    steps, ms = _timed_passes(s, stream, 2000, 500, ppl)
+    roof, launch, spmv = _launch_roofline(lps, opts, [s], s, stream, ppl, "mip20k")
+    s.close()
+    roof["note"] = "working set about 13 MB stays in L2/MALL: the pass is bound by latency, not HBM"
+    return {"workload": cfg["workload"], "variant": cfg["variant"], "m_A": cfg["m_A"], "value": steps / (ms * 1e-3),
+            "unit": "iters/s", "steps": steps, "ms_per_step": ms / steps, **spmv, "launch": launch,
+            "roofline": roof, "solve_fp32": _solve_leg(lps[0], opts, stream, 60.0),
+            "solve_fp64": _solve_leg(lps[0], opts, stream, 60.0, precision=1)}
 
 
 if __name__ == "__main__":

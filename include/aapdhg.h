@@ -150,6 +150,10 @@ typedef struct {
                              u the top 53 bits of output j of SplitMix64 started at `seed`, as
                              a fraction of 2^53 (a random start; a constant one is orthogonal
                              to the dominant singular vector when the rows of K sum to zero) */
+  int32_t length_floor;   /* FAA LengthFilter (Alg 5) when no k passes its test: 0 (default)
+                             keeps no column (the count-down loop runs out), 1 keeps the
+                             newest column (the loop read as stopping at k = 1)            */
+  int32_t reserved1;
 } aapdhg_options;
 
 typedef struct {
@@ -169,6 +173,7 @@ typedef struct {
   double step_tau, step_sigma; /* step sizes in use (they change with the primal weight) */
   double omega;            /* primal weight (sqrt(step_sigma / step_tau))                  */
   int64_t pw_updates;      /* accepted primal-weight updates                               */
+  int64_t faa_empty;       /* FAA steps whose filters left no column (u_AA = u + beta D g) */
 } aapdhg_info;
 
 /* Fills *o with the defaults of Section 5.1: AA-PDHG, float32, m_A = 10, D = 10,
@@ -255,10 +260,14 @@ aapdhg_status aapdhg_result(aapdhg_t h, double *x, double *y, double *lambda, aa
  *   u      [n+m]  current iterate u^k (x then y, scaled problem)
  *   u_prev [n+m]  u^{k-1}            g_prev [n+m]  g^{k-1}
  *   dG     [m_A*(n+m)] history columns by physical slot, W [m_A*(n+m)] = dU + beta D-hat dG
- *   meta   int64[8 + 2*AAPDHG_MAX_MEMORY]: k, status, i, j, nlive, newslot, 0, 0, live slots
- *          (oldest first, AAPDHG_MAX_MEMORY entries), then m_A entries of ||du_slot||^2 bits
- *   gram   double[AAPDHG_MAX_MEMORY^2 + 2*AAPDHG_MAX_MEMORY + 2]: Gram by slot, rhs, du2, n0, gnorm.
- * Any pointer may be NULL to skip it. */
+ *   meta   int64[8 + 2*AAPDHG_MAX_MEMORY]: k, status, i, j, nlive, newslot, branch of the last
+ *          pass (0 none, 1 PDHG, 2 Anderson), nmix (columns the last Anderson step mixed), the
+ *          live slots (oldest first, AAPDHG_MAX_MEMORY entries), then the nmix mixed slots in
+ *          the order of gamma (AAPDHG_MAX_MEMORY entries, zero past nmix)
+ *   gram   double[AAPDHG_MAX_MEMORY^2 + 3*AAPDHG_MAX_MEMORY + 2]: Gram by slot, rhs, du2, n0,
+ *          gnorm, then gamma of the last Anderson step (nmix entries used, zero past them).
+ * Any pointer may be NULL to skip it.  aapdhg_set_state reads meta up to the live slots and
+ * gram up to gnorm. */
 aapdhg_status aapdhg_get_state(aapdhg_t h, double *u, double *u_prev, double *g_prev, double *dG,
                                double *W, int64_t *meta, double *gram);
 /* Restore a state written by aapdhg_get_state (same problem and options). */
@@ -327,7 +336,8 @@ aapdhg_status aapdhg_server_submit(aapdhg_server_t s, int32_t m, int32_t n, int6
                                    uint64_t *ticket);
 /* AAPDHG_PENDING while the request is queued or running; AAPDHG_OK once finished, with the
  * results copied out (x[n], y[m], each may be NULL) and the ticket released.  t_admit and
- * t_done (may be NULL) receive seconds since server start of admission and completion. */
+ * t_done (may be NULL) receive the seconds from submission to admission and to completion
+ * (t_admit is -1 for a request that failed before admission). */
 aapdhg_status aapdhg_server_poll(aapdhg_server_t s, uint64_t ticket, aapdhg_info *info,
                                  double *x, double *y, double *t_admit, double *t_done);
 /* Counters: submitted, admitted, finished, resident now, epochs run, bytes resident now. */

@@ -41,6 +41,8 @@ where it matters, and the GPU library takes the same reading):
     filter its loop runs out and m-bar = 0: the step keeps no history and
     u_AA = u^k + beta D-hat g^k.  This is the reading under which Lemma
     lem:conditioning_after_stab holds for every output of the filter.  The
+    option ``length_floor`` = 1 takes the other reading (the loop stops at
+    k = 1, so m-bar = 1 and the newest column is always kept).  The
     filtered columns become the memory that the next difference pair is
     appended to (Section 5, implemented variant).
   * Infinite bounds contribute nothing to the dual objective; the set Lambda
@@ -376,10 +378,12 @@ def length_bounds(fnorm, cs):
     return b
 
 
-def length_filter(enorm, fnorm, cs, kappa_bar):
+def length_filter(enorm, fnorm, cs, kappa_bar, floor=0):
     """Alg 5: the largest k (counting down from m) with
-    (sum_{j<=k} e_j^2)(sum_{j<=k} b_j) <= kappa_bar^2; 0 if none (the loop
-    runs out).  A NaN product (0 * inf) does not pass."""
+    (sum_{j<=k} e_j^2)(sum_{j<=k} b_j) <= kappa_bar^2.  When no k passes,
+    the count-down loop runs out: ``floor`` = 0 returns 0 (nothing kept),
+    ``floor`` = 1 returns 1 (the loop read as stopping at k = 1, so the
+    newest column is always kept).  A NaN product (0 * inf) does not pass."""
     with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
         b = length_bounds(fnorm, cs)
         m = len(fnorm)
@@ -389,6 +393,8 @@ def length_filter(enorm, fnorm, cs, kappa_bar):
             if C <= kappa_bar * kappa_bar:
                 break
             k -= 1
+    if k < floor and m > 0:
+        k = floor
     return k
 
 
@@ -407,6 +413,7 @@ class Options:
     cs: float = 0.2
     kappa_bar: float = 1e8
     angle_mode: int = 0  # 0: Alg 4 with one factorisation; 1: refreshed after each removal
+    length_floor: int = 0  # Alg 5 when no k passes: 0 keeps nothing, 1 keeps the newest column
     tau: float = 0.0  # <= 0: 0.9 / ||K|| by power iteration
     sigma: float = 0.0
     tol: float = 1e-4
@@ -466,6 +473,7 @@ class Solver:
         self.last_gamma = None
         self.last_kkt = None
         self.kkt_trace = []  # (k, kkt dict without lambda)
+        self.faa_empty = 0  # FAA steps whose filters kept no column
 
     # -- Alg 2, initialisation ------------------------------------------------
     def start(self):
@@ -611,7 +619,10 @@ class Solver:
         E, F = reverse(dU, dG)  # newest first
         keep = angle_filter(E, F, o.cs, sequential=o.angle_mode == 1)
         E, F = E[:, keep], F[:, keep]
-        mbar = length_filter(np.linalg.norm(E, axis=0), np.linalg.norm(F, axis=0), o.cs, o.kappa_bar)
+        mbar = length_filter(np.linalg.norm(E, axis=0), np.linalg.norm(F, axis=0), o.cs, o.kappa_bar,
+                             floor=o.length_floor)
+        if mbar == 0:
+            self.faa_empty += 1
         E, F = E[:, :mbar], F[:, :mbar]
         dU, dG = reverse(E, F)  # oldest first again
         # the filtered columns become the memory

@@ -12,8 +12,10 @@ aapdhg_result_device), Batch (aapdhg_batch_*), Server (aapdhg_server_*).
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -39,7 +41,8 @@ class Options(C.Structure):
                 ("pw_theta", C.c_double), ("pw_eps_zero", C.c_double), ("pw_omega0", C.c_double),
                 ("pw_rho", C.c_double), ("sg_div", C.c_double), ("pw_dhat", C.c_int32),
                 ("restart_period", C.c_int32), ("prep_device", C.c_int32), ("pock_chambolle", C.c_int32),
-                ("angle_mode", C.c_int32), ("seed", C.c_uint64)]
+                ("angle_mode", C.c_int32), ("seed", C.c_uint64), ("length_floor", C.c_int32),
+                ("reserved1", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -48,7 +51,8 @@ class Info(C.Structure):
                 ("dual_obj", C.c_double), ("r_gap", C.c_double), ("r_pri", C.c_double),
                 ("r_dual", C.c_double), ("kkt", C.c_double), ("gnorm", C.c_double),
                 ("g0norm", C.c_double), ("solve_seconds", C.c_double), ("step_tau", C.c_double),
-                ("step_sigma", C.c_double), ("omega", C.c_double), ("pw_updates", C.c_int64)]
+                ("step_sigma", C.c_double), ("omega", C.c_double), ("pw_updates", C.c_int64),
+                ("faa_empty", C.c_int64)]
 
     def to_dict(self):
         d = {name: getattr(self, name) for name, _ in self._fields_ if not name.startswith("reserved")}
@@ -68,6 +72,10 @@ EXPORTS = [
 ]
 
 _lib = None
+# Every open handle, so that the ones a program leaves open are destroyed by an
+# exit hook while the HIP runtime is still up (Python runs it before the
+# process's C exit handlers), never by a finaliser during interpreter teardown.
+_open = {"server": weakref.WeakSet(), "batch": weakref.WeakSet(), "solver": weakref.WeakSet()}
 _P = C.c_void_p
 _dp = C.POINTER(C.c_double)
 _i64p = C.POINTER(C.c_int64)
@@ -197,6 +205,7 @@ class Solver:
         self.h = h
         self.options = opt
         self.memory = int(opt.memory)
+        _open["solver"].add(self)
 
     @classmethod
     def from_device(cls, m, n, rowptr, colidx, val, c, q, l, u, rowtype, stream=None,
@@ -229,6 +238,7 @@ class Solver:
         self.h = h
         self.options = opt
         self.memory = int(opt.memory)
+        _open["solver"].add(self)
         return self
 
     def result_device(self, stream=None):
@@ -308,7 +318,7 @@ class Solver:
         st = {"u": np.empty(N), "u_prev": np.empty(N), "g_prev": np.empty(N),
               "dG": np.empty(M * N), "W": np.empty(M * N),
               "meta": np.zeros(8 + 2 * MAX_MEMORY, dtype=np.int64),
-              "gram": np.zeros(MAX_MEMORY * MAX_MEMORY + 2 * MAX_MEMORY + 2)}
+              "gram": np.zeros(MAX_MEMORY * MAX_MEMORY + 3 * MAX_MEMORY + 2)}
         _check(lib().aapdhg_get_state(self.h, _ptr(st["u"], C.c_double), _ptr(st["u_prev"], C.c_double),
                                       _ptr(st["g_prev"], C.c_double), _ptr(st["dG"], C.c_double),
                                       _ptr(st["W"], C.c_double), _ptr(st["meta"], C.c_int64),
@@ -316,8 +326,11 @@ class Solver:
         st["dG"] = st["dG"].reshape(M, N)
         st["W"] = st["W"].reshape(M, N)
         meta = st["meta"]
+        nmix = int(meta[7])
         st.update(k=int(meta[0]), status=int(meta[1]), i=int(meta[2]), j=int(meta[3]), nlive=int(meta[4]),
-                  newslot=int(meta[5]), live=[int(v) for v in meta[8:8 + int(meta[4])]])
+                  newslot=int(meta[5]), branch=int(meta[6]), nmix=nmix,
+                  live=[int(v) for v in meta[8:8 + int(meta[4])]],
+                  mixslot=[int(v) for v in meta[8 + MAX_MEMORY:8 + MAX_MEMORY + nmix]])
         g = st["gram"]
         S = MAX_MEMORY
         st["G"] = g[:S * S].reshape(S, S)
@@ -325,6 +338,7 @@ class Solver:
         st["du2"] = g[S * S + S:S * S + 2 * S]
         st["n0"] = float(g[S * S + 2 * S])
         st["gnorm"] = float(g[S * S + 2 * S + 1])
+        st["gamma"] = g[S * S + 2 * S + 2:S * S + 2 * S + 2 + nmix].copy()
         return st
 
     def get_weights(self, anchor=True):
@@ -369,6 +383,7 @@ class Batch:
         h = C.c_void_p()
         _check(lib().aapdhg_batch_create(len(self.solvers), arr, C.byref(h)), None)
         self.h = h
+        _open["batch"].add(self)
 
     def solve(self, stream=None):
         _check(lib().aapdhg_batch_solve(self.h, _stream(stream)), None)
@@ -415,6 +430,7 @@ class Server:
         _check(lib().aapdhg_server_start(int(hbm_budget_bytes), int(max_slots), C.byref(opt), C.byref(h)), None)
         self.h = h
         self._dims = {}
+        _open["server"].add(self)
 
     def submit(self, lp) -> int:
         a = _lp_arrays(lp)
@@ -458,3 +474,14 @@ class Server:
     def __del__(self):
         if lib is not None:  # module globals are gone during interpreter teardown
             self.close()
+
+
+def close_all():
+    """Destroy every handle still open: servers (their worker threads stop
+    first), then batches, then solvers.  Runs at interpreter exit."""
+    for kind in ("server", "batch", "solver"):
+        for obj in list(_open[kind]):
+            obj.close()
+
+
+atexit.register(close_all)

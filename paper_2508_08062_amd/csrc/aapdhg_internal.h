@@ -72,6 +72,7 @@ struct alignas(256) Scalars {
   long long pw_updates;   // accepted weight updates
   int pw_flag;            // 1: the weight changed before this pass (memory reset pending)
   int pw_blend;           // set by the pass that re-blended D-hat: 1 alpha = 0.9, 2 alpha = 0.1
+  long long faa_empty;    // FAA steps whose filters kept no column
 };
 
 // Per-LP immutable description (device copy).  Vectors of length N = n + m
@@ -91,6 +92,7 @@ struct LPDesc {
   // epoch's iterates so far (length N, float64)
   int restart;
   int angle_mode;  // FAA angle filter: 0 one factorisation, 1 refreshed after each removal
+  int length_floor;  // FAA length filter keeps at least this many columns (0 or 1)
   double* rsum;
   const int* rowptr;  // CSR of K, rows in the order rmapB
   const int* colidx;

@@ -105,6 +105,8 @@ void default_options(aapdhg_options* o) {
   o->prep_device = 2;
   o->pock_chambolle = 0;
   o->angle_mode = 0;
+  o->length_floor = 0;
+  o->reserved1 = 0;
   o->seed = 0;
 }
 
@@ -113,6 +115,7 @@ static void check_options(const aapdhg_options& o) {
   if (o.prep_device < 0 || o.prep_device > 2) throw Error(AAPDHG_E_ARG, "prep_device must be 0, 1 or 2");
   if (o.pock_chambolle != 0 && o.pock_chambolle != 1) throw Error(AAPDHG_E_ARG, "pock_chambolle must be 0 or 1");
   if (o.angle_mode != 0 && o.angle_mode != 1) throw Error(AAPDHG_E_ARG, "angle_mode must be 0 or 1");
+  if (o.length_floor != 0 && o.length_floor != 1) throw Error(AAPDHG_E_ARG, "length_floor must be 0 or 1");
   if (o.variant == AAPDHG_VARIANT_RPDHG && o.restart_period < 1)
     throw Error(AAPDHG_E_ARG, "restart_period must be >= 1 for restarted PDHG");
   if (o.precision != 0 && o.precision != 1) throw Error(AAPDHG_E_ARG, "precision must be 0 or 1");
@@ -655,6 +658,7 @@ void Problem::fill_desc() {
   desc.cs = opt.cs;
   desc.kappa_bar = opt.kappa_bar;
   desc.angle_mode = opt.angle_mode;
+  desc.length_floor = opt.length_floor;
   desc.tol = opt.tol;
   desc.sg_div = opt.sg_div;
   desc.pw_period = opt.pw_period;
@@ -781,6 +785,7 @@ void Problem::reset_host_state() {
   sc_init.dha[0] = sc_init.dha[1] = 1.0;
   sc_init.dhb[0] = sc_init.dhb[1] = 0.0;
   sc_init.pw_updates = 0;
+  sc_init.faa_empty = 0;
   sc_init.pw_flag = 0;
   sc_init.pw_blend = 0;
 }
@@ -1269,6 +1274,7 @@ static void fill_info(const Scalars& s, double secs, aapdhg_info* info) {
   info->step_sigma = s.sigma;
   info->omega = s.omega;
   info->pw_updates = s.pw_updates;
+  info->faa_empty = s.faa_empty;
 }
 
 // Results into caller device memory: the evaluation pass at the current
@@ -1381,7 +1387,10 @@ void Problem::get_state(double* u, double* u_prev, double* g_prev, double* dG, d
     meta[3] = s.j_pdhg;
     meta[4] = s.nlive;
     meta[5] = s.newslot;
+    meta[6] = s.branch;
+    meta[7] = s.nmix;
     for (int t = 0; t < MAXM; ++t) meta[8 + t] = s.live[t];
+    for (int t = 0; t < s.nmix && t < MAXM; ++t) meta[8 + MAXM + t] = s.mixslot[t];
   }
   if (gram) {
     std::memcpy(gram, s.G, sizeof s.G);
@@ -1389,6 +1398,7 @@ void Problem::get_state(double* u, double* u_prev, double* g_prev, double* dG, d
     std::memcpy(gram + MAXM * MAXM + MAXM, s.du2, sizeof s.du2);
     gram[MAXM * MAXM + 2 * MAXM] = s.n0;
     gram[MAXM * MAXM + 2 * MAXM + 1] = s.gnorm;
+    for (int t = 0; t < MAXM; ++t) gram[MAXM * MAXM + 2 * MAXM + 2 + t] = t < s.nmix ? s.gamma[t] : 0.0;
   }
 }
 

@@ -293,6 +293,8 @@ __device__ int faa_filter(const LPDesc& d, const Scalars* sc, int nl, SolveWork*
       if (se * sb <= kb2) break;
       --kk;
     }
+    // reading of Alg 5 when no k passes: none kept (floor 0) or the newest (floor 1)
+    if (kk < d.length_floor && nk > 0) kk = d.length_floor;
     w->kk = kk;
   }
   wave_sync();
@@ -457,9 +459,11 @@ __device__ void final_step(const LPDesc& d, Scalars* sc, const double* f, bool e
           nmix = nl;
         }
       } else {
+        const int nl_in = nl;
         nl = faa_filter(d, sc, nl, w, lane);  // the survivors become the memory
         if (nl == 0) {
           aa = true;  // no history left: u_AA = u^k + beta D-hat g^k
+          if (L0 && nl_in > 0) sc->faa_empty += 1;
         } else if (solve_gamma(sc, w->live, nl, 0.0, w, lane)) {
           aa = true;
           nmix = nl;

@@ -90,3 +90,17 @@ def brute_force_opt(lp, tol=1e-9):
         if best is None or v < best - tol:
             best, best_x = v, x
     return best, best_x
+
+
+def entrywise_err(got, ref, floor):
+    """Largest entry-wise error max_i |got_i - ref_i| / (|ref_i| + floor * max_j |ref_j|):
+    a value below rtol means every entry agrees to rtol relative to its own size, or to
+    rtol * floor of the vector's largest entry for entries smaller than that."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    assert got.shape == ref.shape
+    if ref.size == 0:
+        return 0.0
+    scale = np.abs(ref) + floor * float(np.abs(ref).max())
+    d = np.abs(got - ref)
+    return float(np.max(np.where(scale > 0, d / np.where(scale > 0, scale, 1.0), np.where(d > 0, np.inf, 0.0))))

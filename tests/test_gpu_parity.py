@@ -10,7 +10,7 @@ import pytest
 
 import lpgen
 import oracle
-from _util import golden
+from _util import entrywise_err, golden
 
 pytestmark = pytest.mark.gpu
 
@@ -141,6 +141,30 @@ def test_faa_filters_removing_columns_on_most_steps_fp64(angle_mode):
     assert all(a == b for a, b in lens), lens
     assert sum(1 for a, _ in lens[10:] if a < 10) >= 5, lens  # the filter did remove columns
     assert max(errs) < 1e-8, errs
+    g.close()
+
+
+@pytest.mark.parametrize("floor", [0, 1])
+def test_faa_length_filter_readings_fp64(floor):
+    """kappa-bar so small that the length filter never passes (every step an
+    FAA step): floor 0 empties the memory on every step, floor 1 keeps the
+    newest pair; the GPU follows the oracle under both readings, pass for
+    pass, and counts the emptied steps as the oracle does."""
+    lp = lpgen.mip_like_lp(12, m=1500, n=3500, nnz=20000, fp32=False)
+    tau = 0.9 / oracle.power_norm(oracle.Problem.from_lpdata(lp))
+    common = dict(variant=2, memory=6, tau=tau, sigma=tau, kkt_every=1, tol=0.0, max_iter=10 ** 6,
+                  kappa_bar=1e-30, D=1e6, length_floor=floor)
+    g = _gpu(lp, precision=1, **common)
+    o = _oracle(lp, **common)
+    o.start()
+    g.iterate(1)
+    for _ in range(30):
+        o.step()
+        g.iterate(1)
+        st = g.get_state()
+        assert entrywise_err(st["u"], np.r_[o.state.x, o.state.y], 1e-3) < 1e-9
+        assert len(st["live"]) == len(o.state.dG) == floor
+    assert g.result()["faa_empty"] == o.faa_empty == (30 if floor == 0 else 0)
     g.close()
 
 

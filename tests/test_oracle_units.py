@@ -567,6 +567,59 @@ def test_faa_memory_never_exceeds_limit_and_filters_bind():
     assert min(sizes[10:]) < 6  # the filters removed columns
 
 
+def test_length_filter_floor_reading():
+    """Alg 5 when no k passes: the count-down loop runs out (0 columns) or,
+    with the floor reading, stops at k = 1; when some k passes both readings
+    give that k."""
+    rng = np.random.default_rng(11)
+    F = _angled_columns(rng, 30, 5, 0.3)
+    E = rng.standard_normal((30, 5))
+    en, fn = np.linalg.norm(E, axis=0), np.linalg.norm(F, axis=0)
+    assert oracle.length_filter(en, fn, 0.3, 1e-30) == 0
+    assert oracle.length_filter(en, fn, 0.3, 1e-30, floor=1) == 1
+    for kbar in (1e300, 1e3, 10.0):
+        assert oracle.length_filter(en, fn, 0.3, kbar, floor=1) == max(1, oracle.length_filter(en, fn, 0.3, kbar))
+    assert oracle.length_filter(np.zeros(0), np.zeros(0), 0.3, 1e-30, floor=1) == 0  # no column to keep
+
+
+def test_faa_floor_one_keeps_the_newest_pair_in_closed_form():
+    """kappa-bar so small that no k passes: with m-bar = 1 the FAA step
+    mixes the newest pair alone, gamma = <f, g> / <f, f> (one-column least
+    squares), u+ = P(u + beta D g - (du + beta D f) gamma); with m-bar = 0
+    it is u+ = P(u + beta D g).  Both are written out here from the
+    definitions, and the memory after the step holds that one pair or
+    nothing."""
+    P = oracle.Problem.from_lpdata(lpgen.tiny_lp(2))
+    n = P.n
+    for floor in (0, 1):
+        f = oracle.Solver(P, oracle.Options(variant=oracle.VARIANT_FAA, cs=0.2, kappa_bar=1e-300, memory=5,
+                                            D=math.inf, kkt_every=0, dhat_mode=1, beta=0.7, length_floor=floor))
+        f.start()
+        for _ in range(6):
+            f.step()
+        S = f.state
+        u = np.r_[S.x, S.y]
+        # the pair the next step appends, and its residual, from the map itself
+        xh, yh = oracle.pdhg_map(P, S.x, S.y, f.opt.tau, f.opt.sigma)
+        g = np.r_[xh, yh] - u
+        du, dg = u - S.u_prev, g - S.g_prev
+        D = f.Dhat
+        if floor == 1:
+            gam = float(dg @ g) / float(dg @ dg)
+            want = u + 0.7 * D * g - (du + 0.7 * D * dg) * gam
+        else:
+            want = u + 0.7 * D * g
+        want = np.r_[oracle.proj_X(P, want[:n]), oracle.proj_Y(P, want[n:])]
+        empty0 = f.faa_empty
+        f.step()
+        assert f.last_branch == "aa"
+        np.testing.assert_allclose(np.r_[f.state.x, f.state.y], want, rtol=1e-12, atol=1e-14)
+        assert len(f.state.dG) == floor
+        assert f.faa_empty == empty0 + (1 - floor)
+        if floor == 1:
+            np.testing.assert_allclose(f.state.dG[0], dg, rtol=0, atol=0)
+
+
 # ---------------------------------------------------------------------------
 # power iteration and Ruiz equilibration (Sections 5.1, 5.2)
 # ---------------------------------------------------------------------------

@@ -47,7 +47,9 @@ MUTATIONS = [
      "(ct + cs) ** (2 * (j - i))"),
     ("length bound: power of cs in the sum one lower", "cs ** (2 * (j - i)))", "cs ** (2 * (j - i - 1)))"),
     ("length bound: norm of the wrong column in the sum", "/ (fnorm[i - 1] ** 2 *", "/ (fnorm[i] ** 2 *"),
-    ("length filter: keeps one more", "            k -= 1\n    return k", "            k -= 1\n    return min(k + 1, m)"),
+    ("length filter: keeps one more", "        k = floor\n    return k", "        k = floor\n    return min(k + 1, m)"),
+    ("length filter: floor of one under either reading", "if k < floor and m > 0:\n        k = floor",
+     "if k < 1 and m > 0:\n        k = 1"),
     ("power iteration: eigenvalue for norm", "new = math.sqrt(nz)", "new = nz"),
     ("Ruiz: column factor inverted", "        d_col = d_col / s\n", "        d_col = d_col * s\n"),
     ("restart: average over R + 1", "avg = S.rsum / R", "avg = S.rsum / (R + 1)"),
