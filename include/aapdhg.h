@@ -237,6 +237,21 @@ aapdhg_status aapdhg_result_device(aapdhg_t h, double *x, double *y, double *lam
  * reset handle the first pass is the init step.  Passes after termination do nothing. */
 aapdhg_status aapdhg_iterate(aapdhg_t h, void *stream, int64_t iters);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same passes as aapdhg_iterate, with
+ * the same results bit for bit, but the passes' scratch (partial-sum records, reduction and
+ * split counters, the persistent kernel's barrier counters and published decisions) lives in
+ * a static device array of the library instead of the handle's buffers.  The call allocates
+ * nothing: it clears the part of the array the LP needs with a fill kernel on `stream` and
+ * enqueues the passes (asynchronous, like aapdhg_iterate).  The array holds 2 MiB per GPU
+ * (kept until the process ends); an LP whose pass tables need more is AAPDHG_E_ARG with the
+ * size in the message.  The need is 384 bytes per workgroup of a pass and per row or column
+ * longer than 2048 entries, plus 16 bytes per 2048 entries of n + m: about 0.8 MiB for a
+ * 1M x 2M LP with 20M entries, 0.2 MiB for a 20k x 50k LP.  Every call on one
+ * GPU uses the same array: calls that overlap on one GPU (other streams, other host threads)
+ * race and must be serialised by the caller; consecutive calls on one stream are safe. */
+aapdhg_status aapdhg_iterate_noalloc(aapdhg_t h, void* stream, int64_t iters);
+
 /* Measurement variant of aapdhg_iterate: `iters` loop passes (after the init step, which is
  * run first and not timed on a fresh or reset handle) with HIP events recorded on `stream`
  * around the launches; waits for completion and fills ms4[0..3]:

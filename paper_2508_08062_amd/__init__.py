@@ -61,7 +61,8 @@ class Info(C.Structure):
 
 
 EXPORTS = [
-    "aapdhg_default_options", "aapdhg_create", "aapdhg_solve", "aapdhg_iterate", "aapdhg_iterate_timed",
+    "aapdhg_default_options", "aapdhg_create", "aapdhg_solve", "aapdhg_iterate", "aapdhg_iterate_noalloc",
+    "aapdhg_iterate_timed",
     "aapdhg_reset",
     "aapdhg_result", "aapdhg_create_device", "aapdhg_result_device", "aapdhg_get_state", "aapdhg_set_state",
     "aapdhg_get_weights", "aapdhg_set_weights",
@@ -95,6 +96,7 @@ def lib():
                                 _dp, _dp, _dp, _dp, _dp, C.POINTER(C.c_uint8), C.POINTER(Options), C.POINTER(_P)]
     L.aapdhg_solve.argtypes = [_P, _P]
     L.aapdhg_iterate.argtypes = [_P, _P, C.c_int64]
+    L.aapdhg_iterate_noalloc.argtypes = [_P, _P, C.c_int64]
     L.aapdhg_iterate_timed.argtypes = [_P, _P, C.c_int64, _dp]
     L.aapdhg_reset.argtypes = [_P, _P]
     L.aapdhg_result.argtypes = [_P, _dp, _dp, _dp, C.POINTER(Info)]
@@ -277,6 +279,12 @@ class Solver:
 
     def iterate(self, iters: int, stream=None):
         _check(lib().aapdhg_iterate(self.h, _stream(stream), int(iters)), self.h)
+        return self
+
+    def iterate_noalloc(self, iters: int, stream=None):
+        """The passes of iterate() with the pass scratch in the library's
+        static device array (aapdhg_iterate_noalloc): no allocation."""
+        _check(lib().aapdhg_iterate_noalloc(self.h, _stream(stream), int(iters)), self.h)
         return self
 
     def iterate_timed(self, iters: int, stream=None):

@@ -797,6 +797,58 @@ void Problem::enqueue_reset(hipStream_t st) {
   pending_init = true;
 }
 
+// The passes of aapdhg_iterate with the per-pass scratch of the launch
+// tables (partial-sum records, reduction-tree and split counters, split and
+// weight-check partials and, for the persistent kernel, its barrier
+// counters, published decisions, weight-check partials and error word) in
+// the library's static device array instead of the handle's buffers.
+// Nothing is allocated: the array's used range is cleared by a fill kernel
+// on `st`, then the passes are enqueued.
+void Problem::iterate_noalloc(hipStream_t st, int64_t iters) {
+  void* base = nullptr;
+  hip_check(static_scratch(&base), "static scratch address");
+  LaunchSet& L = *solo;
+  LaunchTables t = L.t;
+  size_t off = 0;
+  auto take = [&](const DevBuf& b) -> void* {
+    if (!b.p) return nullptr;
+    void* p = (char*)base + off;
+    off += (b.bytes + 255) & ~(size_t)255;
+    return p;
+  };
+  t.rec = (double*)take(L.d_rec);
+  t.ncnt = (unsigned int*)take(L.d_ncnt);
+  t.splitpart = (double*)take(L.d_splitpart);
+  t.splitcnt = (unsigned int*)take(L.d_splitcnt);
+  t.pwpart = (double*)take(L.d_pwpart);
+  t.pwcnt = (unsigned int*)take(L.d_pwcnt);
+  if (t.persistent) {
+    t.sync = (LoopSync*)take(L.d_sync);
+    t.bc = (BcastMsg*)take(L.d_bc);
+    t.err = (int*)take(L.d_err);
+    t.pwrec = (double*)take(L.d_pwrec);
+  }
+  if (off > STATIC_SCRATCH_BYTES)
+    throw Error(AAPDHG_E_ARG, "this LP needs %zu bytes of pass scratch; the no-allocation entry point has %zu",
+                off, STATIC_SCRATCH_BYTES);
+  hip_check(launch_zero(base, off, st), "clear static scratch");
+  if (!started) enqueue_reset(st);
+  if (pending_init && iters > 0) {  // the init step is the first pass
+    hip_check(launch_loop_pass(t, st, MODE_ITER), "initial pass");
+    pending_init = false;
+    --iters;
+  }
+  if (t.persistent) {
+    for (int64_t done = 0; done < iters;) {
+      const int64_t np = std::min<int64_t>(iters - done, LaunchSet::MAX_LOOP_PASSES);
+      hip_check(launch_loop(t, st, np, L.next_tag()), "loop launch");
+      done += np;
+    }
+    return;
+  }
+  for (int64_t it = 0; it < iters; ++it) hip_check(launch_loop_pass(t, st, MODE_ITER), "loop pass");
+}
+
 // Alg 2 set-up: u^1 = T u^0, g^0 and ||g^0|| (the pass with k = 0), on the
 // LP's own three-launch tables.
 void Problem::enqueue_init(hipStream_t st) {
@@ -1603,6 +1655,15 @@ aapdhg_status aapdhg_iterate(aapdhg_t h, void* stream, int64_t iters) {
       --iters;
     }
     h->p.solo->enqueue_passes(st, iters);
+  });
+}
+
+aapdhg_status aapdhg_iterate_noalloc(aapdhg_t h, void* stream, int64_t iters) {
+  if (!h) return AAPDHG_E_ARG;
+  return guard(&h->err, [&] {
+    if (iters < 0) throw Error(AAPDHG_E_ARG, "iters must be >= 0");
+    if (h->p.in_batch) throw Error(AAPDHG_E_STATE, "problem belongs to a live batch");
+    h->p.iterate_noalloc((hipStream_t)stream, iters);
   });
 }
 

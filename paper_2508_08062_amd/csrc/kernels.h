@@ -58,6 +58,15 @@ int loop_capacity(bool fp64, int mt, bool ext);
 // that the device holds at once (0 if the query fails).
 int pass_capacity(bool fp64, int mt, int pass);
 hipError_t launch_start_point(const LPDesc& d, bool fp64, hipStream_t st);
+// Zero `bytes` (a multiple of 4) of device memory with a fill kernel on `st`.
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+
+// Scratch of the no-allocation entry point: a file-scope device array of
+// STATIC_SCRATCH_BYTES per device, held until the process ends.  *out
+// receives its address on the current device (looked up once per device).
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)2 << 20;
+constexpr int MAX_DEVICES = 64;
+hipError_t static_scratch(void** out);
 
 // Scaling of K before the solve: ruiz_iters Ruiz sweeps, then (pock_chambolle)
 // one Pock-Chambolle step with alpha = 1, on the float64 CSR values `val`;

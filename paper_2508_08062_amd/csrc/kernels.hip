@@ -23,6 +23,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "aapdhg_internal.h"
 #include "kernels.h"
@@ -2030,6 +2031,48 @@ int loop_capacity(bool fp64, int mt, bool ext) {
   return nb * cus;
 }
 
+// Zero `words` 32-bit words at p (a fill kernel rather than a memset, so that
+// the clear is an ordinary kernel node when a caller captures the stream).
+__global__ void k_zero_u32(unsigned int* p, size_t words) {
+  for (size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x; i < words; i += (size_t)gridDim.x * BLOCK) p[i] = 0u;
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
+  const size_t words = bytes / 4;
+  if (words == 0) return hipSuccess;
+  const size_t blocks = (words + BLOCK - 1) / BLOCK;
+  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)(blocks < 1024 ? blocks : 1024)), dim3(BLOCK), 0, st,
+                     (unsigned int*)p, words);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// scratch of the no-allocation entry point (aapdhg_iterate_noalloc)
+// ---------------------------------------------------------------------------
+//
+// One array per device, alive until the process ends.  Host code never uses
+// the array's name as an address: static_scratch() looks the device address
+// up once per device (with that device current) and hands it out.
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+hipError_t static_scratch(void** out) {
+  static std::mutex mu;
+  static void* addr[MAX_DEVICES] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return hipSuccess;
+}
+
 hipError_t launch_loop(const LaunchTables& t, hipStream_t st, long long passes, unsigned int tag0) {
   LoopArgs la{};
   la.lps = t.lps;
@@ -2049,7 +2092,7 @@ hipError_t launch_loop(const LaunchTables& t, hipStream_t st, long long passes, 
   la.max_passes = passes;
   la.timeout_ticks = t.timeout_ticks;
   la.tag0 = tag0;
-  hipError_t e = hipMemsetAsync(t.sync, 0, sizeof(LoopSync) * (size_t)t.nlps, st);
+  hipError_t e = launch_zero(t.sync, sizeof(LoopSync) * (size_t)t.nlps, st);
   if (e != hipSuccess) return e;
   void* args[] = {&la};
   return hipLaunchCooperativeKernel(loop_kernel_for(t.fp64, t.mt, t.ext), dim3(t.nwgs), dim3(BLOCK), args, 0, st);

@@ -128,6 +128,7 @@ struct Problem {
   void reset_host_state();
   void enqueue_reset(hipStream_t st);
   void enqueue_init(hipStream_t st);
+  void iterate_noalloc(hipStream_t st, int64_t iters);
   void read_scalars(Scalars& s);
   void download(const void* dev, size_t len, double* host, hipStream_t st);
   void upload_vec(void* dev, const double* host, size_t len, hipStream_t st);
