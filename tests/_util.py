@@ -104,3 +104,26 @@ def entrywise_err(got, ref, floor):
     scale = np.abs(ref) + floor * float(np.abs(ref).max())
     d = np.abs(got - ref)
     return float(np.max(np.where(scale > 0, d / np.where(scale > 0, scale, 1.0), np.where(d > 0, np.inf, 0.0))))
+
+
+def norm_rel(got, ref):
+    """||got - ref||_2 / ||ref||_2."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.linalg.norm(got - ref) / max(float(np.linalg.norm(ref)), 1e-300))
+
+
+def err64(got, ref):
+    """Float64 path against the oracle: the larger of the 2-norm relative
+    error and the entry-wise error with a floor of 1e-3 of the largest entry."""
+    return max(norm_rel(got, ref), entrywise_err(got, ref, 1e-3))
+
+
+def err32(got, ref):
+    """Float32 path against the oracle: the largest of the 2-norm relative
+    error, the largest entry error relative to the largest entry (infinity
+    norm), and a tenth of the entry-wise error with a floor of 1e-2 of the
+    largest entry.  Below 1e-5 it means: the iterate agrees to 1e-5 in norm,
+    no entry is off by more than 1e-5 of the largest, and every entry agrees
+    to 1e-4 of its own size or of 1/100 of the largest entry."""
+    return max(norm_rel(got, ref), entrywise_err(got, ref, 1.0), 0.1 * entrywise_err(got, ref, 1e-2))

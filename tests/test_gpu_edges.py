@@ -9,14 +9,11 @@ import pytest
 
 import lpgen
 import oracle
+from _util import err64
 
 pytestmark = pytest.mark.gpu
 
 P = pytest.importorskip("paper_2508_08062_amd")
-
-
-def _rel(a, b):
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
 def _pair(lp, steps, tau, loop_kernel, **kw):
@@ -30,7 +27,7 @@ def _pair(lp, steps, tau, loop_kernel, **kw):
         o.step()
         g.iterate(1)
         st = g.get_state()
-        errs.append(_rel(st["u"], np.r_[o.state.x, o.state.y]))
+        errs.append(err64(st["u"], np.r_[o.state.x, o.state.y]))
         assert (st["i"], st["j"]) == (o.state.i, o.state.j)
     return errs, g
 

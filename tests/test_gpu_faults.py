@@ -17,14 +17,11 @@ import pytest
 
 import lpgen
 import oracle
+from _util import entrywise_err, norm_rel
 
 pytestmark = pytest.mark.gpu
 
 P = pytest.importorskip("paper_2508_08062_amd")
-
-
-def _rel(a, b):
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
 @pytest.mark.parametrize("loop_kernel", [0, 1])
@@ -83,7 +80,8 @@ def test_zero_history_takes_the_pdhg_branch(loop_kernel):
     st2 = g.get_state()
     assert (st2["i"], st2["j"]) == (st["i"], st["j"] + 1) == (o.state.i, o.state.j)
     assert st2["nlive"] == 3  # the memory was still updated
-    assert _rel(st2["u"], np.r_[o.state.x, o.state.y]) < 1e-13
+    ref = np.r_[o.state.x, o.state.y]
+    assert norm_rel(st2["u"], ref) < 1e-13 and entrywise_err(st2["u"], ref, 1e-3) < 1e-12
     g.close()
 
 
@@ -114,7 +112,7 @@ def test_infeasible_lp_ends_at_the_iteration_limit(variant, precision):
     # float32 each pass rounds an increment of about 0.4 at that magnitude
     # (ulp 6e-5), and 3000 passes (AA steps among them) accumulate it
     tol = 1e-9 if precision == 1 else 5e-3
-    assert _rel(r["y"], ro["y"]) < tol
+    assert norm_rel(r["y"], ro["y"]) < tol and entrywise_err(r["y"], ro["y"], 1.0) < tol
     g.close()
 
 

@@ -1,16 +1,21 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
-same seeded inputs, element by element.  Tolerances:
-  * float64 path: iterates to 1e-9 relative (summation order differs; AA
-    least-squares conditioning amplifies rounding);
-  * float32 path: iterates to 1e-5 relative over the first 50 loop passes
-    (float32 storage of data, iterates and history; float64 reductions).
+same seeded inputs, element by element.  Tolerances (tests/_util.py):
+  * float64 path (err64): every entry to 1e-9 of its own size or of 1e-3 of
+    the largest entry, and the vector to 1e-9 in norm (summation order
+    differs; AA least-squares conditioning amplifies rounding);
+  * float32 path (err32) over the first 50 loop passes: the iterate to 1e-5
+    in norm, no entry off by more than 1e-5 of the largest entry, every
+    entry to 1e-4 of its own size or of 1/100 of the largest (float32
+    storage of data, iterates and history; float64 reductions).  Entries
+    near zero are differences of terms of the size of the vector's entries,
+    so their float32 rounding is relative to those terms.
 """
 import numpy as np
 import pytest
 
 import lpgen
 import oracle
-from _util import entrywise_err, golden
+from _util import entrywise_err, err32, err64, golden, norm_rel
 
 pytestmark = pytest.mark.gpu
 
@@ -23,10 +28,6 @@ def _gpu(lp, **kw):
 
 def _oracle(lp, **kw):
     return oracle.Solver(oracle.Problem.from_lpdata(lp), oracle.Options(**kw))
-
-
-def _rel(a, b):
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
 def _trajectories(lp, steps, precision, variant=1, memory=5, **kw):
@@ -80,7 +81,7 @@ def test_toy_lp_hand_trace_on_gpu():
 def test_tiny_fp64_trajectory_50(seed, loop_kernel):
     lp = lpgen.tiny_lp(seed)
     ug, uo, ctr, _, _ = _trajectories(lp, 50, precision=1, memory=5, loop_kernel=loop_kernel)
-    errs = [_rel(a, b) for a, b in zip(ug, uo)]
+    errs = [err64(a, b) for a, b in zip(ug, uo)]
     assert max(errs) < 1e-9, errs
     for (gi, oi) in ctr:
         assert gi == oi
@@ -91,7 +92,7 @@ def test_tiny_fp64_trajectory_50(seed, loop_kernel):
 def test_mip_like_fp32_trajectory_50(variant, loop_kernel):
     lp = lpgen.mip_like_lp(11, m=2000, n=5000, nnz=25000)
     ug, uo, ctr, _, _ = _trajectories(lp, 50, precision=0, variant=variant, memory=10, loop_kernel=loop_kernel)
-    errs = [_rel(a, b) for a, b in zip(ug, uo)]
+    errs = [err32(a, b) for a, b in zip(ug, uo)]
     assert max(errs) < 1e-5, (max(errs), int(np.argmax(errs)))
     assert ctr[-1][0] == ctr[-1][1]
 
@@ -99,19 +100,31 @@ def test_mip_like_fp32_trajectory_50(variant, loop_kernel):
 @pytest.mark.parametrize("loop_kernel", [0, 1])
 def test_mip_like_fp32_trajectory_faa_refreshed_angle_filter(loop_kernel):
     """FAA-PDHG in float32 with the refreshed angle filter (angle_mode 1)
-    and every step accelerated, so the filter runs on each pass."""
+    and every step accelerated, so the filter runs on each pass.  Free
+    running, the Anderson steps amplify the float32 rounding of the iterates
+    pass after pass (measured: 4.6e-6 in norm and 1.5e-5 of the largest
+    entry after 50 passes), so the bar is 1e-5 in norm and 1e-4 of the
+    largest entry; one pass at a time from the GPU's own state (teacher
+    forcing) every entry agrees to 1e-3 of its size or of 1e-3 of the
+    largest entry: the right-hand sides <dG_t, g^k> are kept up to date
+    with the new float32 difference column (reading 20), whose rounding
+    each update adds, and when an Anderson step cuts the residual by a
+    large factor that error is large next to <dG_t, g^k> (measured up to
+    1e-4 of an entry in one pass).  The standard configurations hold 1e-5
+    under teacher forcing (the ragged LP below)."""
     lp = lpgen.mip_like_lp(11, m=2000, n=5000, nnz=25000)
-    ug, uo, ctr, _, _ = _trajectories(lp, 50, precision=0, variant=2, memory=10, loop_kernel=loop_kernel,
+    ug, uo, ctr, g, o = _trajectories(lp, 50, precision=0, variant=2, memory=10, loop_kernel=loop_kernel,
                                       angle_mode=1, cs=0.5, D=1e6)
-    errs = [_rel(a, b) for a, b in zip(ug, uo)]
-    assert max(errs) < 1e-5, (max(errs), int(np.argmax(errs)))
-    assert all(g == o for g, o in ctr), ctr
+    assert max(norm_rel(a, b) for a, b in zip(ug, uo)) < 1e-5
+    assert max(entrywise_err(a, b, 1.0) for a, b in zip(ug, uo)) < 1e-4
+    assert all(g_ == o_ for g_, o_ in ctr), ctr
+    _teacher_forced(lp, g, o, 20, 1e-3)
 
 
 def test_mip_like_fp64_trajectory_faa():
     lp = lpgen.mip_like_lp(12, m=1500, n=3500, nnz=20000, fp32=False)
     ug, uo, ctr, _, _ = _trajectories(lp, 50, precision=1, variant=2, memory=10)
-    errs = [_rel(a, b) for a, b in zip(ug, uo)]
+    errs = [err64(a, b) for a, b in zip(ug, uo)]
     assert max(errs) < 1e-8, errs
     assert ctr[-1][0] == ctr[-1][1]
 
@@ -121,7 +134,9 @@ def test_faa_filters_removing_columns_on_most_steps_fp64(angle_mode):
     """c_s = 0.8 with every step on the AA branch (D = 1e6): the angle filter
     removes columns on most steps (under both readings of Alg 4, which here
     give different trajectories); the GPU keeps the oracle's memory length
-    and iterate pass for pass."""
+    and iterate pass for pass: to 1e-8 in norm, and every entry to 1e-6 of
+    its size or of 1e-3 of the largest entry (the filtered steps amplify
+    the float64 rounding of the summation order, measured 7.6e-8)."""
     lp = lpgen.mip_like_lp(12, m=1500, n=3500, nnz=20000, fp32=False)
     tau = 0.9 / oracle.power_norm(oracle.Problem.from_lpdata(lp))
     common = dict(variant=2, memory=10, tau=tau, sigma=tau, kkt_every=1, tol=0.0, max_iter=10 ** 6, cs=0.8,
@@ -135,21 +150,23 @@ def test_faa_filters_removing_columns_on_most_steps_fp64(angle_mode):
         o.step()
         g.iterate(1)
         st = g.get_state()
-        errs.append(_rel(st["u"], np.r_[o.state.x, o.state.y]))
+        ref = np.r_[o.state.x, o.state.y]
+        errs.append((norm_rel(st["u"], ref), entrywise_err(st["u"], ref, 1e-3)))
         lens.append((len(st["live"]), len(o.state.dG)))
         assert (st["i"], st["j"]) == (o.state.i, o.state.j)
     assert all(a == b for a, b in lens), lens
     assert sum(1 for a, _ in lens[10:] if a < 10) >= 5, lens  # the filter did remove columns
-    assert max(errs) < 1e-8, errs
+    assert max(e[0] for e in errs) < 1e-8 and max(e[1] for e in errs) < 1e-6, errs
     g.close()
 
 
 @pytest.mark.parametrize("floor", [0, 1])
 def test_faa_length_filter_readings_fp64(floor):
-    """kappa-bar so small that the length filter never passes (every step an
-    FAA step): floor 0 empties the memory on every step, floor 1 keeps the
-    newest pair; the GPU follows the oracle under both readings, pass for
-    pass, and counts the emptied steps as the oracle does."""
+    """kappa-bar so small that the length filter never passes (D large, so
+    nearly every step is an FAA step): after an FAA step floor 0 leaves an
+    empty memory and floor 1 the newest pair; the GPU follows the oracle
+    under both readings, pass for pass, and counts the emptied steps as the
+    oracle does."""
     lp = lpgen.mip_like_lp(12, m=1500, n=3500, nnz=20000, fp32=False)
     tau = 0.9 / oracle.power_norm(oracle.Problem.from_lpdata(lp))
     common = dict(variant=2, memory=6, tau=tau, sigma=tau, kkt_every=1, tol=0.0, max_iter=10 ** 6,
@@ -158,20 +175,27 @@ def test_faa_length_filter_readings_fp64(floor):
     o = _oracle(lp, **common)
     o.start()
     g.iterate(1)
+    faa_steps = 0
     for _ in range(30):
         o.step()
         g.iterate(1)
         st = g.get_state()
-        assert entrywise_err(st["u"], np.r_[o.state.x, o.state.y], 1e-3) < 1e-9
-        assert len(st["live"]) == len(o.state.dG) == floor
-    assert g.result()["faa_empty"] == o.faa_empty == (30 if floor == 0 else 0)
+        assert err64(st["u"], np.r_[o.state.x, o.state.y]) < 1e-9
+        assert (st["i"], st["j"]) == (o.state.i, o.state.j)
+        assert len(st["live"]) == len(o.state.dG)
+        if o.last_branch == "aa":  # the filters ran: the memory is what the reading keeps
+            faa_steps += 1
+            assert len(st["live"]) == floor
+    assert faa_steps >= 20
+    assert g.result()["faa_empty"] == o.faa_empty == (faa_steps if floor == 0 else 0)
     g.close()
 
 
 def _teacher_forced(lp, g, o, steps, tol):
     """For `steps` loop passes: load the GPU's state into the oracle, let both
-    take one pass, compare the next iterates.  Isolates the rounding of one
-    pass from its amplification by later passes."""
+    take one pass, compare the next iterates entry by entry (to `tol` of each
+    entry's size or of 1e-3 of the largest entry).  Isolates the rounding of
+    one pass from its amplification by later passes."""
     errs = []
     for _ in range(steps):
         st = g.get_state()
@@ -186,7 +210,7 @@ def _teacher_forced(lp, g, o, steps, tol):
         o.step()
         g.iterate(1)
         st2 = g.get_state()
-        errs.append(_rel(st2["u"], np.r_[o.state.x, o.state.y]))
+        errs.append(entrywise_err(st2["u"], np.r_[o.state.x, o.state.y], 1e-3))
         assert (st2["i"], st2["j"]) == (o.state.i, o.state.j)
     assert max(errs) < tol, errs
     return errs
@@ -220,7 +244,7 @@ def _ragged_lp():
 def test_long_rows_split_and_empty_rows_and_columns_fp64():
     lp = _ragged_lp()
     ug, uo, ctr, _, _ = _trajectories(lp, 30, precision=1, memory=4)
-    errs = [_rel(a, b) for a, b in zip(ug, uo)]
+    errs = [err64(a, b) for a, b in zip(ug, uo)]
     assert max(errs) < 1e-9, errs
     assert ctr[-1][0] == ctr[-1][1]
 
@@ -229,7 +253,7 @@ def test_long_rows_split_and_empty_rows_and_columns_fp32():
     lp = _ragged_lp()
     # free-running on the (non-expansive) PDHG map
     ug, uo, _, _, _ = _trajectories(lp, 50, precision=0, variant=0)
-    errs = [_rel(a, b) for a, b in zip(ug, uo)]
+    errs = [err32(a, b) for a, b in zip(ug, uo)]
     assert max(errs) < 1e-5, errs
     # AA-PDHG: one pass at a time from the GPU's own state
     _, _, _, g, o = _trajectories(lp, 3, precision=0, memory=4)
@@ -241,7 +265,7 @@ def test_columns_longer_than_a_chunk_in_the_primal_pass():
     colcnt = np.bincount(lp.colidx, minlength=lp.n)
     assert colcnt.max() > 2048  # exercises the split path of the CSC pass
     ug, uo, _, _, _ = _trajectories(lp, 20, precision=0, memory=6, kkt_every=5)
-    errs = [_rel(a, b) for a, b in zip(ug, uo)]
+    errs = [err32(a, b) for a, b in zip(ug, uo)]
     assert max(errs) < 1e-5, errs
 
 
@@ -307,7 +331,7 @@ def test_loop_kernels_agree_over_many_passes(precision):
     a, b = out
     assert a["k"] == b["k"] == 151
     assert (a["i"], a["j"]) == (b["i"], b["j"])
-    assert _rel(a["u"], b["u"]) < (1e-4 if precision == 0 else 1e-9)
+    assert norm_rel(a["u"], b["u"]) < (1e-4 if precision == 0 else 1e-9)
 
 
 @pytest.mark.parametrize("tol", [1e-4, 1e-6])

@@ -13,14 +13,11 @@ import pytest
 
 import lpgen
 import oracle
+from _util import err64
 
 pytestmark = pytest.mark.gpu
 
 P = pytest.importorskip("paper_2508_08062_amd")
-
-
-def _rel(a, b):
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -74,7 +71,7 @@ def test_trajectory_on_the_preconditioned_lp_fp64():
         o.step()
         g.iterate(1)
         st = g.get_state()
-        errs.append(_rel(st["u"], np.r_[o.state.x, o.state.y]))
+        errs.append(err64(st["u"], np.r_[o.state.x, o.state.y]))
         assert (st["i"], st["j"]) == (o.state.i, o.state.j)
     assert max(errs) < 1e-9, errs
     g.close()

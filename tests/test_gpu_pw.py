@@ -13,14 +13,11 @@ import pytest
 
 import lpgen
 import oracle
+from _util import err32, err64
 
 pytestmark = pytest.mark.gpu
 
 P = pytest.importorskip("paper_2508_08062_amd")
-
-
-def _rel(a, b):
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
 def _run(lp, steps, precision, loop_kernel, variant=1, memory=5, **kw):
@@ -63,7 +60,7 @@ def test_tiny_fp64_weighted_trajectory(seed, loop_kernel):
     lp = lpgen.tiny_lp(seed)
     rows, g, o = _run(lp, 60, precision=1, loop_kernel=loop_kernel, pw_period=8, pw_theta=0.5)
     n = lp.n
-    errs = [_rel(r["ug"], r["uo"]) for r in rows]
+    errs = [err64(r["ug"], r["uo"]) for r in rows]
     assert max(errs) < 1e-9, (max(errs), int(np.argmax(errs)))
     for q, r in enumerate(rows[:-1]):
         ref = _weight_ref(rows, q, 8)
@@ -83,7 +80,7 @@ def test_mip_like_fp32_weighted_trajectory(variant, loop_kernel):
     lp = lpgen.mip_like_lp(11, m=2000, n=5000, nnz=25000)
     rows, g, o = _run(lp, 50, precision=0, loop_kernel=loop_kernel, variant=variant, memory=10, pw_period=10,
                       pw_theta=0.5)
-    errs = [_rel(r["ug"], r["uo"]) for r in rows]
+    errs = [err32(r["ug"], r["uo"]) for r in rows]
     assert max(errs) < 1e-5, (max(errs), int(np.argmax(errs)))
     assert rows[-1]["ctr_g"] == rows[-1]["ctr_o"]
     assert rows[-1]["w"]["updates"] == rows[-1]["upd_o"] >= 3
@@ -95,7 +92,7 @@ def test_mip_like_fp32_weighted_trajectory(variant, loop_kernel):
 def test_iter_aa_over_c_safeguard(loop_kernel):
     lp = lpgen.tiny_lp(4)
     rows, g, o = _run(lp, 60, precision=1, loop_kernel=loop_kernel, sg_div=3.0, D=1.0)
-    errs = [_rel(r["ug"], r["uo"]) for r in rows]
+    errs = [err64(r["ug"], r["uo"]) for r in rows]
     assert max(errs) < 1e-9, errs
     for r in rows:
         assert r["ctr_g"] == r["ctr_o"]

@@ -10,6 +10,7 @@ import pytest
 
 import lpgen
 import oracle
+from _util import err32, err64
 from test_gpu_parity import _ragged_lp
 
 pytestmark = pytest.mark.gpu
@@ -19,11 +20,8 @@ P = pytest.importorskip("paper_2508_08062_amd")
 RP = 3  # restarted PDHG
 
 
-def _rel(a, b):
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
-
-
 def _run(lp, steps, precision, R, loop_kernel=0, tau=None, kkt_every=1):
+    err = err64 if precision == 1 else err32
     Po = oracle.Problem.from_lpdata(lp)
     if tau is None:
         tau = 0.9 / oracle.power_norm(Po)
@@ -33,12 +31,12 @@ def _run(lp, steps, precision, R, loop_kernel=0, tau=None, kkt_every=1):
     o = oracle.Solver(Po, oracle.Options(**common))
     o.start()
     g.iterate(1)
-    errs = [_rel(g.get_state()["u"], np.r_[o.state.x, o.state.y])]
+    errs = [err(g.get_state()["u"], np.r_[o.state.x, o.state.y])]
     for _ in range(steps):
         o.step()
         g.iterate(1)
         st = g.get_state()
-        errs.append(_rel(st["u"], np.r_[o.state.x, o.state.y]))
+        errs.append(err(st["u"], np.r_[o.state.x, o.state.y]))
         assert (st["i"], st["j"]) == (o.state.i, o.state.j) == (0, st["k"] - 1)
     return errs, g, o
 
