@@ -620,7 +620,7 @@ def main():
         return _serve(args)
     if args.workload == "serve_curve":
         return _serve_curve(args)
-    if args.workload == "batch256":
+    if args.workload == "batch256" and not args.profile_run:
         return _batch_solve(args)
     if args.workload == "compare":
         return _compare(args)

@@ -202,10 +202,19 @@ aapdhg_status aapdhg_create(int32_t m, int32_t n, int64_t nnz, const int64_t *ro
                             const double *q, const double *l, const double *u,
                             const uint8_t *row_type, const aapdhg_options *opt, aapdhg_t *out);
 
-/* Solve from the start point u^0 = (clip(0, l, u), 0): the init step u^1 = T u^0, then loop
- * passes until the KKT test passes, max_iter, or time_limit_s.  Work is enqueued on `stream`
- * in epochs; the call returns when the solve has finished (it waits on the stream). */
+/* Solve from the start point u^0 = (clip(0, l, u), 0) (Alg 2 initialisation): the init step
+ * u^1 = T u^0, then loop passes (Alg 2 loop; Alg 3 for FAA-PDHG) until the KKT test of Remark
+ * re:constrcution-termi-con passes, max_iter, or time_limit_s.  Asynchronous: the reset and the
+ * init step are enqueued on `stream`, and a thread of the handle enqueues the loop passes in
+ * epochs of `epoch` passes on the same stream, reading the LP's status (decided on the device
+ * by each pass) between epochs; the call returns at once.  aapdhg_result, aapdhg_wait and every
+ * other call on the handle wait for the solve first; a failure of the solve (for example a HIP
+ * error) is returned by the first of them.  The stream must stay valid until then. */
 aapdhg_status aapdhg_solve(aapdhg_t h, void *stream);
+
+/* Wait for a solve started with aapdhg_solve to finish (no-op without one); returns the
+ * solve's error, if it had one. */
+aapdhg_status aapdhg_wait(aapdhg_t h);
 
 /* Device-memory variants, for callers whose data already lives on the GPU (say in torch
  * tensors).  The LP is the one of Section 2 (the standard form the method solves), stored as
@@ -337,12 +346,18 @@ aapdhg_status aapdhg_batch_result(aapdhg_batch_t b, int32_t i, double *x, double
 aapdhg_status aapdhg_batch_destroy(aapdhg_batch_t b);
 
 /* ---- serving: continuous batching of LP requests ----
- * A worker thread admits submitted LPs while their device footprint fits in
- * hbm_budget_bytes and fewer than max_slots are resident, advances all resident LPs in
- * shared epochs, and retires finished ones, so requests that arrive while others run share
- * the device.  opt applies to every request (NULL: defaults). */
+ * An admission thread creates submitted LPs (host tables, uploads, scaling, step sizes, the
+ * init step of Alg 2) on `copy_stream` while their estimated device footprint fits in
+ * hbm_budget_bytes and fewer than max_slots are admitted; an epoch thread takes the created
+ * LPs in at epoch boundaries, advances all resident LPs in shared epochs of loop passes on
+ * `compute_stream`, and retires finished ones.  So requests that arrive while others run are
+ * set up while the device computes, and then share the device.  opt applies to every request
+ * (NULL: defaults).  Streams are hipStream_t passed as void*, distinct, non-blocking
+ * (hipStreamNonBlocking) so that neither waits on the default stream; NULL: the server
+ * creates its own.  Caller-given streams must outlive aapdhg_server_stop. */
 aapdhg_status aapdhg_server_start(size_t hbm_budget_bytes, int32_t max_slots,
-                                  const aapdhg_options *opt, aapdhg_server_t *out);
+                                  const aapdhg_options *opt, void *compute_stream, void *copy_stream,
+                                  aapdhg_server_t *out);
 /* Submit one LP (arguments as aapdhg_create; copied).  Returns at once with *ticket. */
 aapdhg_status aapdhg_server_submit(aapdhg_server_t s, int32_t m, int32_t n, int64_t nnz,
                                    const int64_t *row_ptr, const int32_t *col_idx,
@@ -355,7 +370,8 @@ aapdhg_status aapdhg_server_submit(aapdhg_server_t s, int32_t m, int32_t n, int6
  * (t_admit is -1 for a request that failed before admission). */
 aapdhg_status aapdhg_server_poll(aapdhg_server_t s, uint64_t ticket, aapdhg_info *info,
                                  double *x, double *y, double *t_admit, double *t_done);
-/* Counters: submitted, admitted, finished, resident now, epochs run, bytes resident now. */
+/* Counters: submitted, admitted (taken into the epochs), finished, resident now, epochs run,
+ * estimated device bytes of the admitted requests (being created, ready or resident). */
 aapdhg_status aapdhg_server_stats(aapdhg_server_t s, int64_t *stats6);
 /* Stop the worker (running requests are abandoned) and free everything. */
 aapdhg_status aapdhg_server_stop(aapdhg_server_t s);

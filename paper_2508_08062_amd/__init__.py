@@ -61,7 +61,8 @@ class Info(C.Structure):
 
 
 EXPORTS = [
-    "aapdhg_default_options", "aapdhg_create", "aapdhg_solve", "aapdhg_iterate", "aapdhg_iterate_noalloc",
+    "aapdhg_default_options", "aapdhg_create", "aapdhg_solve", "aapdhg_wait", "aapdhg_iterate",
+    "aapdhg_iterate_noalloc",
     "aapdhg_iterate_timed",
     "aapdhg_reset",
     "aapdhg_result", "aapdhg_create_device", "aapdhg_result_device", "aapdhg_get_state", "aapdhg_set_state",
@@ -95,6 +96,7 @@ def lib():
     L.aapdhg_create.argtypes = [C.c_int32, C.c_int32, C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                                 _dp, _dp, _dp, _dp, _dp, C.POINTER(C.c_uint8), C.POINTER(Options), C.POINTER(_P)]
     L.aapdhg_solve.argtypes = [_P, _P]
+    L.aapdhg_wait.argtypes = [_P]
     L.aapdhg_iterate.argtypes = [_P, _P, C.c_int64]
     L.aapdhg_iterate_noalloc.argtypes = [_P, _P, C.c_int64]
     L.aapdhg_iterate_timed.argtypes = [_P, _P, C.c_int64, _dp]
@@ -118,7 +120,7 @@ def lib():
     L.aapdhg_batch_iterate_timed.argtypes = [_P, _P, C.c_int64, _dp]
     L.aapdhg_batch_result.argtypes = [_P, C.c_int32, _dp, _dp, _dp, C.POINTER(Info)]
     L.aapdhg_batch_destroy.argtypes = [_P]
-    L.aapdhg_server_start.argtypes = [C.c_size_t, C.c_int32, C.POINTER(Options), C.POINTER(_P)]
+    L.aapdhg_server_start.argtypes = [C.c_size_t, C.c_int32, C.POINTER(Options), _P, _P, C.POINTER(_P)]
     L.aapdhg_server_submit.argtypes = [_P, C.c_int32, C.c_int32, C.c_int64, C.POINTER(C.c_int64),
                                        C.POINTER(C.c_int32), _dp, _dp, _dp, _dp, _dp, C.POINTER(C.c_uint8),
                                        C.POINTER(C.c_uint64)]
@@ -273,8 +275,17 @@ class Solver:
     def __exit__(self, *exc):
         self.close()
 
-    def solve(self, stream=None):
+    def solve(self, stream=None, wait=True):
+        """aapdhg_solve (asynchronous); with `wait` the call also waits for
+        the solve to finish (aapdhg_wait)."""
         _check(lib().aapdhg_solve(self.h, _stream(stream)), self.h)
+        if wait:
+            self.wait()
+        return self
+
+    def wait(self):
+        """Wait for a solve in flight (aapdhg_wait)."""
+        _check(lib().aapdhg_wait(self.h), self.h)
         return self
 
     def iterate(self, iters: int, stream=None):
@@ -432,10 +443,15 @@ class Batch:
 class Server:
     """Continuous-batching request loop (aapdhg_server_*)."""
 
-    def __init__(self, hbm_budget_bytes: int, max_slots: int, options: Options | None = None, **kw):
+    def __init__(self, hbm_budget_bytes: int, max_slots: int, options: Options | None = None,
+                 compute_stream=None, copy_stream=None, **kw):
+        """compute_stream / copy_stream: torch streams (or hipStream_t ints)
+        for the epochs and for admitting requests; None lets the server
+        create its own."""
         opt = options if options is not None else default_options(**kw)
         h = C.c_void_p()
-        _check(lib().aapdhg_server_start(int(hbm_budget_bytes), int(max_slots), C.byref(opt), C.byref(h)), None)
+        _check(lib().aapdhg_server_start(int(hbm_budget_bytes), int(max_slots), C.byref(opt),
+                                         _stream(compute_stream), _stream(copy_stream), C.byref(h)), None)
         self.h = h
         self._dims = {}
         _open["server"].add(self)

@@ -12,6 +12,7 @@
 #include <memory>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/aapdhg.h"
@@ -22,6 +23,7 @@
 namespace aapdhg {
 
 thread_local std::string g_thread_error;
+thread_local hipStream_t g_setup_stream = nullptr;
 
 // ---------------------------------------------------------------------------
 // errors
@@ -61,10 +63,33 @@ void DevBuf::alloc(size_t nbytes, const char* what) {
 }
 void DevBuf::upload(const void* src, size_t nbytes, const char* what) {
   alloc(nbytes, what);
-  if (src && nbytes) hip_check(hipMemcpy(p, src, nbytes, hipMemcpyHostToDevice), what);
+  if (!src || !nbytes) return;
+  if (g_setup_stream) {
+    hip_check(hipMemcpyAsync(p, src, nbytes, hipMemcpyHostToDevice, g_setup_stream), what);
+    hip_check(hipStreamSynchronize(g_setup_stream), what);  // src may be a temporary
+  } else {
+    hip_check(hipMemcpy(p, src, nbytes, hipMemcpyHostToDevice), what);
+  }
 }
 void DevBuf::zero(const char* what) {
-  if (p) hip_check(hipMemset(p, 0, bytes), what);
+  if (!p) return;
+  if (g_setup_stream) {
+    hip_check(launch_zero(p, bytes & ~(size_t)3, g_setup_stream), what);
+    hip_check(hipStreamSynchronize(g_setup_stream), what);
+  } else {
+    hip_check(hipMemset(p, 0, bytes), what);
+  }
+}
+
+// Copy device memory to the host on the set-up stream (see g_setup_stream).
+static void setup_download(void* dst, const void* src, size_t nbytes, const char* what) {
+  if (!nbytes) return;
+  if (g_setup_stream) {
+    hip_check(hipMemcpyAsync(dst, src, nbytes, hipMemcpyDeviceToHost, g_setup_stream), what);
+    hip_check(hipStreamSynchronize(g_setup_stream), what);
+  } else {
+    hip_check(hipMemcpy(dst, src, nbytes, hipMemcpyDeviceToHost), what);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -739,20 +764,21 @@ void Problem::scale_on_device() {
   a.dcol = (double*)b_dcol.p;
   a.ruiz_iters = opt.ruiz_iters;
   a.pock_chambolle = opt.pock_chambolle != 0;
-  hip_check(launch_scaling(a, nullptr), "scaling launch");
-  if (nnz > 0) hip_check(hipMemcpy(val.data(), b_val.p, (size_t)nnz * 8, hipMemcpyDeviceToHost), "scaled values");
-  hip_check(hipMemcpy(d_row.data(), b_drow.p, (size_t)m * 8, hipMemcpyDeviceToHost), "d_row");
-  hip_check(hipMemcpy(d_col.data(), b_dcol.p, (size_t)n * 8, hipMemcpyDeviceToHost), "d_col");
+  hip_check(launch_scaling(a, g_setup_stream), "scaling launch");
+  setup_download(val.data(), b_val.p, (size_t)nnz * 8, "scaled values");
+  setup_download(d_row.data(), b_drow.p, (size_t)m * 8, "d_row");
+  setup_download(d_col.data(), b_dcol.p, (size_t)n * 8, "d_col");
 }
 
 double Problem::power_norm() {
   DevBuf work, est;
   work.alloc(((size_t)2 * n + m + 1024) * 8, "power iteration work");
   est.alloc(((size_t)opt.power_iters + 1) * 8, "power iteration estimates");
-  hip_check(launch_power_iteration(desc, fp64, opt.power_iters, opt.seed, (double*)work.p, (double*)est.p, nullptr),
+  hip_check(launch_power_iteration(desc, fp64, opt.power_iters, opt.seed, (double*)work.p, (double*)est.p,
+                                   g_setup_stream),
             "power iteration launch");
   std::vector<double> e(opt.power_iters + 1);
-  hip_check(hipMemcpy(e.data(), est.p, e.size() * 8, hipMemcpyDeviceToHost), "power iteration result");
+  setup_download(e.data(), est.p, e.size() * 8, "power iteration result");
   return std::sqrt(std::max(0.0, e.back()));
 }
 
@@ -1502,6 +1528,14 @@ using namespace aapdhg;
 struct aapdhg_problem {
   Problem p;
   std::string err;
+  // aapdhg_solve runs its epochs on this thread; every other call on the
+  // handle waits for it first (hguard)
+  std::thread solver;
+  aapdhg_status solve_status = AAPDHG_OK;
+  std::string solve_msg;
+  void join() {
+    if (solver.joinable()) solver.join();
+  }
 };
 
 struct aapdhg_batch {
@@ -1528,6 +1562,21 @@ static aapdhg_status guard(std::string* err, F&& f) {
     g_thread_error = e.what();
     return AAPDHG_E_ARG;
   }
+}
+
+// Entry points on a handle: wait for a solve in flight, then run f; a
+// failure of that solve is reported by the first call after it.
+template <typename F>
+static aapdhg_status hguard(aapdhg_t h, F&& f) {
+  h->join();
+  if (h->solve_status != AAPDHG_OK) {
+    const aapdhg_status s = h->solve_status;
+    h->err = h->solve_msg;
+    g_thread_error = h->solve_msg;
+    h->solve_status = AAPDHG_OK;
+    return s;
+  }
+  return guard(&h->err, std::forward<F>(f));
 }
 
 extern "C" {
@@ -1629,23 +1678,38 @@ aapdhg_status aapdhg_create_device(int32_t m, int32_t n, int64_t nnz, const int6
 aapdhg_status aapdhg_result_device(aapdhg_t h, double* x, double* y, double* lambda, aapdhg_info* info,
                                    void* stream) {
   if (!h) return AAPDHG_E_ARG;
-  return guard(&h->err, [&] { h->p.result_device(x, y, lambda, info, (hipStream_t)stream); });
+  return hguard(h, [&] { h->p.result_device(x, y, lambda, info, (hipStream_t)stream); });
 }
 
 aapdhg_status aapdhg_solve(aapdhg_t h, void* stream) {
   if (!h) return AAPDHG_E_ARG;
-  return guard(&h->err, [&] {
+  return hguard(h, [&] {
     if (h->p.in_batch) throw Error(AAPDHG_E_STATE, "problem belongs to a live batch");
     hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    hip_check(hipGetDevice(&dev), "device");
     h->p.enqueue_reset(st);
     h->p.enqueue_init(st);
-    h->p.last_solve_seconds = h->p.solo->run_to_completion(st, h->p.opt.epoch, h->p.opt.time_limit_s);
+    // the epochs are enqueued by a thread of the handle: the call returns
+    // at once; termination is decided on the device (the status each pass
+    // leaves in the LP's scalars), the thread only stops enqueuing
+    h->solver = std::thread([h, st, dev] {
+      h->solve_status = guard(&h->solve_msg, [&] {
+        hip_check(hipSetDevice(dev), "solve device");
+        h->p.last_solve_seconds = h->p.solo->run_to_completion(st, h->p.opt.epoch, h->p.opt.time_limit_s);
+      });
+    });
   });
+}
+
+aapdhg_status aapdhg_wait(aapdhg_t h) {
+  if (!h) return AAPDHG_E_ARG;
+  return hguard(h, [] {});
 }
 
 aapdhg_status aapdhg_iterate(aapdhg_t h, void* stream, int64_t iters) {
   if (!h) return AAPDHG_E_ARG;
-  return guard(&h->err, [&] {
+  return hguard(h, [&] {
     if (iters < 0) throw Error(AAPDHG_E_ARG, "iters must be >= 0");
     if (h->p.in_batch) throw Error(AAPDHG_E_STATE, "problem belongs to a live batch");
     hipStream_t st = (hipStream_t)stream;
@@ -1660,7 +1724,7 @@ aapdhg_status aapdhg_iterate(aapdhg_t h, void* stream, int64_t iters) {
 
 aapdhg_status aapdhg_iterate_noalloc(aapdhg_t h, void* stream, int64_t iters) {
   if (!h) return AAPDHG_E_ARG;
-  return guard(&h->err, [&] {
+  return hguard(h, [&] {
     if (iters < 0) throw Error(AAPDHG_E_ARG, "iters must be >= 0");
     if (h->p.in_batch) throw Error(AAPDHG_E_STATE, "problem belongs to a live batch");
     h->p.iterate_noalloc((hipStream_t)stream, iters);
@@ -1669,7 +1733,7 @@ aapdhg_status aapdhg_iterate_noalloc(aapdhg_t h, void* stream, int64_t iters) {
 
 aapdhg_status aapdhg_iterate_timed(aapdhg_t h, void* stream, int64_t iters, double* ms4) {
   if (!h || !ms4) return AAPDHG_E_ARG;
-  return guard(&h->err, [&] {
+  return hguard(h, [&] {
     if (h->p.in_batch) throw Error(AAPDHG_E_STATE, "problem belongs to a live batch");
     hipStream_t st = (hipStream_t)stream;
     if (!h->p.started) h->p.enqueue_reset(st);
@@ -1680,38 +1744,39 @@ aapdhg_status aapdhg_iterate_timed(aapdhg_t h, void* stream, int64_t iters, doub
 
 aapdhg_status aapdhg_reset(aapdhg_t h, void* stream) {
   if (!h) return AAPDHG_E_ARG;
-  return guard(&h->err, [&] { h->p.enqueue_reset((hipStream_t)stream); });
+  return hguard(h, [&] { h->p.enqueue_reset((hipStream_t)stream); });
 }
 
 aapdhg_status aapdhg_result(aapdhg_t h, double* x, double* y, double* lambda, aapdhg_info* info) {
   if (!h) return AAPDHG_E_ARG;
-  return guard(&h->err, [&] { h->p.result(x, y, lambda, info, true); });
+  return hguard(h, [&] { h->p.result(x, y, lambda, info, true); });
 }
 
 aapdhg_status aapdhg_get_state(aapdhg_t h, double* u, double* u_prev, double* g_prev, double* dG, double* W,
                                int64_t* meta, double* gram) {
   if (!h) return AAPDHG_E_ARG;
-  return guard(&h->err, [&] { h->p.get_state(u, u_prev, g_prev, dG, W, meta, gram); });
+  return hguard(h, [&] { h->p.get_state(u, u_prev, g_prev, dG, W, meta, gram); });
 }
 
 aapdhg_status aapdhg_set_state(aapdhg_t h, const double* u, const double* u_prev, const double* g_prev,
                                const double* dG, const double* W, const int64_t* meta, const double* gram) {
   if (!h) return AAPDHG_E_ARG;
-  return guard(&h->err, [&] { h->p.set_state(u, u_prev, g_prev, dG, W, meta, gram); });
+  return hguard(h, [&] { h->p.set_state(u, u_prev, g_prev, dG, W, meta, gram); });
 }
 
 aapdhg_status aapdhg_get_weights(aapdhg_t h, double* anchor, double* w) {
   if (!h) return AAPDHG_E_ARG;
-  return guard(&h->err, [&] { h->p.get_weights(anchor, w); });
+  return hguard(h, [&] { h->p.get_weights(anchor, w); });
 }
 
 aapdhg_status aapdhg_set_weights(aapdhg_t h, const double* anchor, const double* w) {
   if (!h) return AAPDHG_E_ARG;
-  return guard(&h->err, [&] { h->p.set_weights(anchor, w); });
+  return hguard(h, [&] { h->p.set_weights(anchor, w); });
 }
 
 aapdhg_status aapdhg_get_dims(aapdhg_t h, int32_t* m, int32_t* n, int64_t* nnz, double* tau, double* sigma) {
   if (!h) return AAPDHG_E_ARG;
+  h->join();
   if (m) *m = h->p.m;
   if (n) *n = h->p.n;
   if (nnz) *nnz = h->p.nnz;
@@ -1722,6 +1787,7 @@ aapdhg_status aapdhg_get_dims(aapdhg_t h, int32_t* m, int32_t* n, int64_t* nnz, 
 
 aapdhg_status aapdhg_get_scaling(aapdhg_t h, double* d_row, double* d_col) {
   if (!h) return AAPDHG_E_ARG;
+  h->join();
   if (d_row) std::copy(h->p.d_row.begin(), h->p.d_row.end(), d_row);
   if (d_col) std::copy(h->p.d_col.begin(), h->p.d_col.end(), d_col);
   return AAPDHG_OK;
@@ -1729,6 +1795,7 @@ aapdhg_status aapdhg_get_scaling(aapdhg_t h, double* d_row, double* d_col) {
 
 aapdhg_status aapdhg_destroy(aapdhg_t h) {
   if (!h) return AAPDHG_E_ARG;
+  h->join();
   (void)hipDeviceSynchronize();
   delete h;
   return AAPDHG_OK;
@@ -1751,6 +1818,7 @@ aapdhg_status aapdhg_batch_create(int32_t count, const aapdhg_t* problems, aapdh
     std::vector<Problem*> ps;
     for (int i = 0; i < count; ++i) {
       if (!problems[i]) throw Error(AAPDHG_E_ARG, "problem %d is NULL", i);
+      problems[i]->join();  // a solve of its own in flight finishes first
       if (problems[i]->p.in_batch) throw Error(AAPDHG_E_STATE, "problem %d already belongs to a batch", i);
       for (int j = 0; j < i; ++j)
         if (problems[j] == problems[i]) throw Error(AAPDHG_E_ARG, "problem %d appears twice", i);

@@ -24,6 +24,10 @@ struct Error {
 void hip_check(hipError_t e, const char* what);
 void default_options(aapdhg_options* o);
 extern thread_local std::string g_thread_error;
+// Stream of the calling thread's set-up work in Problem::create (uploads,
+// scaling, power iteration): nullptr is the default stream; the server's
+// admission thread sets its copy stream.
+extern thread_local hipStream_t g_setup_stream;
 
 // Owning device allocation.
 struct DevBuf {

@@ -245,7 +245,7 @@ int main() {
   // server: admission, epochs, retirement, a request beyond the budget
   {
     aapdhg_server_t s = nullptr;
-    CHECK(aapdhg_server_start((size_t)64 << 20, 4, &o, &s) == AAPDHG_OK);
+    CHECK(aapdhg_server_start((size_t)64 << 20, 4, &o, nullptr, nullptr, &s) == AAPDHG_OK);
     std::vector<uint64_t> tickets;
     std::vector<LP> reqs;
     for (int i = 0; i < 7; ++i) reqs.push_back(make_lp(200 + 30 * i, std::vector<int>(60 + 10 * i, 5), 20 + i));
