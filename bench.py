@@ -307,9 +307,26 @@ def _batch_leg(args, stream, cpu_baseline=False):
     import paper_2508_08062_amd as P
     lps, opts, cfg = _workload("batch256")
     kw = dict(opts, tol=1e-4, max_iter=200000)
-    solvers = [P.Solver(lp, **kw) for lp in lps]
-    print(f"# created {len(solvers)} LPs", file=sys.stderr, flush=True)
-    # aggregate batch iteration: 64 passes, far from any member's termination
+    # whole batch passes (64, far from any member's termination) with the
+    # built-in or the autotuned work tables, launched directly or replayed
+    # from a HIP graph; the batch is then solved in the fastest of the four
+    configs = {}
+    for tune in (0, 1):
+        for graph in (0, 1):
+            t0 = time.perf_counter()
+            solvers = [P.Solver(lp, autotune=tune, graph=graph, **kw) for lp in lps]
+            t_create = time.perf_counter() - t0
+            batch = P.Batch(solvers)
+            _, ms = _timed_passes(batch, stream, 64, 8, 64)
+            batch.close()
+            for sv in solvers:
+                sv.close()
+            configs[f"autotune{tune}_graph{graph}"] = {"ms_per_batch_pass": ms / 64, "create_seconds": t_create}
+            print(f"# autotune {tune} graph {graph}: {ms / 64:.3f} ms per batch pass (created in {t_create:.1f} s)",
+                  file=sys.stderr, flush=True)
+    best_cfg = min(configs, key=lambda c: configs[c]["ms_per_batch_pass"])
+    tune, graph = int(best_cfg[8]), int(best_cfg[-1])
+    solvers = [P.Solver(lp, autotune=tune, graph=graph, **kw) for lp in lps]
     batch = P.Batch(solvers)
     batch.iterate(1, stream)
     batch.iterate(8, stream)
@@ -358,7 +375,9 @@ def _batch_leg(args, stream, cpu_baseline=False):
            "lps_done_by_p50_per_s": 0.5 * len(lps) / float(np.percentile(done_s, 50)),
            "batch_iteration": {"roofline": roof, "launch": launch, **spmv,
                                "ms_per_batch_iteration": launch.get("primal", 0) + launch.get("dual", 0)
-                               + launch.get("aa_fraction", 0) * launch.get("mix", 0)},
+                               + launch.get("aa_fraction", 0) * launch.get("mix", 0),
+                               "configurations": configs, "solved_with": best_cfg,
+                               "note": "launch durations (roofline) are timed with events per launch"},
            **single}
     if cpu_baseline:
         cb = _cpu_batch_baseline(lps, opts, args.cpu_seconds)
@@ -578,6 +597,8 @@ def main():
     ap.add_argument("--serve-leg-seconds", type=float, default=5.0, help="length of the serving leg's stream")
     ap.add_argument("--serve-leg-drain", type=float, default=25.0, help="drain of the serving leg")
     ap.add_argument("--solve-seconds", type=float, default=150.0, help="time limit of the solve-to-1e-4 legs")
+    ap.add_argument("--knee-rates", type=float, nargs="*", default=[2.0, 8.0],
+                    help="powerlaw1m: arrival rates of the short streams that locate the serving knee")
     ap.add_argument("--no-legs", action="store_true",
                     help="powerlaw1m: only the headline passes (no batch, serving and 20k x 50k legs)")
     ap.add_argument("--curve-rates", type=float, nargs="+", default=[1.0, 2.0, 4.0, 8.0, 16.0],
@@ -693,6 +714,16 @@ def main():
         sv = _serve(args, rate=args.rate, seconds=args.serve_leg_seconds, pool_size=args.pool,
                     drain=args.serve_leg_drain, emit=False)
         line["serving"] = _serving_summary(sv)
+        # where the latency-throughput curve bends: short streams below the 200/s overload
+        knee = []
+        for rate in args.knee_rates:
+            sv = _serve(args, rate=rate, seconds=5.0, pool_size=16, drain=10.0, emit=False)
+            knee.append({"rate_per_s": rate, "lps_per_s": sv["value"], "finished": sv["finished"],
+                         "unfinished": sv["unfinished"], "latency_p50_s": sv["latency_p50_s"],
+                         "latency_p99_s": sv["latency_p99_s"]})
+            print(f"# knee: {rate}/s -> {sv['value']:.2f} LPs/s, p50 {sv['latency_p50_s']}", file=sys.stderr,
+                  flush=True)
+        line["serving"]["knee"] = knee
         print("# cache-resident leg", file=sys.stderr, flush=True)
         line["cache_resident"] = _c1_leg(args, stream)
     elif args.serve_rate > 0 and len(lps) == 1:

@@ -153,6 +153,15 @@ typedef struct {
   int32_t length_floor;   /* FAA LengthFilter (Alg 5) when no k passes its test: 0 (default)
                              keeps no column (the count-down loop runs out), 1 keeps the
                              newest column (the loop read as stopping at k = 1)            */
+  int32_t graph;          /* 1: the three-launch passes of an epoch are captured once in a HIP
+                             graph and replayed (a set uses the graph when any member asks;
+                             the persistent kernel is one launch already); 0 (default) off.
+                             The same kernels run in the same order: results are unchanged */
+  int32_t autotune;       /* 1: the LP's work-table parameters (row weight of the chunking,
+                             chunks per workgroup, loop kernel) are chosen at create by timing
+                             candidates on the device, or taken from the tuning cache (file
+                             AAPDHG_TUNE_CACHE, default ~/.cache/aapdhg/tune.txt) for LPs of
+                             the same shape class; 0 (default): the built-in choice        */
   int32_t reserved1;
 } aapdhg_options;
 
@@ -242,8 +251,11 @@ aapdhg_status aapdhg_create_device(int32_t m, int32_t n, int64_t nnz, const int6
 aapdhg_status aapdhg_result_device(aapdhg_t h, double *x, double *y, double *lambda, aapdhg_info *info,
                                    void *stream);
 
-/* Enqueue `iters` loop passes on `stream` without waiting (asynchronous).  On a fresh or
- * reset handle the first pass is the init step.  Passes after termination do nothing. */
+/* Enqueue `iters` loop passes on `stream` without waiting (asynchronous): each pass is one
+ * iteration of the loop of Alg 2 (Alg 3 for FAA-PDHG; eq. pdhg for the map T), with the KKT
+ * test of Remark re:constrcution-termi-con every kkt_every passes.  On a fresh or reset handle
+ * the first pass is the init step (Alg 2 initialisation).  Passes after termination do
+ * nothing. */
 aapdhg_status aapdhg_iterate(aapdhg_t h, void *stream, int64_t iters);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
@@ -271,16 +283,21 @@ aapdhg_status aapdhg_iterate_noalloc(aapdhg_t h, void* stream, int64_t iters);
  *     launches, so use aapdhg_iterate for throughput. */
 aapdhg_status aapdhg_iterate_timed(aapdhg_t h, void *stream, int64_t iters, double *ms4);
 
-/* Return to the start point (discard iterate, history and counters). */
+/* Return to the start point u^0 of Alg 2's initialisation (discard iterate, history and
+ * counters); asynchronous on `stream`. */
 aapdhg_status aapdhg_reset(aapdhg_t h, void *stream);
 
-/* Wait for the handle's work, evaluate the KKT quantities at the current iterate, and copy
- * results to host memory: x double[n], y double[m], lambda double[n] (= P_Lambda(c - K^T y)),
- * each may be NULL.  Values refer to the original (unscaled) problem when Ruiz scaling was
+/* Wait for the handle's work, evaluate the KKT quantities of Remark re:constrcution-termi-con
+ * at the current iterate (primal and dual objectives, relative gap, primal and dual
+ * residuals, lambda = P_Lambda(c - K^T y) by the cases of eq. lambda-case), and copy results
+ * to host memory: x double[n], y double[m], lambda double[n], each may be NULL.  Values refer to the original (unscaled) problem when Ruiz scaling was
  * used; info (may be NULL) reports the KKT pieces of the problem as solved. */
 aapdhg_status aapdhg_result(aapdhg_t h, double *x, double *y, double *lambda, aapdhg_info *info);
 
-/* Copy the full iteration state to host memory (checkpoint).  Buffers, all double:
+/* Copy the full iteration state to host memory (checkpoint): what Alg 2 carries from k to
+ * k+1 (the iterate, the previous iterate and residual, the memory Delta G and Delta U, the
+ * latter kept as W = Delta U + beta D-hat Delta G, and the counters i, j).  Buffers, all
+ * double:
  *   u      [n+m]  current iterate u^k (x then y, scaled problem)
  *   u_prev [n+m]  u^{k-1}            g_prev [n+m]  g^{k-1}
  *   dG     [m_A*(n+m)] history columns by physical slot, W [m_A*(n+m)] = dU + beta D-hat dG
@@ -325,6 +342,8 @@ aapdhg_status aapdhg_destroy(aapdhg_t h);
 const char *aapdhg_last_error(aapdhg_t h);
 
 /* ---- batched solves: many LPs of uneven sizes advance in the same kernel launches ----
+ * Each member runs its own Alg 2 / Alg 3 loop (the paper solves one LP at a time; batching
+ * is how this library fills the device with independent solves).
  * The batch refers to the problems' device state; they must outlive the batch, must share
  * the precision and may not be used on their own while the batch is alive.  Each problem
  * keeps its own options, tiles and reduction order, so its iterates do not depend on the
@@ -345,7 +364,8 @@ aapdhg_status aapdhg_batch_result(aapdhg_batch_t b, int32_t i, double *x, double
                                   aapdhg_info *info);
 aapdhg_status aapdhg_batch_destroy(aapdhg_batch_t b);
 
-/* ---- serving: continuous batching of LP requests ----
+/* ---- serving: continuous batching of LP requests (not in the paper: a serving form of the
+ * batched solves; each request is solved by Alg 2 as aapdhg_solve would) ----
  * An admission thread creates submitted LPs (host tables, uploads, scaling, step sizes, the
  * init step of Alg 2) on `copy_stream` while their estimated device footprint fits in
  * hbm_budget_bytes and fewer than max_slots are admitted; an epoch thread takes the created

@@ -42,7 +42,7 @@ class Options(C.Structure):
                 ("pw_rho", C.c_double), ("sg_div", C.c_double), ("pw_dhat", C.c_int32),
                 ("restart_period", C.c_int32), ("prep_device", C.c_int32), ("pock_chambolle", C.c_int32),
                 ("angle_mode", C.c_int32), ("seed", C.c_uint64), ("length_floor", C.c_int32),
-                ("reserved1", C.c_int32)]
+                ("graph", C.c_int32), ("autotune", C.c_int32), ("reserved1", C.c_int32)]
 
 
 class Info(C.Structure):

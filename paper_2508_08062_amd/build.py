@@ -46,7 +46,7 @@ def build(verbose: bool = True) -> str:
     hipcc = _hipcc()
     os.makedirs(BUILD, exist_ok=True)
     objs = []
-    for src, device in (("kernels.hip", True), ("host.cpp", False), ("server.cpp", False)):
+    for src, device in (("kernels.hip", True), ("host.cpp", False), ("server.cpp", False), ("tuner.cpp", False)):
         obj = os.path.join(BUILD, src + ".o")
         cmd = [hipcc] + COMMON + ["-I", CSRC]
         if device:

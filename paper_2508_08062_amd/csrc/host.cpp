@@ -131,6 +131,8 @@ void default_options(aapdhg_options* o) {
   o->pock_chambolle = 0;
   o->angle_mode = 0;
   o->length_floor = 0;
+  o->graph = 0;
+  o->autotune = 0;
   o->reserved1 = 0;
   o->seed = 0;
 }
@@ -141,6 +143,8 @@ static void check_options(const aapdhg_options& o) {
   if (o.pock_chambolle != 0 && o.pock_chambolle != 1) throw Error(AAPDHG_E_ARG, "pock_chambolle must be 0 or 1");
   if (o.angle_mode != 0 && o.angle_mode != 1) throw Error(AAPDHG_E_ARG, "angle_mode must be 0 or 1");
   if (o.length_floor != 0 && o.length_floor != 1) throw Error(AAPDHG_E_ARG, "length_floor must be 0 or 1");
+  if (o.graph != 0 && o.graph != 1) throw Error(AAPDHG_E_ARG, "graph must be 0 or 1");
+  if (o.autotune != 0 && o.autotune != 1) throw Error(AAPDHG_E_ARG, "autotune must be 0 or 1");
   if (o.variant == AAPDHG_VARIANT_RPDHG && o.restart_period < 1)
     throw Error(AAPDHG_E_ARG, "restart_period must be >= 1 for restarted PDHG");
   if (o.precision != 0 && o.precision != 1) throw Error(AAPDHG_E_ARG, "precision must be 0 or 1");
@@ -221,13 +225,14 @@ static void reorder_rows(const std::vector<int>& ptr, const std::vector<int>& id
 // Cut the positions [0, R) of a reordered matrix into chunks (see Chunk):
 //  - runs of short rows form multi-row chunks of at most CHUNK_ROWS rows and
 //    CHUNK_NNZ entries, weighted so that short rows (whose epilogue
-//    dominates) do not crowd a chunk;
+//    dominates) do not crowd a chunk: each row counts row_weight entries
+//    beyond its own (4 by default; the autotuner may choose another);
 //  - longer rows are grouped by up to four (one wave each), at most CHUNK_NNZ
 //    entries per group; a group of one is reduced by the whole workgroup;
 //  - a row with more than CHUNK_NNZ entries is split into parts of SPLIT_NNZ.
 static void build_chunks(const std::vector<int>& ptr, int R, std::vector<Chunk>& chunks,
-                         std::vector<SplitRow>& splits, int& nparts_total) {
-  constexpr int ROW_WEIGHT = 4;
+                         std::vector<SplitRow>& splits, int& nparts_total, int row_weight) {
+  const int ROW_WEIGHT = row_weight;
   chunks.clear();
   splits.clear();
   nparts_total = 0;
@@ -509,8 +514,10 @@ void Problem::create(int32_t m_, int32_t n_, int64_t nnz_, const int64_t* row_pt
   std::vector<double> valA, valB;
   reorder_rows(colptr, rowidx, valT, n, rmapA, ptrA, idxA, valA);
   reorder_rows(rowptr, colidx, val, m, rmapB, ptrB, idxB, valB);
-  build_chunks(ptrA, n, chunksA, splitsA, npartsA);
-  build_chunks(ptrB, m, chunksB, splitsB, npartsB);
+  dev_ptrA = ptrA;
+  dev_ptrB = ptrB;
+  build_chunks(ptrA, n, chunksA, splitsA, npartsA, row_weight);
+  build_chunks(ptrB, m, chunksB, splitsB, npartsB, row_weight);
   tiles.clear();
   for (int e = 0; e < N; e += MIX_TILE) {
     MixTile t{};
@@ -657,6 +664,17 @@ void Problem::create(int32_t m_, int32_t n_, int64_t nnz_, const int64_t* row_pt
   std::vector<Problem*> one{this};
   solo->build(one);
   reset_host_state();
+  if (opt.autotune) autotune();
+}
+
+// The work tables again, after row_weight or the launch options changed:
+// the multi-row chunks of both passes and the LP's own launch set.
+void Problem::rebuild_tables() {
+  build_chunks(dev_ptrA, n, chunksA, splitsA, npartsA, row_weight);
+  build_chunks(dev_ptrB, m, chunksB, splitsB, npartsB, row_weight);
+  solo = std::make_unique<LaunchSet>();
+  std::vector<Problem*> one{this};
+  solo->build(one);
 }
 
 void Problem::fill_desc() {
@@ -888,7 +906,37 @@ void Problem::enqueue_init(hipStream_t st) {
 // ---------------------------------------------------------------------------
 
 LaunchSet::~LaunchSet() {
+  drop_graph();
   if (h_status) (void)hipHostFree(h_status);
+}
+
+void LaunchSet::drop_graph() {
+  if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+  graph_exec = nullptr;
+  graph_passes = 0;
+}
+
+// Capture `iters` three-launch loop passes on a private stream and
+// instantiate the graph; replays run the same kernels with the same
+// arguments (every table and state they read is in device memory).
+void LaunchSet::build_graph(int64_t iters) {
+  drop_graph();
+  hipStream_t cap = nullptr;
+  hip_check(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "capture stream");
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t el = hipSuccess;
+    for (int64_t it = 0; it < iters && el == hipSuccess; ++it) el = launch_loop_pass(t, cap, MODE_ITER);
+    e = hipStreamEndCapture(cap, &g);
+    if (el != hipSuccess) e = el;
+  }
+  (void)hipStreamDestroy(cap);
+  if (e == hipSuccess) e = hipGraphInstantiate(&graph_exec, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess) graph_exec = nullptr;
+  hip_check(e, "graph capture of the loop passes");
+  graph_passes = iters;
 }
 
 size_t LaunchSet::device_bytes() const {
@@ -901,6 +949,7 @@ size_t LaunchSet::device_bytes() const {
 }
 
 void LaunchSet::build(const std::vector<Problem*>& lps) {
+  drop_graph();
   members = lps;
   const int count = (int)lps.size();
   if (count == 0) throw Error(AAPDHG_E_ARG, "empty launch set");
@@ -1087,7 +1136,10 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
 
   // ---- persistent loop kernel: a group of resident workgroups per LP ----
   t.persistent = false;
+  use_graph = false;
+  for (auto* p : lps) use_graph |= p->opt.graph != 0;
   if (!persist) return;
+  use_graph = false;
   // cost of a unit (one chunk): a chunk's dependent chain of loads costs
   // about as much as 3000 gathered entries
   auto unit_weight = [&](const BlockWork& w) -> double {
@@ -1210,6 +1262,11 @@ void LaunchSet::enqueue_passes(hipStream_t st, int64_t iters) {
       hip_check(launch_loop(t, st, np, next_tag()), "loop launch");
       done += np;
     }
+    return;
+  }
+  if (use_graph && iters > 1) {
+    if (graph_passes != iters) build_graph(iters);
+    hip_check(hipGraphLaunch(graph_exec, st), "graph launch");
     return;
   }
   for (int64_t it = 0; it < iters; ++it) hip_check(launch_loop_pass(t, st, MODE_ITER), "loop pass");

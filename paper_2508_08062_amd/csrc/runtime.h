@@ -87,6 +87,13 @@ struct LaunchSet {
                            const std::chrono::steady_clock::time_point* t0 = nullptr);
   bool compacted = false;
   size_t device_bytes() const;
+  // three-launch passes captured in a HIP graph and replayed (some member
+  // asked for it and the set is not persistent)
+  bool use_graph = false;
+  hipGraphExec_t graph_exec = nullptr;
+  int64_t graph_passes = 0;
+  void build_graph(int64_t iters);
+  void drop_graph();
 };
 
 // One LP: host copies of the data as solved, its device arrays and state.
@@ -119,6 +126,8 @@ struct Problem {
   bool panels = false;
   int pcoff[PANELS + 1] = {};
   std::vector<Chunk> chunksBp;  // dual pass in a launch of its own with panels: 256-row chunks
+  int row_weight = 4;           // chunk cost model: entries a row counts beyond its own
+  std::vector<int> dev_ptrA, dev_ptrB;  // row pointers of the device row orders (host copies)
   LPDesc desc{};
   Scalars sc_init{};
   std::unique_ptr<LaunchSet> solo;
@@ -145,6 +154,12 @@ struct Problem {
   void set_state(const double* u, const double* u_prev, const double* g_prev, const double* dG, const double* W,
                  const int64_t* meta, const double* gram);
   size_t device_bytes() const;
+  void rebuild_tables();
+  // autotuner (tuner.cpp): row_weight, chunks_per_block and loop_kernel
+  // from the tuning cache, or timed on the device and stored there
+  void autotune();
+  std::string tune_key() const;
+  double time_candidate();
 };
 
 }  // namespace aapdhg

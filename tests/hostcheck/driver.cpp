@@ -135,6 +135,14 @@ int main() {
   o3.pock_chambolle = 1;
   o3.variant = AAPDHG_VARIANT_RPDHG;
   exercise(rag, o3);
+  // captured passes and the autotuner (its cache in the working directory)
+  aapdhg_options o4 = o;
+  o4.graph = 1;
+  o4.autotune = 1;
+  o4.loop_kernel = 1;
+  setenv("AAPDHG_TUNE_CACHE", "hostcheck_tune.txt", 1);
+  exercise(rag, o4);
+  exercise(rag, o4);  // the second takes the cached choice
   // transposed shape: columns longer than a chunk in the CSC pass
   std::vector<int> tall(4000, 3);
   LP tl = make_lp(40, tall, 2);

@@ -27,7 +27,7 @@ def test_host_library_under_address_and_undefined_behaviour_sanitizers(tmp_path)
     common = ["-std=c++17", "-O1", "-g"] + SAN + ["-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I", CSRC,
                                                   "-I", os.path.join(ROOT, "include")]
     objs = []
-    for src in (os.path.join(CSRC, "host.cpp"), os.path.join(CSRC, "server.cpp"),
+    for src in (os.path.join(CSRC, "host.cpp"), os.path.join(CSRC, "server.cpp"), os.path.join(CSRC, "tuner.cpp"),
                 os.path.join(HERE, "hip_stub.cpp"), os.path.join(HERE, "driver.cpp")):
         obj = str(tmp_path / (os.path.basename(src) + ".o"))
         r = subprocess.run([gxx] + common + ["-c", src, "-o", obj], capture_output=True, text=True)
@@ -39,5 +39,5 @@ def test_host_library_under_address_and_undefined_behaviour_sanitizers(tmp_path)
     # verify_asan_link_order=0: the process environment may preload a library ahead of the runtime
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:halt_on_error=1:verify_asan_link_order=0",
                UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
-    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=500)
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=500, cwd=str(tmp_path))
     assert r.returncode == 0 and "hostcheck ok" in r.stdout, (r.stdout[-2000:] + r.stderr[-6000:])
