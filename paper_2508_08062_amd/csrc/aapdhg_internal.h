@@ -15,7 +15,7 @@ constexpr int CHUNK_NNZ = 2048;   // nnz staged in LDS by one multi-row chunk
 constexpr int CHUNK_ROWS = 256;   // rows of one multi-row chunk (one per thread at most)
 constexpr int ROWS_PER_THREAD = CHUNK_ROWS / BLOCK;
 constexpr int SPLIT_NNZ = 8192;   // nnz per part of a split (very long) row
-constexpr int FAN = 48;           // children per node of the reduction tree
+constexpr int DECIDE_RECORDS = 256;  // records added by one workgroup of the decision launch
 constexpr int MIX_TILE = 2048;    // elements per block of the mix pass
 constexpr int NDOT = 2 * MAXM + 16;  // stride of one partial-sum record (doubles)
 constexpr int PANELS = 8;         // column panels of the dual product (one per XCD)
@@ -145,18 +145,14 @@ struct Chunk {
   int pad[4];
 };
 
-// Node of the per-LP reduction tree.  Its children are records of the record
-// array (leaf records first, then node records); node i owns record
-// (nleaves + i).  Only dual-pass records arrive; each first-level node also
-// adds a slice of the primal pass's leaf records, written by the previous
-// launch.
-struct Node {
-  int first;   // children that arrive (records [first, first + count))
-  int count;
-  int parent;  // node index, -1 at the root
-  int first2;  // records complete before the launch, added after the children
-  int count2;
-  int pad[3];
+// One workgroup of the decision launch (three-launch path): positions
+// [r0, r1) of its LP's record list (the LP's primal-pass records, then its
+// dual-pass records), summed into partial `slot`.
+struct DecideBlock {
+  int lp;
+  int r0, r1;
+  int slot;
+  int pad[4];
 };
 
 struct SplitRow {
@@ -164,8 +160,7 @@ struct SplitRow {
   int nparts;
   int part0;    // first slot in the split partial buffer
   int leaf;     // record that receives the row's dot sums (written by the last part)
-  int parent;   // tree node above that record
-  int pad[3];
+  int pad[4];
 };
 
 // One workgroup of an SpMV pass.  kind 0: the multi-row chunks [c0, c1) of
@@ -176,15 +171,16 @@ struct BlockWork {
   int kind;
   int c0, c1;
   int leaf;
-  int parent;
-  int pad[2];
+  int pad[3];
 };
 
-// Per-LP entry of a launch table: the root of its reduction tree (built over
-// the records of both passes; the dual pass climbs it).
+// Per-LP entry of a launch table: its records (primal pass [leafA, leafA +
+// nA), dual pass [leafB, leafB + nB)) and its workgroups of the decision
+// launch [blk0, blk0 + nblk) (their partials have the same indices).
 struct LaunchLP {
-  int root;
-  int pad[3];
+  int leafA, nA, leafB, nB;
+  int blk0, nblk;
+  int pad[2];
 };
 
 struct MixTile {
@@ -200,10 +196,11 @@ struct PassArgs {
   const LaunchLP* llp;
   const BlockWork* blocks;
   const Chunk* chunks;
-  const Node* nodes;
+  const DecideBlock* dblocks;
   const SplitRow* splits;
-  double* rec;          // [nleaves + nnodes][NDOT] partial-sum records
-  unsigned int* ncnt;   // [nnodes] arrival counters
+  double* rec;          // [nleaves][NDOT] partial-sum records
+  double* dpart;        // [decision workgroups][NDOT] partial sums of the records
+  unsigned int* dcnt;   // [LPs] arrivals of the decision workgroups
   double* splitpart;    // [split parts][2]
   unsigned int* splitcnt;  // [split rows]
   int nleaves;          // leaf records of both passes (workgroups and split rows)

@@ -301,46 +301,6 @@ static void build_chunks(const std::vector<int>& ptr, int R, std::vector<Chunk>&
   }
 }
 
-// Reduction tree of one LP: the nB dual-pass leaf records starting at record
-// leafB arrive; the nA primal-pass leaf records starting at record leafA are
-// complete before the dual pass starts and are spread over the first-level
-// nodes.  Nodes of at most FAN arriving children are appended to `nodes`;
-// parent[i] receives the node above dual leaf i.  Returns the root.
-static int build_tree(int leafB, int nB, int leafA, int nA, int nleaves_total, std::vector<Node>& nodes,
-                      std::vector<int>& parent) {
-  parent.assign(nB, -1);
-  std::vector<int> level;
-  const int nl1 = (nB + FAN - 1) / FAN;
-  for (int j = 0; j < nl1; ++j) {
-    Node nd{};
-    nd.first = leafB + j * FAN;
-    nd.count = std::min(FAN, nB - j * FAN);
-    nd.parent = -1;
-    const int a0 = (int)((long long)j * nA / nl1), a1 = (int)((long long)(j + 1) * nA / nl1);
-    nd.first2 = leafA + a0;
-    nd.count2 = a1 - a0;
-    const int id = (int)nodes.size();
-    for (int t = 0; t < nd.count; ++t) parent[j * FAN + t] = id;
-    nodes.push_back(nd);
-    level.push_back(id);
-  }
-  while (level.size() > 1) {
-    std::vector<int> next;
-    for (size_t i = 0; i < level.size(); i += FAN) {
-      Node nd{};
-      nd.first = nleaves_total + level[i];
-      nd.count = (int)std::min<size_t>(FAN, level.size() - i);
-      nd.parent = -1;
-      const int id = (int)nodes.size();
-      for (int t = 0; t < nd.count; ++t) nodes[level[i + t]].parent = id;
-      nodes.push_back(nd);
-      next.push_back(id);
-    }
-    level.swap(next);
-  }
-  return level[0];
-}
-
 // ---------------------------------------------------------------------------
 // problem creation
 // ---------------------------------------------------------------------------
@@ -861,7 +821,8 @@ void Problem::iterate_noalloc(hipStream_t st, int64_t iters) {
     return p;
   };
   t.rec = (double*)take(L.d_rec);
-  t.ncnt = (unsigned int*)take(L.d_ncnt);
+  t.dpart = (double*)take(L.d_dpart);
+  t.dcnt = (unsigned int*)take(L.d_dcnt);
   t.splitpart = (double*)take(L.d_splitpart);
   t.splitcnt = (unsigned int*)take(L.d_splitcnt);
   t.pwpart = (double*)take(L.d_pwpart);
@@ -941,8 +902,8 @@ void LaunchSet::build_graph(int64_t iters) {
 
 size_t LaunchSet::device_bytes() const {
   size_t b = 0;
-  const DevBuf* bufs[] = {&d_lps, &d_llp, &d_chunks, &d_blocksA, &d_blocksB, &d_nodes, &d_splits, &d_rec,
-                          &d_ncnt, &d_splitpart, &d_splitcnt, &d_tiles, &d_status, &d_wgs, &d_looplps,
+  const DevBuf* bufs[] = {&d_lps, &d_llp, &d_chunks, &d_blocksA, &d_blocksB, &d_dblocks, &d_splits, &d_rec,
+                          &d_dpart, &d_dcnt, &d_splitpart, &d_splitcnt, &d_tiles, &d_status, &d_wgs, &d_looplps,
                           &d_sync, &d_bc, &d_err, &d_pwpart, &d_pwcnt, &d_pwrec};
   for (auto* p : bufs) b += p->bytes;
   return b;
@@ -958,7 +919,7 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
   std::vector<LaunchLP> llp(count);
   std::vector<Chunk> chunks;
   std::vector<BlockWork> bA, bB;
-  std::vector<Node> nodes;
+  std::vector<DecideBlock> dblocks;
   std::vector<SplitRow> splits;
   std::vector<MixTile> tl;
   t = LaunchTables{};
@@ -1051,7 +1012,7 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
         w.lp = i;
         w.kind = 1;
         w.c0 = w.c1 = c_off + c;
-        w.leaf = w.parent = -1;
+        w.leaf = -1;
         bw.push_back(w);
       }
       pi.bend = (int)bw.size();
@@ -1066,28 +1027,31 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
       tl.push_back(x);
     }
   }
-  // leaves and trees: primal leaves need no parent (the primal pass does not
-  // climb); the dual pass climbs one tree per LP over both passes' leaves
+  // records and decision workgroups: every LP's records (its primal-pass
+  // workgroups and split columns, then its dual-pass workgroups and split
+  // rows) are added by DECIDE_RECORDS-position workgroups of the decision launch
   for (int i = 0; i < count; ++i) {
     PassInfo& pa = info[2 * i];
     PassInfo& pb = info[2 * i + 1];
-    for (int b = 0; b < pa.nb; ++b) {
-      bA[pa.b0 + b].leaf = pa.leaf0 + b;
-      bA[pa.b0 + b].parent = -1;
-    }
-    for (int q = 0; q < pa.ns; ++q) {
-      splits[pa.s0 + q].leaf = pa.leaf0 + pa.nb + q;
-      splits[pa.s0 + q].parent = -1;
-    }
-    std::vector<int> parent;
-    llp[i].root = build_tree(pb.leaf0, pb.nb + pb.ns, pa.leaf0, pa.nb + pa.ns, nleaves, nodes, parent);
-    for (int b = 0; b < pb.nb; ++b) {
-      bB[pb.b0 + b].leaf = pb.leaf0 + b;
-      bB[pb.b0 + b].parent = parent[b];
-    }
-    for (int q = 0; q < pb.ns; ++q) {
-      splits[pb.s0 + q].leaf = pb.leaf0 + pb.nb + q;
-      splits[pb.s0 + q].parent = parent[pb.nb + q];
+    for (int b = 0; b < pa.nb; ++b) bA[pa.b0 + b].leaf = pa.leaf0 + b;
+    for (int q = 0; q < pa.ns; ++q) splits[pa.s0 + q].leaf = pa.leaf0 + pa.nb + q;
+    for (int b = 0; b < pb.nb; ++b) bB[pb.b0 + b].leaf = pb.leaf0 + b;
+    for (int q = 0; q < pb.ns; ++q) splits[pb.s0 + q].leaf = pb.leaf0 + pb.nb + q;
+    LaunchLP& L = llp[i];
+    L.leafA = pa.leaf0;
+    L.nA = pa.nb + pa.ns;
+    L.leafB = pb.leaf0;
+    L.nB = pb.nb + pb.ns;
+    const int total = L.nA + L.nB;
+    L.blk0 = (int)dblocks.size();
+    L.nblk = std::max(1, (total + DECIDE_RECORDS - 1) / DECIDE_RECORDS);
+    for (int g = 0; g < L.nblk; ++g) {
+      DecideBlock d{};
+      d.lp = i;
+      d.r0 = g * DECIDE_RECORDS;
+      d.r1 = std::min(total, (g + 1) * DECIDE_RECORDS);
+      d.slot = L.blk0 + g;
+      dblocks.push_back(d);
     }
   }
   t.mt = mt;
@@ -1099,12 +1063,13 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
   d_chunks.upload(chunks.data(), chunks.size() * sizeof(Chunk), "chunks");
   d_blocksA.upload(bA.data(), bA.size() * sizeof(BlockWork), "workgroups A");
   d_blocksB.upload(bB.data(), bB.size() * sizeof(BlockWork), "workgroups B");
-  d_nodes.upload(nodes.data(), nodes.size() * sizeof(Node), "tree nodes");
+  d_dblocks.upload(dblocks.data(), dblocks.size() * sizeof(DecideBlock), "decision workgroups");
   d_splits.upload(splits.data(), std::max<size_t>(splits.size(), 1) * sizeof(SplitRow), "splits");
-  d_rec.alloc(((size_t)nleaves + nodes.size()) * NDOT * 8, "partial records");
+  d_rec.alloc((size_t)std::max(nleaves, 1) * NDOT * 8, "partial records");
   d_rec.zero("partial records");
-  d_ncnt.alloc(nodes.size() * 4, "tree counters");
-  d_ncnt.zero("tree counters");
+  d_dpart.alloc(dblocks.size() * NDOT * 8, "decision partials");
+  d_dcnt.alloc((size_t)count * 4, "decision counters");
+  d_dcnt.zero("decision counters");
   d_splitpart.alloc((size_t)std::max(parts, 1) * 2 * 8, "split partials");
   d_splitcnt.alloc(std::max<size_t>(splits.size(), 1) * 4, "split counters");
   d_splitcnt.zero("split counters");
@@ -1122,11 +1087,12 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
   t.blocksB = (const BlockWork*)d_blocksB.p;
   t.nblocksB = (int)bB.size();
   t.nleaves = nleaves;
-  t.nodes = (const Node*)d_nodes.p;
-  t.nnodes = (int)nodes.size();
+  t.dblocks = (const DecideBlock*)d_dblocks.p;
+  t.ndblocks = (int)dblocks.size();
   t.splits = (const SplitRow*)d_splits.p;
   t.rec = (double*)d_rec.p;
-  t.ncnt = (unsigned int*)d_ncnt.p;
+  t.dpart = (double*)d_dpart.p;
+  t.dcnt = (unsigned int*)d_dcnt.p;
   t.splitpart = (double*)d_splitpart.p;
   t.splitcnt = (unsigned int*)d_splitcnt.p;
   t.tiles = (const MixTile*)d_tiles.p;

@@ -20,11 +20,12 @@ struct LaunchTables {
   const BlockWork* blocksB = nullptr;
   int nblocksB = 0;
   int nleaves = 0;
-  const Node* nodes = nullptr;
-  int nnodes = 0;
+  const DecideBlock* dblocks = nullptr;
+  int ndblocks = 0;
   const SplitRow* splits = nullptr;
   double* rec = nullptr;
-  unsigned int* ncnt = nullptr;
+  double* dpart = nullptr;
+  unsigned int* dcnt = nullptr;
   double* splitpart = nullptr;
   unsigned int* splitcnt = nullptr;
   const MixTile* tiles = nullptr;
@@ -45,9 +46,9 @@ struct LaunchTables {
   unsigned long long timeout_ticks = 0;
 };
 
-// One loop pass (passes A, B and, in MODE_ITER, C) for every LP of the table.
-// With ev != nullptr, events ev[0..3] are recorded before A, after A, after B
-// and after C on the same stream.
+// One loop pass (passes A, B, the decisions D and, in MODE_ITER, C) for every
+// LP of the table.  With ev != nullptr, events ev[0..3] are recorded before
+// A, after A, after D and after C on the same stream.
 hipError_t launch_loop_pass(const LaunchTables& t, hipStream_t st, int mode, hipEvent_t* ev = nullptr);
 // `passes` loop passes of every LP of the table in one cooperative launch of
 // the persistent loop kernel (t.persistent must be set).

@@ -1022,17 +1022,12 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
   using DT = Dot<MT>;
   __shared__ double s_prod[CHUNK_NNZ];
   __shared__ double s_red[BLOCK / 64][NDOT];
-  __shared__ double s_fin[NDOT];
   __shared__ double s_racc[NDOT];  // dot sums of one split row
   __shared__ double s_tmp[4];
   __shared__ int s_live[MAXM];
-  __shared__ int s_flag;
   __shared__ int s_own;
-  __shared__ SolveWork s_work;
-  __shared__ Scalars s_sc;
 
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wv = tid >> 6;
   const BlockWork bw = a.blocks[blockIdx.x];
   const LPDesc* dp = a.lps + bw.lp;
   Scalars* sc = dp->sc;
@@ -1043,64 +1038,9 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
   const PassView v = make_view(*dp, sc->k, sc->nlive, sc->newslot, s_live, eval, &sc->tau);
   const PassCtx<T, MT, PASS, false, true> P(dp, v);
 
-  // ---- reduction tree: the last child of a node adds the children in order.
-  // Every thread calls it; returns true in the block that completed the root.
-  auto climb = [&](int node) -> bool {
-    for (;;) {
-      const Node nd = a.nodes[node];
-      __syncthreads();
-      if (wv == 0) {
-        wait_stores();
-        if (tid == 0) s_flag = arrive(&a.ncnt[node], (unsigned)nd.count);
-      }
-      __syncthreads();
-      if (!s_flag) return false;
-      if (tid == 0) reset_counter(&a.ncnt[node]);
-      double sum = 0.0;
-      const int per = CHUNK_NNZ / DT::COUNT;  // records per round through LDS
-      const int total = nd.count + nd.count2;
-      for (int c0 = 0; c0 < total; c0 += per) {
-        const int nrec = min(per, total - c0);
-        const int nval = nrec * DT::COUNT;
-        __syncthreads();
-#pragma unroll 4
-        for (int i = tid; i < nval; i += BLOCK) {
-          const int c = c0 + i / DT::COUNT, q = i % DT::COUNT;
-          const int rix = c < nd.count ? nd.first + c : nd.first2 + (c - nd.count);
-          s_prod[i] = ld_coh(a.rec, rix * NDOT + q);
-        }
-        __syncthreads();
-        if (tid < DT::COUNT)
-          for (int c = 0; c < nrec; ++c) sum += s_prod[c * DT::COUNT + tid];
-      }
-      if (tid < DT::COUNT) st_agent(&a.rec[(size_t)(a.nleaves + node) * NDOT + tid], sum);
-      if (nd.parent < 0) return true;
-      node = nd.parent;
-    }
-  };
-
-  // ---- dual-pass root: finish the loop pass of this LP ----
-  auto finish_lp = [&]() {
-    const LaunchLP L = a.llp[bw.lp];
-    __syncthreads();
-    if (wv == 0) wait_stores();
-    if (tid < DT::COUNT) s_fin[tid] = ld_coh(a.rec, (a.nleaves + L.root) * NDOT + tid);
-    // the decisions run on an LDS copy of the LP's scalars
-    constexpr int SW = sizeof(Scalars) / 8;
-    unsigned long long* gsc = reinterpret_cast<unsigned long long*>(sc);
-    unsigned long long* lsc = reinterpret_cast<unsigned long long*>(&s_sc);
-    for (int q = tid; q < SW; q += BLOCK) lsc[q] = gsc[q];
-    __syncthreads();
-    if (wv == 0) final_step<MT>(*dp, &s_sc, s_fin, eval, v.kkt, v.init, &s_work, lane);
-    __syncthreads();
-    for (int q = tid; q < SW; q += BLOCK) gsc[q] = lsc[q];
-  };
-
   if (bw.kind == 1) {
     const Chunk ch = a.chunks[bw.c0];
-    if (P.split_part(ch, a.splits, a.splitpart, a.splitcnt, a.rec, s_tmp, s_racc, &s_own)) {
-      if (PASS == 1 && climb(a.splits[ch.split].parent)) finish_lp();
-    }
+    P.split_part(ch, a.splits, a.splitpart, a.splitcnt, a.rec, s_tmp, s_racc, &s_own);
     return;
   }
 
@@ -1119,7 +1059,81 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
     }
   }
   write_record<MT>(acc, s_red, a.rec + (size_t)bw.leaf * NDOT, lane0, s_prod);
-  if (PASS == 1 && climb(bw.parent)) finish_lp();
+}
+
+// Decisions of a loop pass on the three-launch path, after pass B: every LP's
+// records of both passes are added in a fixed order and its last workgroup
+// runs final_step.  Workgroup b adds positions [r0, r1) of its LP's record
+// list (thread (t, q) adds value q of positions r0 + t, r0 + t + PT, ... in
+// order; then the PT sums of each value in order) into partial b; the last
+// of the LP's workgroups to arrive adds the LP's partials in order.  The
+// records were written by the previous launches, so only the partials need
+// agent-scope stores and an arrival count.
+template <typename T, int MT>
+__global__ __launch_bounds__(BLOCK) void k_decide(PassArgs a) {
+  using DT = Dot<MT>;
+  constexpr int C = DT::COUNT;
+  constexpr int PT = BLOCK / C;  // positions read at once
+  __shared__ double s_part[BLOCK];
+  __shared__ double s_fin[NDOT];
+  __shared__ int s_live[MAXM];
+  __shared__ int s_flag;
+  __shared__ SolveWork s_work;
+  __shared__ Scalars s_sc;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const DecideBlock db = a.dblocks[blockIdx.x];
+  const LPDesc* dp = a.lps + db.lp;
+  Scalars* sc = dp->sc;
+  const bool eval = a.mode == MODE_EVAL;
+  if (!eval && sc->status != ST_RUNNING) return;
+  const LaunchLP L = a.llp[db.lp];
+  const int t = tid / C, q = tid - (tid / C) * C;
+  double s = 0.0;
+  if (t < PT) {
+#pragma unroll 4
+    for (int p = db.r0 + t; p < db.r1; p += PT) {
+      const int rix = p < L.nA ? L.leafA + p : L.leafB + (p - L.nA);
+      s += a.rec[(size_t)rix * NDOT + q];
+    }
+  }
+  s_part[tid] = s;
+  __syncthreads();
+  double part = 0.0;
+  if (tid < C) {
+    for (int tt = 0; tt < PT; ++tt) part += s_part[tt * C + tid];
+  }
+  if (L.nblk > 1) {
+    if (tid < C) st_agent(&a.dpart[(size_t)db.slot * NDOT + tid], part);
+    __syncthreads();
+    if (wv == 0) {
+      wait_stores();
+      if (tid == 0) s_flag = arrive(&a.dcnt[db.lp], (unsigned)L.nblk);
+    }
+    __syncthreads();
+    if (!s_flag) return;
+    if (tid == 0) reset_counter(&a.dcnt[db.lp]);
+    if (tid < C) {
+      double sum = 0.0;
+      for (int g = 0; g < L.nblk; ++g) sum += ld_coh(a.dpart, (L.blk0 + g) * NDOT + tid);
+      s_fin[tid] = sum;
+    }
+  } else if (tid < C) {
+    s_fin[tid] = 0.0 + part;  // the ordered sum of the one partial
+  }
+  if (tid < MAXM) s_live[tid] = sc->live[tid];
+  __syncthreads();
+  const PassView v = make_view(*dp, sc->k, sc->nlive, sc->newslot, s_live, eval, &sc->tau);
+  // the decisions run on an LDS copy of the LP's scalars
+  constexpr int SW = sizeof(Scalars) / 8;
+  unsigned long long* gsc = reinterpret_cast<unsigned long long*>(sc);
+  unsigned long long* lsc = reinterpret_cast<unsigned long long*>(&s_sc);
+  for (int w = tid; w < SW; w += BLOCK) lsc[w] = gsc[w];
+  __syncthreads();
+  if (wv == 0) final_step<MT>(*dp, &s_sc, s_fin, eval, v.kkt, v.init, &s_work, lane);
+  __syncthreads();
+  for (int w = tid; w < SW; w += BLOCK) gsc[w] = lsc[w];
 }
 
 // ---------------------------------------------------------------------------
@@ -1954,10 +1968,11 @@ static hipError_t launch_passes_mt(const LaunchTables& t, hipStream_t st, int mo
   pa.lps = t.lps;
   pa.llp = t.llp;
   pa.chunks = t.chunks;
-  pa.nodes = t.nodes;
+  pa.dblocks = t.dblocks;
   pa.splits = t.splits;
   pa.rec = t.rec;
-  pa.ncnt = t.ncnt;
+  pa.dpart = t.dpart;
+  pa.dcnt = t.dcnt;
   pa.splitpart = t.splitpart;
   pa.splitcnt = t.splitcnt;
   pa.nleaves = t.nleaves;
@@ -1969,6 +1984,7 @@ static hipError_t launch_passes_mt(const LaunchTables& t, hipStream_t st, int mo
   if (t.panels) hipLaunchKernelGGL((k_panel<T>), dim3(PANELS * PANEL_GROUPS), dim3(BLOCK), 0, st, t.lps, mode);
   pa.blocks = t.blocksB;
   if (t.nblocksB > 0) hipLaunchKernelGGL((k_pass<T, MT, 1>), dim3(t.nblocksB), dim3(BLOCK), 0, st, pa);
+  if (t.ndblocks > 0) hipLaunchKernelGGL((k_decide<T, MT>), dim3(t.ndblocks), dim3(BLOCK), 0, st, pa);
   if (ev) (void)hipEventRecord(ev[2], st);
   if (mode == MODE_ITER && t.ntiles > 0) {
     MixArgs ma{t.lps, t.tiles, t.pwpart, t.pwcnt};

@@ -60,7 +60,7 @@ struct LaunchSet {
   static constexpr int64_t MAX_LOOP_PASSES = 65535;  // per launch of the persistent loop kernel
   std::vector<Problem*> members;
   LaunchTables t;
-  DevBuf d_lps, d_llp, d_chunks, d_blocksA, d_blocksB, d_nodes, d_splits, d_rec, d_ncnt, d_splitpart,
+  DevBuf d_lps, d_llp, d_chunks, d_blocksA, d_blocksB, d_dblocks, d_splits, d_rec, d_dpart, d_dcnt, d_splitpart,
       d_splitcnt, d_tiles, d_status, d_wgs, d_looplps, d_sync, d_bc, d_err, d_pwpart, d_pwcnt, d_pwrec;
   int* h_status = nullptr;  // pinned, 2 x MAX_STATUS
   int64_t last_epochs = 0;
