@@ -7,7 +7,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
+#include <new>
 #include <random>
+#include <thread>
 #include <vector>
 
 #include <hip/hip_runtime.h>
@@ -22,6 +25,23 @@ static int g_fail = 0;
       ++g_fail;                                                          \
     }                                                                    \
   } while (0)
+
+// Allocation failure on demand, on this thread only: while g_fail_at is
+// nonzero, operator new throws std::bad_alloc for requests of at least that
+// many bytes (the library's host copies of a submission go through it).
+static thread_local size_t g_fail_at = 0;
+void* operator new(size_t sz) {
+  if (g_fail_at && sz >= g_fail_at) throw std::bad_alloc();
+  if (void* p = std::malloc(sz ? sz : 1)) return p;
+  throw std::bad_alloc();
+}
+void* operator new(size_t sz, const std::nothrow_t&) noexcept {
+  if (g_fail_at && sz >= g_fail_at) return nullptr;
+  return std::malloc(sz ? sz : 1);
+}
+void operator delete(void* p) noexcept { std::free(p); }
+void operator delete(void* p, size_t) noexcept { std::free(p); }
+void operator delete(void* p, const std::nothrow_t&) noexcept { std::free(p); }
 
 struct LP {
   int m = 0, n = 0;
@@ -278,6 +298,28 @@ int main() {
       }
     }
     CHECK(done == 7 && failed == 1);
+    // a submission whose host copy of the values cannot be allocated fails with
+    // E_NOMEM, frees what it had copied, and the server goes on admitting
+    {
+      const LP& p = reqs[6];
+      uint64_t t = 0;
+      g_fail_at = (size_t)p.nnz() * sizeof(double);
+      const aapdhg_status st = aapdhg_server_submit(s, p.m, p.n, p.nnz(), p.rowptr.data(), p.col.data(),
+                                                    p.val.data(), p.c.data(), p.q.data(), p.l.data(),
+                                                    p.u.data(), p.rt.data(), &t);
+      g_fail_at = 0;
+      CHECK(st == AAPDHG_E_NOMEM);
+      CHECK(std::strstr(aapdhg_last_error(nullptr), "allocation") != nullptr);
+      CHECK(aapdhg_server_submit(s, p.m, p.n, p.nnz(), p.rowptr.data(), p.col.data(), p.val.data(), p.c.data(),
+                                 p.q.data(), p.l.data(), p.u.data(), p.rt.data(), &t) == AAPDHG_OK);
+      aapdhg_status ps = AAPDHG_PENDING;
+      std::vector<double> x(p.n), y(p.m);
+      for (int spin = 0; spin < 20000 && ps == AAPDHG_PENDING; ++spin) {
+        ps = aapdhg_server_poll(s, t, nullptr, x.data(), y.data(), nullptr, nullptr);
+        if (ps == AAPDHG_PENDING) std::this_thread::sleep_for(std::chrono::milliseconds(1));
+      }
+      CHECK(ps == AAPDHG_OK);
+    }
     int64_t stats[6];
     CHECK(aapdhg_server_stats(s, stats) == AAPDHG_OK);
     CHECK(aapdhg_server_poll(s, 999999, nullptr, nullptr, nullptr, nullptr, nullptr) == AAPDHG_E_ARG);
