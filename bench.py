@@ -85,8 +85,10 @@ def _traffic(workload, kernel, ppl):
     if k is None or "hbm_bytes_per_pass" not in k:
         return None
     b = k["hbm_bytes_per_pass"]
-    if kernel == "dual" and "panel" in ks:  # the dual launch's events bracket the panel kernel too
-        b += ks["panel"]["hbm_bytes_per_pass"]
+    if kernel == "dual":  # the dual launch's events bracket the panel kernel and the decisions too
+        for extra in ("panel", "decide"):
+            if extra in ks:
+                b += ks[extra]["hbm_bytes_per_pass"]
     return b * ppl
 
 
@@ -700,6 +702,17 @@ def main():
         ws = (16 * Z + 4 * (2 * opts["memory"] + 12) * (n + m)) / 1e6
         line["roofline"]["note"] = (f"working set about {ws:.0f} MB stays in L2/MALL: the pass is bound by "
                                     "latency, not HBM")
+
+    if args.workload == "powerlaw1m" and not args.no_legs:
+        # the same passes in float64 (the float32 path's gain where bandwidth decides)
+        s64 = P.Solver(lps[0], tol=0.0, max_iter=10 ** 9, **{**opts, "precision": 1})
+        st64, ms64 = _timed_passes(s64, stream, 500, 50, 500)
+        kt64 = s64.iterate_timed(100, stream)
+        s64.close()
+        line["fp64_passes"] = {"value": st64 / (ms64 * 1e-3), "unit": "iters/s", "steps": st64,
+                               "ms_per_step": ms64 / st64, "launch_ms": kt64,
+                               "note": "same LP and method with float64 data and iterates"}
+        print(f"# float64 passes: {st64 / (ms64 * 1e-3):.0f} iters/s", file=sys.stderr, flush=True)
 
     if not args.no_solve and len(lps) == 1:
         print("# solve to rel KKT 1e-4, float32", file=sys.stderr, flush=True)
