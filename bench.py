@@ -46,18 +46,22 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 
 
-def _bytes_model(n, m, Z, M, kkt_frac):
+def _bytes_model(n, m, Z, M, kkt_frac, dots=True):
     """Algorithmic bytes of one launch of each pass (float32 data, int32
     indices), with a full memory of M columns: the matrix once (value and
     index), the gathered vector once, and every vector the epilogue reads or
-    writes once; the dots read the M - 1 live history columns that are not
-    being replaced, and the new column pair is written."""
-    hist = (M - 1) * 4  # dot products read the live columns except the replaced one
+    writes once, and the new column pair is written.  With dots (the
+    persistent kernel) the passes also read the M - 1 live history columns
+    that are not being replaced, for the new Gram row; the three-launch
+    passes leave that to the Gram launch, which on an Anderson step reads the
+    M live columns and g ("gram")."""
+    hist = (M - 1) * 4 if dots else 0
     primal = 8 * Z + 4 * (n + 1) + 4 * m + n * (7 * 4 + hist + 5 * 4)
     dual = 8 * Z + 4 * (m + 1) + 4 * n * (1 + kkt_frac) + m * (5 * 4 + 1 + hist + 4 * 4)
     mix = n * (5 * 4 + M * 4 + 4) + m * (3 * 4 + 1 + M * 4 + 4)
+    gram = 0 if dots else (M + 1) * 4 * (n + m)
     spmv = 16 * Z + 8 * (n + m)
-    return {"primal": primal, "dual": dual, "mix": mix, "spmv": spmv}
+    return {"primal": primal, "dual": dual, "mix": mix, "gram": gram, "spmv": spmv}
 
 
 def _src_hash():
@@ -144,16 +148,18 @@ def _launch_roofline(lps, opts, solvers, runner, stream, ppl, workload):
     m = sum(lp.m for lp in lps)
     Z = sum(lp.nnz for lp in lps)
     M = opts["memory"]
-    bm = _bytes_model(n, m, Z, M, 1.0 / opts["kkt_every"])
-    def aa_steps():
+    def results():
         if runner in solvers:
-            return sum(s.result()["aa_steps"] for s in solvers)
-        return sum(runner.result(i)["aa_steps"] for i in range(len(solvers)))
+            return [s.result() for s in solvers]
+        return [runner.result(i) for i in range(len(solvers))]
 
-    aa0 = aa_steps()
+    r0 = results()
     kt = [runner.iterate_timed(ppl, stream) for _ in range(3)]
-    aa1 = aa_steps()
-    aa_frac = (aa1 - aa0) / (3.0 * ppl * len(solvers))
+    r1 = results()
+    aa_frac = sum(b["aa_steps"] - a["aa_steps"] for a, b in zip(r0, r1)) / (3.0 * ppl * len(solvers))
+    # the three-launch passes take the per-pass Gram dots unless every LP forms the Gram on demand
+    dots = kt[0]["kernel"] == "persistent" or any(not r["gram_on_demand"] for r in r1)
+    bm = _bytes_model(n, m, Z, M, 1.0 / opts["kkt_every"], dots=dots)
     if kt[0]["kernel"] == "persistent":
         launch_ms = sum(k["launch_ms"] for k in kt) / len(kt)
         per_pass = bm["primal"] + bm["dual"] + aa_frac * bm["mix"]
@@ -311,24 +317,26 @@ def _batch_leg(args, stream, cpu_baseline=False):
     kw = dict(opts, tol=1e-4, max_iter=200000)
     # whole batch passes (64, far from any member's termination) with the
     # built-in or the autotuned work tables, launched directly or replayed
-    # from a HIP graph; the batch is then solved in the fastest of the four
-    configs = {}
-    for tune in (0, 1):
-        for graph in (0, 1):
-            t0 = time.perf_counter()
-            solvers = [P.Solver(lp, autotune=tune, graph=graph, **kw) for lp in lps]
-            t_create = time.perf_counter() - t0
-            batch = P.Batch(solvers)
-            _, ms = _timed_passes(batch, stream, 64, 8, 64)
-            batch.close()
-            for sv in solvers:
-                sv.close()
-            configs[f"autotune{tune}_graph{graph}"] = {"ms_per_batch_pass": ms / 64, "create_seconds": t_create}
-            print(f"# autotune {tune} graph {graph}: {ms / 64:.3f} ms per batch pass (created in {t_create:.1f} s)",
-                  file=sys.stderr, flush=True)
+    # from a HIP graph, and with the Gram matrix formed on every pass (the
+    # default for these LPs, which the persistent kernel can take alone) or
+    # on demand (gram_mode 2); the batch is then solved in the fastest
+    configs, params = {}, {}
+    for tune, graph, gram in ((0, 0, 0), (0, 1, 0), (1, 0, 0), (1, 1, 0), (0, 0, 2), (0, 1, 2)):
+        name = f"autotune{tune}_graph{graph}_gram{gram}"
+        t0 = time.perf_counter()
+        solvers = [P.Solver(lp, autotune=tune, graph=graph, gram_mode=gram, **kw) for lp in lps]
+        t_create = time.perf_counter() - t0
+        batch = P.Batch(solvers)
+        _, ms = _timed_passes(batch, stream, 64, 8, 64)
+        batch.close()
+        for sv in solvers:
+            sv.close()
+        configs[name] = {"ms_per_batch_pass": ms / 64, "create_seconds": t_create}
+        params[name] = dict(autotune=tune, graph=graph, gram_mode=gram)
+        print(f"# autotune {tune} graph {graph} gram_mode {gram}: {ms / 64:.3f} ms per batch pass "
+              f"(created in {t_create:.1f} s)", file=sys.stderr, flush=True)
     best_cfg = min(configs, key=lambda c: configs[c]["ms_per_batch_pass"])
-    tune, graph = int(best_cfg[8]), int(best_cfg[-1])
-    solvers = [P.Solver(lp, autotune=tune, graph=graph, **kw) for lp in lps]
+    solvers = [P.Solver(lp, **params[best_cfg], **kw) for lp in lps]
     batch = P.Batch(solvers)
     batch.iterate(1, stream)
     batch.iterate(8, stream)

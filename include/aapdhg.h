@@ -162,12 +162,25 @@ typedef struct {
                              candidates on the device, or taken from the tuning cache (file
                              AAPDHG_TUNE_CACHE, default ~/.cache/aapdhg/tune.txt) for LPs of
                              the same shape class; 0 (default): the built-in choice        */
-  int32_t reserved1;
+  int32_t gram_mode;      /* how Alg 2's Gram matrix of the memory and its right-hand side are
+                             formed.  The persistent loop kernel updates them on every pass
+                             (dots of the new difference column with the stored ones).  The
+                             three launches per pass can instead form them from the stored
+                             columns only for Anderson steps, which saves reading the memory
+                             on every pass.  0 (default): on demand for an LP that cannot run
+                             in the persistent kernel by itself (so it always runs in three
+                             launches), every pass otherwise, so an LP's iterates do not
+                             depend on the other LPs of its batch or server set; 1: every
+                             pass; 2: on demand whenever the LP runs in three launches (an
+                             LP that moves between the kernels, such as a batch member or a
+                             served request whose set changes, can then differ from its solo
+                             run in rounding)                                            */
 } aapdhg_options;
 
 typedef struct {
   int32_t term;            /* aapdhg_term                                                  */
-  int32_t reserved0;
+  int32_t gram_on_demand;  /* 1: the LP's three-launch passes form the Gram matrix only for
+                              Anderson steps (option gram_mode); 0: on every pass          */
   int64_t iters;           /* index k of the returned iterate u^k                          */
   int64_t aa_steps;        /* i^k: Anderson steps taken                                    */
   int64_t pdhg_steps;      /* j^k: plain PDHG steps taken                                  */
@@ -260,15 +273,18 @@ aapdhg_status aapdhg_iterate(aapdhg_t h, void *stream, int64_t iters);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): the same passes as aapdhg_iterate, with
- * the same results bit for bit, but the passes' scratch (partial-sum records, reduction and
- * split counters, the persistent kernel's barrier counters and published decisions) lives in
+ * the same results bit for bit, but the passes' scratch (partial-sum records, decision, split
+ * and Gram-launch partials and counters, the persistent kernel's barrier counters and
+ * published decisions) lives in
  * a static device array of the library instead of the handle's buffers.  The call allocates
  * nothing: it clears the part of the array the LP needs with a fill kernel on `stream` and
  * enqueues the passes (asynchronous, like aapdhg_iterate).  The array holds 2 MiB per GPU
  * (kept until the process ends); an LP whose pass tables need more is AAPDHG_E_ARG with the
  * size in the message.  The need is 384 bytes per workgroup of a pass and per row or column
- * longer than 2048 entries, plus 16 bytes per 2048 entries of n + m: about 0.8 MiB for a
- * 1M x 2M LP with 20M entries, 0.2 MiB for a 20k x 50k LP.  Every call on one
+ * longer than 2048 entries, plus, per 2048 entries of n + m, 16 bytes and 8 (M (M + 1) / 2 + M)
+ * bytes of Gram partials (M: m_A rounded up to 4, 8, 10 or 16): about 1.5 MiB for a
+ * 1M x 2M LP with 20M entries and m_A = 10 (too much with m_A = 16), 0.2 MiB for a
+ * 20k x 50k LP.  Every call on one
  * GPU uses the same array: calls that overlap on one GPU (other streams, other host threads)
  * race and must be serialised by the caller; consecutive calls on one stream are safe. */
 aapdhg_status aapdhg_iterate_noalloc(aapdhg_t h, void* stream, int64_t iters);
@@ -279,8 +295,8 @@ aapdhg_status aapdhg_iterate_noalloc(aapdhg_t h, void* stream, int64_t iters);
  *   persistent loop kernel: {1, duration in ms of its one launch, iters, 1}
  *     (iters <= 65535);
  *   three launches per pass: {0, mean ms of the primal CSC launch, of the dual CSR launch
- *     with the float64 decisions, of the mix launch}; the events add a small gap between
- *     launches, so use aapdhg_iterate for throughput. */
+ *     with the float64 decisions, of the Gram launch and the mix launch}; the events add a
+ *     small gap between launches, so use aapdhg_iterate for throughput. */
 aapdhg_status aapdhg_iterate_timed(aapdhg_t h, void *stream, int64_t iters, double *ms4);
 
 /* Return to the start point u^0 of Alg 2's initialisation (discard iterate, history and
@@ -307,6 +323,9 @@ aapdhg_status aapdhg_result(aapdhg_t h, double *x, double *y, double *lambda, aa
  *          the order of gamma (AAPDHG_MAX_MEMORY entries, zero past nmix)
  *   gram   double[AAPDHG_MAX_MEMORY^2 + 3*AAPDHG_MAX_MEMORY + 2]: Gram by slot, rhs, du2, n0,
  *          gnorm, then gamma of the last Anderson step (nmix entries used, zero past them).
+ *          The Gram entries of the live slots and rhs (<dG[slot], g^{k-1}>) are current: passes
+ *          that leave them stale (three launches per pass form them only for Anderson steps)
+ *          are followed by a refresh on the device before they are copied.
  * Any pointer may be NULL to skip it.  aapdhg_set_state reads meta up to the live slots and
  * gram up to gnorm. */
 aapdhg_status aapdhg_get_state(aapdhg_t h, double *u, double *u_prev, double *g_prev, double *dG,

@@ -42,11 +42,11 @@ class Options(C.Structure):
                 ("pw_rho", C.c_double), ("sg_div", C.c_double), ("pw_dhat", C.c_int32),
                 ("restart_period", C.c_int32), ("prep_device", C.c_int32), ("pock_chambolle", C.c_int32),
                 ("angle_mode", C.c_int32), ("seed", C.c_uint64), ("length_floor", C.c_int32),
-                ("graph", C.c_int32), ("autotune", C.c_int32), ("reserved1", C.c_int32)]
+                ("graph", C.c_int32), ("autotune", C.c_int32), ("gram_mode", C.c_int32)]
 
 
 class Info(C.Structure):
-    _fields_ = [("term", C.c_int32), ("reserved0", C.c_int32), ("iters", C.c_int64),
+    _fields_ = [("term", C.c_int32), ("gram_on_demand", C.c_int32), ("iters", C.c_int64),
                 ("aa_steps", C.c_int64), ("pdhg_steps", C.c_int64), ("primal_obj", C.c_double),
                 ("dual_obj", C.c_double), ("r_gap", C.c_double), ("r_pri", C.c_double),
                 ("r_dual", C.c_double), ("kkt", C.c_double), ("gnorm", C.c_double),

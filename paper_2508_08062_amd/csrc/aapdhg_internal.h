@@ -36,7 +36,10 @@ struct Dot {
 };
 
 enum Status : int { ST_CONVERGED = 0, ST_ITER_LIMIT = 1, ST_TIME_LIMIT = 2, ST_NUMERICAL = 3, ST_RUNNING = 4 };
-enum Branch : int { BR_NONE = 0, BR_PDHG = 1, BR_AA = 2 };
+// BR_GRAM: the safeguard test of the pass passed with a non-empty memory on
+// the three-launch path; the Gram launch forms the history's Gram matrix and
+// finishes the pass (the branch is then BR_AA or BR_PDHG).
+enum Branch : int { BR_NONE = 0, BR_PDHG = 1, BR_AA = 2, BR_GRAM = 3 };
 enum Variant : int { V_PDHG = 0, V_AA = 1, V_FAA = 2, V_RPDHG = 3 };
 enum Mode : int { MODE_ITER = 0, MODE_EVAL = 1 };
 
@@ -73,6 +76,12 @@ struct alignas(256) Scalars {
   int pw_flag;            // 1: the weight changed before this pass (memory reset pending)
   int pw_blend;           // set by the pass that re-blended D-hat: 1 alpha = 0.9, 2 alpha = 0.1
   long long faa_empty;    // FAA steps whose filters kept no column
+  // 1: G and rhs hold the Gram matrix of the live slots and <dG[slot], g^{k-1}>.
+  // The persistent kernel keeps them so from pass to pass; the passes of the
+  // three-launch path leave them stale (0) and form them only for Anderson
+  // steps (the Gram launch), or when a refresh asks for them.
+  int gram_ok;
+  int pad1;
 };
 
 // Per-LP immutable description (device copy).  Vectors of length N = n + m
@@ -93,6 +102,10 @@ struct LPDesc {
   int restart;
   int angle_mode;  // FAA angle filter: 0 one factorisation, 1 refreshed after each removal
   int length_floor;  // FAA length filter keeps at least this many columns (0 or 1)
+  // 1: the three-launch passes leave out the dots of the new difference column
+  // with the stored ones; G and rhs are formed by the Gram launch when a step
+  // needs them (the persistent kernel keeps them pass by pass either way)
+  int lazy_gram;
   double* rsum;
   const int* rowptr;  // CSR of K, rows in the order rmapB
   const int* colidx;
@@ -205,6 +218,18 @@ struct PassArgs {
   unsigned int* splitcnt;  // [split rows]
   int nleaves;          // leaf records of both passes (workgroups and split rows)
   int mode;
+};
+
+// The Gram launch (three-launch path): one workgroup per mix tile.  Partials
+// of an LP are stored value-major: value q of the LP's tile j (of nt) at
+// gpart[t0 * nv + q * nt + j], with t0 the LP's first tile and nv the values
+// per tile of the launch's memory bound.
+struct GramArgs {
+  const LPDesc* lps;
+  const MixTile* tiles;
+  double* gpart;
+  unsigned int* gcnt;    // [LPs] arrivals
+  int refresh;           // 1: only bring G and rhs up to date where gram_ok is 0
 };
 
 struct MixArgs {

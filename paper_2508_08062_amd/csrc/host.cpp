@@ -133,7 +133,7 @@ void default_options(aapdhg_options* o) {
   o->length_floor = 0;
   o->graph = 0;
   o->autotune = 0;
-  o->reserved1 = 0;
+  o->gram_mode = 0;
   o->seed = 0;
 }
 
@@ -145,6 +145,7 @@ static void check_options(const aapdhg_options& o) {
   if (o.length_floor != 0 && o.length_floor != 1) throw Error(AAPDHG_E_ARG, "length_floor must be 0 or 1");
   if (o.graph != 0 && o.graph != 1) throw Error(AAPDHG_E_ARG, "graph must be 0 or 1");
   if (o.autotune != 0 && o.autotune != 1) throw Error(AAPDHG_E_ARG, "autotune must be 0 or 1");
+  if (o.gram_mode < 0 || o.gram_mode > 2) throw Error(AAPDHG_E_ARG, "gram_mode must be 0, 1 or 2");
   if (o.variant == AAPDHG_VARIANT_RPDHG && o.restart_period < 1)
     throw Error(AAPDHG_E_ARG, "restart_period must be >= 1 for restarted PDHG");
   if (o.precision != 0 && o.precision != 1) throw Error(AAPDHG_E_ARG, "precision must be 0 or 1");
@@ -619,6 +620,7 @@ void Problem::create(int32_t m_, int32_t n_, int64_t nnz_, const int64_t* row_pt
                 opt.tau * opt.sigma * norm_est * norm_est, norm_est);
   }
   fill_desc();
+  set_gram_mode();
   d_desc.upload(&desc, sizeof desc, "descriptor");
   solo = std::make_unique<LaunchSet>();
   std::vector<Problem*> one{this};
@@ -632,9 +634,28 @@ void Problem::create(int32_t m_, int32_t n_, int64_t nnz_, const int64_t* row_pt
 void Problem::rebuild_tables() {
   build_chunks(dev_ptrA, n, chunksA, splitsA, npartsA, row_weight);
   build_chunks(dev_ptrB, m, chunksB, splitsB, npartsB, row_weight);
+  set_gram_mode();
   solo = std::make_unique<LaunchSet>();
   std::vector<Problem*> one{this};
   solo->build(one);
+}
+
+// Whether the three-launch passes form the Gram matrix on demand (option
+// gram_mode; by default only for an LP that the persistent kernel cannot
+// take by itself, by the rule LaunchSet::build applies to a set of one).
+void Problem::set_gram_mode() {
+  bool lazy = opt.gram_mode == 2;
+  if (opt.gram_mode == 0) {
+    bool alone = opt.loop_kernel == 0;
+    if (alone) {
+      const bool ext = opt.pw_period > 0 || opt.variant == AAPDHG_VARIANT_RPDHG;
+      const int cap = loop_capacity(fp64, std::max(1, opt.memory), ext);
+      const long long need = (long long)std::max(chunksA.size(), chunksB.size());
+      alone = cap >= 1 && need <= 2LL * cap;
+    }
+    lazy = !alone;
+  }
+  desc.lazy_gram = lazy ? 1 : 0;
 }
 
 void Problem::fill_desc() {
@@ -790,6 +811,7 @@ void Problem::reset_host_state() {
   sc_init.dhb[0] = sc_init.dhb[1] = 0.0;
   sc_init.pw_updates = 0;
   sc_init.faa_empty = 0;
+  sc_init.gram_ok = 1;  // empty memory
   sc_init.pw_flag = 0;
   sc_init.pw_blend = 0;
 }
@@ -802,9 +824,10 @@ void Problem::enqueue_reset(hipStream_t st) {
 }
 
 // The passes of aapdhg_iterate with the per-pass scratch of the launch
-// tables (partial-sum records, reduction-tree and split counters, split and
-// weight-check partials and, for the persistent kernel, its barrier
-// counters, published decisions, weight-check partials and error word) in
+// tables (partial-sum records, decision partials and counters, split,
+// weight-check and Gram-launch partials and counters and, for the persistent
+// kernel, its barrier counters, published decisions, weight-check partials
+// and error word) in
 // the library's static device array instead of the handle's buffers.
 // Nothing is allocated: the array's used range is cleared by a fill kernel
 // on `st`, then the passes are enqueued.
@@ -827,6 +850,8 @@ void Problem::iterate_noalloc(hipStream_t st, int64_t iters) {
   t.splitcnt = (unsigned int*)take(L.d_splitcnt);
   t.pwpart = (double*)take(L.d_pwpart);
   t.pwcnt = (unsigned int*)take(L.d_pwcnt);
+  t.gpart = (double*)take(L.d_gpart);
+  t.gcnt = (unsigned int*)take(L.d_gcnt);
   if (t.persistent) {
     t.sync = (LoopSync*)take(L.d_sync);
     t.bc = (BcastMsg*)take(L.d_bc);
@@ -904,7 +929,7 @@ size_t LaunchSet::device_bytes() const {
   size_t b = 0;
   const DevBuf* bufs[] = {&d_lps, &d_llp, &d_chunks, &d_blocksA, &d_blocksB, &d_dblocks, &d_splits, &d_rec,
                           &d_dpart, &d_dcnt, &d_splitpart, &d_splitcnt, &d_tiles, &d_status, &d_wgs, &d_looplps,
-                          &d_sync, &d_bc, &d_err, &d_pwpart, &d_pwcnt, &d_pwrec};
+                          &d_sync, &d_bc, &d_err, &d_pwpart, &d_pwcnt, &d_pwrec, &d_gpart, &d_gcnt};
   for (auto* p : bufs) b += p->bytes;
   return b;
 }
@@ -982,7 +1007,7 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
         // device at once, in one round (the pass B kernel holds fewer per CU);
         // the count depends on the LP's own options only, so the LP's
         // reduction order is the same alone and in any batch
-        int pcap = pass_capacity(p->fp64, p->opt.memory, pass);
+        int pcap = pass_capacity(p->fp64, p->opt.memory, pass, p->desc.lazy_gram == 0);
         if (pcap <= 0) pcap = 1024;
         cpb = std::max(1, (nch + pcap - 1) / pcap);
       }
@@ -1077,6 +1102,9 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
   d_pwpart.alloc(std::max<size_t>(tl.size(), 1) * 2 * 8, "weight-check partials");
   d_pwcnt.alloc((size_t)count * 4, "weight-check counters");
   d_pwcnt.zero("weight-check counters");
+  d_gpart.alloc(std::max<size_t>(tl.size(), 1) * gram_partials_per_tile(mt) * 8, "Gram partials");
+  d_gcnt.alloc((size_t)count * 4, "Gram counters");
+  d_gcnt.zero("Gram counters");
   d_status.alloc(count * 4, "status");
   if (!h_status) hip_check(hipHostMalloc((void**)&h_status, sizeof(int) * 2 * MAX_STATUS, hipHostMallocDefault), "pinned status");
   t.lps = (const LPDesc*)d_lps.p;
@@ -1099,6 +1127,17 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
   t.ntiles = (int)tl.size();
   t.pwpart = (double*)d_pwpart.p;
   t.pwcnt = (unsigned int*)d_pwcnt.p;
+  t.gpart = (double*)d_gpart.p;
+  t.gcnt = (unsigned int*)d_gcnt.p;
+  // the Gram launch serves the LPs that form the Gram matrix on demand; the
+  // pass kernels form the per-pass dots when some LP needs them
+  t.gram = false;
+  t.dots = false;
+  for (auto* p : lps) {
+    const bool aa = p->opt.variant == AAPDHG_VARIANT_AA || p->opt.variant == AAPDHG_VARIANT_FAA;
+    t.gram |= aa && p->desc.lazy_gram != 0;
+    t.dots |= p->desc.lazy_gram == 0;
+  }
 
   // ---- persistent loop kernel: a group of resident workgroups per LP ----
   t.persistent = false;
@@ -1395,7 +1434,10 @@ void Problem::result_device(double* x, double* y, double* lam, aapdhg_info* info
   }
   hip_check(launch_unscale(d_u[(int)(s.k & 1)].p, d_lam.p, (const double*)d_scale.p, fp64, n, m, x, y, lam, st),
             "unscale launch");
-  if (info) fill_info(s, last_solve_seconds, info);
+  if (info) {
+    fill_info(s, last_solve_seconds, info);
+    info->gram_on_demand = desc.lazy_gram;
+  }
 }
 
 void Problem::result(double* x, double* y, double* lam, aapdhg_info* info, bool run_eval) {
@@ -1421,7 +1463,10 @@ void Problem::result(double* x, double* y, double* lam, aapdhg_info* info, bool 
     for (int j = 0; j < n; ++j) lam[j] = l[j] / d_col[j];
   }
   (void)ts;
-  if (info) fill_info(s, last_solve_seconds, info);
+  if (info) {
+    fill_info(s, last_solve_seconds, info);
+    info->gram_on_demand = desc.lazy_gram;
+  }
 }
 
 // primal-weight state: see aapdhg_get_weights in aapdhg.h
@@ -1468,6 +1513,9 @@ void Problem::set_weights(const double* anchor, const double* w) {
 // checkpoint layout: see aapdhg_get_state in aapdhg.h
 void Problem::get_state(double* u, double* u_prev, double* g_prev, double* dG, double* W, int64_t* meta,
                         double* gram) {
+  hip_check(hipDeviceSynchronize(), "state sync");
+  // G and rhs as the persistent kernel keeps them (three-launch passes leave them stale)
+  hip_check(launch_gram_refresh(solo->t, nullptr), "Gram refresh");
   hip_check(hipDeviceSynchronize(), "state sync");
   Scalars s;
   read_scalars(s);

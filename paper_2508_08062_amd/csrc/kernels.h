@@ -32,6 +32,10 @@ struct LaunchTables {
   int ntiles = 0;
   double* pwpart = nullptr;       // [tiles][2] weight-check partial sums
   unsigned int* pwcnt = nullptr;  // [LPs] weight-check arrivals
+  double* gpart = nullptr;        // [tiles][gram_partials_per_tile(mt)] Gram-launch partials
+  unsigned int* gcnt = nullptr;   // [LPs] Gram-launch arrivals
+  bool gram = false;  // some LP of the table forms its Gram matrix on demand (the Gram launch runs)
+  bool dots = true;   // some LP of the table needs the per-pass dots in the three-launch passes
   // persistent loop kernel (when the set fits the resident workgroups)
   bool panels = false;  // the one LP of the table has column panels for its dual product
   bool persistent = false;
@@ -46,18 +50,26 @@ struct LaunchTables {
   unsigned long long timeout_ticks = 0;
 };
 
-// One loop pass (passes A, B, the decisions D and, in MODE_ITER, C) for every
-// LP of the table.  With ev != nullptr, events ev[0..3] are recorded before
-// A, after A, after D and after C on the same stream.
+// One loop pass (passes A, B, the decisions D and, in MODE_ITER, the Gram
+// launch and the mix C) for every LP of the table.  With ev != nullptr,
+// events ev[0..3] are recorded before A, after A, after D and after C on the
+// same stream.
 hipError_t launch_loop_pass(const LaunchTables& t, hipStream_t st, int mode, hipEvent_t* ev = nullptr);
 // `passes` loop passes of every LP of the table in one cooperative launch of
-// the persistent loop kernel (t.persistent must be set).
+// the persistent loop kernel (t.persistent must be set), after a Gram refresh
+// of the LPs whose three-launch passes left G and rhs stale.
 hipError_t launch_loop(const LaunchTables& t, hipStream_t st, long long passes, unsigned int tag0);
+// Gram refresh: G and rhs of the live slots of every LP of the table whose
+// scalars say they are stale (no work for the others).
+hipError_t launch_gram_refresh(const LaunchTables& t, hipStream_t st);
+// Doubles per mix tile of the Gram launch's partials for memory bound mt.
+int gram_partials_per_tile(int mt);
 // Workgroups of the persistent loop kernel that fit on the device at once.
 int loop_capacity(bool fp64, int mt, bool ext);
 // Workgroups of pass A (pass 0) or pass B (pass 1) of the three-launch path
-// that the device holds at once (0 if the query fails).
-int pass_capacity(bool fp64, int mt, int pass);
+// that the device holds at once (0 if the query fails), for the kernel with
+// (dots) or without the per-pass dots of the new difference column.
+int pass_capacity(bool fp64, int mt, int pass, bool dots);
 hipError_t launch_start_point(const LPDesc& d, bool fp64, hipStream_t st);
 // Zero `bytes` (a multiple of 4) of device memory with a fill kernel on `st`.
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);

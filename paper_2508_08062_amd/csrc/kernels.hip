@@ -333,9 +333,48 @@ __device__ __forceinline__ bool pw_decide(const LPDesc& d, double dx2, double dy
   return true;
 }
 
+// The end of a loop pass, once its branch is known: the mix coefficients, the
+// live slots, the slot of the next difference pair and the counters.
+__device__ void finish_pass(const LPDesc& d, Scalars* sc, SolveWork* w, bool aa, int nmix, int nl, long long k,
+                            long long i_aa, int lane) {
+  const bool L0 = lane == 0;
+  wave_sync();
+  if (lane < nmix) {
+    sc->mixslot[lane] = w->live[lane];
+    sc->gamma[lane] = w->gam[lane];
+  }
+  if (lane < nl) sc->live[lane] = w->live[lane];
+  // slot for the next difference pair: the lowest free one, else the oldest
+  unsigned int used = lane < nl ? 1u << w->live[lane] : 0u;
+#pragma unroll
+  for (int off = 1; off < MAXM; off <<= 1) used |= __shfl_xor(used, off, 64);
+  used = __shfl(used, 0, 64);  // lanes 0..MAXM-1 hold every live slot
+  const unsigned int freem = ~used & ((1u << d.M) - 1u);
+  const int ns = (nl < d.M && freem != 0u) ? __ffs(freem) - 1 : w->live[0];
+  wave_sync();
+  if (L0) {
+    sc->nmix = nmix;
+    if (aa) {
+      sc->branch = BR_AA;
+      sc->i_aa = i_aa + 1;
+    } else {
+      sc->branch = BR_PDHG;
+      sc->j_pdhg += 1;
+    }
+    sc->nlive = nl;
+    sc->newslot = ns;
+    sc->k = k + 1;
+  }
+}
+
+// The decisions of a loop pass (wave 0 of one workgroup), from the summed
+// records f.  With lazy set (three-launch path) the records carry no dots of
+// the new difference column with the stored ones: G and rhs are left stale,
+// and a pass whose safeguard test passes with a non-empty memory ends with
+// branch BR_GRAM, for the Gram launch to finish (gram_decide).
 template <int MT>
 __device__ void final_step(const LPDesc& d, Scalars* sc, const double* f, bool eval, bool kkt, bool init,
-                           SolveWork* w, int lane) {
+                           SolveWork* w, int lane, bool lazy) {
   using DT = Dot<MT>;
   const bool L0 = lane == 0;
   double kktv = 0.0;
@@ -409,7 +448,7 @@ __device__ void final_step(const LPDesc& d, Scalars* sc, const double* f, bool e
       }
     }
   }
-  if (!pw_reset && lane < nl_old) {
+  if (!pw_reset && !lazy && lane < nl_old) {
     const int slot = sc->live[lane];
     if (slot != s) {  // the oldest column is replaced
       const double gv = f[DT::G + lane];
@@ -428,11 +467,14 @@ __device__ void final_step(const LPDesc& d, Scalars* sc, const double* f, bool e
       const int nk = __popcll(bal);
       w->live[nk] = s;
       w->nl = nk + 1;
-      sc->G[s * MAXM + s] = f[DT::DGDG];
-      sc->rhs[s] = f[DT::DGG];
+      if (!lazy) {
+        sc->G[s * MAXM + s] = f[DT::DGDG];
+        sc->rhs[s] = f[DT::DGG];
+      }
       sc->du2[s] = f[DT::DU2];
     }
   }
+  if (lazy && L0) sc->gram_ok = 0;
   wave_sync();
   int nl = w->nl;
 
@@ -450,6 +492,16 @@ __device__ void final_step(const LPDesc& d, Scalars* sc, const double* f, bool e
         sc->thr = thr;
         sc->thr_i = i_aa + 1;
       }
+    }
+    if (gnorm <= thr && lazy && nl > 0) {
+      // the Gram launch forms G and rhs of the live slots and finishes the pass
+      wave_sync();
+      if (lane < nl) sc->live[lane] = w->live[lane];
+      if (L0) {
+        sc->nlive = nl;
+        sc->branch = BR_GRAM;
+      }
+      return;
     }
     if (gnorm <= thr) {
       if (d.variant == V_AA) {
@@ -472,33 +524,39 @@ __device__ void final_step(const LPDesc& d, Scalars* sc, const double* f, bool e
       }
     }
   }
+  finish_pass(d, sc, w, aa, nmix, nl, k, i_aa, lane);
+}
+
+// The pending decisions of a pass left with branch BR_GRAM (wave 0 of the
+// last workgroup of the Gram launch), once G and rhs hold the Gram matrix of
+// the live slots and their dots with g^k: the regularised solve of Alg 2, or
+// the filters and the least-squares solve of Alg 3, then the end of the pass.
+__device__ void gram_decide(const LPDesc& d, Scalars* sc, SolveWork* w, int lane) {
+  const int nl_in = sc->nlive;
+  if (lane < nl_in) w->live[lane] = sc->live[lane];
   wave_sync();
-  if (lane < nmix) {
-    sc->mixslot[lane] = w->live[lane];
-    sc->gamma[lane] = w->gam[lane];
-  }
-  if (lane < nl) sc->live[lane] = w->live[lane];
-  // slot for the next difference pair: the lowest free one, else the oldest
-  unsigned int used = lane < nl ? 1u << w->live[lane] : 0u;
-#pragma unroll
-  for (int off = 1; off < MAXM; off <<= 1) used |= __shfl_xor(used, off, 64);
-  used = __shfl(used, 0, 64);  // lanes 0..MAXM-1 hold every live slot
-  const unsigned int freem = ~used & ((1u << d.M) - 1u);
-  const int ns = (nl < d.M && freem != 0u) ? __ffs(freem) - 1 : w->live[0];
-  wave_sync();
-  if (L0) {
-    sc->nmix = nmix;
-    if (aa) {
-      sc->branch = BR_AA;
-      sc->i_aa = i_aa + 1;
-    } else {
-      sc->branch = BR_PDHG;
-      sc->j_pdhg += 1;
+  int nl = nl_in;
+  bool aa = false;
+  int nmix = 0;
+  if (d.variant == V_AA) {
+    if (solve_gamma(sc, w->live, nl, d.eta, w, lane)) {
+      aa = true;
+      nmix = nl;
     }
-    sc->nlive = nl;
-    sc->newslot = ns;
-    sc->k = k + 1;
+  } else {
+    nl = faa_filter(d, sc, nl, w, lane);  // the survivors become the memory
+    if (nl == 0) {
+      aa = true;  // no history left: u_AA = u^k + beta D-hat g^k
+      if (lane == 0) sc->faa_empty += 1;
+    } else if (solve_gamma(sc, w->live, nl, 0.0, w, lane)) {
+      aa = true;
+      nmix = nl;
+    }
   }
+  finish_pass(d, sc, w, aa, nmix, nl, sc->k, sc->i_aa, lane);
+  // G and rhs of the kept slots are current (rhs against g^k, the residual
+  // before the new iteration index)
+  if (lane == 0) sc->gram_ok = 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -541,6 +599,7 @@ struct RowIn {
 struct PassView {
   long long k;
   int nl, s_new;
+  int ndot;  // stored columns the new difference column is dotted with (nl, or 0 on the three-launch path)
   const int* live;  // live history slots, oldest first (LDS)
   bool eval, init, kkt, hist_on, skip0;
   bool restart_now;  // restarted PDHG: this pass ends an epoch
@@ -555,6 +614,7 @@ __device__ __forceinline__ PassView make_view(const LPDesc& d, long long k, int 
   v.steps = steps;
   v.k = k;
   v.nl = nl;
+  v.ndot = nl;
   v.s_new = s_new;
   v.live = live;
   v.eval = eval;
@@ -680,7 +740,7 @@ struct PassCtx {
       in.dh = dhat[e];
 #pragma unroll
       for (int t = 0; t < MT; ++t)
-        if (t < v.nl && !(t == 0 && v.skip0)) in.hv[t] = ld(dG + (size_t)v.live[t] * N, e, row_coh);
+        if (t < v.ndot && !(t == 0 && v.skip0)) in.hv[t] = ld(dG + (size_t)v.live[t] * N, e, row_coh);
     }
   }
 
@@ -734,7 +794,7 @@ struct PassCtx {
       accv[DT::DU2] += du * du;
 #pragma unroll
       for (int t = 0; t < MT; ++t) {
-        if (t < v.nl && !(t == 0 && v.skip0)) {
+        if (t < v.ndot && !(t == 0 && v.skip0)) {
           const double hv = (double)in.hv[t];
           accv[DT::G + t] += dg * hv;
         }
@@ -1017,7 +1077,9 @@ __device__ __forceinline__ void write_record(double* acc, double (*s_red)[NDOT],
   if (q < C && part == 0) st_agent(&out[q], v);
 }
 
-template <typename T, int MT, int PASS>
+// DOTS: some LP of the launch takes the per-pass dots of the new difference
+// column with the stored ones (gram_mode); without it they are compiled out.
+template <typename T, int MT, int PASS, bool DOTS>
 __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
   using DT = Dot<MT>;
   __shared__ double s_prod[CHUNK_NNZ];
@@ -1035,7 +1097,9 @@ __global__ __launch_bounds__(BLOCK) void k_pass(PassArgs a) {
   if (!eval && sc->status != ST_RUNNING) return;
   if (tid < MAXM) s_live[tid] = sc->live[tid];
   __syncthreads();
-  const PassView v = make_view(*dp, sc->k, sc->nlive, sc->newslot, s_live, eval, &sc->tau);
+  PassView v = make_view(*dp, sc->k, sc->nlive, sc->newslot, s_live, eval, &sc->tau);
+  // an LP that forms its Gram matrix on demand takes no dots with the stored columns
+  if (!DOTS || dp->lazy_gram) v.ndot = 0;
   const PassCtx<T, MT, PASS, false, true> P(dp, v);
 
   if (bw.kind == 1) {
@@ -1131,7 +1195,146 @@ __global__ __launch_bounds__(BLOCK) void k_decide(PassArgs a) {
   unsigned long long* lsc = reinterpret_cast<unsigned long long*>(&s_sc);
   for (int w = tid; w < SW; w += BLOCK) lsc[w] = gsc[w];
   __syncthreads();
-  if (wv == 0) final_step<MT>(*dp, &s_sc, s_fin, eval, v.kkt, v.init, &s_work, lane);
+  if (wv == 0) final_step<MT>(*dp, &s_sc, s_fin, eval, v.kkt, v.init, &s_work, lane, dp->lazy_gram != 0);
+  __syncthreads();
+  for (int w = tid; w < SW; w += BLOCK) gsc[w] = lsc[w];
+}
+
+// ---------------------------------------------------------------------------
+// Gram launch (three-launch path): the history's Gram matrix on demand
+// ---------------------------------------------------------------------------
+//
+// The passes of the three-launch path leave out the dots of each new
+// difference column with the stored ones: those would read the whole history
+// on every pass, while Anderson steps are a small share of the passes.  When
+// a pass's safeguard test passes with a non-empty memory, its decisions are
+// left pending (branch BR_GRAM); this launch then forms, from the stored
+// columns, G = dG_L^T dG_L and r = dG_L^T g^k for the live slots L (Alg 2's
+// Gram matrix and right-hand side) and the LP's last workgroup takes the
+// step's decisions (gram_decide).  With refresh set it only brings G and
+// r = dG_L^T g^{k-1} up to date for LPs whose passes left them stale, before
+// the persistent kernel, which updates them pass by pass, takes the LPs over,
+// or before they are read back.
+// Workgroup b (mix tile b) adds its entries' products per thread in entry
+// order, then within each wave (fixed DPP sequence) and over the four waves in
+// order, and stores the values value-major; the last workgroup of the LP to
+// arrive adds each value's partials in a fixed order (lane l: tiles l, l + 64,
+// ... in order, then the wave's DPP sum).  Values: G[a][b] for a <= b < MT at
+// a MT - a (a - 1) / 2 + (b - a), then r[a] at MT (MT + 1) / 2 + a.
+template <int MT>
+__host__ __device__ constexpr int gram_values() {
+  return MT * (MT + 1) / 2 + MT;
+}
+
+template <typename T, int MT>
+__global__ __launch_bounds__(BLOCK) void k_gram(GramArgs a) {
+  constexpr int NG = MT * (MT + 1) / 2;
+  constexpr int NV = gram_values<MT>();
+  constexpr int NW = BLOCK / 64;
+  __shared__ double s_red[NW][NV];
+  __shared__ int s_live[MAXM];
+  __shared__ int s_flag;
+  __shared__ SolveWork s_work;
+  __shared__ Scalars s_sc;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const MixTile tl = a.tiles[blockIdx.x];
+  const LPDesc& d = a.lps[tl.lp];
+  Scalars* sc = d.sc;
+  if (a.refresh) {
+    if (sc->gram_ok != 0 || sc->nlive == 0) return;
+  } else if (sc->status != ST_RUNNING || sc->branch != BR_GRAM) {
+    return;
+  }
+  const int nl = sc->nlive;
+  const long long k = sc->k;
+  if (tid < MAXM) s_live[tid] = sc->live[tid];
+  __syncthreads();
+  // the residual of the last finished pass: g^k while its decisions are
+  // pending, g^{k-1} once they are taken
+  const T* __restrict__ g = (const T*)d.g[(int)((a.refresh ? k - 1 : k) & 1)];
+  const T* __restrict__ dG = (const T*)d.dG;
+  const size_t N = (size_t)d.N;
+  double acc[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+  for (int e = tl.e0 + tid; e < tl.e1; e += BLOCK) {
+    double h[MT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) h[t] = t < nl ? (double)dG[(size_t)s_live[t] * N + e] : 0.0;
+    const double gv = (double)g[e];
+    int q = 0;
+#pragma unroll
+    for (int i = 0; i < MT; ++i) {
+#pragma unroll
+      for (int j = i; j < MT; ++j) acc[q++] += h[i] * h[j];
+    }
+#pragma unroll
+    for (int i = 0; i < MT; ++i) acc[NG + i] += h[i] * gv;
+  }
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    const double v = wave_sum(acc[q]);
+    if (lane == 0) s_red[wv][q] = v;
+  }
+  __syncthreads();
+  const int j = blockIdx.x - tl.t0;
+  double* part = a.gpart + (size_t)tl.t0 * NV;
+  for (int q = tid; q < NV; q += BLOCK) {
+    double v = s_red[0][q];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) v += s_red[w][q];
+    st_agent(&part[(size_t)q * tl.nt + j], v);
+  }
+  wait_stores();
+  __syncthreads();
+  if (tid == 0) s_flag = arrive(&a.gcnt[tl.lp], (unsigned)tl.nt);
+  __syncthreads();
+  if (!s_flag) return;
+  if (tid == 0) reset_counter(&a.gcnt[tl.lp]);
+  // the LP's scalars in LDS: the decisions run there
+  constexpr int SW = sizeof(Scalars) / 8;
+  unsigned long long* gsc = reinterpret_cast<unsigned long long*>(sc);
+  unsigned long long* lsc = reinterpret_cast<unsigned long long*>(&s_sc);
+  for (int w = tid; w < SW; w += BLOCK) lsc[w] = gsc[w];
+  // each value's partials over the LP's tiles (into s_red[0])
+  for (int q = wv; q < NV; q += NW) {
+    double v = 0.0;
+#pragma unroll 8
+    for (int b = lane; b < tl.nt; b += 64) v += ld_coh(part, q * tl.nt + b);
+    v = wave_sum(v);
+    if (lane == 0) s_red[0][q] = v;
+  }
+  __syncthreads();
+  if (tid < NV) {
+    // value tid -> (row, column) of G, or the row of r
+    int ia = -1, ib = -1;
+    if (tid >= NG) {
+      ia = tid - NG;
+    } else {
+      int q = tid, i = 0;
+      while (q >= MT - i) {
+        q -= MT - i;
+        ++i;
+      }
+      ia = i;
+      ib = i + q;
+    }
+    const double v = s_red[0][tid];
+    if (ib < 0) {
+      if (ia < nl) s_sc.rhs[s_live[ia]] = v;
+    } else if (ia < nl && ib < nl) {
+      s_sc.G[s_live[ia] * MAXM + s_live[ib]] = v;
+      s_sc.G[s_live[ib] * MAXM + s_live[ia]] = v;
+    }
+  }
+  __syncthreads();
+  if (wv == 0) {
+    if (a.refresh) {
+      if (lane == 0) s_sc.gram_ok = 1;
+    } else {
+      gram_decide(d, &s_sc, &s_work, lane);
+    }
+  }
   __syncthreads();
   for (int w = tid; w < SW; w += BLOCK) gsc[w] = lsc[w];
 }
@@ -1554,7 +1757,7 @@ __global__ __launch_bounds__(BLOCK) void k_loop(LoopArgs a) {
         break;
       }
       reduce_records<MT>(a.rec + (size_t)(L.leaf0 + L.nleafA) * NDOT, L.nleaf - L.nleafA, s_part, s_fin, true);
-      if (wv == 0) final_step<MT>(*dp, &s_sc, s_fin, false, v.kkt, false, &s_work, lane);
+      if (wv == 0) final_step<MT>(*dp, &s_sc, s_fin, false, v.kkt, false, &s_work, lane, false);
       __syncthreads();
       if (tid == 0) {
         s_bc.k = s_sc.k;
@@ -1979,14 +2182,28 @@ static hipError_t launch_passes_mt(const LaunchTables& t, hipStream_t st, int mo
   pa.mode = mode;
   pa.blocks = t.blocksA;
   if (ev) (void)hipEventRecord(ev[0], st);
-  if (t.nblocksA > 0) hipLaunchKernelGGL((k_pass<T, MT, 0>), dim3(t.nblocksA), dim3(BLOCK), 0, st, pa);
+  if (t.nblocksA > 0) {
+    if (t.dots)
+      hipLaunchKernelGGL((k_pass<T, MT, 0, true>), dim3(t.nblocksA), dim3(BLOCK), 0, st, pa);
+    else
+      hipLaunchKernelGGL((k_pass<T, MT, 0, false>), dim3(t.nblocksA), dim3(BLOCK), 0, st, pa);
+  }
   if (ev) (void)hipEventRecord(ev[1], st);
   if (t.panels) hipLaunchKernelGGL((k_panel<T>), dim3(PANELS * PANEL_GROUPS), dim3(BLOCK), 0, st, t.lps, mode);
   pa.blocks = t.blocksB;
-  if (t.nblocksB > 0) hipLaunchKernelGGL((k_pass<T, MT, 1>), dim3(t.nblocksB), dim3(BLOCK), 0, st, pa);
+  if (t.nblocksB > 0) {
+    if (t.dots)
+      hipLaunchKernelGGL((k_pass<T, MT, 1, true>), dim3(t.nblocksB), dim3(BLOCK), 0, st, pa);
+    else
+      hipLaunchKernelGGL((k_pass<T, MT, 1, false>), dim3(t.nblocksB), dim3(BLOCK), 0, st, pa);
+  }
   if (t.ndblocks > 0) hipLaunchKernelGGL((k_decide<T, MT>), dim3(t.ndblocks), dim3(BLOCK), 0, st, pa);
   if (ev) (void)hipEventRecord(ev[2], st);
   if (mode == MODE_ITER && t.ntiles > 0) {
+    if (t.gram) {
+      const GramArgs ga{t.lps, t.tiles, t.gpart, t.gcnt, 0};
+      hipLaunchKernelGGL((k_gram<T, MT>), dim3(t.ntiles), dim3(BLOCK), 0, st, ga);
+    }
     MixArgs ma{t.lps, t.tiles, t.pwpart, t.pwcnt};
     hipLaunchKernelGGL((k_mix<T>), dim3(t.ntiles), dim3(BLOCK), 0, st, ma);
   }
@@ -2006,6 +2223,35 @@ hipError_t launch_loop_pass(const LaunchTables& t, hipStream_t st, int mode, hip
   return t.fp64 ? launch_passes_t<double>(t, st, mode, ev) : launch_passes_t<float>(t, st, mode, ev);
 }
 
+// the memory bounds the kernels are instantiated for
+static int mt_bucket(int mt) { return mt <= 4 ? 4 : mt <= 8 ? 8 : mt <= 10 ? 10 : 16; }
+
+int gram_partials_per_tile(int mt) {
+  switch (mt_bucket(mt)) {
+    case 4: return gram_values<4>();
+    case 8: return gram_values<8>();
+    case 10: return gram_values<10>();
+    default: return gram_values<16>();
+  }
+}
+
+template <typename T>
+static hipError_t gram_refresh_t(const LaunchTables& t, hipStream_t st) {
+  if (t.ntiles <= 0 || !t.gram) return hipSuccess;
+  const GramArgs ga{t.lps, t.tiles, t.gpart, t.gcnt, 1};
+  switch (mt_bucket(t.mt)) {
+    case 4: hipLaunchKernelGGL((k_gram<T, 4>), dim3(t.ntiles), dim3(BLOCK), 0, st, ga); break;
+    case 8: hipLaunchKernelGGL((k_gram<T, 8>), dim3(t.ntiles), dim3(BLOCK), 0, st, ga); break;
+    case 10: hipLaunchKernelGGL((k_gram<T, 10>), dim3(t.ntiles), dim3(BLOCK), 0, st, ga); break;
+    default: hipLaunchKernelGGL((k_gram<T, 16>), dim3(t.ntiles), dim3(BLOCK), 0, st, ga); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_refresh(const LaunchTables& t, hipStream_t st) {
+  return t.fp64 ? gram_refresh_t<double>(t, st) : gram_refresh_t<float>(t, st);
+}
+
 template <typename T, bool EXT>
 static const void* loop_kernel_mt(int mt) {
   if (mt <= 4) return reinterpret_cast<const void*>(&k_loop<T, 4, EXT>);
@@ -2019,20 +2265,25 @@ static const void* loop_kernel_for(bool fp64, int mt, bool ext) {
   return ext ? loop_kernel_mt<float, true>(mt) : loop_kernel_mt<float, false>(mt);
 }
 
-template <typename T, int PASS>
+template <typename T, int PASS, bool DOTS>
 static const void* pass_kernel_mt(int mt) {
-  if (mt <= 4) return reinterpret_cast<const void*>(&k_pass<T, 4, PASS>);
-  if (mt <= 8) return reinterpret_cast<const void*>(&k_pass<T, 8, PASS>);
-  if (mt <= 10) return reinterpret_cast<const void*>(&k_pass<T, 10, PASS>);
-  return reinterpret_cast<const void*>(&k_pass<T, 16, PASS>);
+  if (mt <= 4) return reinterpret_cast<const void*>(&k_pass<T, 4, PASS, DOTS>);
+  if (mt <= 8) return reinterpret_cast<const void*>(&k_pass<T, 8, PASS, DOTS>);
+  if (mt <= 10) return reinterpret_cast<const void*>(&k_pass<T, 10, PASS, DOTS>);
+  return reinterpret_cast<const void*>(&k_pass<T, 16, PASS, DOTS>);
 }
 
-int pass_capacity(bool fp64, int mt, int pass) {
+template <typename T, bool DOTS>
+static const void* pass_kernel_for(int mt, int pass) {
+  return pass == 0 ? pass_kernel_mt<T, 0, DOTS>(mt) : pass_kernel_mt<T, 1, DOTS>(mt);
+}
+
+int pass_capacity(bool fp64, int mt, int pass, bool dots) {
   int dev = 0, cus = 0, nb = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  const void* k = fp64 ? (pass == 0 ? pass_kernel_mt<double, 0>(mt) : pass_kernel_mt<double, 1>(mt))
-                       : (pass == 0 ? pass_kernel_mt<float, 0>(mt) : pass_kernel_mt<float, 1>(mt));
+  const void* k = fp64 ? (dots ? pass_kernel_for<double, true>(mt, pass) : pass_kernel_for<double, false>(mt, pass))
+                       : (dots ? pass_kernel_for<float, true>(mt, pass) : pass_kernel_for<float, false>(mt, pass));
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, BLOCK, 0) != hipSuccess) return 0;
   return nb * cus;
 }
@@ -2108,7 +2359,9 @@ hipError_t launch_loop(const LaunchTables& t, hipStream_t st, long long passes, 
   la.max_passes = passes;
   la.timeout_ticks = t.timeout_ticks;
   la.tag0 = tag0;
-  hipError_t e = launch_zero(t.sync, sizeof(LoopSync) * (size_t)t.nlps, st);
+  hipError_t e = launch_gram_refresh(t, st);
+  if (e != hipSuccess) return e;
+  e = launch_zero(t.sync, sizeof(LoopSync) * (size_t)t.nlps, st);
   if (e != hipSuccess) return e;
   void* args[] = {&la};
   return hipLaunchCooperativeKernel(loop_kernel_for(t.fp64, t.mt, t.ext), dim3(t.nwgs), dim3(BLOCK), args, 0, st);

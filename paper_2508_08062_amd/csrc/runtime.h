@@ -61,7 +61,8 @@ struct LaunchSet {
   std::vector<Problem*> members;
   LaunchTables t;
   DevBuf d_lps, d_llp, d_chunks, d_blocksA, d_blocksB, d_dblocks, d_splits, d_rec, d_dpart, d_dcnt, d_splitpart,
-      d_splitcnt, d_tiles, d_status, d_wgs, d_looplps, d_sync, d_bc, d_err, d_pwpart, d_pwcnt, d_pwrec;
+      d_splitcnt, d_tiles, d_status, d_wgs, d_looplps, d_sync, d_bc, d_err, d_pwpart, d_pwcnt, d_pwrec, d_gpart,
+      d_gcnt;
   int* h_status = nullptr;  // pinned, 2 x MAX_STATUS
   int64_t last_epochs = 0;
   std::vector<double> finish_s;  // per member: seconds into run_to_completion when seen stopped
@@ -137,6 +138,7 @@ struct Problem {
               const double* val, const double* c, const double* q, const double* l, const double* u,
               const uint8_t* row_type, const aapdhg_options* opt);
   void fill_desc();
+  void set_gram_mode();
   double power_norm();
   void reset_host_state();
   void enqueue_reset(hipStream_t st);

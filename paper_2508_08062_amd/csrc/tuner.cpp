@@ -9,7 +9,7 @@
 // loop passes of the LP from its start point, after a short warm-up, with
 // tolerance 0 so that no pass is skipped) and keeps the fastest.  Results go
 // to a cache file, keyed by the device and the LP's shape class (precision,
-// method, memory, the loop kernel asked for, the binary logarithms of m, n,
+// method, memory, the loop kernel asked for, gram_mode, the binary logarithms of m, n,
 // the entry count and the longest row and column), so LPs of the same class
 // take the cached choice
 // without timing.  The choice is part of the LP, so its reduction order, and
@@ -92,9 +92,9 @@ std::string Problem::tune_key() const {
   std::string arch(prop.gcnArchName);
   arch = arch.substr(0, arch.find(':'));
   char buf[512];
-  std::snprintf(buf, sizeof buf, "%s:%d:%s:v%d:M%d:e%d:k%d:m%d:n%d:z%d:r%d:c%d", arch.c_str(),
+  std::snprintf(buf, sizeof buf, "%s:%d:%s:v%d:M%d:e%d:k%d:g%d:m%d:n%d:z%d:r%d:c%d", arch.c_str(),
                 prop.multiProcessorCount, fp64 ? "f64" : "f32", opt.variant, opt.memory, ext ? 1 : 0,
-                opt.loop_kernel, lg(m), lg(n), lg(nnz), lg(maxr), lg(maxc));
+                opt.loop_kernel, opt.gram_mode, lg(m), lg(n), lg(nnz), lg(maxr), lg(maxc));
   for (char* p = buf; *p; ++p)
     if (*p == ' ') *p = '_';
   return buf;

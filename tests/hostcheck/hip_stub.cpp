@@ -96,8 +96,10 @@ void roctxMarkA(const char*) {}
 namespace aapdhg {
 hipError_t launch_loop_pass(const LaunchTables&, hipStream_t, int, hipEvent_t*) { return hipSuccess; }
 hipError_t launch_loop(const LaunchTables&, hipStream_t, long long, unsigned int) { return hipSuccess; }
+hipError_t launch_gram_refresh(const LaunchTables&, hipStream_t) { return hipSuccess; }
+int gram_partials_per_tile(int mt) { return mt * (mt + 1) / 2 + mt; }
 int loop_capacity(bool, int, bool) { return 512; }
-int pass_capacity(bool, int, int pass) { return pass == 0 ? 1024 : 768; }
+int pass_capacity(bool, int, int pass, bool) { return pass == 0 ? 1024 : 768; }
 hipError_t launch_start_point(const LPDesc&, bool, hipStream_t) { return hipSuccess; }
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t) { std::memset(p, 0, bytes); return hipSuccess; }
 hipError_t static_scratch(void** out) {

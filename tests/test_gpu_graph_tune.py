@@ -66,7 +66,7 @@ def test_autotuned_lps_equal_alone_and_in_a_graph_batch(tmp_path, monkeypatch):
     assert 1 <= len(lines) <= len(lps)  # LPs of one shape class share an entry
     for ln in lines:
         key, w, cpb, lk, ms = ln.split()
-        assert key.count(":") == 11 and int(w) in (2, 4, 8) and int(cpb) in (0, 2) and int(lk) == 1
+        assert key.count(":") == 12 and int(w) in (2, 4, 8) and int(cpb) in (0, 2) and int(lk) == 1
     # members created again take the cached choices (no new entries) and, in a
     # batch replayed from a graph, give their solo results bit for bit
     members = [P.Solver(lp, autotune=1, graph=1, loop_kernel=1, **OPTS) for lp in lps]

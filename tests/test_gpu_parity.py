@@ -37,9 +37,10 @@ def _trajectories(lp, steps, precision, variant=1, memory=5, **kw):
     nrm = oracle.power_norm(Po)
     tau = sigma = 0.9 / nrm
     loop_kernel = kw.pop("loop_kernel", 0)
+    gram_mode = kw.pop("gram_mode", 0)
     common = dict(variant=variant, memory=memory, tau=tau, sigma=sigma, kkt_every=kw.pop("kkt_every", 1),
                   tol=kw.pop("tol", 0.0), max_iter=10 ** 6, **kw)
-    g = _gpu(lp, precision=precision, loop_kernel=loop_kernel, **common)
+    g = _gpu(lp, precision=precision, loop_kernel=loop_kernel, gram_mode=gram_mode, **common)
     o = _oracle(lp, **common)
     o.start()
     g.iterate(1)
@@ -76,22 +77,29 @@ def test_toy_lp_hand_trace_on_gpu():
     np.testing.assert_allclose(np.r_[r["x"], r["y"]], gld["optimum"], atol=1e-9)
 
 
-@pytest.mark.parametrize("loop_kernel", [0, 1])
+# (loop_kernel, gram_mode): the persistent kernel; three launches per pass with
+# the Gram matrix formed on demand (the default for an LP held to three launches);
+# three launches with the per-pass dots
+PATHS = [(0, 0), (1, 0), (1, 1)]
+
+
+@pytest.mark.parametrize("loop_kernel,gram_mode", PATHS)
 @pytest.mark.parametrize("seed", [0, 1])
-def test_tiny_fp64_trajectory_50(seed, loop_kernel):
+def test_tiny_fp64_trajectory_50(seed, loop_kernel, gram_mode):
     lp = lpgen.tiny_lp(seed)
-    ug, uo, ctr, _, _ = _trajectories(lp, 50, precision=1, memory=5, loop_kernel=loop_kernel)
+    ug, uo, ctr, _, _ = _trajectories(lp, 50, precision=1, memory=5, loop_kernel=loop_kernel, gram_mode=gram_mode)
     errs = [err64(a, b) for a, b in zip(ug, uo)]
     assert max(errs) < 1e-9, errs
     for (gi, oi) in ctr:
         assert gi == oi
 
 
-@pytest.mark.parametrize("loop_kernel", [0, 1])
+@pytest.mark.parametrize("loop_kernel,gram_mode", PATHS)
 @pytest.mark.parametrize("variant", [0, 1, 2])
-def test_mip_like_fp32_trajectory_50(variant, loop_kernel):
+def test_mip_like_fp32_trajectory_50(variant, loop_kernel, gram_mode):
     lp = lpgen.mip_like_lp(11, m=2000, n=5000, nnz=25000)
-    ug, uo, ctr, _, _ = _trajectories(lp, 50, precision=0, variant=variant, memory=10, loop_kernel=loop_kernel)
+    ug, uo, ctr, _, _ = _trajectories(lp, 50, precision=0, variant=variant, memory=10, loop_kernel=loop_kernel,
+                                      gram_mode=gram_mode)
     errs = [err32(a, b) for a, b in zip(ug, uo)]
     assert max(errs) < 1e-5, (max(errs), int(np.argmax(errs)))
     assert ctr[-1][0] == ctr[-1][1]
@@ -332,6 +340,53 @@ def test_loop_kernels_agree_over_many_passes(precision):
     assert a["k"] == b["k"] == 151
     assert (a["i"], a["j"]) == (b["i"], b["j"])
     assert norm_rel(a["u"], b["u"]) < (1e-4 if precision == 0 else 1e-9)
+
+
+@pytest.mark.parametrize("gram_mode", [0, 2])
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("variant", [1, 2])
+def test_three_launch_passes_then_persistent_passes(precision, variant, gram_mode):
+    """With gram_mode 2 the three-launch passes leave the history's Gram
+    matrix stale (it is formed only when a step needs it); before the
+    persistent kernel, which updates it pass by pass, takes the LP over, a
+    refresh forms it.  With gram_mode 0 this LP (which the persistent kernel
+    can take alone) keeps the per-pass dots in three launches too.  Either
+    way the LP advanced first by three-launch passes (in a batch with a member
+    held to them) and then by persistent launches takes the same steps as the
+    LP advanced by persistent launches throughout, and reaches the same
+    iterate up to summation order; its Gram matrix then equals the dots of its
+    history."""
+    lp = lpgen.mip_like_lp(13, m=3000, n=7000, nnz=40000)
+    other = lpgen.mip_like_lp(14, m=1000, n=2500, nnz=10000)
+    kw = dict(precision=precision, variant=variant, memory=10, kkt_every=16, tol=0.0, max_iter=10 ** 6)
+    ref = _gpu(lp, loop_kernel=0, **kw)
+    ref.iterate(1)
+    ref.iterate(150)
+    a = ref.get_state()
+    ref.close()
+    g = _gpu(lp, loop_kernel=0, gram_mode=gram_mode, **kw)
+    h = _gpu(other, loop_kernel=1, **kw)
+    b = P.Batch([g, h])
+    assert b.iterate_timed(80)["kernel"] == "three"  # k = 81 (the first pass is the init step)
+    b.close()
+    assert g.iterate_timed(70)["kernel"] == "persistent"
+    st = g.get_state()
+    h.close()
+    assert a["k"] == st["k"] == 151
+    assert (a["i"], a["j"]) == (st["i"], st["j"]) and a["i"] > 5
+    assert norm_rel(a["u"], st["u"]) < (1e-4 if precision == 0 else 1e-9)
+    live, G, gp = st["live"], st["G"], st["g_prev"]
+    big = max(np.sqrt(G[y, y]) for y in live)
+    for x in live:
+        for y in live:
+            want = float(np.dot(st["dG"][x], st["dG"][y]))
+            assert abs(G[x, y] - want) <= 1e-9 * np.sqrt(G[x, x] * G[y, y]) + 1e-300
+        # rhs = <dG[x], g^{k-1}>, updated pass by pass since the refresh (float32: the
+        # identity adds the dots of the rounded differences)
+        upd = 4 * 10 * 2.0 ** -24 * np.sqrt(G[x, x]) * big if precision == 0 else 0.0
+        want = float(np.dot(st["dG"][x], gp))
+        assert abs(st["rhs"][x] - want) <= 1e-9 * np.sqrt(G[x, x] * float(gp @ gp)) + upd + 1e-300
+    g.close()
 
 
 @pytest.mark.parametrize("tol", [1e-4, 1e-6])
