@@ -1151,8 +1151,16 @@ __global__ __launch_bounds__(BLOCK) void k_decide(PassArgs a) {
   const LPDesc* dp = a.lps + db.lp;
   Scalars* sc = dp->sc;
   const bool eval = a.mode == MODE_EVAL;
-  if (!eval && sc->status != ST_RUNNING) return;
   const LaunchLP L = a.llp[db.lp];
+  // the LP's scalars (the decisions run on an LDS copy), loaded together with
+  // the records; nothing in this launch writes them before its last workgroup
+  constexpr int SW = sizeof(Scalars) / 8;
+  constexpr int SPT = (SW + BLOCK - 1) / BLOCK;
+  unsigned long long* gsc = reinterpret_cast<unsigned long long*>(sc);
+  unsigned long long* lsc = reinterpret_cast<unsigned long long*>(&s_sc);
+  unsigned long long sreg[SPT];
+#pragma unroll
+  for (int i = 0; i < SPT; ++i) sreg[i] = tid + i * BLOCK < SW ? gsc[tid + i * BLOCK] : 0ull;
   const int t = tid / C, q = tid - (tid / C) * C;
   double s = 0.0;
   if (t < PT) {
@@ -1162,8 +1170,12 @@ __global__ __launch_bounds__(BLOCK) void k_decide(PassArgs a) {
       s += a.rec[(size_t)rix * NDOT + q];
     }
   }
+#pragma unroll
+  for (int i = 0; i < SPT; ++i)
+    if (tid + i * BLOCK < SW) lsc[tid + i * BLOCK] = sreg[i];
   s_part[tid] = s;
   __syncthreads();
+  if (!eval && s_sc.status != ST_RUNNING) return;
   double part = 0.0;
   if (tid < C) {
     for (int tt = 0; tt < PT; ++tt) part += s_part[tt * C + tid];
@@ -1186,15 +1198,9 @@ __global__ __launch_bounds__(BLOCK) void k_decide(PassArgs a) {
   } else if (tid < C) {
     s_fin[tid] = 0.0 + part;  // the ordered sum of the one partial
   }
-  if (tid < MAXM) s_live[tid] = sc->live[tid];
+  if (tid < MAXM) s_live[tid] = s_sc.live[tid];
   __syncthreads();
-  const PassView v = make_view(*dp, sc->k, sc->nlive, sc->newslot, s_live, eval, &sc->tau);
-  // the decisions run on an LDS copy of the LP's scalars
-  constexpr int SW = sizeof(Scalars) / 8;
-  unsigned long long* gsc = reinterpret_cast<unsigned long long*>(sc);
-  unsigned long long* lsc = reinterpret_cast<unsigned long long*>(&s_sc);
-  for (int w = tid; w < SW; w += BLOCK) lsc[w] = gsc[w];
-  __syncthreads();
+  const PassView v = make_view(*dp, s_sc.k, s_sc.nlive, s_sc.newslot, s_live, eval, &s_sc.tau);
   if (wv == 0) final_step<MT>(*dp, &s_sc, s_fin, eval, v.kkt, v.init, &s_work, lane, dp->lazy_gram != 0);
   __syncthreads();
   for (int w = tid; w < SW; w += BLOCK) gsc[w] = lsc[w];
@@ -1215,29 +1221,55 @@ __global__ __launch_bounds__(BLOCK) void k_decide(PassArgs a) {
 // r = dG_L^T g^{k-1} up to date for LPs whose passes left them stale, before
 // the persistent kernel, which updates them pass by pass, takes the LPs over,
 // or before they are read back.
-// Workgroup b (mix tile b) adds its entries' products per thread in entry
-// order, then within each wave (fixed DPP sequence) and over the four waves in
-// order, and stores the values value-major; the last workgroup of the LP to
-// arrive adds each value's partials in a fixed order (lane l: tiles l, l + 64,
-// ... in order, then the wave's DPP sum).  Values: G[a][b] for a <= b < MT at
-// a MT - a (a - 1) / 2 + (b - a), then r[a] at MT (MT + 1) / 2 + a.
+// Workgroup b takes mix tile b (one tile each: on the passes that need nothing
+// every workgroup reads the LP's scalars once and exits, all at the same
+// time).  A tile's entries are added per thread in entry order, then within
+// each wave (fixed DPP sequence) and over the four waves in order; the tile's
+// values are stored value-major.  The workgroup that finishes the LP's last
+// tile adds each value's partials in a fixed order (per LP): with at most 64
+// tiles, one wave per value (lane l holds tile l) and its DPP sum; with more,
+// thread t adds tiles t, t + BLOCK, ... in order, then the same block
+// reduction.  Values: G[a][b] for a <= b < MT at a MT - a (a - 1) / 2 + (b - a),
+// then r[a] at MT (MT + 1) / 2 + a.
 template <int MT>
 __host__ __device__ constexpr int gram_values() {
   return MT * (MT + 1) / 2 + MT;
+}
+
+// Block-wide sums of the NV values of acc[] (fixed order: DPP within each
+// wave, then the waves in order) into out[0..NV).
+template <int NV>
+__device__ __forceinline__ void block_sums(const double* acc, double (*s_red)[NV], double* out) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  constexpr int NW = BLOCK / 64;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    const double v = wave_sum(acc[q]);
+    if (lane == 0) s_red[wv][q] = v;
+  }
+  __syncthreads();
+  for (int q = tid; q < NV; q += BLOCK) {
+    double v = s_red[0][q];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) v += s_red[w][q];
+    out[q] = v;
+  }
+  __syncthreads();
 }
 
 template <typename T, int MT>
 __global__ __launch_bounds__(BLOCK) void k_gram(GramArgs a) {
   constexpr int NG = MT * (MT + 1) / 2;
   constexpr int NV = gram_values<MT>();
-  constexpr int NW = BLOCK / 64;
-  __shared__ double s_red[NW][NV];
+  __shared__ double s_red[BLOCK / 64][NV];
+  __shared__ double s_val[NV];
   __shared__ int s_live[MAXM];
   __shared__ int s_flag;
   __shared__ SolveWork s_work;
   __shared__ Scalars s_sc;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const MixTile tl = a.tiles[blockIdx.x];
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int tix = blockIdx.x;
+  const MixTile tl = a.tiles[tix];
   const LPDesc& d = a.lps[tl.lp];
   Scalars* sc = d.sc;
   if (a.refresh) {
@@ -1271,40 +1303,37 @@ __global__ __launch_bounds__(BLOCK) void k_gram(GramArgs a) {
 #pragma unroll
     for (int i = 0; i < MT; ++i) acc[NG + i] += h[i] * gv;
   }
-#pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    const double v = wave_sum(acc[q]);
-    if (lane == 0) s_red[wv][q] = v;
-  }
-  __syncthreads();
-  const int j = blockIdx.x - tl.t0;
+  block_sums<NV>(acc, s_red, s_val);
+  const int j = tix - tl.t0;
   double* part = a.gpart + (size_t)tl.t0 * NV;
-  for (int q = tid; q < NV; q += BLOCK) {
-    double v = s_red[0][q];
-#pragma unroll
-    for (int w = 1; w < NW; ++w) v += s_red[w][q];
-    st_agent(&part[(size_t)q * tl.nt + j], v);
-  }
+  for (int q = tid; q < NV; q += BLOCK) st_agent(&part[(size_t)q * tl.nt + j], s_val[q]);
   wait_stores();
   __syncthreads();
   if (tid == 0) s_flag = arrive(&a.gcnt[tl.lp], (unsigned)tl.nt);
   __syncthreads();
   if (!s_flag) return;
+  // ---- the LP's last tile: the sums over its tiles, then the decisions ----
   if (tid == 0) reset_counter(&a.gcnt[tl.lp]);
-  // the LP's scalars in LDS: the decisions run there
   constexpr int SW = sizeof(Scalars) / 8;
   unsigned long long* gsc = reinterpret_cast<unsigned long long*>(sc);
   unsigned long long* lsc = reinterpret_cast<unsigned long long*>(&s_sc);
   for (int w = tid; w < SW; w += BLOCK) lsc[w] = gsc[w];
-  // each value's partials over the LP's tiles (into s_red[0])
-  for (int q = wv; q < NV; q += NW) {
-    double v = 0.0;
-#pragma unroll 8
-    for (int b = lane; b < tl.nt; b += 64) v += ld_coh(part, q * tl.nt + b);
-    v = wave_sum(v);
-    if (lane == 0) s_red[0][q] = v;
+  if (tl.nt <= 64) {
+    // few tiles: wave w adds values w, w + 4, ... (lane l holds tile l), DPP sum
+    for (int q = wv; q < NV; q += BLOCK / 64) {
+      const double v = wave_sum(lane < tl.nt ? ld_coh(part, q * tl.nt + lane) : 0.0);
+      if (lane == 0) s_val[q] = v;
+    }
+    __syncthreads();
+  } else {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+    for (int b = tid; b < tl.nt; b += BLOCK) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) acc[q] += ld_coh(part, q * tl.nt + b);
+    }
+    block_sums<NV>(acc, s_red, s_val);
   }
-  __syncthreads();
   if (tid < NV) {
     // value tid -> (row, column) of G, or the row of r
     int ia = -1, ib = -1;
@@ -1319,7 +1348,7 @@ __global__ __launch_bounds__(BLOCK) void k_gram(GramArgs a) {
       ia = i;
       ib = i + q;
     }
-    const double v = s_red[0][tid];
+    const double v = s_val[tid];
     if (ib < 0) {
       if (ia < nl) s_sc.rhs[s_live[ia]] = v;
     } else if (ia < nl && ib < nl) {
@@ -2239,11 +2268,12 @@ template <typename T>
 static hipError_t gram_refresh_t(const LaunchTables& t, hipStream_t st) {
   if (t.ntiles <= 0 || !t.gram) return hipSuccess;
   const GramArgs ga{t.lps, t.tiles, t.gpart, t.gcnt, 1};
+  const dim3 grid(t.ntiles);
   switch (mt_bucket(t.mt)) {
-    case 4: hipLaunchKernelGGL((k_gram<T, 4>), dim3(t.ntiles), dim3(BLOCK), 0, st, ga); break;
-    case 8: hipLaunchKernelGGL((k_gram<T, 8>), dim3(t.ntiles), dim3(BLOCK), 0, st, ga); break;
-    case 10: hipLaunchKernelGGL((k_gram<T, 10>), dim3(t.ntiles), dim3(BLOCK), 0, st, ga); break;
-    default: hipLaunchKernelGGL((k_gram<T, 16>), dim3(t.ntiles), dim3(BLOCK), 0, st, ga); break;
+    case 4: hipLaunchKernelGGL((k_gram<T, 4>), grid, dim3(BLOCK), 0, st, ga); break;
+    case 8: hipLaunchKernelGGL((k_gram<T, 8>), grid, dim3(BLOCK), 0, st, ga); break;
+    case 10: hipLaunchKernelGGL((k_gram<T, 10>), grid, dim3(BLOCK), 0, st, ga); break;
+    default: hipLaunchKernelGGL((k_gram<T, 16>), grid, dim3(BLOCK), 0, st, ga); break;
   }
   return hipGetLastError();
 }
