@@ -163,6 +163,13 @@ int main() {
   setenv("AAPDHG_TUNE_CACHE", "hostcheck_tune.txt", 1);
   exercise(rag, o4);
   exercise(rag, o4);  // the second takes the cached choice
+  // the Gram matrix on demand for every three-launch set, and on every pass
+  aapdhg_options o5 = o;
+  o5.gram_mode = 2;
+  exercise(rag, o5);
+  o5.gram_mode = 1;
+  o5.loop_kernel = 1;
+  exercise(rag, o5);
   // transposed shape: columns longer than a chunk in the CSC pass
   std::vector<int> tall(4000, 3);
   LP tl = make_lp(40, tall, 2);
@@ -201,6 +208,9 @@ int main() {
     CHECK(create(bad, &ob, &h) == AAPDHG_E_ARG);
     ob = o;
     ob.length_floor = 2;
+    CHECK(create(bad, &ob, &h) == AAPDHG_E_ARG);
+    ob.length_floor = 0;
+    ob.gram_mode = 3;
     CHECK(create(bad, &ob, &h) == AAPDHG_E_ARG);
     CHECK(aapdhg_create(0, 5, 0, bad.rowptr.data(), nullptr, nullptr, bad.c.data(), bad.q.data(), bad.l.data(),
                         bad.u.data(), bad.rt.data(), &o, &h) == AAPDHG_E_ARG);
