@@ -1286,14 +1286,24 @@ __global__ __launch_bounds__(BLOCK) void k_gram(GramArgs a) {
   const T* __restrict__ g = (const T*)d.g[(int)((a.refresh ? k - 1 : k) & 1)];
   const T* __restrict__ dG = (const T*)d.dG;
   const size_t N = (size_t)d.N;
+  // offsets of the live columns (uniform, from the scalars).  Every column
+  // load is made and the unused ones masked (a load under a condition of its
+  // own would be waited for before the next); those read the first live
+  // column again.
+  size_t col[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t) col[t] = (size_t)sc->live[t < nl ? t : 0] * N;
   double acc[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) acc[q] = 0.0;
   for (int e = tl.e0 + tid; e < tl.e1; e += BLOCK) {
+    T hv[MT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) hv[t] = dG[col[t] + e];
+    const double gv = (double)g[e];
     double h[MT];
 #pragma unroll
-    for (int t = 0; t < MT; ++t) h[t] = t < nl ? (double)dG[(size_t)s_live[t] * N + e] : 0.0;
-    const double gv = (double)g[e];
+    for (int t = 0; t < MT; ++t) h[t] = t < nl ? (double)hv[t] : 0.0;
     int q = 0;
 #pragma unroll
     for (int i = 0; i < MT; ++i) {
