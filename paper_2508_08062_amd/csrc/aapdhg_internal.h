@@ -159,13 +159,19 @@ struct Chunk {
 };
 
 // One workgroup of the decision launch (three-launch path): positions
-// [r0, r1) of its LP's record list (the LP's primal-pass records, then its
-// dual-pass records), summed into partial `slot`.
+// [r0, r1) of its LP's record list (the LP's primal-pass records [leafA,
+// leafA + nA), then its dual-pass records from leafB), summed into partial
+// `slot`; the LP's partials are [blk0, blk0 + nblk).  The LP's scalars and
+// record ranges are copied here so that the launch's first loads depend on
+// this entry alone.
 struct DecideBlock {
+  Scalars* sc;
   int lp;
   int r0, r1;
   int slot;
-  int pad[4];
+  int leafA, nA, leafB;
+  int blk0, nblk;
+  int pad;
 };
 
 struct SplitRow {
@@ -197,10 +203,11 @@ struct LaunchLP {
 };
 
 struct MixTile {
+  Scalars* sc;  // the LP's scalars (the launches' first check reads them)
   int lp;
   int e0, e1;
   int t0, nt;  // the LP's tiles: [t0, t0 + nt)
-  int pad[3];
+  int pad;
 };
 
 // Everything a pass kernel needs; passed by value.

@@ -1046,6 +1046,7 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
     }
     const int t0 = (int)tl.size();
     for (auto x : p->tiles) {
+      x.sc = p->desc.sc;
       x.lp = i;
       x.t0 = t0;
       x.nt = (int)p->tiles.size();
@@ -1072,10 +1073,16 @@ void LaunchSet::build(const std::vector<Problem*>& lps) {
     L.nblk = std::max(1, (total + DECIDE_RECORDS - 1) / DECIDE_RECORDS);
     for (int g = 0; g < L.nblk; ++g) {
       DecideBlock d{};
+      d.sc = lps[i]->desc.sc;
       d.lp = i;
       d.r0 = g * DECIDE_RECORDS;
       d.r1 = std::min(total, (g + 1) * DECIDE_RECORDS);
       d.slot = L.blk0 + g;
+      d.leafA = L.leafA;
+      d.nA = L.nA;
+      d.leafB = L.leafB;
+      d.blk0 = L.blk0;
+      d.nblk = L.nblk;
       dblocks.push_back(d);
     }
   }

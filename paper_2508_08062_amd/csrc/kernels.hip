@@ -1149,9 +1149,8 @@ __global__ __launch_bounds__(BLOCK) void k_decide(PassArgs a) {
   const int lane = tid & 63, wv = tid >> 6;
   const DecideBlock db = a.dblocks[blockIdx.x];
   const LPDesc* dp = a.lps + db.lp;
-  Scalars* sc = dp->sc;
+  Scalars* sc = db.sc;
   const bool eval = a.mode == MODE_EVAL;
-  const LaunchLP L = a.llp[db.lp];
   // the LP's scalars (the decisions run on an LDS copy), loaded together with
   // the records; nothing in this launch writes them before its last workgroup
   constexpr int SW = sizeof(Scalars) / 8;
@@ -1166,7 +1165,7 @@ __global__ __launch_bounds__(BLOCK) void k_decide(PassArgs a) {
   if (t < PT) {
 #pragma unroll 4
     for (int p = db.r0 + t; p < db.r1; p += PT) {
-      const int rix = p < L.nA ? L.leafA + p : L.leafB + (p - L.nA);
+      const int rix = p < db.nA ? db.leafA + p : db.leafB + (p - db.nA);
       s += a.rec[(size_t)rix * NDOT + q];
     }
   }
@@ -1180,19 +1179,19 @@ __global__ __launch_bounds__(BLOCK) void k_decide(PassArgs a) {
   if (tid < C) {
     for (int tt = 0; tt < PT; ++tt) part += s_part[tt * C + tid];
   }
-  if (L.nblk > 1) {
+  if (db.nblk > 1) {
     if (tid < C) st_agent(&a.dpart[(size_t)db.slot * NDOT + tid], part);
     __syncthreads();
     if (wv == 0) {
       wait_stores();
-      if (tid == 0) s_flag = arrive(&a.dcnt[db.lp], (unsigned)L.nblk);
+      if (tid == 0) s_flag = arrive(&a.dcnt[db.lp], (unsigned)db.nblk);
     }
     __syncthreads();
     if (!s_flag) return;
     if (tid == 0) reset_counter(&a.dcnt[db.lp]);
     if (tid < C) {
       double sum = 0.0;
-      for (int g = 0; g < L.nblk; ++g) sum += ld_coh(a.dpart, (L.blk0 + g) * NDOT + tid);
+      for (int g = 0; g < db.nblk; ++g) sum += ld_coh(a.dpart, (db.blk0 + g) * NDOT + tid);
       s_fin[tid] = sum;
     }
   } else if (tid < C) {
@@ -1271,7 +1270,7 @@ __global__ __launch_bounds__(BLOCK) void k_gram(GramArgs a) {
   const int tix = blockIdx.x;
   const MixTile tl = a.tiles[tix];
   const LPDesc& d = a.lps[tl.lp];
-  Scalars* sc = d.sc;
+  Scalars* sc = tl.sc;
   if (a.refresh) {
     if (sc->gram_ok != 0 || sc->nlive == 0) return;
   } else if (sc->status != ST_RUNNING || sc->branch != BR_GRAM) {
@@ -2028,7 +2027,7 @@ __global__ __launch_bounds__(BLOCK) void k_mix(MixArgs a) {
   __shared__ int s_last;
   const MixTile tl = a.tiles[blockIdx.x];
   const LPDesc& d = a.lps[tl.lp];
-  Scalars* sc = d.sc;
+  Scalars* sc = tl.sc;
   if (sc->status != ST_RUNNING) return;
   const bool mix = sc->branch == BR_AA;
   const bool check = d.pw_period > 0 && sc->k % d.pw_period == 0;
