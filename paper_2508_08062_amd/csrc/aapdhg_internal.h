@@ -18,7 +18,7 @@ constexpr int SPLIT_NNZ = 8192;   // nnz per part of a split (very long) row
 constexpr int DECIDE_RECORDS = 256;  // records added by one workgroup of the decision launch
 constexpr int MIX_TILE = 2048;    // elements per block of the mix pass
 constexpr int NDOT = 2 * MAXM + 16;  // stride of one partial-sum record (doubles)
-constexpr int PANELS = 8;         // column panels of the dual product (one per XCD)
+constexpr int PANELS = 4;         // column panels of the dual product (each taken by two XCDs)
 constexpr int PANEL_ROWS = 1024;  // rows of one panel chunk (four per thread)
 
 // Partial-sum record: MT = memory bound of the kernel instantiation.

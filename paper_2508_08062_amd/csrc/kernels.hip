@@ -1905,9 +1905,10 @@ __global__ __launch_bounds__(BLOCK) void k_loop(LoopArgs a) {
 // column panels of the dual product (large LPs): row sums per panel
 // ---------------------------------------------------------------------------
 
-// Workgroup b works on panel b % PANELS: workgroups are dealt to the XCDs in
-// turn, so each XCD gathers from one 1/PANELS slice of x_bar, which stays in
-// its L2.  A workgroup takes every (gridDim / PANELS)-th chunk of its panel:
+// Workgroup b works on panel b % PANELS: workgroups are dealt to the eight
+// XCDs in turn, so each XCD gathers from one 1/PANELS slice of x_bar (XCDs p
+// and p + 4 share panel p), which stays in its L2.  A workgroup takes every
+// (gridDim / PANELS)-th chunk of its panel:
 // stages the chunk's products in LDS (eight gathers in flight per thread),
 // then each thread adds the entries of up to four rows in order.  Writes
 // part[0][p][r] (x_bar, or x^k when evaluating) and, on KKT passes,
@@ -2201,7 +2202,7 @@ __global__ void k_convert(const S* src, D* dst, size_t len) {
 // host-side launchers
 // ---------------------------------------------------------------------------
 
-constexpr int PANEL_GROUPS = 128;  // workgroups per panel (4 per CU of an XCD: every one resident)
+constexpr int PANEL_GROUPS = 256;  // workgroups per panel (4 per CU of its two XCDs: every one resident)
 
 template <typename T, int MT>
 static hipError_t launch_passes_mt(const LaunchTables& t, hipStream_t st, int mode, hipEvent_t* ev) {
