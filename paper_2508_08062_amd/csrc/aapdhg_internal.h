@@ -18,7 +18,11 @@ constexpr int SPLIT_NNZ = 8192;   // nnz per part of a split (very long) row
 constexpr int DECIDE_RECORDS = 256;  // records added by one workgroup of the decision launch
 constexpr int MIX_TILE = 2048;    // elements per block of the mix pass
 constexpr int NDOT = 2 * MAXM + 16;  // stride of one partial-sum record (doubles)
-constexpr int PANELS = 4;         // column panels of the dual product (each taken by two XCDs)
+// Column panels of the dual product: 4 in float32 (each x_bar slice, 2 MB on
+// the 1M x 2M LP, taken by two XCDs), 8 in float64 (one slice per XCD, so that
+// a slice still fits an XCD's L2).
+constexpr int MAX_PANELS = 8;
+__host__ __device__ constexpr int panel_count(bool fp64) { return fp64 ? 8 : 4; }
 constexpr int PANEL_ROWS = 1024;  // rows of one panel chunk (four per thread)
 
 // Partial-sum record: MT = memory bound of the kernel instantiation.
@@ -131,8 +135,8 @@ struct LPDesc {
   // Column panels of the CSR (large LPs in launches of their own): the
   // entries of row position r whose column lies in panel p are
   // [pptr[p (m+1) + r], pptr[p (m+1) + r + 1]) of pidx / pval; part holds the
-  // panel row sums [2][PANELS][m] (x_bar, and x^k on KKT passes).
-  int panels;  // 0 or PANELS
+  // panel row sums [2][panels][m] (x_bar, and x^k on KKT passes).
+  int panels;  // 0 or panel_count(the LP's precision)
   const int* pptr;
   const int* pidx;
   const void* pval;
@@ -142,7 +146,7 @@ struct LPDesc {
   // entry pchunk[2 (pcoff[p] + c) + 1]; the list of each panel ends with
   // (m, the panel's last entry + 1)
   const int* pchunk;
-  int pcoff[PANELS + 1];
+  int pcoff[MAX_PANELS + 1];
 };
 
 // One workgroup's share of an SpMV pass.  "Rows" are columns of K in the

@@ -513,20 +513,21 @@ void Problem::create(int32_t m_, int32_t n_, int64_t nnz_, const int64_t* row_pt
   }
   d_rowtype.upload(rowtype.data(), rowtype.size(), "rowtype");
   // ---- column panels of the dual product for large LPs without split rows:
-  // the workgroups of panel p gather only the 1/PANELS of x_bar it covers,
-  // which stays in the L2 of the XCD that runs them ----
-  panels = (int64_t)nnz >= PANEL_MIN_NNZ && splitsB.empty() && n >= PANELS * 1024;
+  // the workgroups of panel p gather only the 1/np of x_bar it covers,
+  // which stays in the L2s of the XCDs that run them ----
+  const int np = panel_count(fp64);
+  panels = (int64_t)nnz >= PANEL_MIN_NNZ && splitsB.empty() && n >= np * 1024;
   if (panels) {
-    std::vector<int> pptr((size_t)PANELS * (m + 1), 0), pidx(nnz);
+    std::vector<int> pptr((size_t)np * (m + 1), 0), pidx(nnz);
     std::vector<double> pval(nnz);
-    auto panel_of = [&](int col) { return (int)((int64_t)col * PANELS / n); };
-    std::vector<int64_t> cnt(PANELS, 0);
+    auto panel_of = [&](int col) { return (int)((int64_t)col * np / n); };
+    std::vector<int64_t> cnt(np, 0);
     for (int q = 0; q < nnz; ++q) cnt[panel_of(idxB[q])]++;
-    std::vector<int64_t> base(PANELS + 1, 0);
-    for (int p = 0; p < PANELS; ++p) base[p + 1] = base[p] + cnt[p];
+    std::vector<int64_t> base(np + 1, 0);
+    for (int p = 0; p < np; ++p) base[p + 1] = base[p] + cnt[p];
     std::vector<int64_t> fill(base.begin(), base.end() - 1);
     for (int r = 0; r < m; ++r) {
-      for (int p = 0; p < PANELS; ++p) pptr[(size_t)p * (m + 1) + r] = (int)fill[p];
+      for (int p = 0; p < np; ++p) pptr[(size_t)p * (m + 1) + r] = (int)fill[p];
       for (int q = ptrB[r]; q < ptrB[r + 1]; ++q) {
         const int p = panel_of(idxB[q]);
         pidx[fill[p]] = idxB[q];
@@ -534,20 +535,20 @@ void Problem::create(int32_t m_, int32_t n_, int64_t nnz_, const int64_t* row_pt
         ++fill[p];
       }
     }
-    for (int p = 0; p < PANELS; ++p) pptr[(size_t)p * (m + 1) + m] = (int)fill[p];
+    for (int p = 0; p < np; ++p) pptr[(size_t)p * (m + 1) + m] = (int)fill[p];
     d_pptr.upload(pptr.data(), pptr.size() * 4, "panel pointers");
     d_pidx.upload(pidx.data(), pidx.size() * 4, "panel indices");
     if (fp64)
       upload_as<double>(d_pval, pval, "panel values");
     else
       upload_as<float>(d_pval, pval, "panel values");
-    d_part.alloc((size_t)2 * PANELS * m * 8, "panel sums");
+    d_part.alloc((size_t)2 * np * m * 8, "panel sums");
     // chunks of each panel for k_panel: consecutive rows, at most PANEL_ROWS
     // of them and CHUNK_NNZ entries; each listed as (first row, first entry),
     // the list of a panel closed by (m, the panel's end)
     std::vector<int> pchunk;
     int nlist = 0;
-    for (int p = 0; p < PANELS; ++p) {
+    for (int p = 0; p < np; ++p) {
       pcoff[p] = nlist;
       const int* pp = pptr.data() + (size_t)p * (m + 1);
       int r = 0;
@@ -568,7 +569,7 @@ void Problem::create(int32_t m_, int32_t n_, int64_t nnz_, const int64_t* row_pt
       pchunk.push_back(pp[m]);
       ++nlist;
     }
-    pcoff[PANELS] = nlist;
+    pcoff[np] = nlist;
     d_pchunk.upload(pchunk.data(), pchunk.size() * 4, "panel chunks");
     // the dual epilogue then only adds panel sums: chunks of BLOCK rows
     chunksBp.clear();
@@ -716,13 +717,13 @@ void Problem::fill_desc() {
   desc.W = d_hist_W.p;
   desc.lam = d_lam.p;
   desc.sc = (Scalars*)d_sc.p;
-  desc.panels = panels ? PANELS : 0;
+  desc.panels = panels ? panel_count(fp64) : 0;
   desc.pptr = (const int*)d_pptr.p;
   desc.pidx = (const int*)d_pidx.p;
   desc.pval = d_pval.p;
   desc.part = (double*)d_part.p;
   desc.pchunk = (const int*)d_pchunk.p;
-  for (int p = 0; p <= PANELS; ++p) desc.pcoff[p] = pcoff[p];
+  for (int p = 0; p <= MAX_PANELS; ++p) desc.pcoff[p] = pcoff[p];
 }
 
 // The scaling loops of create() on the device: the CSR (float64 values) and

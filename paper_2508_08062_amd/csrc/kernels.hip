@@ -639,6 +639,7 @@ __device__ __forceinline__ PassView make_view(const LPDesc& d, long long k, int 
 template <typename T, int MT, int PASS, bool COH, bool EXT>
 struct PassCtx {
   using DT = Dot<MT>;
+  static constexpr int NPAN = panel_count(sizeof(T) == 8);  // column panels of the dual product
   const LPDesc* dp;
   PassView v;
   int n, N;
@@ -853,10 +854,10 @@ struct PassCtx {
             row[j] = rmap[r];
             load_row(row[j], rin[j], false);
 #pragma unroll
-            for (int p = 0; p < PANELS; ++p) s1[j] += dp->part[(size_t)p * m + r];
+            for (int p = 0; p < NPAN; ++p) s1[j] += dp->part[(size_t)p * m + r];
             if (two) {
 #pragma unroll
-              for (int p = 0; p < PANELS; ++p) s2[j] += dp->part[(size_t)(PANELS + p) * m + r];
+              for (int p = 0; p < NPAN; ++p) s2[j] += dp->part[(size_t)(NPAN + p) * m + r];
             }
           }
         }
@@ -889,10 +890,10 @@ struct PassCtx {
         const int m = dp->m;
         double sum1 = 0.0, sum2 = 0.0;
 #pragma unroll
-        for (int p = 0; p < PANELS; ++p) sum1 += dp->part[(size_t)p * m + r];
+        for (int p = 0; p < NPAN; ++p) sum1 += dp->part[(size_t)p * m + r];
         if (two) {
 #pragma unroll
-          for (int p = 0; p < PANELS; ++p) sum2 += dp->part[(size_t)(PANELS + p) * m + r];
+          for (int p = 0; p < NPAN; ++p) sum2 += dp->part[(size_t)(NPAN + p) * m + r];
         }
         finish_row(row, rin, sum1, sum2, acc, false);
       }
@@ -1905,10 +1906,10 @@ __global__ __launch_bounds__(BLOCK) void k_loop(LoopArgs a) {
 // column panels of the dual product (large LPs): row sums per panel
 // ---------------------------------------------------------------------------
 
-// Workgroup b works on panel b % PANELS: workgroups are dealt to the eight
-// XCDs in turn, so each XCD gathers from one 1/PANELS slice of x_bar (XCDs p
-// and p + 4 share panel p), which stays in its L2.  A workgroup takes every
-// (gridDim / PANELS)-th chunk of its panel:
+// Workgroup b works on panel b % NP (NP = panel_count): workgroups are dealt
+// to the eight XCDs in turn, so each XCD gathers from one 1/NP slice of x_bar
+// (with 4 panels XCDs p and p + 4 share panel p), which stays in its L2.  A
+// workgroup takes every (gridDim / NP)-th chunk of its panel:
 // stages the chunk's products in LDS (eight gathers in flight per thread),
 // then each thread adds the entries of up to four rows in order.  Writes
 // part[0][p][r] (x_bar, or x^k when evaluating) and, on KKT passes,
@@ -1933,8 +1934,9 @@ __global__ __launch_bounds__(BLOCK) void k_panel(const LPDesc* lps, int mode) {
   const T* __restrict__ gv2 = ucur;
   const bool two = kkt && !eval;
   const int tid = threadIdx.x;
-  const int p = blockIdx.x % PANELS;
-  const int j = blockIdx.x / PANELS, nj = gridDim.x / PANELS;
+  constexpr int NP = panel_count(sizeof(T) == 8);
+  const int p = blockIdx.x % NP;
+  const int j = blockIdx.x / NP, nj = gridDim.x / NP;
   const int m = d.m;
   const int* __restrict__ ptr = d.pptr + (size_t)p * (m + 1);
   const int* __restrict__ idx = d.pidx;
@@ -1942,7 +1944,7 @@ __global__ __launch_bounds__(BLOCK) void k_panel(const LPDesc* lps, int mode) {
   const int* __restrict__ cst = d.pchunk + 2 * d.pcoff[p];  // (first row, first entry) per chunk
   const int nch = d.pcoff[p + 1] - d.pcoff[p] - 1;
   double* __restrict__ out1 = d.part + (size_t)p * m;
-  double* __restrict__ out2 = d.part + (size_t)(PANELS + p) * m;
+  double* __restrict__ out2 = d.part + (size_t)(NP + p) * m;
   // the chunk's loads: column indices, values and this thread's row ranges
   int ci[UNR], ra[RPT], rb[RPT];
   T vv[UNR];
@@ -2202,7 +2204,7 @@ __global__ void k_convert(const S* src, D* dst, size_t len) {
 // host-side launchers
 // ---------------------------------------------------------------------------
 
-constexpr int PANEL_GROUPS = 256;  // workgroups per panel (4 per CU of its two XCDs: every one resident)
+constexpr int PANEL_BLOCKS = 1024;  // workgroups of the panel kernel (4 per CU: every one resident)
 
 template <typename T, int MT>
 static hipError_t launch_passes_mt(const LaunchTables& t, hipStream_t st, int mode, hipEvent_t* ev) {
@@ -2228,7 +2230,7 @@ static hipError_t launch_passes_mt(const LaunchTables& t, hipStream_t st, int mo
       hipLaunchKernelGGL((k_pass<T, MT, 0, false>), dim3(t.nblocksA), dim3(BLOCK), 0, st, pa);
   }
   if (ev) (void)hipEventRecord(ev[1], st);
-  if (t.panels) hipLaunchKernelGGL((k_panel<T>), dim3(PANELS * PANEL_GROUPS), dim3(BLOCK), 0, st, t.lps, mode);
+  if (t.panels) hipLaunchKernelGGL((k_panel<T>), dim3(PANEL_BLOCKS), dim3(BLOCK), 0, st, t.lps, mode);
   pa.blocks = t.blocksB;
   if (t.nblocksB > 0) {
     if (t.dots)

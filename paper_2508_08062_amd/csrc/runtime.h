@@ -125,7 +125,7 @@ struct Problem {
   DevBuf d_scale;   // d_col then d_row, for results written to device memory (made on first use)
   DevBuf d_pptr, d_pidx, d_pval, d_part, d_pchunk;  // column panels of the dual product
   bool panels = false;
-  int pcoff[PANELS + 1] = {};
+  int pcoff[MAX_PANELS + 1] = {};
   std::vector<Chunk> chunksBp;  // dual pass in a launch of its own with panels: 256-row chunks
   int row_weight = 4;           // chunk cost model: entries a row counts beyond its own
   std::vector<int> dev_ptrA, dev_ptrB;  // row pointers of the device row orders (host copies)
