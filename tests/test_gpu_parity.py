@@ -224,6 +224,60 @@ def _teacher_forced(lp, g, o, steps, tol):
     return errs
 
 
+@pytest.mark.parametrize("variant,cs", [(1, 0.8), (2, 0.8), (2, 0.05)])
+def test_gamma_from_the_gram_matches_least_squares_fp64(variant, cs):
+    """The mixing weights against the oracle's, one pass at a time from the
+    GPU's own state: the GPU solves the normal equations of its float64 Gram
+    (dG^T dG + eta I) gamma = dG^T g (Alg 2) and runs the filters of Alg 4-5
+    on that Gram; the oracle factors by Cholesky (AA) or filters and solves by
+    Householder QR of dG itself (FAA).  With c_s = 0.8 the angle filter
+    removes columns on more than half the steps, so kept columns sit near
+    its limit; with 0.05 it keeps nearly all and the length filter (Alg 5)
+    holds the memory at six columns.  Both sides keep the same columns and
+    gamma agrees to 1e-11 of max(1, |gamma|): the two solutions differ by
+    about cond(G) times the float64 rounding, cond(G) stays below 500 on
+    these memories (largest with plain AA, whose Gram is never filtered),
+    and the largest difference measured is 1.9e-14."""
+    lp = lpgen.mip_like_lp(12, m=1500, n=3500, nnz=20000, fp32=False)
+    tau = 0.9 / oracle.power_norm(oracle.Problem.from_lpdata(lp))
+    common = dict(variant=variant, memory=10, tau=tau, sigma=tau, kkt_every=1, tol=0.0, max_iter=10 ** 6, cs=cs,
+                  D=1e6)
+    g = _gpu(lp, precision=1, **common)
+    o = _oracle(lp, **common)
+    o.start()
+    g.iterate(1)
+    for _ in range(12):  # fill the memory
+        o.step()
+        g.iterate(1)
+    beta = o.opt.beta
+    compared, filtered, worst = 0, 0, 0.0
+    for _ in range(30):
+        st = g.get_state()
+        S = o.state
+        S.k = st["k"]
+        S.x, S.y = st["u"][:lp.n].copy(), st["u"][lp.n:].copy()
+        S.u_prev, S.g_prev = st["u_prev"].copy(), st["g_prev"].copy()
+        S.dG = [st["dG"][t].copy() for t in st["live"]]
+        S.dU = [st["W"][t] - beta * o.Dhat * st["dG"][t] for t in st["live"]]
+        S.i, S.j, S.n0 = st["i"], st["j"], st["n0"]
+        o.step()
+        g.iterate(1)
+        st2 = g.get_state()
+        assert (st2["i"], st2["j"]) == (o.state.i, o.state.j)
+        if o.last_branch != "aa" or len(o.last_gamma) == 0:
+            continue
+        ref = np.asarray(o.last_gamma)
+        assert st2["nmix"] == ref.size
+        filtered += ref.size < min(len(st["live"]) + 1, 10)
+        worst = max(worst, float(np.max(np.abs(st2["gamma"] - ref)) / max(1.0, float(np.max(np.abs(ref))))))
+        compared += 1
+    assert compared >= 25
+    if variant == 2 and cs == 0.8:
+        assert filtered >= 10  # the angle filter removed columns
+    assert worst < 1e-11, worst
+    g.close()
+
+
 def _ragged_lp():
     # rows longer than one chunk (split into parts with a fix-up), a row long
     # enough for a whole-block reduction, empty rows and empty columns
