@@ -499,6 +499,61 @@ def _sweep(args):
     print(json.dumps(line), flush=True)
 
 
+def _dsweep(args):
+    """The safeguard constant D (Alg 2's safeguard test; Section 5.1 shows the
+    KKT history of AA-PDHG with m_A = 5 under several D): AA-PDHG with
+    m_A = 5, eta = 1e-10, epsilon = 1 and D from 1e-2 to 1e6 on the sweep
+    LP, float32, every value a member of one batch.  Every `dsweep_every`
+    passes the relative KKT residual of each member is evaluated at its
+    current iterate, until every member converged (1e-4) or reached the pass
+    limit."""
+    import numpy as np
+    import torch
+
+    import lpgen
+    import paper_2508_08062_amd as P
+    lp = lpgen.mip_like_lp(args.sweep_seed, m=args.sweep_m, n=int(2.5 * args.sweep_m), nnz=int(12.5 * args.sweep_m))
+    Ds = [1e-2, 1e-1, 1.0, 10.0, 1e2, 1e4, 1e6]
+    base = dict(variant=1, precision=0, memory=5, eta=1e-10, eps_sg=1.0, kkt_every=64, ruiz_iters=10, dhat_mode=0,
+                tol=1e-4, max_iter=args.sweep_max_iter)
+    solvers = [P.Solver(lp, D=D, **base) for D in Ds]
+    batch = P.Batch(solvers)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    every = args.dsweep_every
+    hist = [[] for _ in Ds]
+    t0 = time.perf_counter()
+    done = 0
+    while done <= args.sweep_max_iter + every:  # members stop at the pass limit on their own
+        batch.iterate(every, stream)
+        done += every
+        res = batch.results()
+        for h, r in zip(hist, res):
+            if r["status"] == "running" or not h or h[-1][0] < r["iters"]:
+                h.append((r["iters"], r["kkt"]))
+        if all(r["status"] != "running" for r in res):
+            break
+    el = time.perf_counter() - t0
+    res = batch.results()
+    rows = [{"D": D, "status": r["status"], "iters": r["iters"], "aa_steps": r["aa_steps"],
+             "aa_fraction": r["aa_steps"] / max(1, r["iters"]), "kkt": r["kkt"],
+             "kkt_history": [[int(k), float(v)] for k, v in h]}
+            for D, r, h in zip(Ds, res, hist)]
+    batch.close()
+    for sv in solvers:
+        sv.close()
+    for r in rows:
+        print(f"# D={r['D']:.0e}: {r['status']} {r['iters']} passes, {r['aa_steps']} Anderson steps, "
+              f"KKT {r['kkt']:.2e}", file=sys.stderr, flush=True)
+    line = _line("AA-PDHG safeguard constant sweep: passes to rel KKT 1e-4 (batched float32)",
+                 len(rows) / el, "configurations/s",
+                 {"workload": f"one LP {lp.m}x{lp.n}, {lp.nnz} nnz (mip_like_lp seed {args.sweep_seed}), "
+                              f"{len(rows)} values of D in one batch", "variant": "AA-PDHG", "m_A": 5},
+                 {"batch_seconds": el, "kkt_every_passes": every, "configurations": rows,
+                  "median_passes": float(np.median([r["iters"] for r in rows]))}, ms=el * 1e3)
+    print(json.dumps(line), flush=True)
+
+
 def _serve_curve(args):
     """Latency against throughput of the server: Poisson streams at rising
     rates (each 10 s with up to 40 s of drain), the knee of the curve beside
@@ -591,11 +646,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="powerlaw1m", choices=["mip20k", "powerlaw1m", "batch256", "serve", "serve_curve", "compare", "sweep"])
+    ap.add_argument("--workload", default="powerlaw1m", choices=["mip20k", "powerlaw1m", "batch256", "serve", "serve_curve", "compare", "sweep",
+                                                                 "dsweep"])
     ap.add_argument("--compare-max-iter", type=int, default=300000, help="compare: pass limit per method")
     ap.add_argument("--sweep-m", type=int, default=20000, help="sweep: rows of the LP (columns 2.5x, 12.5 nnz/row)")
     ap.add_argument("--sweep-seed", type=int, default=1)
     ap.add_argument("--sweep-max-iter", type=int, default=100000)
+    ap.add_argument("--dsweep-every", type=int, default=1000, help="dsweep: passes between KKT evaluations")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: requests per second")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="serve: length of the arrival stream")
     ap.add_argument("--pool", type=int, default=64, help="serve: distinct LPs cycled through the stream")
@@ -657,6 +714,8 @@ def main():
         return _compare(args)
     if args.workload == "sweep":
         return _sweep(args)
+    if args.workload == "dsweep":
+        return _dsweep(args)
     lps, opts, cfg = _workload(args.workload)
     if args.chunks_per_block:
         opts["chunks_per_block"] = args.chunks_per_block
