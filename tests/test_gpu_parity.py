@@ -224,8 +224,9 @@ def _teacher_forced(lp, g, o, steps, tol):
     return errs
 
 
+@pytest.mark.parametrize("loop_kernel,gram_mode", [(0, 0), (1, 2)])
 @pytest.mark.parametrize("variant,cs", [(1, 0.8), (2, 0.8), (2, 0.05)])
-def test_gamma_from_the_gram_matches_least_squares_fp64(variant, cs):
+def test_gamma_from_the_gram_matches_least_squares_fp64(variant, cs, loop_kernel, gram_mode):
     """The mixing weights against the oracle's, one pass at a time from the
     GPU's own state: the GPU solves the normal equations of its float64 Gram
     (dG^T dG + eta I) gamma = dG^T g (Alg 2) and runs the filters of Alg 4-5
@@ -237,12 +238,14 @@ def test_gamma_from_the_gram_matches_least_squares_fp64(variant, cs):
     gamma agrees to 1e-11 of max(1, |gamma|): the two solutions differ by
     about cond(G) times the float64 rounding, cond(G) stays below 500 on
     these memories (largest with plain AA, whose Gram is never filtered),
-    and the largest difference measured is 1.9e-14."""
+    and the largest difference measured is 1.9e-14.  Both ways of forming
+    the Gram matrix: updated pass by pass in the persistent kernel, and from
+    the stored columns by the Gram launch of the three-launch path."""
     lp = lpgen.mip_like_lp(12, m=1500, n=3500, nnz=20000, fp32=False)
     tau = 0.9 / oracle.power_norm(oracle.Problem.from_lpdata(lp))
     common = dict(variant=variant, memory=10, tau=tau, sigma=tau, kkt_every=1, tol=0.0, max_iter=10 ** 6, cs=cs,
                   D=1e6)
-    g = _gpu(lp, precision=1, **common)
+    g = _gpu(lp, precision=1, loop_kernel=loop_kernel, gram_mode=gram_mode, **common)
     o = _oracle(lp, **common)
     o.start()
     g.iterate(1)
@@ -275,6 +278,7 @@ def test_gamma_from_the_gram_matches_least_squares_fp64(variant, cs):
     if variant == 2 and cs == 0.8:
         assert filtered >= 10  # the angle filter removed columns
     assert worst < 1e-11, worst
+    assert g.result()["gram_on_demand"] == (gram_mode == 2)
     g.close()
 
 
