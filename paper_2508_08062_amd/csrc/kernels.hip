@@ -96,6 +96,24 @@ __device__ __forceinline__ double ld_coh(const double* base, int idx) {
   const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), 0, 0x7fffffff, 0x00020000);
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, idx * 8, 0, 16));
 }
+// Sum of base[first + i * stride] for i = 0 .. count - 1, added in that
+// order, with U coherent loads issued together: a loop that adds each value
+// as it is loaded waits for every load on its own.  The loads past count read
+// the last value again and are not added, so the sum is the plain in-order
+// one bit for bit.
+template <int U>
+__device__ __forceinline__ double ordered_sum_coh(const double* base, int first, int stride, int count) {
+  double s = 0.0;
+  for (int i0 = 0; i0 < count; i0 += U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = ld_coh(base, first + (i0 + u < count ? i0 + u : count - 1) * stride);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i0 + u < count) s += v[u];
+  }
+  return s;
+}
 __device__ __forceinline__ void wait_stores() {
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's stores are complete
 }
@@ -1013,11 +1031,9 @@ struct PassCtx {
       RowIn<T, MT> in;
       const int row = rmap[sr.row];
       load_row(row, in, true);
-      double t1 = 0.0, t2 = 0.0;
-      for (int p = 0; p < sr.nparts; ++p) {
-        t1 += ld_coh(splitpart, 2 * (sr.part0 + p) + 0);
-        t2 += ld_coh(splitpart, 2 * (sr.part0 + p) + 1);
-      }
+      // the parts' sums in part order
+      const double t1 = ordered_sum_coh<16>(splitpart, 2 * sr.part0 + 0, 2, sr.nparts);
+      const double t2 = ordered_sum_coh<16>(splitpart, 2 * sr.part0 + 1, 2, sr.nparts);
       for (int q = 0; q < DT::COUNT; ++q) s_racc[q] = 0.0;
       finish_row(row, in, t1, t2, s_racc, true);
       double* rp = rec + (size_t)sr.leaf * NDOT;
@@ -1164,10 +1180,20 @@ __global__ __launch_bounds__(BLOCK) void k_decide(PassArgs a) {
   const int t = tid / C, q = tid - (tid / C) * C;
   double s = 0.0;
   if (t < PT) {
-#pragma unroll 4
-    for (int p = db.r0 + t; p < db.r1; p += PT) {
-      const int rix = p < db.nA ? db.leafA + p : db.leafB + (p - db.nA);
-      s += a.rec[(size_t)rix * NDOT + q];
+    // positions r0 + t, r0 + t + PT, ... added in order, RB loads issued
+    // together (those past r1 read position p0 again and are not added)
+    constexpr int RB = 16;
+    for (int p0 = db.r0 + t; p0 < db.r1; p0 += RB * PT) {
+      double v[RB];
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        const int p = p0 + u * PT < db.r1 ? p0 + u * PT : p0;
+        const int rix = p < db.nA ? db.leafA + p : db.leafB + (p - db.nA);
+        v[u] = a.rec[(size_t)rix * NDOT + q];
+      }
+#pragma unroll
+      for (int u = 0; u < RB; ++u)
+        if (p0 + u * PT < db.r1) s += v[u];
     }
   }
 #pragma unroll
@@ -1191,9 +1217,7 @@ __global__ __launch_bounds__(BLOCK) void k_decide(PassArgs a) {
     if (!s_flag) return;
     if (tid == 0) reset_counter(&a.dcnt[db.lp]);
     if (tid < C) {
-      double sum = 0.0;
-      for (int g = 0; g < db.nblk; ++g) sum += ld_coh(a.dpart, (db.blk0 + g) * NDOT + tid);
-      s_fin[tid] = sum;
+      s_fin[tid] = ordered_sum_coh<16>(a.dpart, db.blk0 * NDOT + tid, NDOT, db.nblk);
     }
   } else if (tid < C) {
     s_fin[tid] = 0.0 + part;  // the ordered sum of the one partial
@@ -1228,8 +1252,9 @@ __global__ __launch_bounds__(BLOCK) void k_decide(PassArgs a) {
 // values are stored value-major.  The workgroup that finishes the LP's last
 // tile adds each value's partials in a fixed order (per LP): with at most 64
 // tiles, one wave per value (lane l holds tile l) and its DPP sum; with more,
-// thread t adds tiles t, t + BLOCK, ... in order, then the same block
-// reduction.  Values: G[a][b] for a <= b < MT at a MT - a (a - 1) / 2 + (b - a),
+// lane l of the value's wave first adds tiles l, l + 64, ... in order.  The
+// partials are read with many loads in flight: this sum is the serial tail of
+// an Anderson step.  Values: G[a][b] for a <= b < MT at a MT - a (a - 1) / 2 + (b - a),
 // then r[a] at MT (MT + 1) / 2 + a.
 template <int MT>
 __host__ __device__ constexpr int gram_values() {
@@ -1329,20 +1354,35 @@ __global__ __launch_bounds__(BLOCK) void k_gram(GramArgs a) {
   unsigned long long* lsc = reinterpret_cast<unsigned long long*>(&s_sc);
   for (int w = tid; w < SW; w += BLOCK) lsc[w] = gsc[w];
   if (tl.nt <= 64) {
-    // few tiles: wave w adds values w, w + 4, ... (lane l holds tile l), DPP sum
-    for (int q = wv; q < NV; q += BLOCK / 64) {
-      const double v = wave_sum(lane < tl.nt ? ld_coh(part, q * tl.nt + lane) : 0.0);
-      if (lane == 0) s_val[q] = v;
+    // few tiles: wave w adds values w, w + 4, ... (lane l holds tile l), DPP
+    // sum; the wave's loads are issued together first (lanes past the tiles
+    // and values past NV read an existing partial, which is not used)
+    constexpr int NW = BLOCK / 64;
+    constexpr int QPW = (NV + NW - 1) / NW;
+    const int tl_lane = lane < tl.nt ? lane : 0;
+    double pv[QPW];
+#pragma unroll
+    for (int i = 0; i < QPW; ++i) {
+      const int q = wv + i * NW;
+      pv[i] = ld_coh(part, (q < NV ? q : 0) * tl.nt + tl_lane);
+    }
+#pragma unroll
+    for (int i = 0; i < QPW; ++i) {
+      const int q = wv + i * NW;
+      const double v = wave_sum(lane < tl.nt ? pv[i] : 0.0);
+      if (q < NV && lane == 0) s_val[q] = v;
     }
     __syncthreads();
   } else {
-#pragma unroll
-    for (int q = 0; q < NV; ++q) acc[q] = 0.0;
-    for (int b = tid; b < tl.nt; b += BLOCK) {
-#pragma unroll
-      for (int q = 0; q < NV; ++q) acc[q] += ld_coh(part, q * tl.nt + b);
+    // many tiles: wave w adds values w, w + 4, ...; lane l adds tiles l,
+    // l + 64, ... of the value in order (24 loads issued together), then the
+    // DPP sum over the lanes
+    for (int q = wv; q < NV; q += BLOCK / 64) {
+      const int cnt = lane < tl.nt ? (tl.nt - lane + 63) / 64 : 0;
+      const double v = wave_sum(ordered_sum_coh<24>(part, q * tl.nt + lane, 64, cnt));
+      if (lane == 0) s_val[q] = v;
     }
-    block_sums<NV>(acc, s_red, s_val);
+    __syncthreads();
   }
   if (tid < NV) {
     // value tid -> (row, column) of G, or the row of r
