@@ -96,6 +96,10 @@ __device__ __forceinline__ double ld_coh(const double* base, int idx) {
   const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), 0, 0x7fffffff, 0x00020000);
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, idx * 8, 0, 16));
 }
+// A value the same in every lane (a chunk bound from a table), made known to
+// the compiler as such, so that a test on it branches once for the wave.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // Sum of base[first + i * stride] for i = 0 .. count - 1, added in that
 // order, with U coherent loads issued together: a loop that adds each value
 // as it is loaded waits for every load on its own.  The loads past count read
@@ -917,22 +921,29 @@ struct PassCtx {
       }
       return;
     }
+    // Every load of the chunk is made, positions past its end reading its
+    // last entry (their products are not staged): a load under a bounds test
+    // of its own is waited for before the next one is issued, which the
+    // persistent kernel, one wave per SIMD, cannot hide.  ne is the same for
+    // the whole workgroup; an empty chunk gathers entry 0 (m, n >= 1).
+    const bool ne = uni(ke) > uni(kb);
     int ci[UNR];
     T vv[UNR];
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
-      const int q = kb + tid + u * BLOCK;
+      const int o = tid + u * BLOCK;
+      const int oc = kb + o < ke ? o : ke - 1 - kb;
       ci[u] = 0;
       vv[u] = (T)0;
-      if (q < ke) {
+      if (ne) {
         if constexpr (COH) {
-          ci[u] = CACHED ? cidx[tid + u * BLOCK] : idx[q];
-          vv[u] = val[q];
+          ci[u] = CACHED ? cidx[oc] : idx[kb + oc];
+          vv[u] = val[kb + oc];
         } else {
           // a launch streams the matrix once: non-temporal, so the gathered
           // vector keeps its place in L2
-          ci[u] = __builtin_nontemporal_load(&idx[q]);
-          vv[u] = __builtin_nontemporal_load(&val[q]);
+          ci[u] = __builtin_nontemporal_load(&idx[kb + oc]);
+          vv[u] = __builtin_nontemporal_load(&val[kb + oc]);
         }
       }
     }
@@ -949,7 +960,7 @@ struct PassCtx {
       const T* gv = sw == 0 ? gv1 : gv2;
       T gg[UNR];
 #pragma unroll
-      for (int u = 0; u < UNR; ++u) gg[u] = (kb + tid + u * BLOCK < ke) ? gather(gv, ci[u]) : (T)0;
+      for (int u = 0; u < UNR; ++u) gg[u] = gather(gv, ci[u]);
       __syncthreads();  // s_prod is free
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
@@ -995,21 +1006,30 @@ struct PassCtx {
     for (int base = kb; base < ke; base += UNR * BLOCK) {
       int ci[UNR];
       T vv[UNR], g1[UNR], g2[UNR];
+      // every load is made (positions past the part's end read its last
+      // entry) and the values past the end are then set to zero
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
         const int q = base + tid + u * BLOCK;
-        ci[u] = 0;
-        vv[u] = (T)0;
-        if (q < ke) {
-          ci[u] = COH ? idx[q] : __builtin_nontemporal_load(&idx[q]);
-          vv[u] = COH ? val[q] : __builtin_nontemporal_load(&val[q]);
-        }
+        const int qc = q < ke ? q : ke - 1;
+        ci[u] = COH ? idx[qc] : __builtin_nontemporal_load(&idx[qc]);
+        vv[u] = COH ? val[qc] : __builtin_nontemporal_load(&val[qc]);
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) g1[u] = gather(gv1, ci[u]);
+      if (two) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) g2[u] = gather(gv2, ci[u]);
+      } else {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) g2[u] = (T)0;
       }
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
         const bool ok = base + tid + u * BLOCK < ke;
-        g1[u] = ok ? gather(gv1, ci[u]) : (T)0;
-        g2[u] = (ok && two) ? gather(gv2, ci[u]) : (T)0;
+        vv[u] = ok ? vv[u] : (T)0;
+        g1[u] = ok ? g1[u] : (T)0;
+        g2[u] = ok ? g2[u] : (T)0;
       }
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
